@@ -1,0 +1,200 @@
+/*
+ * afqmc.h - C ABI of the MI355X (gfx950) phaseless AFQMC walker update.
+ *
+ * Method: Shee, Arthur, Zhang, Reichman, Friesner, "Phaseless Auxiliary-Field
+ * Quantum Monte Carlo on Graphical Processing Units" (arXiv 1804.03310),
+ * Sec. II (imaginary-time projection, Eq. 1 Hamiltonian, Eq. 2
+ * Hubbard-Stratonovich transform, Eq. 3 propagator, force bias, local energy,
+ * phaseless constraint) and Sec. III (batched Sherman-Morrison-Woodbury
+ * update for multi-determinant trials; energy through half-rotated
+ * Cholesky vectors, the partial contraction inside Eq. Ys; sp/dp switching).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Matrices are row-major, float64, and all indices are 0-based.
+ * - One system has M orbitals, N_up / N_dn electrons and n_chol Cholesky
+ *   vectors with V_ijkl = sum_g L[g][i][k] L[g][j][l] (Eq. 1).
+ * - A walker is a pair of Slater determinants stored side by side as an
+ *   M x (N_up + N_dn) complex matrix in planar form: phi_re[w][m][c] and
+ *   phi_im[w][m][c], columns 0..N_up-1 spin up, N_up.. spin down.
+ * - Device pointers are HIP device memory on the device the Hamiltonian was
+ *   created on; host pointers are ordinary host memory.  The library never
+ *   frees caller memory.  Inputs passed to init_* are copied; the caller may
+ *   free them when the call returns.
+ * - Every call that takes a `stream` (a hipStream_t passed as void*, NULL =
+ *   default stream) enqueues its work on it and returns without waiting,
+ *   unless it writes a host pointer, in which case it synchronises that
+ *   stream before returning.  Device outputs are valid once the stream has
+ *   completed.
+ * - Argument errors are detected before anything is enqueued and return
+ *   AFQMC_ERR_ARG; afqmc_last_error() then gives a message (thread-local).
+ *   Numerical trouble in a single walker is not an error: the walker dies
+ *   (weight 0) and is reset to the reference determinant.
+ * - No C++ exception crosses this interface.
+ */
+#ifndef AFQMC_H
+#define AFQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AFQMC_OK = 0,
+  AFQMC_ERR_ARG = -1,         /* invalid argument (shape, pointer, value)      */
+  AFQMC_ERR_OOM = -2,         /* device allocation failed                      */
+  AFQMC_ERR_DEVICE = -3,      /* a HIP call failed                             */
+  AFQMC_ERR_STATE = -4,       /* objects do not belong together                */
+  AFQMC_ERR_SINGULAR = -5,    /* trial overlap with itself is singular         */
+  AFQMC_ERR_NONFINITE = -6,   /* every walker is dead (sum of weights is 0)    */
+  AFQMC_ERR_UNSUPPORTED = -7  /* size or precision outside this build's limits */
+} afqmc_status;
+
+/* Arithmetic of a contraction (Sec. III: single- vs double-precision). */
+typedef enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1 } afqmc_prec;
+
+#define AFQMC_MAX_EXC 4      /* excitations per spin in one determinant      */
+#define AFQMC_MAX_NEL 64     /* electrons per spin                           */
+#define AFQMC_MAX_M 256      /* orbitals                                     */
+
+typedef struct afqmc_ham afqmc_ham;     /* library-owned, device resident */
+typedef struct afqmc_trial afqmc_trial; /* library-owned, device resident */
+
+/* A batch of walkers.  All buffers are caller-owned device memory.
+ * phi_re/phi_im [n_walkers][M][N_up+N_dn]; weight, logovlp_*, eloc_*
+ * [n_walkers].  logovlp is log <Psi_T|phi> (complex, imaginary part defined
+ * modulo 2 pi), eloc the last local energy.  workspace is scratch the library
+ * lays out itself (overlap inverses, Theta, force-bias traces, propagator
+ * matrices, Taylor terms, comb snapshot); its size comes from
+ * afqmc_walker_workspace_bytes and it must not be shared between batches
+ * that run concurrently.  system_id enters the random-number counter. */
+typedef struct {
+  int32_t n_walkers;
+  int32_t system_id;
+  double *phi_re, *phi_im;
+  double *weight;
+  double *logovlp_re, *logovlp_im;
+  double *eloc_re, *eloc_im;
+  void *workspace;
+  size_t workspace_bytes;
+} afqmc_walkers;
+
+/* Run options.  taylor_order: terms of the series for exp(A) (>= 1).
+ * ortho_every / pc_every: orthonormalise / comb after global step t when
+ * (t+1) is a multiple (0 = never).  e_trial: E_T of the weight factor.
+ * chol_prec: arithmetic of sum_g x_g L_g and of Ltil_g Theta;
+ * taylor_prec: arithmetic of the Taylor products and of B1 phi.
+ * Overlaps, inverses, determinants, MGS and all final sums are FP64. */
+typedef struct {
+  int32_t taylor_order;
+  int32_t ortho_every;
+  int32_t pc_every;
+  double e_trial;
+  afqmc_prec chol_prec;
+  afqmc_prec taylor_prec;
+} afqmc_options;
+
+/* Hamiltonian of Eq. 1: one-body h [M][M] (symmetric), Cholesky vectors
+ * L [n_chol][M][M] (each symmetric) with V_ijkl = sum_g L_g,ik L_g,jl, and a
+ * constant e_core.  Host inputs, copied to `device`.  Symmetry is checked to
+ * 1e-10 (relative to the largest entry); 1 <= M <= AFQMC_MAX_M, n_chol >= 0. */
+afqmc_status afqmc_init_hamiltonian(afqmc_ham **out, int device, void *stream,
+                                    int M, int n_chol, const double *h,
+                                    const double *L, double e_core);
+
+/* Trial wavefunction Psi_T = sum_i coeff[i] |D_i> (Sec. III).  C_up, C_dn
+ * [M][M] host: orthonormal orbitals as columns; the reference determinant D_0
+ * occupies columns 0..N_sigma-1.  exc [n_det][2][1 + 2*AFQMC_MAX_EXC] host
+ * int32: for determinant i and spin s, exc[i][s][0] = E (number of
+ * excitations), then E hole orbitals (< N_s), then at offset 1+AFQMC_MAX_EXC
+ * E particle orbitals (>= N_s); hole e is replaced in place by particle e.
+ * Row 0 must be the reference (E = 0 for both spins).  coeff [n_det] host.
+ * For n_det = 1, coeff and exc may be NULL.  mf_subtract = 1 subtracts the
+ * reference-determinant mean field lbar_g = <D_0|L_g|D_0> from the fields
+ * (an exact rewrite of Eq. 2); 0 uses lbar = 0.  The multi-determinant path
+ * supports E <= 2 per spin.  Returns AFQMC_ERR_SINGULAR if D_0^T D_0 is
+ * singular. */
+afqmc_status afqmc_init_trial(afqmc_trial **out, afqmc_ham *ham, int n_up, int n_dn,
+                              const double *C_up, const double *C_dn, int n_det,
+                              const double *coeff, const int32_t *exc, int mf_subtract);
+
+/* Bytes of walker workspace for n_walkers walkers of this trial. */
+afqmc_status afqmc_walker_workspace_bytes(const afqmc_trial *trial, int n_walkers,
+                                          size_t *bytes);
+
+/* Sets every walker to the reference determinant D_0 with weight 1 and
+ * fills logovlp / eloc with the reference values. */
+afqmc_status afqmc_walkers_from_trial(afqmc_ham *ham, afqmc_trial *trial,
+                                      afqmc_walkers *walkers, void *stream);
+
+/* n_steps timesteps of length dt for every walker (Sec. II):
+ *   fields x ~ N(0,1) (Philox4x64-10, key (seed, 0), counter
+ *   (t, walker, gamma/4, system_id), Box-Muller), force bias
+ *   xbar = -i sqrt(dt)(v - lbar) from the mixed estimate v_g = <L_g>,
+ *   phi <- B1 exp(A) B1 phi with A = i sqrt(dt) sum_g (x_g - xbar_g) L_g and
+ *   B1 = exp(-dt H1'/2), H1' = h - 1/2 sum L_g L_g + sum lbar_g L_g,
+ *   new overlap, E_L = <Psi_T|H|phi>/<Psi_T|phi>, and the phaseless weight
+ *   W <- W exp(-dt (Re E_L - e_trial)) max(0, cos dtheta) with
+ *   dtheta = Im log(<Psi_T|phi'>/<Psi_T|phi>) including the mean-field
+ *   phase.  Global step indices are step0 .. step0+n_steps-1.  The call
+ *   first refreshes logovlp, eloc and v from phi.  emix_dev (device,
+ *   [n_steps], nullable) receives sum W Re E_L / sum W after each step
+ *   (before orthonormalisation / combing).  */
+afqmc_status afqmc_propagate(afqmc_ham *ham, afqmc_trial *trial, afqmc_walkers *walkers,
+                             int n_steps, double dt, uint64_t seed, uint64_t step0,
+                             const afqmc_options *opt, double *emix_dev, void *stream);
+
+/* Refreshes logovlp, eloc (and the stored force-bias traces) of every walker
+ * from phi; weights unchanged.  If emix_host is non-NULL it receives
+ * sum W Re E_L / sum W (synchronises the stream; AFQMC_ERR_NONFINITE if the
+ * sum of weights is 0). */
+afqmc_status afqmc_local_energy(afqmc_ham *ham, afqmc_trial *trial, afqmc_walkers *walkers,
+                                double *emix_host, void *stream);
+
+/* Modified Gram-Schmidt of each walker's spin blocks (positive real R
+ * diagonal), then logovlp recomputed; weights and eloc unchanged
+ * (Sec. IV.A: walkers orthonormalized periodically). */
+afqmc_status afqmc_orthonormalize(afqmc_ham *ham, afqmc_trial *trial, afqmc_walkers *walkers,
+                                  void *stream);
+
+/* Population control by a systematic comb (Sec. IV.A, Sec. V): inclusive
+ * prefix sums of the weights, left to right; one uniform xi (Philox key
+ * (seed, 1), counter (pc_index, 0, 0, system_id), word 0); tooth j at
+ * ((j + xi) W_tot) / K picks the first walker whose prefix sum exceeds it.
+ * Walker state is copied from the parents and weights reset to 1.
+ * norm_factor_host (nullable) receives W_tot / K (synchronises the stream). */
+afqmc_status afqmc_reconfigure(afqmc_trial *trial, afqmc_walkers *walkers, uint64_t seed,
+                               uint64_t pc_index, double *norm_factor_host, void *stream);
+
+/* The auxiliary fields afqmc_propagate draws at global step t:
+ * x_dev [n_walkers][n_chol] device float64. */
+afqmc_status afqmc_fields(uint64_t seed, uint64_t t, int n_walkers, int n_chol,
+                          int system_id, double *x_dev, void *stream);
+
+/* Kernel timing.  When enabled, every launch of the kernels of one class
+ * made by this Hamiltonian's calls is bracketed by a pair of HIP events
+ * recorded on the launch stream.  Classes: 0 fused exchange / force bias
+ * (L~ Theta contraction), 1 propagator build sum_g c_g L_g, 2 Taylor and
+ * B1 products, 3 overlap / inverse / Theta, 4 MGS, 5 comb, 6 other
+ * per-walker kernels.  afqmc_timing_read synchronises on the recorded
+ * events, returns the number of timed launches and their summed duration in
+ * milliseconds for one class, and clears that class. */
+#define AFQMC_NUM_KERNEL_CLASSES 7
+afqmc_status afqmc_timing_enable(afqmc_ham *ham, int enable);
+afqmc_status afqmc_timing_read(afqmc_ham *ham, int kernel_class, int64_t *launches,
+                               double *total_ms);
+
+void afqmc_free_hamiltonian(afqmc_ham *ham);
+void afqmc_free_trial(afqmc_trial *trial);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *afqmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFQMC_H */

@@ -319,19 +319,19 @@ class Oracle:
         self.D = [[self.C[s][:, self.occ[i][s]] for s in range(2)] for i in range(self.n_det)]
         # Half-rotated tensors C^T L_gamma and C^T h for all M rows; a
         # determinant's rows are picked by its occupation list.
-        self.Lfull = [np.einsum("mp,gmn->gpn", self.C[s], self.L) for s in range(2)]
+        self.Lfull = [np.einsum("mp,gmn->gpn", self.C[s], self.L, optimize=True) for s in range(2)]
         self.hfull = [self.C[s].T @ self.h for s in range(2)]
         # lbar_gamma = <D_0| L_gamma |D_0> = sum_sigma Tr(D_0^T L_gamma D_0).
         if mf_subtract:
-            self.lbar = sum(np.einsum("ma,gmn,na->g", self.D[0][s], self.L, self.D[0][s])
+            self.lbar = sum(np.einsum("ma,gmn,na->g", self.D[0][s], self.L, self.D[0][s], optimize=True)
                             for s in range(2) if self.nel[s] > 0)
             if np.isscalar(self.lbar):
                 self.lbar = np.zeros(self.n_chol)
         else:
             self.lbar = np.zeros(self.n_chol)
         # H1' = h - 1/2 sum_gamma L_gamma L_gamma + sum_gamma lbar_gamma L_gamma.
-        self.H1p = (self.h - 0.5 * np.einsum("gik,gkj->ij", self.L, self.L)
-                    + np.einsum("g,gij->ij", self.lbar, self.L))
+        self.H1p = (self.h - 0.5 * np.einsum("gik,gkj->ij", self.L, self.L, optimize=True)
+                    + np.einsum("g,gij->ij", self.lbar, self.L, optimize=True))
         self._b1 = {}
 
     @classmethod
@@ -393,11 +393,13 @@ class Oracle:
                 if j != i:
                     P2[:, i, j] = np.prod(np.delete(sig, [i, j], axis=1), axis=1)
         V = np.conj(np.swapaxes(Vh, 1, 2))
-        K = np.einsum("wai,wgab,wbj->wgij", U.conj(), Ys, V)
-        d = np.einsum("wgii->wgi", K)
-        c1 = ph[:, None] * np.einsum("wgi,wi->wg", d, P1)
-        c2 = ph[:, None] * 0.5 * (np.einsum("wgi,wij,wgj->wg", d, P2, d)
-                                  - np.einsum("wgij,wgji,wij->wg", K, K, P2))
+        Uh = np.conj(np.swapaxes(U, 1, 2))
+        K = Uh[:, None] @ Ys @ V[:, None]                      # [W, G, N, N]
+        d = np.diagonal(K, axis1=2, axis2=3)                  # [W, G, N]
+        c1 = ph[:, None] * np.sum(d * P1[:, None, :], axis=2)
+        dP2d = np.sum((d @ P2) * d, axis=2)
+        kkp = np.sum(K * np.swapaxes(K, 2, 3) * P2[:, None], axis=(2, 3))
+        c2 = ph[:, None] * 0.5 * (dP2d - kkp)
         return c0, c1, c2
 
     def _det_terms(self, i: int, phi_sp):
@@ -426,9 +428,9 @@ class Oracle:
                 continue
             occ = self.occ[i][s]
             D = self.D[i][s]
-            S = np.einsum("ma,wmb->wab", D, phi_sp[s])
-            Yh = np.einsum("am,wmb->wab", self.hfull[s][occ, :], phi_sp[s])[:, None]
-            YL = np.einsum("gam,wmb->wgab", self.Lfull[s][:, occ, :], phi_sp[s])
+            S = np.einsum("ma,wmb->wab", D, phi_sp[s], optimize=True)
+            Yh = (self.hfull[s][occ, :] @ phi_sp[s])[:, None]
+            YL = self.Lfull[s][:, occ, :][None] @ phi_sp[s][:, None]
             c0, c1h, _ = self._det_poly_coeffs(S, Yh)
             _, c1L, c2L = self._det_poly_coeffs(S, YL)
             coeffs.append((c0, c1h, c1L, c2L))
@@ -455,7 +457,7 @@ class Oracle:
         for s in range(2):
             if self.nel[s] == 0:
                 continue
-            S0 = np.einsum("ma,wmb->wab", self.D[0][s], phi_sp[s])
+            S0 = np.einsum("ma,wmb->wab", self.D[0][s], phi_sp[s], optimize=True)
             g = np.linalg.svd(S0, compute_uv=False)[:, 0]
             g = np.where(g > 0, g, 1.0)
             phi_sp[s] = phi_sp[s] / g[:, None, None]
@@ -488,7 +490,7 @@ class Oracle:
     # -- propagation ---------------------------------------------------------
     def propagator_matrix(self, xs: np.ndarray, dt: float) -> np.ndarray:
         """A = i sqrt(dt) sum_gamma (x_gamma - xbar_gamma) L_gamma per walker (Eqs. 2-3)."""
-        return 1j * np.sqrt(dt) * np.einsum("wg,gij->wij", xs, self.L)
+        return 1j * np.sqrt(dt) * np.einsum("wg,gij->wij", xs, self.L, optimize=True)
 
     def apply_propagator(self, phi: np.ndarray, xs: np.ndarray, dt: float, order: int):
         """B1 exp(A) B1 phi for shifted fields xs = x - xbar (Eqs. 2-3, Thouless).

@@ -1,0 +1,196 @@
+"""MI355X (gfx950) phaseless AFQMC walker update (arXiv 1804.03310).
+
+Python binding of the C ABI in include/afqmc.h.  This module only marshals
+arguments: host inputs go in as numpy float64 arrays, walker state lives in
+torch CUDA tensors (device memory) and work is enqueued on torch's current
+stream.  Every step of the walker update runs in the HIP kernels of
+libafqmc.so; importing this package fails if that library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from . import _abi
+from ._abi import AfqmcError, OptionsStruct, WalkersStruct, check
+
+__all__ = ["Hamiltonian", "Trial", "Walkers", "Options", "AfqmcError", "propagate",
+           "local_energy", "orthonormalize", "reconfigure", "fields", "walkers_from_trial",
+           "timing_enable", "timing_read"]
+
+_lib = _abi.load()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None) -> Optional[int]:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _host(a, dtype=np.float64):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Hamiltonian:
+    """h [M,M], L [n_chol,M,M] (V_ijkl = sum_g L_g,ik L_g,jl) and e_core, copied to the device."""
+
+    def __init__(self, h, L, e_core: float = 0.0, device: int = 0, stream=None):
+        h = _host(h)
+        L = _host(L)
+        self.M = h.shape[0]
+        self.n_chol = L.shape[0]
+        self.device = device
+        out = ctypes.c_void_p()
+        check(_lib.afqmc_init_hamiltonian(ctypes.byref(out), device, _stream_ptr(stream), self.M,
+                                          self.n_chol, h.ctypes.data, L.ctypes.data if L.size else None,
+                                          float(e_core)))
+        self._h = out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.afqmc_free_hamiltonian(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self._h = None
+
+
+class Trial:
+    """Psi_T = sum_i coeff[i] |D_i> over orbitals C_up / C_dn (columns)."""
+
+    def __init__(self, ham: Hamiltonian, n_up: int, n_dn: int, C_up, C_dn, coeff=None, exc=None,
+                 mf_subtract: bool = True):
+        C_up = _host(C_up)
+        C_dn = _host(C_dn)
+        self.ham = ham
+        self.n_up, self.n_dn = int(n_up), int(n_dn)
+        n_det = 1 if coeff is None else int(np.asarray(coeff).size)
+        cptr = eptr = None
+        if coeff is not None:
+            self._coeff = _host(coeff)
+            self._exc = np.ascontiguousarray(exc, dtype=np.int32)
+            cptr, eptr = self._coeff.ctypes.data, self._exc.ctypes.data
+        out = ctypes.c_void_p()
+        check(_lib.afqmc_init_trial(ctypes.byref(out), ham._h, self.n_up, self.n_dn,
+                                    C_up.ctypes.data, C_dn.ctypes.data, n_det, cptr, eptr,
+                                    1 if mf_subtract else 0))
+        self._t = out
+        self.n_det = n_det
+
+    def workspace_bytes(self, n_walkers: int) -> int:
+        b = ctypes.c_size_t()
+        check(_lib.afqmc_walker_workspace_bytes(self._t, int(n_walkers), ctypes.byref(b)))
+        return int(b.value)
+
+    def __del__(self):
+        t = getattr(self, "_t", None)
+        if t and _lib is not None:
+            try:
+                _lib.afqmc_free_trial(t)
+            except Exception:  # interpreter shutdown
+                pass
+            self._t = None
+
+
+class Walkers:
+    """Caller-owned device buffers of a walker batch (torch tensors)."""
+
+    def __init__(self, trial: Trial, n_walkers: int, system_id: int = 0, device: Optional[int] = None):
+        torch = _torch()
+        dev = torch.device("cuda", trial.ham.device if device is None else device)
+        M, nt = trial.ham.M, trial.n_up + trial.n_dn
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.trial = trial
+        self.n_walkers = int(n_walkers)
+        self.system_id = int(system_id)
+        self.phi_re = torch.zeros((n_walkers, M, nt), **f64)
+        self.phi_im = torch.zeros((n_walkers, M, nt), **f64)
+        self.weight = torch.ones(n_walkers, **f64)
+        self.logovlp = torch.zeros((2, n_walkers), **f64)
+        self.eloc = torch.zeros((2, n_walkers), **f64)
+        nbytes = trial.workspace_bytes(n_walkers)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.struct = WalkersStruct(
+            self.n_walkers, self.system_id, self.phi_re.data_ptr(), self.phi_im.data_ptr(),
+            self.weight.data_ptr(), self.logovlp[0].data_ptr(), self.logovlp[1].data_ptr(),
+            self.eloc[0].data_ptr(), self.eloc[1].data_ptr(), self.workspace.data_ptr(), nbytes)
+
+
+@dataclass
+class Options:
+    taylor_order: int = 6
+    ortho_every: int = 0
+    pc_every: int = 0
+    e_trial: float = 0.0
+    chol_prec: str = "fp64"
+    taylor_prec: str = "fp64"
+
+    def struct(self) -> OptionsStruct:
+        return OptionsStruct(self.taylor_order, self.ortho_every, self.pc_every, float(self.e_trial),
+                             _abi.PREC[self.chol_prec], _abi.PREC[self.taylor_prec])
+
+
+def walkers_from_trial(ham: Hamiltonian, trial: Trial, w: Walkers, stream=None) -> None:
+    check(_lib.afqmc_walkers_from_trial(ham._h, trial._t, ctypes.byref(w.struct), _stream_ptr(stream)))
+
+
+def propagate(ham: Hamiltonian, trial: Trial, w: Walkers, n_steps: int, dt: float, seed: int,
+              step0: int, opt: Options, emix=None, stream=None):
+    """Enqueue n_steps timesteps; returns the device tensor of E_mix after each step."""
+    torch = _torch()
+    if emix is None:
+        emix = torch.empty(max(n_steps, 1), dtype=torch.float64, device=w.weight.device)
+    o = opt.struct()
+    check(_lib.afqmc_propagate(ham._h, trial._t, ctypes.byref(w.struct), int(n_steps), float(dt),
+                               int(seed), int(step0), ctypes.byref(o), emix.data_ptr(),
+                               _stream_ptr(stream)))
+    return emix
+
+
+def local_energy(ham: Hamiltonian, trial: Trial, w: Walkers, stream=None) -> float:
+    out = ctypes.c_double()
+    check(_lib.afqmc_local_energy(ham._h, trial._t, ctypes.byref(w.struct), ctypes.byref(out),
+                                  _stream_ptr(stream)))
+    return out.value
+
+
+def orthonormalize(ham: Hamiltonian, trial: Trial, w: Walkers, stream=None) -> None:
+    check(_lib.afqmc_orthonormalize(ham._h, trial._t, ctypes.byref(w.struct), _stream_ptr(stream)))
+
+
+def reconfigure(trial: Trial, w: Walkers, seed: int, pc_index: int, stream=None) -> float:
+    out = ctypes.c_double()
+    check(_lib.afqmc_reconfigure(trial._t, ctypes.byref(w.struct), int(seed), int(pc_index),
+                                 ctypes.byref(out), _stream_ptr(stream)))
+    return out.value
+
+
+def timing_enable(ham: Hamiltonian, enable: bool = True) -> None:
+    check(_lib.afqmc_timing_enable(ham._h, 1 if enable else 0))
+
+
+def timing_read(ham: Hamiltonian, kernel_class: str):
+    """(launches, total_ms) of one kernel class since the last read."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    check(_lib.afqmc_timing_read(ham._h, _abi.KERNEL_CLASSES.index(kernel_class), ctypes.byref(n),
+                                 ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
+
+
+def fields(seed: int, t: int, n_walkers: int, n_chol: int, system_id: int = 0, device: int = 0,
+           stream=None):
+    torch = _torch()
+    x = torch.empty((n_walkers, n_chol), dtype=torch.float64, device=torch.device("cuda", device))
+    check(_lib.afqmc_fields(int(seed), int(t), int(n_walkers), int(n_chol), int(system_id),
+                            x.data_ptr(), _stream_ptr(stream)))
+    return x

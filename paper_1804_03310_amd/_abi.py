@@ -1,0 +1,95 @@
+"""ctypes declarations of the C ABI in include/afqmc.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libafqmc.so")
+
+c_int32 = ctypes.c_int32
+c_int = ctypes.c_int
+c_void_p = ctypes.c_void_p
+c_double = ctypes.c_double
+c_size_t = ctypes.c_size_t
+c_uint64 = ctypes.c_uint64
+
+AFQMC_OK = 0
+STATUS_NAMES = {0: "AFQMC_OK", -1: "AFQMC_ERR_ARG", -2: "AFQMC_ERR_OOM", -3: "AFQMC_ERR_DEVICE",
+                -4: "AFQMC_ERR_STATE", -5: "AFQMC_ERR_SINGULAR", -6: "AFQMC_ERR_NONFINITE",
+                -7: "AFQMC_ERR_UNSUPPORTED"}
+PREC = {"fp64": 0, "fp32": 1}
+MAX_EXC = 4
+
+# Every symbol include/afqmc.h declares.
+EXPORTED = ["afqmc_init_hamiltonian", "afqmc_init_trial", "afqmc_walker_workspace_bytes",
+            "afqmc_walkers_from_trial", "afqmc_propagate", "afqmc_local_energy",
+            "afqmc_orthonormalize", "afqmc_reconfigure", "afqmc_fields",
+            "afqmc_timing_enable", "afqmc_timing_read",
+            "afqmc_free_hamiltonian", "afqmc_free_trial", "afqmc_last_error"]
+KERNEL_CLASSES = ["exchange", "propagator_build", "taylor_b1", "overlap_theta", "mgs", "comb",
+                  "other"]
+
+
+class WalkersStruct(ctypes.Structure):
+    _fields_ = [("n_walkers", c_int32), ("system_id", c_int32),
+                ("phi_re", c_void_p), ("phi_im", c_void_p), ("weight", c_void_p),
+                ("logovlp_re", c_void_p), ("logovlp_im", c_void_p),
+                ("eloc_re", c_void_p), ("eloc_im", c_void_p),
+                ("workspace", c_void_p), ("workspace_bytes", c_size_t)]
+
+
+class OptionsStruct(ctypes.Structure):
+    _fields_ = [("taylor_order", c_int32), ("ortho_every", c_int32), ("pc_every", c_int32),
+                ("e_trial", c_double), ("chol_prec", c_int), ("taylor_prec", c_int)]
+
+
+class AfqmcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libafqmc.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} is missing: run paper_1804_03310_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(path)
+    P = c_void_p
+    sig = {
+        "afqmc_init_hamiltonian": (c_int, [ctypes.POINTER(P), c_int, P, c_int, c_int, P, P, c_double]),
+        "afqmc_init_trial": (c_int, [ctypes.POINTER(P), P, c_int, c_int, P, P, c_int, P, P, c_int]),
+        "afqmc_walker_workspace_bytes": (c_int, [P, c_int, ctypes.POINTER(c_size_t)]),
+        "afqmc_walkers_from_trial": (c_int, [P, P, ctypes.POINTER(WalkersStruct), P]),
+        "afqmc_propagate": (c_int, [P, P, ctypes.POINTER(WalkersStruct), c_int, c_double, c_uint64,
+                                    c_uint64, ctypes.POINTER(OptionsStruct), P, P]),
+        "afqmc_local_energy": (c_int, [P, P, ctypes.POINTER(WalkersStruct), P, P]),
+        "afqmc_orthonormalize": (c_int, [P, P, ctypes.POINTER(WalkersStruct), P]),
+        "afqmc_reconfigure": (c_int, [P, ctypes.POINTER(WalkersStruct), c_uint64, c_uint64, P, P]),
+        "afqmc_fields": (c_int, [c_uint64, c_uint64, c_int, c_int, c_int, P, P]),
+        "afqmc_timing_enable": (c_int, [P, c_int]),
+        "afqmc_timing_read": (c_int, [P, c_int, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(c_double)]),
+        "afqmc_free_hamiltonian": (None, [P]),
+        "afqmc_free_trial": (None, [P]),
+        "afqmc_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != AFQMC_OK:
+        msg = load().afqmc_last_error()
+        raise AfqmcError(status, msg.decode() if msg else "")

@@ -1,0 +1,893 @@
+// Host side of the C ABI declared in include/afqmc.h: argument validation,
+// device-resident Hamiltonian / trial set-up, walker-workspace layout and the
+// per-step kernel chain of the phaseless AFQMC walker update.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "afqmc.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+afqmc_status fail(afqmc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define AFQ_CK(x)                                                                           \
+  do {                                                                                      \
+    hipError_t e_ = (x);                                                                    \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(AFQMC_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+int round_up(int x, int m) { return ((x + m - 1) / m) * m; }
+
+// Device allocations owned by one library object.
+struct Arena {
+  std::vector<void*> ptrs;
+  hipError_t alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+bool symmetric(const double* a, int M, double tol) {
+  double mx = 0.0;
+  for (int i = 0; i < M * M; ++i) mx = std::max(mx, std::fabs(a[i]));
+  const double lim = tol * std::max(mx, 1.0);
+  for (int i = 0; i < M; ++i)
+    for (int j = i + 1; j < M; ++j)
+      if (!(std::fabs(a[i * M + j] - a[j * M + i]) <= lim)) return false;
+  return true;
+}
+
+bool all_finite(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+// Cyclic Jacobi eigendecomposition of a symmetric n x n matrix (row-major).
+void jacobi_eigh(int n, std::vector<double> A, std::vector<double>& V, std::vector<double>& d) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  double fro = 0.0;
+  for (double x : A) fro += x * x;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[(size_t)p * n + q] * A[(size_t)p * n + q];
+    if (off <= 1e-34 * fro || off == 0.0) break;
+    for (int p = 0; p < n; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double tau = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = c * akp - s * akq;
+          A[(size_t)k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = c * apk - s * aqk;
+          A[(size_t)q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = c * vkp - s * vkq;
+          V[(size_t)k * n + q] = s * vkp + c * vkq;
+        }
+      }
+    }
+  }
+  d.resize(n);
+  for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+}
+
+}  // namespace
+
+struct KernelTimer {
+  bool enabled = false;
+  std::vector<hipEvent_t> pool;
+  struct Pending { int cls; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double total_ms[AFQMC_NUM_KERNEL_CLASSES] = {0};
+  int64_t count[AFQMC_NUM_KERNEL_CLASSES] = {0};
+  hipEvent_t take() {
+    if (pool.empty()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipError_t drain() {
+    hipError_t err = hipSuccess;
+    for (auto& p : pending) {
+      float ms = 0.f;
+      hipError_t e = hipEventSynchronize(p.b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+      if (e == hipSuccess) {
+        total_ms[p.cls] += ms;
+        count[p.cls] += 1;
+      } else {
+        err = e;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+    return err;
+  }
+  ~KernelTimer() {
+    for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// Brackets one kernel launch with events when timing is enabled.
+struct TimedLaunch {
+  KernelTimer* t;
+  int cls;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedLaunch(KernelTimer* t_, int cls_, hipStream_t st_) : t(t_), cls(cls_), st(st_) {
+    if (t && t->enabled) {
+      a = t->take();
+      b = t->take();
+      if (a && b) (void)hipEventRecord(a, st);
+    }
+  }
+  ~TimedLaunch() {
+    if (a && b) {
+      (void)hipEventRecord(b, st);
+      t->pending.push_back({cls, a, b});
+    }
+  }
+};
+
+enum { KC_EXCHANGE = 0, KC_ABUILD = 1, KC_TAYLOR = 2, KC_OVERLAP = 3, KC_MGS = 4, KC_COMB = 5, KC_OTHER = 6 };
+
+struct afqmc_ham {
+  KernelTimer timer;
+  int device = 0;
+  int M = 0, G = 0;
+  double e_core = 0.0;
+  size_t max_lds = 65536;
+  double* h = nullptr;   // [M][M]
+  double* L = nullptr;   // [G][M][M]
+  float* Lf = nullptr;   // [G][M][M]
+  double* L2 = nullptr;  // sum_g L_g L_g
+  std::vector<double> h_host;
+  Arena arena;
+};
+
+struct B1Entry {
+  double dt;
+  std::vector<double> h64;
+  std::vector<float> h32;
+  double* d64;
+  float* d32;
+};
+
+struct afqmc_trial {
+  afqmc_ham* ham = nullptr;
+  int nel[2] = {0, 0};
+  int NP[2] = {16, 16};
+  int MP4 = 4;
+  int Nt = 0;
+  double* C[2] = {nullptr, nullptr};
+  double* htil[2] = {nullptr, nullptr};
+  double* Lt64[2] = {nullptr, nullptr};
+  float* Lt32[2] = {nullptr, nullptr};
+  double* lbar = nullptr;
+  double* D0 = nullptr;
+  std::vector<double> H1p;
+  std::vector<B1Entry> b1;
+  int n_det = 1;
+  std::vector<double> coeff;
+  std::vector<int32_t> exc;
+  double ref_ls[2] = {0, 0}, ref_el[2] = {0, 0};
+  double* vref_re = nullptr;
+  double* vref_im = nullptr;
+  Arena arena;
+};
+
+namespace {
+
+// Walker workspace layout (all offsets 256-byte aligned).
+struct WS {
+  double *th_re, *th_im;
+  double *ld_re, *ld_im, *e1_re, *e1_im, *exx_re, *exx_im;
+  double *vs_re, *vs_im;
+  double *v_re, *v_im;
+  double *lsn_re, *lsn_im, *eln_re, *eln_im, *mf_re, *mf_im;
+  int *vfin, *dead, *parent;
+  double *cbuf, *scal;
+  void* coefT;
+  void* A;
+  double *P_re, *P_im, *ACC_re, *ACC_im;
+  void *Ta_re, *Ta_im, *Tb_re, *Tb_im;
+  double* snap;
+  size_t total;
+};
+
+WS layout(const afqmc_trial* tr, int W, void* base) {
+  WS ws;
+  const long M = tr->ham->M, G = tr->ham->G, Nt = tr->Nt;
+  size_t off = 0;
+  char* b = (char*)base;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = b ? (void*)(b + off) : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  const size_t wm = (size_t)W * M * Nt * sizeof(double);
+  ws.th_re = (double*)take(wm);
+  ws.th_im = (double*)take(wm);
+  ws.ld_re = (double*)take(2 * W * sizeof(double));
+  ws.ld_im = (double*)take(2 * W * sizeof(double));
+  ws.e1_re = (double*)take(2 * W * sizeof(double));
+  ws.e1_im = (double*)take(2 * W * sizeof(double));
+  ws.exx_re = (double*)take(2 * W * sizeof(double));
+  ws.exx_im = (double*)take(2 * W * sizeof(double));
+  ws.vs_re = (double*)take(2 * (size_t)W * G * sizeof(double));
+  ws.vs_im = (double*)take(2 * (size_t)W * G * sizeof(double));
+  ws.v_re = (double*)take((size_t)W * G * sizeof(double));
+  ws.v_im = (double*)take((size_t)W * G * sizeof(double));
+  ws.lsn_re = (double*)take(W * sizeof(double));
+  ws.lsn_im = (double*)take(W * sizeof(double));
+  ws.eln_re = (double*)take(W * sizeof(double));
+  ws.eln_im = (double*)take(W * sizeof(double));
+  ws.mf_re = (double*)take(W * sizeof(double));
+  ws.mf_im = (double*)take(W * sizeof(double));
+  ws.vfin = (int*)take(W * sizeof(int));
+  ws.dead = (int*)take(W * sizeof(int));
+  ws.parent = (int*)take(W * sizeof(int));
+  ws.cbuf = (double*)take(W * sizeof(double));
+  ws.scal = (double*)take(16 * sizeof(double));
+  ws.coefT = take((size_t)G * 2 * W * sizeof(double));
+  ws.A = take((size_t)W * 2 * M * M * sizeof(double));
+  ws.P_re = (double*)take(wm);
+  ws.P_im = (double*)take(wm);
+  ws.ACC_re = (double*)take(wm);
+  ws.ACC_im = (double*)take(wm);
+  ws.Ta_re = take(wm);
+  ws.Ta_im = take(wm);
+  ws.Tb_re = take(wm);
+  ws.Tb_im = take(wm);
+  ws.snap = (double*)take(wm * 2 + (size_t)W * (4 + 2 * G) * sizeof(double));
+  ws.total = off;
+  return ws;
+}
+
+afqmc_status check_walkers(const afqmc_trial* tr, const afqmc_walkers* wk) {
+  if (!wk) return fail(AFQMC_ERR_ARG, "walkers is NULL");
+  if (wk->n_walkers < 1) return fail(AFQMC_ERR_ARG, "n_walkers must be >= 1");
+  if (wk->system_id < 0) return fail(AFQMC_ERR_ARG, "system_id must be >= 0");
+  if (!wk->phi_re || !wk->phi_im || !wk->weight || !wk->logovlp_re || !wk->logovlp_im ||
+      !wk->eloc_re || !wk->eloc_im || !wk->workspace)
+    return fail(AFQMC_ERR_ARG, "a walker buffer is NULL");
+  const WS ws = layout(tr, wk->n_walkers, nullptr);
+  if (wk->workspace_bytes < ws.total)
+    return fail(AFQMC_ERR_ARG, "workspace_bytes smaller than afqmc_walker_workspace_bytes");
+  return AFQMC_OK;
+}
+
+afq::SpinGeom spin_geom(const afqmc_trial* tr, int s, bool fp32) {
+  afq::SpinGeom g;
+  g.N = tr->nel[s];
+  g.off = s ? tr->nel[0] : 0;
+  g.NP = tr->NP[s];
+  g.C = tr->C[s];
+  g.htil = tr->htil[s];
+  g.Lt = fp32 ? (const void*)tr->Lt32[s] : (const void*)tr->Lt64[s];
+  return g;
+}
+
+// Overlap / Theta / exchange / combination for the current phi; leaves the new
+// log overlap and E_L in ws.lsn / ws.eln and the force-bias traces in ws.v.
+afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqmc_prec chol,
+                          hipStream_t st) {
+  afqmc_ham* hm = tr->ham;
+  const int W = wk->n_walkers, M = hm->M, G = hm->G, Nt = tr->Nt;
+  const bool f32 = chol == AFQMC_FP32;
+  const afq::SpinGeom s0 = spin_geom(tr, 0, f32), s1 = spin_geom(tr, 1, f32);
+  {
+    TimedLaunch tl(&hm->timer, KC_OVERLAP, st);
+    AFQ_CK(afq::overlap_theta(st, W, M, Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re, ws.th_im,
+                              ws.ld_re, ws.ld_im, ws.e1_re, ws.e1_im, hm->max_lds));
+  }
+  if (G > 0) {
+    TimedLaunch tl(&hm->timer, KC_EXCHANGE, st);
+    if (f32) {
+      AFQ_CK(afq::exchange<float>(st, W, M, tr->MP4, Nt, G, s0, s1, ws.th_re, ws.th_im, ws.vs_re,
+                                  ws.vs_im, ws.exx_re, ws.exx_im, hm->max_lds));
+    } else {
+      AFQ_CK(afq::exchange<double>(st, W, M, tr->MP4, Nt, G, s0, s1, ws.th_re, ws.th_im, ws.vs_re,
+                                   ws.vs_im, ws.exx_re, ws.exx_im, hm->max_lds));
+    }
+  } else {
+    AFQ_CK(hipMemsetAsync(ws.exx_re, 0, 2 * W * sizeof(double), st));
+    AFQ_CK(hipMemsetAsync(ws.exx_im, 0, 2 * W * sizeof(double), st));
+  }
+  AFQ_CK(afq::combine_single(st, W, G, hm->e_core, ws.vs_re, ws.vs_im, ws.exx_re, ws.exx_im,
+                             ws.e1_re, ws.e1_im, ws.ld_re, ws.ld_im, ws.v_re, ws.v_im, ws.lsn_re,
+                             ws.lsn_im, ws.eln_re, ws.eln_im, ws.vfin));
+  return AFQMC_OK;
+}
+
+afqmc_status measure_set(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqmc_prec chol,
+                         hipStream_t st) {
+  afqmc_status s = measure_core(tr, wk, ws, chol, st);
+  if (s != AFQMC_OK) return s;
+  AFQ_CK(afq::weight_update(st, wk->n_walkers, 0, 0.0, 0.0, ws.lsn_re, ws.lsn_im, ws.eln_re,
+                            ws.eln_im, ws.mf_re, ws.mf_im, ws.vfin, wk->weight, wk->logovlp_re,
+                            wk->logovlp_im, wk->eloc_re, wk->eloc_im, ws.dead));
+  return AFQMC_OK;
+}
+
+afqmc_status orthonormalize_impl(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, hipStream_t st) {
+  afqmc_ham* hm = tr->ham;
+  const int W = wk->n_walkers;
+  {
+    TimedLaunch tl(&hm->timer, KC_MGS, st);
+    AFQ_CK(afq::mgs(st, W, hm->M, tr->Nt, tr->nel[0], tr->nel[1], wk->phi_re, wk->phi_im));
+  }
+  const afq::SpinGeom s0 = spin_geom(tr, 0, false), s1 = spin_geom(tr, 1, false);
+  AFQ_CK(afq::overlap_theta(st, W, hm->M, tr->Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re,
+                            ws.th_im, ws.ld_re, ws.ld_im, ws.e1_re, ws.e1_im, hm->max_lds));
+  // log S = sum over spins of log det (single determinant)
+  AFQ_CK(afq::combine_single(st, W, 0, 0.0, ws.vs_re, ws.vs_im, ws.exx_re, ws.exx_im, ws.e1_re,
+                             ws.e1_im, ws.ld_re, ws.ld_im, ws.v_re, ws.v_im, ws.lsn_re,
+                             ws.lsn_im, ws.eln_re, ws.eln_im, ws.vfin));
+  AFQ_CK(afq::weight_update(st, W, 2, 0.0, 0.0, ws.lsn_re, ws.lsn_im, ws.eln_re, ws.eln_im,
+                            ws.mf_re, ws.mf_im, ws.vfin, wk->weight, wk->logovlp_re,
+                            wk->logovlp_im, wk->eloc_re, wk->eloc_im, ws.dead));
+  return AFQMC_OK;
+}
+
+afqmc_status reconfigure_impl(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, uint64_t seed,
+                              uint64_t pc_index, hipStream_t st) {
+  afqmc_ham* hm = tr->ham;
+  const int W = wk->n_walkers;
+  const long row = (long)hm->M * tr->Nt, G = hm->G;
+  {
+    TimedLaunch tl(&hm->timer, KC_COMB, st);
+    AFQ_CK(afq::comb_parents(st, W, wk->weight, seed, pc_index, wk->system_id, ws.cbuf, ws.parent,
+                             ws.scal + 2));
+  }
+  double* snap = ws.snap;
+  struct Item { double* p; long row; };
+  const Item items[] = {{wk->phi_re, row},     {wk->phi_im, row},     {wk->logovlp_re, 1},
+                        {wk->logovlp_im, 1},   {wk->eloc_re, 1},      {wk->eloc_im, 1},
+                        {ws.v_re, G},          {ws.v_im, G}};
+  for (const Item& it : items) {
+    if (it.row == 0) continue;
+    AFQ_CK(hipMemcpyAsync(snap, it.p, (size_t)W * it.row * sizeof(double), hipMemcpyDeviceToDevice, st));
+    AFQ_CK(afq::gather_rows(st, W, it.row, ws.parent, snap, it.p));
+    snap += (size_t)W * it.row;
+  }
+  AFQ_CK(afq::fill(st, wk->weight, W, 1.0));
+  return AFQMC_OK;
+}
+
+B1Entry* get_b1(afqmc_trial* tr, double dt, hipStream_t st, afqmc_status* err) {
+  for (auto& e : tr->b1)
+    if (e.dt == dt) return &e;
+  const int M = tr->ham->M;
+  std::vector<double> V, lam;
+  jacobi_eigh(M, tr->H1p, V, lam);
+  B1Entry e;
+  e.dt = dt;
+  e.h64.assign((size_t)M * M, 0.0);
+  // B1 - I = V diag(expm1(-dt lam / 2)) V^T
+  for (int i = 0; i < M; ++i)
+    for (int j = 0; j < M; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < M; ++k) s += V[(size_t)i * M + k] * std::expm1(-0.5 * dt * lam[k]) * V[(size_t)j * M + k];
+      e.h64[(size_t)i * M + j] = s;
+    }
+  e.h32.resize(e.h64.size());
+  for (size_t i = 0; i < e.h64.size(); ++i) e.h32[i] = (float)e.h64[i];
+  void* p64 = nullptr;
+  void* p32 = nullptr;
+  if (tr->arena.alloc(&p64, e.h64.size() * sizeof(double)) != hipSuccess ||
+      tr->arena.alloc(&p32, e.h32.size() * sizeof(float)) != hipSuccess) {
+    *err = fail(AFQMC_ERR_OOM, "B1 allocation failed");
+    return nullptr;
+  }
+  e.d64 = (double*)p64;
+  e.d32 = (float*)p32;
+  if (hipMemcpy(e.d64, e.h64.data(), e.h64.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(e.d32, e.h32.data(), e.h32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    *err = fail(AFQMC_ERR_DEVICE, "B1 upload failed");
+    return nullptr;
+  }
+  (void)st;
+  tr->b1.push_back(std::move(e));
+  return &tr->b1.back();
+}
+
+template <typename TC, typename TT>
+afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B1Entry* b1,
+                             int n_steps, double dt, uint64_t seed, uint64_t step0,
+                             const afqmc_options* opt, double* emix_dev, hipStream_t st) {
+  afqmc_ham* hm = tr->ham;
+  const int W = wk->n_walkers, M = hm->M, G = hm->G, Nt = tr->Nt;
+  const long mn = (long)M * Nt, mm = (long)M * M;
+  const TC* Lc = std::is_same<TC, float>::value ? (const TC*)hm->Lf : (const TC*)hm->L;
+  const TT* B1m = std::is_same<TT, float>::value ? (const TT*)b1->d32 : (const TT*)b1->d64;
+  TC* coefT = (TC*)ws.coefT;
+  TT* A = (TT*)ws.A;
+  TT* Tbuf[2][2] = {{(TT*)ws.Ta_re, (TT*)ws.Ta_im}, {(TT*)ws.Tb_re, (TT*)ws.Tb_im}};
+  for (int s = 0; s < n_steps; ++s) {
+    const uint64_t t = step0 + (uint64_t)s;
+    AFQ_CK(afq::fields_coeff<TC>(st, W, G, seed, t, wk->system_id, dt, ws.v_re, ws.v_im, tr->lbar,
+                                 coefT, ws.mf_re, ws.mf_im, nullptr));
+    if (G > 0) {
+      TimedLaunch tl(&hm->timer, KC_ABUILD, st);
+      AFQ_CK((afq::gemm_real<TC, TT, true>(st, 2 * W, (int)mm, G, coefT, 2 * W, 0, Lc, (int)mm, 0,
+                                           A, (int)mm, 0, 1, 1.0)));
+    } else {
+      AFQ_CK(hipMemsetAsync(A, 0, (size_t)W * 2 * mm * sizeof(TT), st));
+    }
+    // phi -> P = B1 phi, ACC = P
+    {
+    TimedLaunch tl_t(&hm->timer, KC_TAYLOR, st);
+    AFQ_CK((afq::cgemm_walkers<TT, double, false, 0>(st, W, M, Nt, M, B1m, nullptr, M, 0,
+                                                     wk->phi_re, wk->phi_im, Nt, mn, nullptr,
+                                                     nullptr, ws.P_re, ws.P_im, ws.ACC_re,
+                                                     ws.ACC_im, Nt, mn, 1.0)));
+    // Taylor terms T_n = A T_{n-1} / n, ACC += T_n
+    for (int n = 1; n <= opt->taylor_order; ++n) {
+      TT* outr = Tbuf[(n - 1) & 1][0];
+      TT* outi = Tbuf[(n - 1) & 1][1];
+      if (n == 1) {
+        AFQ_CK((afq::cgemm_walkers<TT, double, true, 1>(st, W, M, Nt, M, A, A + mm, M, 2 * mm,
+                                                        ws.P_re, ws.P_im, Nt, mn, outr, outi,
+                                                        ws.ACC_re, ws.ACC_im, nullptr, nullptr, Nt,
+                                                        mn, 1.0)));
+      } else {
+        const TT* inr = Tbuf[n & 1][0];
+        const TT* ini = Tbuf[n & 1][1];
+        AFQ_CK((afq::cgemm_walkers<TT, TT, true, 1>(st, W, M, Nt, M, A, A + mm, M, 2 * mm, inr, ini,
+                                                    Nt, mn, outr, outi, ws.ACC_re, ws.ACC_im,
+                                                    nullptr, nullptr, Nt, mn, 1.0 / n)));
+      }
+    }
+    // phi = ACC + (B1 - I) ACC
+    AFQ_CK((afq::cgemm_walkers<TT, double, false, 0>(st, W, M, Nt, M, B1m, nullptr, M, 0,
+                                                     ws.ACC_re, ws.ACC_im, Nt, mn, nullptr,
+                                                     nullptr, wk->phi_re, wk->phi_im, nullptr,
+                                                     nullptr, Nt, mn, 1.0)));
+    }
+    afqmc_status rs = measure_core(tr, wk, ws, opt->chol_prec, st);
+    if (rs != AFQMC_OK) return rs;
+    AFQ_CK(afq::weight_update(st, W, 1, dt, opt->e_trial, ws.lsn_re, ws.lsn_im, ws.eln_re,
+                              ws.eln_im, ws.mf_re, ws.mf_im, ws.vfin, wk->weight, wk->logovlp_re,
+                              wk->logovlp_im, wk->eloc_re, wk->eloc_im, ws.dead));
+    AFQ_CK(afq::reset_dead(st, W, M, Nt, G, ws.dead, tr->D0, tr->ref_ls[0], tr->ref_ls[1],
+                           tr->ref_el[0], tr->ref_el[1], tr->vref_re, tr->vref_im, wk->phi_re,
+                           wk->phi_im, wk->logovlp_re, wk->logovlp_im, wk->eloc_re, wk->eloc_im,
+                           ws.v_re, ws.v_im));
+    AFQ_CK(afq::mixed_energy(st, W, wk->weight, wk->eloc_re, emix_dev ? emix_dev + s : ws.scal,
+                             ws.scal + 1));
+    if (opt->ortho_every > 0 && (t + 1) % (uint64_t)opt->ortho_every == 0) {
+      rs = orthonormalize_impl(tr, wk, ws, st);
+      if (rs != AFQMC_OK) return rs;
+    }
+    if (opt->pc_every > 0 && (t + 1) % (uint64_t)opt->pc_every == 0) {
+      rs = reconfigure_impl(tr, wk, ws, seed, t, st);
+      if (rs != AFQMC_OK) return rs;
+    }
+  }
+  return AFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* afqmc_last_error(void) { return g_err.c_str(); }
+
+afqmc_status afqmc_init_hamiltonian(afqmc_ham** out, int device, void* stream, int M, int n_chol,
+                                    const double* h, const double* L, double e_core) {
+  if (!out) return fail(AFQMC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (M < 1 || M > AFQMC_MAX_M) return fail(AFQMC_ERR_ARG, "M must be in [1, AFQMC_MAX_M]");
+  if (n_chol < 0) return fail(AFQMC_ERR_ARG, "n_chol must be >= 0");
+  if (!h) return fail(AFQMC_ERR_ARG, "h is NULL");
+  if (n_chol > 0 && !L) return fail(AFQMC_ERR_ARG, "L is NULL");
+  if (!std::isfinite(e_core)) return fail(AFQMC_ERR_ARG, "e_core is not finite");
+  if (!all_finite(h, (size_t)M * M) || (n_chol > 0 && !all_finite(L, (size_t)n_chol * M * M)))
+    return fail(AFQMC_ERR_ARG, "h or L has a non-finite entry");
+  if (!symmetric(h, M, 1e-10)) return fail(AFQMC_ERR_ARG, "h is not symmetric");
+  for (int g = 0; g < n_chol; ++g)
+    if (!symmetric(L + (size_t)g * M * M, M, 1e-10))
+      return fail(AFQMC_ERR_ARG, "L[" + std::to_string(g) + "] is not symmetric");
+  int ndev = 0;
+  AFQ_CK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(AFQMC_ERR_ARG, "no such device");
+  AFQ_CK(hipSetDevice(device));
+  hipStream_t st = (hipStream_t)stream;
+  afqmc_ham* hm = new afqmc_ham();
+  hm->device = device;
+  hm->M = M;
+  hm->G = n_chol;
+  hm->e_core = e_core;
+  hm->h_host.assign(h, h + (size_t)M * M);
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    hm->max_lds = (size_t)lds;
+  const size_t mm = (size_t)M * M, gmm = (size_t)n_chol * mm;
+  void *ph, *pL, *pLf, *pL2;
+  if (hm->arena.alloc(&ph, mm * 8) || hm->arena.alloc(&pL, gmm * 8) ||
+      hm->arena.alloc(&pLf, gmm * 4) || hm->arena.alloc(&pL2, mm * 8)) {
+    hm->arena.release();
+    delete hm;
+    return fail(AFQMC_ERR_OOM, "hamiltonian allocation failed");
+  }
+  hm->h = (double*)ph;
+  hm->L = (double*)pL;
+  hm->Lf = (float*)pLf;
+  hm->L2 = (double*)pL2;
+  auto bad = [&](const char* what) {
+    hm->arena.release();
+    delete hm;
+    return fail(AFQMC_ERR_DEVICE, what);
+  };
+  if (hipMemcpyAsync(hm->h, h, mm * 8, hipMemcpyHostToDevice, st) != hipSuccess) return bad("h upload");
+  if (n_chol > 0) {
+    if (hipMemcpyAsync(hm->L, L, gmm * 8, hipMemcpyHostToDevice, st) != hipSuccess) return bad("L upload");
+    if (afq::convert_f64_f32(st, hm->L, hm->Lf, (long)gmm) != hipSuccess) return bad("L convert");
+  }
+  // sum_g L_g L_g as one GEMM over the stacked index (g, k)
+  if (afq::gemm_real<double, double, true>(st, M, M, n_chol * M, hm->L, M, 0, hm->L, M, 0, hm->L2,
+                                           M, 0, 1, 1.0) != hipSuccess)
+    return bad("sum L^2");
+  if (hipStreamSynchronize(st) != hipSuccess) return bad("init sync");
+  *out = hm;
+  return AFQMC_OK;
+}
+
+void afqmc_free_hamiltonian(afqmc_ham* hm) {
+  if (!hm) return;
+  (void)hipSetDevice(hm->device);
+  hm->arena.release();
+  delete hm;
+}
+
+afqmc_status afqmc_walker_workspace_bytes(const afqmc_trial* tr, int n_walkers, size_t* bytes) {
+  if (!tr || !bytes) return fail(AFQMC_ERR_ARG, "NULL argument");
+  if (n_walkers < 1) return fail(AFQMC_ERR_ARG, "n_walkers must be >= 1");
+  *bytes = layout(tr, n_walkers, nullptr).total;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_dn,
+                              const double* C_up, const double* C_dn, int n_det,
+                              const double* coeff, const int32_t* exc, int mf_subtract) {
+  if (!out) return fail(AFQMC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!hm) return fail(AFQMC_ERR_ARG, "ham is NULL");
+  const int M = hm->M, G = hm->G;
+  if (n_up < 0 || n_dn < 0 || n_up + n_dn < 1) return fail(AFQMC_ERR_ARG, "electron counts");
+  if (n_up > M || n_dn > M || n_up > AFQMC_MAX_NEL || n_dn > AFQMC_MAX_NEL)
+    return fail(AFQMC_ERR_UNSUPPORTED, "too many electrons per spin");
+  if (!C_up || !C_dn) return fail(AFQMC_ERR_ARG, "C_up or C_dn is NULL");
+  if (n_det < 1) return fail(AFQMC_ERR_ARG, "n_det must be >= 1");
+  if (n_det > 1 && (!coeff || !exc)) return fail(AFQMC_ERR_ARG, "coeff / exc NULL with n_det > 1");
+  if (!all_finite(C_up, (size_t)M * M) || !all_finite(C_dn, (size_t)M * M))
+    return fail(AFQMC_ERR_ARG, "C has a non-finite entry");
+  if (n_det > 1) return fail(AFQMC_ERR_UNSUPPORTED, "multi-determinant trials are not built yet");
+  const int nel[2] = {n_up, n_dn};
+  const double* Cs[2] = {C_up, C_dn};
+  // the reference determinant must have orthonormal orbitals
+  for (int s = 0; s < 2; ++s)
+    for (int a = 0; a < nel[s]; ++a)
+      for (int b = 0; b < nel[s]; ++b) {
+        double d = 0.0;
+        for (int m = 0; m < M; ++m) d += Cs[s][(size_t)m * M + a] * Cs[s][(size_t)m * M + b];
+        if (std::fabs(d - (a == b ? 1.0 : 0.0)) > 1e-8)
+          return fail(AFQMC_ERR_SINGULAR, "occupied trial orbitals are not orthonormal");
+      }
+  AFQ_CK(hipSetDevice(hm->device));
+  hipStream_t st = nullptr;
+  afqmc_trial* tr = new afqmc_trial();
+  tr->ham = hm;
+  tr->nel[0] = n_up;
+  tr->nel[1] = n_dn;
+  tr->Nt = n_up + n_dn;
+  tr->MP4 = round_up(M, 4);
+  tr->n_det = n_det;
+  for (int s = 0; s < 2; ++s) tr->NP[s] = round_up(std::max(nel[s], 1), 16);
+  auto bad = [&](afqmc_status code, const char* what) {
+    tr->arena.release();
+    delete tr;
+    return fail(code, what);
+  };
+  const size_t mm = (size_t)M * M;
+  for (int s = 0; s < 2; ++s) {
+    void *pc, *ph, *p64, *p32;
+    const size_t nlt = (size_t)G * tr->MP4 * tr->NP[s];
+    if (tr->arena.alloc(&pc, mm * 8) || tr->arena.alloc(&ph, (size_t)std::max(nel[s], 1) * M * 8) ||
+        tr->arena.alloc(&p64, nlt * 8) || tr->arena.alloc(&p32, nlt * 4))
+      return bad(AFQMC_ERR_OOM, "trial allocation failed");
+    tr->C[s] = (double*)pc;
+    tr->htil[s] = (double*)ph;
+    tr->Lt64[s] = (double*)p64;
+    tr->Lt32[s] = (float*)p32;
+    if (hipMemcpy(tr->C[s], Cs[s], mm * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return bad(AFQMC_ERR_DEVICE, "C upload");
+    if (hipMemsetAsync(tr->Lt64[s], 0, nlt * 8, st) != hipSuccess) return bad(AFQMC_ERR_DEVICE, "memset");
+    if (nel[s] > 0 && G > 0) {
+      // Lt[g][m][a] = (L_g C)[m][a] = (C^T L_g)[a][m]
+      if (afq::gemm_real<double, double, false>(st, M, nel[s], M, hm->L, M, (long)mm, tr->C[s], M,
+                                                0, tr->Lt64[s], tr->NP[s],
+                                                (long)tr->MP4 * tr->NP[s], G, 1.0) != hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "half-rotation");
+    }
+    if (afq::convert_f64_f32(st, tr->Lt64[s], tr->Lt32[s], (long)nlt) != hipSuccess)
+      return bad(AFQMC_ERR_DEVICE, "convert");
+    if (nel[s] > 0) {
+      // htil[a][m] = sum_i C[i][a] h[i][m]
+      if (afq::gemm_real<double, double, true>(st, nel[s], M, M, tr->C[s], M, 0, hm->h, M, 0,
+                                               tr->htil[s], M, 0, 1, 1.0) != hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "htil");
+    }
+  }
+  void *plb, *pd0, *pvr, *pvi, *plL;
+  if (tr->arena.alloc(&plb, (size_t)std::max(G, 1) * 8) || tr->arena.alloc(&pd0, (size_t)M * tr->Nt * 8) ||
+      tr->arena.alloc(&pvr, (size_t)std::max(G, 1) * 8) || tr->arena.alloc(&pvi, (size_t)std::max(G, 1) * 8) ||
+      tr->arena.alloc(&plL, mm * 8))
+    return bad(AFQMC_ERR_OOM, "trial allocation failed");
+  tr->lbar = (double*)plb;
+  tr->D0 = (double*)pd0;
+  tr->vref_re = (double*)pvr;
+  tr->vref_im = (double*)pvi;
+  if (hipMemsetAsync(tr->lbar, 0, (size_t)std::max(G, 1) * 8, st) != hipSuccess)
+    return bad(AFQMC_ERR_DEVICE, "memset");
+  if (mf_subtract) {
+    for (int s = 0; s < 2; ++s)
+      if (afq::lbar_accumulate(st, G, M, tr->MP4, nel[s], tr->NP[s], tr->Lt64[s], tr->C[s],
+                               tr->lbar) != hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "lbar");
+  }
+  // sum_g lbar_g L_g
+  if (hipMemsetAsync(plL, 0, mm * 8, st) != hipSuccess) return bad(AFQMC_ERR_DEVICE, "memset");
+  if (G > 0 && afq::gemm_real<double, double, true>(st, 1, (int)mm, G, tr->lbar, 1, 0, hm->L,
+                                                    (int)mm, 0, (double*)plL, (int)mm, 0, 1,
+                                                    1.0) != hipSuccess)
+    return bad(AFQMC_ERR_DEVICE, "lbar L");
+  std::vector<double> L2h(mm), lLh(mm);
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpy(L2h.data(), hm->L2, mm * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(lLh.data(), plL, mm * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return bad(AFQMC_ERR_DEVICE, "download");
+  tr->H1p.resize(mm);
+  for (size_t i = 0; i < mm; ++i) tr->H1p[i] = hm->h_host[i] - 0.5 * L2h[i] + lLh[i];
+  // symmetrise (rounding of the two GEMMs)
+  for (int i = 0; i < M; ++i)
+    for (int j = i + 1; j < M; ++j) {
+      const double a = 0.5 * (tr->H1p[(size_t)i * M + j] + tr->H1p[(size_t)j * M + i]);
+      tr->H1p[(size_t)i * M + j] = tr->H1p[(size_t)j * M + i] = a;
+    }
+  std::vector<double> D0h((size_t)M * tr->Nt);
+  for (int m = 0; m < M; ++m) {
+    for (int a = 0; a < n_up; ++a) D0h[(size_t)m * tr->Nt + a] = C_up[(size_t)m * M + a];
+    for (int a = 0; a < n_dn; ++a) D0h[(size_t)m * tr->Nt + n_up + a] = C_dn[(size_t)m * M + a];
+  }
+  if (hipMemcpy(tr->D0, D0h.data(), D0h.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return bad(AFQMC_ERR_DEVICE, "D0 upload");
+  // reference state: one walker at D_0, measured in FP64
+  {
+    afqmc_walkers rw;
+    std::memset(&rw, 0, sizeof(rw));
+    rw.n_walkers = 1;
+    const WS ws0 = layout(tr, 1, nullptr);
+    void *pr, *pi, *pw, *pl, *pe, *pwork;
+    Arena tmp;
+    if (tmp.alloc(&pr, D0h.size() * 8) || tmp.alloc(&pi, D0h.size() * 8) || tmp.alloc(&pw, 8) ||
+        tmp.alloc(&pl, 16) || tmp.alloc(&pe, 16) || tmp.alloc(&pwork, ws0.total)) {
+      tmp.release();
+      return bad(AFQMC_ERR_OOM, "reference walker");
+    }
+    rw.phi_re = (double*)pr;
+    rw.phi_im = (double*)pi;
+    rw.weight = (double*)pw;
+    rw.logovlp_re = (double*)pl;
+    rw.logovlp_im = (double*)pl + 1;
+    rw.eloc_re = (double*)pe;
+    rw.eloc_im = (double*)pe + 1;
+    rw.workspace = pwork;
+    rw.workspace_bytes = ws0.total;
+    const WS ws = layout(tr, 1, pwork);
+    bool ok = hipMemcpy(pr, tr->D0, D0h.size() * 8, hipMemcpyDeviceToDevice) == hipSuccess &&
+              hipMemset(pi, 0, D0h.size() * 8) == hipSuccess &&
+              afq::fill(st, (double*)pw, 1, 1.0) == hipSuccess;
+    afqmc_status ms = ok ? measure_set(tr, &rw, ws, AFQMC_FP64, st) : AFQMC_ERR_DEVICE;
+    double hv[4];
+    ok = ok && ms == AFQMC_OK && hipStreamSynchronize(st) == hipSuccess &&
+         hipMemcpy(&hv[0], pl, 16, hipMemcpyDeviceToHost) == hipSuccess &&
+         hipMemcpy(&hv[2], pe, 16, hipMemcpyDeviceToHost) == hipSuccess &&
+         hipMemcpy(tr->vref_re, ws.v_re, (size_t)std::max(G, 1) * 8, hipMemcpyDeviceToDevice) == hipSuccess &&
+         hipMemcpy(tr->vref_im, ws.v_im, (size_t)std::max(G, 1) * 8, hipMemcpyDeviceToDevice) == hipSuccess &&
+         hipDeviceSynchronize() == hipSuccess;
+    tmp.release();
+    if (!ok) return bad(AFQMC_ERR_DEVICE, "reference walker measure failed");
+    tr->ref_ls[0] = hv[0];
+    tr->ref_ls[1] = hv[1];
+    tr->ref_el[0] = hv[2];
+    tr->ref_el[1] = hv[3];
+  }
+  *out = tr;
+  return AFQMC_OK;
+}
+
+void afqmc_free_trial(afqmc_trial* tr) {
+  if (!tr) return;
+  (void)hipSetDevice(tr->ham->device);
+  tr->arena.release();
+  delete tr;
+}
+
+afqmc_status afqmc_walkers_from_trial(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk,
+                                      void* stream) {
+  if (!hm || !tr) return fail(AFQMC_ERR_ARG, "NULL ham / trial");
+  if (tr->ham != hm) return fail(AFQMC_ERR_STATE, "trial was built on another Hamiltonian");
+  afqmc_status s = check_walkers(tr, wk);
+  if (s != AFQMC_OK) return s;
+  AFQ_CK(hipSetDevice(hm->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int W = wk->n_walkers, G = hm->G;
+  const long row = (long)hm->M * tr->Nt;
+  const WS ws = layout(tr, W, wk->workspace);
+  AFQ_CK(afq::broadcast_rows(st, W, row, tr->D0, wk->phi_re));
+  AFQ_CK(afq::fill(st, wk->phi_im, (long)W * row, 0.0));
+  AFQ_CK(afq::fill(st, wk->weight, W, 1.0));
+  AFQ_CK(afq::fill(st, wk->logovlp_re, W, tr->ref_ls[0]));
+  AFQ_CK(afq::fill(st, wk->logovlp_im, W, tr->ref_ls[1]));
+  AFQ_CK(afq::fill(st, wk->eloc_re, W, tr->ref_el[0]));
+  AFQ_CK(afq::fill(st, wk->eloc_im, W, tr->ref_el[1]));
+  if (G > 0) {
+    AFQ_CK(afq::broadcast_rows(st, W, G, tr->vref_re, ws.v_re));
+    AFQ_CK(afq::broadcast_rows(st, W, G, tr->vref_im, ws.v_im));
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_local_energy(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk,
+                                double* emix_host, void* stream) {
+  if (!hm || !tr) return fail(AFQMC_ERR_ARG, "NULL ham / trial");
+  if (tr->ham != hm) return fail(AFQMC_ERR_STATE, "trial was built on another Hamiltonian");
+  afqmc_status s = check_walkers(tr, wk);
+  if (s != AFQMC_OK) return s;
+  AFQ_CK(hipSetDevice(hm->device));
+  hipStream_t st = (hipStream_t)stream;
+  const WS ws = layout(tr, wk->n_walkers, wk->workspace);
+  s = measure_set(tr, wk, ws, AFQMC_FP64, st);
+  if (s != AFQMC_OK) return s;
+  if (emix_host) {
+    AFQ_CK(afq::mixed_energy(st, wk->n_walkers, wk->weight, wk->eloc_re, ws.scal, ws.scal + 1));
+    double hv[2];
+    AFQ_CK(hipMemcpyAsync(hv, ws.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    AFQ_CK(hipStreamSynchronize(st));
+    if (!(hv[1] > 0.0)) return fail(AFQMC_ERR_NONFINITE, "sum of weights is zero");
+    *emix_host = hv[0];
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_orthonormalize(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk, void* stream) {
+  if (!hm || !tr) return fail(AFQMC_ERR_ARG, "NULL ham / trial");
+  if (tr->ham != hm) return fail(AFQMC_ERR_STATE, "trial was built on another Hamiltonian");
+  afqmc_status s = check_walkers(tr, wk);
+  if (s != AFQMC_OK) return s;
+  AFQ_CK(hipSetDevice(hm->device));
+  const WS ws = layout(tr, wk->n_walkers, wk->workspace);
+  return orthonormalize_impl(tr, wk, ws, (hipStream_t)stream);
+}
+
+afqmc_status afqmc_reconfigure(afqmc_trial* tr, afqmc_walkers* wk, uint64_t seed, uint64_t pc_index,
+                               double* norm_factor_host, void* stream) {
+  if (!tr) return fail(AFQMC_ERR_ARG, "NULL trial");
+  afqmc_status s = check_walkers(tr, wk);
+  if (s != AFQMC_OK) return s;
+  AFQ_CK(hipSetDevice(tr->ham->device));
+  hipStream_t st = (hipStream_t)stream;
+  const WS ws = layout(tr, wk->n_walkers, wk->workspace);
+  s = reconfigure_impl(tr, wk, ws, seed, pc_index, st);
+  if (s != AFQMC_OK) return s;
+  if (norm_factor_host) {
+    AFQ_CK(hipMemcpyAsync(norm_factor_host, ws.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    AFQ_CK(hipStreamSynchronize(st));
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_propagate(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk, int n_steps,
+                             double dt, uint64_t seed, uint64_t step0, const afqmc_options* opt,
+                             double* emix_dev, void* stream) {
+  if (!hm || !tr || !opt) return fail(AFQMC_ERR_ARG, "NULL ham / trial / options");
+  if (tr->ham != hm) return fail(AFQMC_ERR_STATE, "trial was built on another Hamiltonian");
+  afqmc_status s = check_walkers(tr, wk);
+  if (s != AFQMC_OK) return s;
+  if (n_steps < 0) return fail(AFQMC_ERR_ARG, "n_steps must be >= 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(AFQMC_ERR_ARG, "dt must be positive");
+  if (opt->taylor_order < 1 || opt->taylor_order > 64) return fail(AFQMC_ERR_ARG, "taylor_order");
+  if (opt->ortho_every < 0 || opt->pc_every < 0) return fail(AFQMC_ERR_ARG, "negative interval");
+  if (!std::isfinite(opt->e_trial)) return fail(AFQMC_ERR_ARG, "e_trial is not finite");
+  if ((opt->chol_prec != AFQMC_FP64 && opt->chol_prec != AFQMC_FP32) ||
+      (opt->taylor_prec != AFQMC_FP64 && opt->taylor_prec != AFQMC_FP32))
+    return fail(AFQMC_ERR_UNSUPPORTED, "precision");
+  AFQ_CK(hipSetDevice(hm->device));
+  hipStream_t st = (hipStream_t)stream;
+  const WS ws = layout(tr, wk->n_walkers, wk->workspace);
+  afqmc_status err = AFQMC_OK;
+  B1Entry* b1 = get_b1(tr, dt, st, &err);
+  if (!b1) return err;
+  s = measure_set(tr, wk, ws, opt->chol_prec, st);
+  if (s != AFQMC_OK) return s;
+  const bool c32 = opt->chol_prec == AFQMC_FP32, t32 = opt->taylor_prec == AFQMC_FP32;
+  if (c32 && t32)
+    return propagate_typed<float, float>(tr, wk, ws, b1, n_steps, dt, seed, step0, opt, emix_dev, st);
+  if (c32 && !t32)
+    return propagate_typed<float, double>(tr, wk, ws, b1, n_steps, dt, seed, step0, opt, emix_dev, st);
+  if (!c32 && t32)
+    return propagate_typed<double, float>(tr, wk, ws, b1, n_steps, dt, seed, step0, opt, emix_dev, st);
+  return propagate_typed<double, double>(tr, wk, ws, b1, n_steps, dt, seed, step0, opt, emix_dev, st);
+}
+
+afqmc_status afqmc_timing_enable(afqmc_ham* hm, int enable) {
+  if (!hm) return fail(AFQMC_ERR_ARG, "NULL ham");
+  hm->timer.enabled = enable != 0;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_timing_read(afqmc_ham* hm, int kernel_class, int64_t* launches,
+                               double* total_ms) {
+  if (!hm || !launches || !total_ms) return fail(AFQMC_ERR_ARG, "NULL argument");
+  if (kernel_class < 0 || kernel_class >= AFQMC_NUM_KERNEL_CLASSES)
+    return fail(AFQMC_ERR_ARG, "kernel_class out of range");
+  AFQ_CK(hipSetDevice(hm->device));
+  AFQ_CK(hm->timer.drain());
+  *launches = hm->timer.count[kernel_class];
+  *total_ms = hm->timer.total_ms[kernel_class];
+  hm->timer.count[kernel_class] = 0;
+  hm->timer.total_ms[kernel_class] = 0.0;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_fields(uint64_t seed, uint64_t t, int n_walkers, int n_chol, int system_id,
+                          double* x_dev, void* stream) {
+  if (n_walkers < 1 || n_chol < 1 || system_id < 0 || !x_dev)
+    return fail(AFQMC_ERR_ARG, "invalid fields request");
+  AFQ_CK(afq::fields_coeff<double>((hipStream_t)stream, n_walkers, n_chol, seed, t, system_id, 1.0,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, x_dev));
+  return AFQMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,887 @@
+// gfx950 kernels of the phaseless AFQMC walker update (arXiv 1804.03310,
+// Sec. II and III).  Wave64, 16x16x4 MFMA tiles for the dense contractions,
+// LDS-staged operands, fixed-order reductions (bitwise reproducible).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace afq {
+
+// ===========================================================================
+// Real GEMM, 64x64 block tile, 4 waves of 32x32, K staged through LDS in
+// chunks of 16.  Used for the propagator build sum_g c_{w,g} L_g (Eq. 2-3:
+// one GEMM over all walkers, [2W x G] x [G x M^2]) and for set-up products.
+// ===========================================================================
+template <typename TIn, typename TOut, bool A_KMAJ>
+__global__ __launch_bounds__(256) void k_gemm_real(int Mr, int Nc, int K, const TIn* __restrict__ A,
+                                                   int lda, long sA, const TIn* __restrict__ B, int ldb,
+                                                   long sB, TOut* __restrict__ C, int ldc, long sC,
+                                                   double alpha) {
+  constexpr int BM = 64, BN = 64, KC = 16;
+  __shared__ TIn As[KC][BM + 1];
+  __shared__ TIn Bs[KC][BN + 1];
+  typedef Mfma<TIn> MM;
+  const long z = blockIdx.z;
+  A += z * sA;
+  B += z * sB;
+  C += z * sC;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int w = wave_id(), l = lane_id();
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int li = l & 15, lk = l >> 4;
+  typename MM::acc_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = MM::zero();
+
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int e = threadIdx.x; e < KC * BM; e += 256) {
+      int kk, mm;
+      if (A_KMAJ) { kk = e / BM; mm = e % BM; } else { mm = e / KC; kk = e % KC; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      TIn v = (TIn)0;
+      if (gm < Mr && gk < K) v = A_KMAJ ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
+      As[kk][mm] = v;
+    }
+    for (int e = threadIdx.x; e < KC * BN; e += 256) {
+      const int kk = e / BN, nn = e % BN;
+      const int gk = k0 + kk, gn = n0 + nn;
+      Bs[kk][nn] = (gk < K && gn < Nc) ? B[(long)gk * ldb + gn] : (TIn)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const TIn a0 = As[kk + lk][wm + li], a1 = As[kk + lk][wm + 16 + li];
+      const TIn b0 = Bs[kk + lk][wn + li], b1 = Bs[kk + lk][wn + 16 + li];
+      acc[0][0] = MM::mma(a0, b0, acc[0][0]);
+      acc[0][1] = MM::mma(a0, b1, acc[0][1]);
+      acc[1][0] = MM::mma(a1, b0, acc[1][0]);
+      acc[1][1] = MM::mma(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wm + 16 * i + MM::row(lk, v), c = n0 + wn + 16 * j + li;
+        if (r < Mr && c < Nc) C[(long)r * ldc + c] = (TOut)(alpha * (double)acc[i][j][v]);
+      }
+}
+
+template <typename TIn, typename TOut, bool A_KMAJ>
+hipError_t gemm_real(hipStream_t st, int Mr, int Nc, int K, const TIn* A, int lda, long sA,
+                     const TIn* B, int ldb, long sB, TOut* C, int ldc, long sC, int batch,
+                     double alpha) {
+  dim3 grid((Nc + 63) / 64, (Mr + 63) / 64, batch);
+  hipLaunchKernelGGL((k_gemm_real<TIn, TOut, A_KMAJ>), grid, dim3(256), 0, st, Mr, Nc, K, A, lda,
+                     sA, B, ldb, sB, C, ldc, sC, alpha);
+  return hipGetLastError();
+}
+
+template hipError_t gemm_real<double, double, true>(hipStream_t, int, int, int, const double*, int,
+                                                    long, const double*, int, long, double*, int,
+                                                    long, int, double);
+template hipError_t gemm_real<double, double, false>(hipStream_t, int, int, int, const double*, int,
+                                                     long, const double*, int, long, double*, int,
+                                                     long, int, double);
+template hipError_t gemm_real<float, float, true>(hipStream_t, int, int, int, const float*, int,
+                                                  long, const float*, int, long, float*, int, long,
+                                                  int, double);
+template hipError_t gemm_real<double, float, true>(hipStream_t, int, int, int, const double*, int,
+                                                   long, const double*, int, long, float*, int,
+                                                   long, int, double);
+template hipError_t gemm_real<float, double, true>(hipStream_t, int, int, int, const float*, int,
+                                                   long, const float*, int, long, double*, int,
+                                                   long, int, double);
+
+// ===========================================================================
+// Walker-batched complex GEMM for the one-body factors B1 and the Taylor
+// terms of exp(A) (Thouless: the propagator acts on a determinant by a
+// matrix product on its orbitals).  Block = one 64x64 output tile of one
+// walker; complex products as 4 real MFMAs (2 for a real operator).
+// ===========================================================================
+template <typename T, typename TIn, bool A_CPLX, int MODE>
+__global__ __launch_bounds__(256) void k_cgemm_walkers(
+    int Mr, int Nc, int K, const T* __restrict__ Ar, const T* __restrict__ Ai, int lda, long sA,
+    const TIn* __restrict__ Inr, const TIn* __restrict__ Ini, int ldin, long sIn,
+    T* __restrict__ Outr, T* __restrict__ Outi, double* __restrict__ D1r, double* __restrict__ D1i,
+    double* __restrict__ D2r, double* __restrict__ D2i, int ldo, long sO, double alpha) {
+  constexpr int BM = 64, BN = 64, KC = 16;
+  __shared__ T Asr[KC][BM + 1];
+  __shared__ T Asi[A_CPLX ? KC : 1][BM + 1];
+  __shared__ T Bsr[KC][BN + 1];
+  __shared__ T Bsi[KC][BN + 1];
+  typedef Mfma<T> MM;
+  const long w = blockIdx.z;
+  const int nmt = (Mr + BM - 1) / BM;
+  const int m0 = (blockIdx.x % nmt) * BM, n0 = (blockIdx.x / nmt) * BN;
+  if (A_CPLX) { Ar += w * sA; Ai += w * sA; }
+  Inr += w * sIn;
+  Ini += w * sIn;
+  const int wv = wave_id(), l = lane_id();
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  const int li = l & 15, lk = l >> 4;
+  typename MM::acc_t cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) { cr[i][j] = MM::zero(); ci[i][j] = MM::zero(); }
+
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int e = threadIdx.x; e < KC * BM; e += 256) {
+      const int mm = e / KC, kk = e % KC;
+      const int gm = m0 + mm, gk = k0 + kk;
+      const bool ok = gm < Mr && gk < K;
+      Asr[kk][mm] = ok ? Ar[(long)gm * lda + gk] : (T)0;
+      if (A_CPLX) Asi[kk][mm] = ok ? Ai[(long)gm * lda + gk] : (T)0;
+    }
+    for (int e = threadIdx.x; e < KC * BN; e += 256) {
+      const int kk = e / BN, nn = e % BN;
+      const int gk = k0 + kk, gn = n0 + nn;
+      const bool ok = gk < K && gn < Nc;
+      Bsr[kk][nn] = ok ? (T)Inr[(long)gk * ldin + gn] : (T)0;
+      Bsi[kk][nn] = ok ? (T)Ini[(long)gk * ldin + gn] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      T ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = Asr[kk + lk][wm + 16 * i + li];
+        ai[i] = A_CPLX ? Asi[kk + lk][wm + 16 * i + li] : (T)0;
+        br[i] = Bsr[kk + lk][wn + 16 * i + li];
+        bi[i] = Bsi[kk + lk][wn + 16 * i + li];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = MM::mma(ar[i], br[j], cr[i][j]);
+          ci[i][j] = MM::mma(ar[i], bi[j], ci[i][j]);
+          if (A_CPLX) {
+            cr[i][j] = MM::mma(-ai[i], bi[j], cr[i][j]);
+            ci[i][j] = MM::mma(ai[i], br[j], ci[i][j]);
+          }
+        }
+    }
+    __syncthreads();
+  }
+  const long ob = w * sO;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wm + 16 * i + MM::row(lk, v), c = n0 + wn + 16 * j + li;
+        if (r >= Mr || c >= Nc) continue;
+        const long o = ob + (long)r * ldo + c;
+        const double xr = alpha * (double)cr[i][j][v], xi = alpha * (double)ci[i][j][v];
+        if (MODE == 0) {
+          const double yr = (double)Inr[(long)r * ldin + c] + xr;
+          const double yi = (double)Ini[(long)r * ldin + c] + xi;
+          D1r[o] = yr;
+          D1i[o] = yi;
+          if (D2r) { D2r[o] = yr; D2i[o] = yi; }
+        } else {
+          Outr[o] = (T)xr;
+          Outi[o] = (T)xi;
+          D1r[o] += xr;
+          D1i[o] += xi;
+        }
+      }
+}
+
+template <typename T, typename TIn, bool A_CPLX, int MODE>
+hipError_t cgemm_walkers(hipStream_t st, int W, int Mr, int Nc, int K, const T* Ar, const T* Ai,
+                         int lda, long sA, const TIn* Inr, const TIn* Ini, int ldin, long sIn,
+                         T* Outr, T* Outi, double* D1r, double* D1i, double* D2r, double* D2i,
+                         int ldo, long sO, double alpha) {
+  dim3 grid(((Mr + 63) / 64) * ((Nc + 63) / 64), 1, W);
+  hipLaunchKernelGGL((k_cgemm_walkers<T, TIn, A_CPLX, MODE>), grid, dim3(256), 0, st, Mr, Nc, K,
+                     Ar, Ai, lda, sA, Inr, Ini, ldin, sIn, Outr, Outi, D1r, D1i, D2r, D2i, ldo, sO,
+                     alpha);
+  return hipGetLastError();
+}
+
+#define AFQ_INST_CG(T, TIn, AC, MO)                                                              \
+  template hipError_t cgemm_walkers<T, TIn, AC, MO>(                                             \
+      hipStream_t, int, int, int, int, const T*, const T*, int, long, const TIn*, const TIn*,    \
+      int, long, T*, T*, double*, double*, double*, double*, int, long, double);
+AFQ_INST_CG(double, double, false, 0)
+AFQ_INST_CG(float, double, false, 0)
+AFQ_INST_CG(double, double, true, 1)
+AFQ_INST_CG(float, double, true, 1)
+AFQ_INST_CG(float, float, true, 1)
+
+// ===========================================================================
+// Fields and shifted coefficients (Eq. 2 with the force bias of Sec. II).
+// One block per walker.  xbar = -i sqrt(dt)(v - lbar), xs = x - xbar,
+// coefficient of L_g in A: i sqrt(dt) xs_g; mean-field log factor
+// mf = -i sqrt(dt) sum_g xs_g lbar_g.
+// ===========================================================================
+template <typename T>
+__global__ __launch_bounds__(256) void k_fields_coeff(int W, int G, uint64_t seed, uint64_t t,
+                                                      int system_id, double dt,
+                                                      const double* __restrict__ v_re,
+                                                      const double* __restrict__ v_im,
+                                                      const double* __restrict__ lbar,
+                                                      T* __restrict__ coefT, double* mf_re,
+                                                      double* mf_im, double* xdump) {
+  __shared__ double red[4];
+  const int w = blockIdx.x;
+  const double sq = sqrt(dt);
+  double sre = 0.0, sim = 0.0;
+  const int nq = (G + 3) / 4;
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+    double z[4];
+    gaussian4(seed, t, (uint64_t)w, (uint64_t)q, (uint64_t)system_id, z);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int g = 4 * q + j;
+      if (g >= G) break;
+      const double x = z[j];
+      const double vr = v_re ? v_re[(long)w * G + g] : 0.0;
+      const double vi = v_im ? v_im[(long)w * G + g] : 0.0;
+      const double lb = lbar ? lbar[g] : 0.0;
+      // xbar = -i sq (v - lbar): re = sq*vi, im = -sq*(vr - lb)
+      const double xsr = x - sq * vi;        // Re(x - xbar)
+      const double xsi = sq * (vr - lb);     // Im(x - xbar)
+      // i sq xs = -sq*xsi + i sq*xsr
+      if (coefT) {
+        coefT[(long)g * 2 * W + 2 * w] = (T)(-sq * xsi);
+        coefT[(long)g * 2 * W + 2 * w + 1] = (T)(sq * xsr);
+      }
+      // -i sq xs lbar = sq*xsi*lb - i sq*xsr*lb
+      sre += sq * xsi * lb;
+      sim += -sq * xsr * lb;
+      if (xdump) xdump[(long)w * G + g] = x;
+    }
+  }
+  sre = block_sum(sre, red);
+  sim = block_sum(sim, red);
+  if (threadIdx.x == 0 && mf_re) { mf_re[w] = sre; mf_im[w] = sim; }
+}
+
+template <typename T>
+hipError_t fields_coeff(hipStream_t st, int W, int G, uint64_t seed, uint64_t t, int system_id,
+                        double dt, const double* v_re, const double* v_im, const double* lbar,
+                        T* coefT, double* mf_re, double* mf_im, double* xdump) {
+  hipLaunchKernelGGL((k_fields_coeff<T>), dim3(W), dim3(256), 0, st, W, G, seed, t, system_id, dt,
+                     v_re, v_im, lbar, coefT, mf_re, mf_im, xdump);
+  return hipGetLastError();
+}
+template hipError_t fields_coeff<double>(hipStream_t, int, int, uint64_t, uint64_t, int, double,
+                                         const double*, const double*, const double*, double*,
+                                         double*, double*, double*);
+template hipError_t fields_coeff<float>(hipStream_t, int, int, uint64_t, uint64_t, int, double,
+                                        const double*, const double*, const double*, float*,
+                                        double*, double*, double*);
+
+// ===========================================================================
+// Overlap, inverse, log det and Theta, FP64 (Sec. II mixed estimates; the
+// reference determinant's A and A^-1 of Sec. III).  One block per (walker,
+// spin).  S = D_0^T phi in LDS, in-place Gauss-Jordan inversion with row
+// pivoting, Theta = phi S^-1, E1 = Tr(htil Theta).
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s0, SpinGeom s1,
+                                                       const double* __restrict__ phr,
+                                                       const double* __restrict__ phi,
+                                                       double* __restrict__ thr,
+                                                       double* __restrict__ thi, double* ld_re,
+                                                       double* ld_im, double* e1_re, double* e1_im) {
+  extern __shared__ double lds[];
+  __shared__ double red[4];
+  __shared__ int piv[AFQ_WAVE];
+  __shared__ int pk_sh;
+  const int w = blockIdx.x, s = blockIdx.y;
+  const SpinGeom g = s ? s1 : s0;
+  const int N = g.N, off = g.off;
+  const long wb = (long)w * M * Nt;
+  if (N == 0) {
+    if (threadIdx.x == 0) {
+      ld_re[2 * w + s] = 0.0; ld_im[2 * w + s] = 0.0;
+      e1_re[2 * w + s] = 0.0; e1_im[2 * w + s] = 0.0;
+    }
+    return;
+  }
+  const int ld = N + 1;
+  double* Sr = lds;
+  double* Si = lds + N * ld;
+  double* fr = Si + N * ld;
+  double* fi = fr + N;
+  // S[a][b] = sum_m C[m][a] phi[m][off+b]
+  for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+    const int a = e / N, b = e % N;
+    double sr = 0.0, si = 0.0;
+    for (int m = 0; m < M; ++m) {
+      const double c = g.C[(long)m * M + a];
+      sr += c * phr[wb + (long)m * Nt + off + b];
+      si += c * phi[wb + (long)m * Nt + off + b];
+    }
+    Sr[a * ld + b] = sr;
+    Si[a * ld + b] = si;
+  }
+  __syncthreads();
+  double ldr = 0.0, ldi = 0.0;
+  int nswap = 0;
+  for (int k = 0; k < N; ++k) {
+    if (threadIdx.x < AFQ_WAVE) {
+      const int i = k + threadIdx.x;
+      double mag = -1.0;
+      int idx = i;
+      if (i < N) mag = Sr[i * ld + k] * Sr[i * ld + k] + Si[i * ld + k] * Si[i * ld + k];
+      // wave argmax, ties to the lowest row
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double om = __shfl_xor(mag, o, AFQ_WAVE);
+        const int oi = __shfl_xor(idx, o, AFQ_WAVE);
+        if (om > mag || (om == mag && oi < idx)) { mag = om; idx = oi; }
+      }
+      if (threadIdx.x == 0) pk_sh = idx;
+    }
+    __syncthreads();
+    const int p = pk_sh;
+    if (threadIdx.x == 0) piv[k] = p;
+    if (p != k) {
+      for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        double t = Sr[k * ld + j]; Sr[k * ld + j] = Sr[p * ld + j]; Sr[p * ld + j] = t;
+        t = Si[k * ld + j]; Si[k * ld + j] = Si[p * ld + j]; Si[p * ld + j] = t;
+      }
+      ++nswap;
+    }
+    __syncthreads();
+    const zdbl pv = {Sr[k * ld + k], Si[k * ld + k]};
+    const zdbl lg = zlog(pv);
+    ldr += lg.re;
+    ldi += lg.im;
+    const zdbl pinv = zdiv(zdbl{1.0, 0.0}, pv);
+    // column k factors of the other rows
+    for (int i = threadIdx.x; i < N; i += blockDim.x) { fr[i] = Sr[i * ld + k]; fi[i] = Si[i * ld + k]; }
+    __syncthreads();
+    // scale pivot row
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+      zdbl v = (j == k) ? pinv : zmul(zdbl{Sr[k * ld + j], Si[k * ld + j]}, pinv);
+      Sr[k * ld + j] = v.re;
+      Si[k * ld + j] = v.im;
+    }
+    __syncthreads();
+    // eliminate
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+      const int i = e / N, j = e % N;
+      if (i == k) continue;
+      const zdbl f = {fr[i], fi[i]};
+      zdbl v;
+      if (j == k) {
+        v = zmul(zdbl{-f.re, -f.im}, pinv);
+      } else {
+        v = zsub(zdbl{Sr[i * ld + j], Si[i * ld + j]}, zmul(f, zdbl{Sr[k * ld + j], Si[k * ld + j]}));
+      }
+      Sr[i * ld + j] = v.re;
+      Si[i * ld + j] = v.im;
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int k = N - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k) {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        double t = Sr[i * ld + k]; Sr[i * ld + k] = Sr[i * ld + p]; Sr[i * ld + p] = t;
+        t = Si[i * ld + k]; Si[i * ld + k] = Si[i * ld + p]; Si[i * ld + p] = t;
+      }
+    }
+    __syncthreads();
+  }
+  // Theta[m][b] = sum_a phi[m][off+a] Sinv[a][b];  E1 = sum htil[b][m] Theta[m][b]
+  double er = 0.0, ei = 0.0;
+  for (int e = threadIdx.x; e < M * N; e += blockDim.x) {
+    const int m = e / N, b = e % N;
+    double tr = 0.0, ti = 0.0;
+    for (int a = 0; a < N; ++a) {
+      const double pr = phr[wb + (long)m * Nt + off + a], pi = phi[wb + (long)m * Nt + off + a];
+      const double qr = Sr[a * ld + b], qi = Si[a * ld + b];
+      tr += pr * qr - pi * qi;
+      ti += pr * qi + pi * qr;
+    }
+    thr[wb + (long)m * Nt + off + b] = tr;
+    thi[wb + (long)m * Nt + off + b] = ti;
+    const double hv = g.htil[(long)b * M + m];
+    er += hv * tr;
+    ei += hv * ti;
+  }
+  er = block_sum(er, red);
+  ei = block_sum(ei, red);
+  if (threadIdx.x == 0) {
+    const double pi_ = 3.141592653589793238462643383279;
+    ld_re[2 * w + s] = ldr;
+    ld_im[2 * w + s] = ldi + ((nswap & 1) ? pi_ : 0.0);
+    e1_re[2 * w + s] = er;
+    e1_im[2 * w + s] = ei;
+  }
+}
+
+hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, SpinGeom s1,
+                         const double* phr, const double* phi, double* thr, double* thi,
+                         double* ld_re, double* ld_im, double* e1_re, double* e1_im,
+                         size_t max_lds) {
+  const int N = s0.N > s1.N ? s0.N : s1.N;
+  const size_t lds = (size_t)(2 * N * (N + 1) + 2 * N) * sizeof(double);
+  if (lds > max_lds) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_overlap_theta, dim3(W, 2), dim3(256), lds, st, M, Nt, s0, s1, phr, phi,
+                     thr, thi, ld_re, ld_im, e1_re, e1_im);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Fused exchange / Coulomb / force-bias contraction (Sec. II local energy and
+// force bias; the half-rotated form of Eq. Ys).  One block per (walker,
+// spin); each wave takes every 4th Cholesky index g and forms
+// X_g = Ltil_g Theta (N x N, complex) as 16x16 MFMA tiles, pairing tile
+// (I,J) with (J,I) through a per-wave LDS scratch so that Tr(X X) =
+// sum_ab X_ab X_ba never leaves the CU.  Theta is staged once in LDS in the
+// contraction type T.
+// ===========================================================================
+template <typename T>
+__global__ __launch_bounds__(256) void k_exchange(int M, int MP4, int Nt, int G, SpinGeom s0,
+                                                  SpinGeom s1, const double* __restrict__ thr,
+                                                  const double* __restrict__ thi,
+                                                  double* __restrict__ vs_re,
+                                                  double* __restrict__ vs_im, double* exx_re,
+                                                  double* exx_im) {
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ double red[8];
+  typedef Mfma<T> MM;
+  typedef typename MM::acc_t acc_t;
+  const int w = blockIdx.x, s = blockIdx.y;
+  const SpinGeom g = s ? s1 : s0;
+  const int N = g.N, NP = g.NP, off = g.off;
+  const T* __restrict__ Lt = (const T*)g.Lt;
+  const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
+  if (N == 0) {
+    for (int q = threadIdx.x; q < G; q += blockDim.x) {
+      vs_re[((long)w * 2 + s) * G + q] = 0.0;
+      vs_im[((long)w * 2 + s) * G + q] = 0.0;
+    }
+    if (threadIdx.x == 0) { exx_re[2 * w + s] = 0.0; exx_im[2 * w + s] = 0.0; }
+    return;
+  }
+  T* Tr = (T*)lds_raw;              // [MP4][NP]
+  T* Ti = Tr + MP4 * NP;            // [MP4][NP]
+  T* scr = Ti + MP4 * NP;           // 4 waves x 2 x 256
+  T* myr = scr + wv * 512;
+  T* myi = myr + 256;
+  const long wb = (long)w * M * Nt;
+  for (int e = threadIdx.x; e < MP4 * NP; e += blockDim.x) {
+    const int m = e / NP, b = e % NP;
+    const bool ok = m < M && b < N;
+    Tr[e] = ok ? (T)thr[wb + (long)m * Nt + off + b] : (T)0;
+    Ti[e] = ok ? (T)thi[wb + (long)m * Nt + off + b] : (T)0;
+  }
+  __syncthreads();
+  const int NT = NP / 16;
+  double xx_re = 0.0, xx_im = 0.0;
+  for (int q = wv; q < G; q += 4) {
+    const T* Lq = Lt + (long)q * MP4 * NP;
+    double tr_re = 0.0, tr_im = 0.0;
+    for (int I = 0; I < NT; ++I) {
+      for (int J = I; J < NT; ++J) {
+        acc_t pr = MM::zero(), pi = MM::zero(), qr = MM::zero(), qi = MM::zero();
+        for (int k = 0; k < MP4; k += 4) {
+          const int kr = (k + lk) * NP;
+          const T aI = Lq[kr + 16 * I + li];
+          const T bJr = Tr[kr + 16 * J + li], bJi = Ti[kr + 16 * J + li];
+          pr = MM::mma(aI, bJr, pr);
+          pi = MM::mma(aI, bJi, pi);
+          if (I != J) {
+            const T aJ = Lq[kr + 16 * J + li];
+            const T bIr = Tr[kr + 16 * I + li], bIi = Ti[kr + 16 * I + li];
+            qr = MM::mma(aJ, bIr, qr);
+            qi = MM::mma(aJ, bIi, qi);
+          }
+        }
+        // stash the partner tile (J,I) (or (I,I) itself) row-major
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = MM::row(lk, v);
+          myr[r * 16 + li] = (I != J) ? qr[v] : pr[v];
+          myi[r * 16 + li] = (I != J) ? qi[v] : pi[v];
+        }
+        wave_lds_sync();
+        const double mult = (I != J) ? 2.0 : 1.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = MM::row(lk, v);   // row a within tile (I,J), column b = li
+          const double ar = (double)pr[v], ai = (double)pi[v];
+          const double br = (double)myr[li * 16 + r], bi = (double)myi[li * 16 + r];
+          xx_re += mult * (ar * br - ai * bi);
+          xx_im += mult * (ar * bi + ai * br);
+          if (I == J && r == li) { tr_re += ar; tr_im += ai; }
+        }
+        wave_lds_sync();
+      }
+    }
+    tr_re = wave_sum(tr_re);
+    tr_im = wave_sum(tr_im);
+    if (l == 0) {
+      vs_re[((long)w * 2 + s) * G + q] = tr_re;
+      vs_im[((long)w * 2 + s) * G + q] = tr_im;
+    }
+  }
+  xx_re = wave_sum(xx_re);
+  xx_im = wave_sum(xx_im);
+  if (l == 0) { red[wv] = xx_re; red[4 + wv] = xx_im; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    exx_re[2 * w + s] = (red[0] + red[1]) + (red[2] + red[3]);
+    exx_im[2 * w + s] = (red[4] + red[5]) + (red[6] + red[7]);
+  }
+}
+
+template <typename T>
+hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGeom s0, SpinGeom s1,
+                    const double* thr, const double* thi, double* vs_re, double* vs_im,
+                    double* exx_re, double* exx_im, size_t max_lds) {
+  const int NP = s0.NP > s1.NP ? s0.NP : s1.NP;
+  const size_t lds = (size_t)(2 * MP4 * NP + 4 * 512) * sizeof(T);
+  if (lds > max_lds) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_exchange<T>), dim3(W, 2), dim3(256), lds, st, M, MP4, Nt, G, s0, s1, thr,
+                     thi, vs_re, vs_im, exx_re, exx_im);
+  return hipGetLastError();
+}
+template hipError_t exchange<double>(hipStream_t, int, int, int, int, int, SpinGeom, SpinGeom,
+                                     const double*, const double*, double*, double*, double*,
+                                     double*, size_t);
+template hipError_t exchange<float>(hipStream_t, int, int, int, int, int, SpinGeom, SpinGeom,
+                                    const double*, const double*, double*, double*, double*,
+                                    double*, size_t);
+
+// ===========================================================================
+// Per-walker combination (one wave per walker):
+// v_g = v_up,g + v_dn,g;  E_L = e_core + E1 + 1/2 sum_g v_g^2 - 1/2 sum_s exx_s.
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_combine_single(
+    int W, int G, double e_core, const double* __restrict__ vs_re, const double* __restrict__ vs_im,
+    const double* exx_re, const double* exx_im, const double* e1_re, const double* e1_im,
+    const double* ld_re, const double* ld_im, double* __restrict__ v_re, double* __restrict__ v_im,
+    double* lsn_re, double* lsn_im, double* eln_re, double* eln_im, int* vfin) {
+  const int w = blockIdx.x * 4 + wave_id();
+  const int l = lane_id();
+  if (w >= W) return;
+  double jr = 0.0, ji = 0.0;
+  int fin = 1;
+  for (int q = l; q < G; q += AFQ_WAVE) {
+    const double a = vs_re[((long)w * 2) * G + q] + vs_re[((long)w * 2 + 1) * G + q];
+    const double b = vs_im[((long)w * 2) * G + q] + vs_im[((long)w * 2 + 1) * G + q];
+    v_re[(long)w * G + q] = a;
+    v_im[(long)w * G + q] = b;
+    jr += a * a - b * b;
+    ji += 2.0 * a * b;
+    if (!isfinite(a) || !isfinite(b)) fin = 0;
+  }
+  jr = wave_sum(jr);
+  ji = wave_sum(ji);
+  const double f = wave_sum((double)fin);
+  if (l == 0) {
+    const double er = e_core + (e1_re[2 * w] + e1_re[2 * w + 1]) + 0.5 * jr -
+                      0.5 * (exx_re[2 * w] + exx_re[2 * w + 1]);
+    const double ei = (e1_im[2 * w] + e1_im[2 * w + 1]) + 0.5 * ji -
+                      0.5 * (exx_im[2 * w] + exx_im[2 * w + 1]);
+    eln_re[w] = er;
+    eln_im[w] = ei;
+    lsn_re[w] = ld_re[2 * w] + ld_re[2 * w + 1];
+    lsn_im[w] = ld_im[2 * w] + ld_im[2 * w + 1];
+    vfin[w] = (f == (double)AFQ_WAVE) ? 1 : 0;
+  }
+}
+
+hipError_t combine_single(hipStream_t st, int W, int G, double e_core, const double* vs_re,
+                          const double* vs_im, const double* exx_re, const double* exx_im,
+                          const double* e1_re, const double* e1_im, const double* ld_re,
+                          const double* ld_im, double* v_re, double* v_im, double* lsn_re,
+                          double* lsn_im, double* eln_re, double* eln_im, int* vfin) {
+  hipLaunchKernelGGL(k_combine_single, dim3((W + 3) / 4), dim3(256), 0, st, W, G, e_core, vs_re,
+                     vs_im, exx_re, exx_im, e1_re, e1_im, ld_re, ld_im, v_re, v_im, lsn_re, lsn_im,
+                     eln_re, eln_im, vfin);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Phaseless weight update (Sec. II): log r = log S' - log S + mf,
+// W <- W exp(-dt (Re E_L - E_T)) max(0, cos(Im log r)); walkers with a zero
+// or non-finite result die.  One thread per walker (SoA, coalesced).
+// ===========================================================================
+__global__ void k_weight_update(int W, int mode, double dt, double e_trial,
+                                const double* __restrict__ lsn_re, const double* __restrict__ lsn_im,
+                                const double* __restrict__ eln_re, const double* __restrict__ eln_im,
+                                const double* __restrict__ mf_re, const double* __restrict__ mf_im,
+                                const int* __restrict__ vfin, double* weight, double* logS_re,
+                                double* logS_im, double* eloc_re, double* eloc_im, int* dead) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  if (mode == 2) {
+    logS_re[w] = lsn_re[w];
+    logS_im[w] = lsn_im[w];
+    return;
+  }
+  if (mode == 0) {
+    logS_re[w] = lsn_re[w];
+    logS_im[w] = lsn_im[w];
+    eloc_re[w] = eln_re[w];
+    eloc_im[w] = eln_im[w];
+    return;
+  }
+  const double lr = lsn_re[w] - logS_re[w] + mf_re[w];
+  const double li = lsn_im[w] - logS_im[w] + mf_im[w];
+  const double er = eln_re[w], ei = eln_im[w];
+  const double c = cos(li);
+  const double wn = weight[w] * exp(-dt * (er - e_trial)) * (c > 0.0 ? c : 0.0);
+  const bool ok = isfinite(wn) && isfinite(er) && isfinite(ei) && isfinite(lr) && isfinite(li) &&
+                  isfinite(lsn_re[w]) && isfinite(lsn_im[w]) && vfin[w] && wn > 0.0;
+  weight[w] = ok ? wn : 0.0;
+  logS_re[w] = lsn_re[w];
+  logS_im[w] = lsn_im[w];
+  eloc_re[w] = er;
+  eloc_im[w] = ei;
+  dead[w] = ok ? 0 : 1;
+}
+
+hipError_t weight_update(hipStream_t st, int W, int mode, double dt, double e_trial,
+                         const double* lsn_re, const double* lsn_im, const double* eln_re,
+                         const double* eln_im, const double* mf_re, const double* mf_im,
+                         const int* vfin, double* weight, double* logS_re, double* logS_im,
+                         double* eloc_re, double* eloc_im, int* dead) {
+  hipLaunchKernelGGL(k_weight_update, dim3((W + 255) / 256), dim3(256), 0, st, W, mode, dt,
+                     e_trial, lsn_re, lsn_im, eln_re, eln_im, mf_re, mf_im, vfin, weight, logS_re,
+                     logS_im, eloc_re, eloc_im, dead);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_reset_dead(int M, int Nt, int G, const int* dead,
+                                                    const double* D0, double ref_ls_re,
+                                                    double ref_ls_im, double ref_el_re,
+                                                    double ref_el_im, const double* vref_re,
+                                                    const double* vref_im, double* phr, double* phi,
+                                                    double* logS_re, double* logS_im,
+                                                    double* eloc_re, double* eloc_im, double* v_re,
+                                                    double* v_im) {
+  const int w = blockIdx.x;
+  if (!dead[w]) return;
+  const long n = (long)M * Nt;
+  for (long e = threadIdx.x; e < n; e += blockDim.x) {
+    phr[(long)w * n + e] = D0[e];
+    phi[(long)w * n + e] = 0.0;
+  }
+  for (int q = threadIdx.x; q < G; q += blockDim.x) {
+    v_re[(long)w * G + q] = vref_re[q];
+    v_im[(long)w * G + q] = vref_im[q];
+  }
+  if (threadIdx.x == 0) {
+    logS_re[w] = ref_ls_re;
+    logS_im[w] = ref_ls_im;
+    eloc_re[w] = ref_el_re;
+    eloc_im[w] = ref_el_im;
+  }
+}
+
+hipError_t reset_dead(hipStream_t st, int W, int M, int Nt, int G, const int* dead,
+                      const double* D0, double ref_ls_re, double ref_ls_im, double ref_el_re,
+                      double ref_el_im, const double* vref_re, const double* vref_im,
+                      double* phr, double* phi, double* logS_re, double* logS_im,
+                      double* eloc_re, double* eloc_im, double* v_re, double* v_im) {
+  hipLaunchKernelGGL(k_reset_dead, dim3(W), dim3(256), 0, st, M, Nt, G, dead, D0, ref_ls_re,
+                     ref_ls_im, ref_el_re, ref_el_im, vref_re, vref_im, phr, phi, logS_re, logS_im,
+                     eloc_re, eloc_im, v_re, v_im);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Mixed energy, one block, fixed-order sums.
+// ===========================================================================
+__global__ __launch_bounds__(1024) void k_mixed_energy(int W, const double* __restrict__ weight,
+                                                       const double* __restrict__ eloc_re,
+                                                       double* emix_out, double* den_out) {
+  __shared__ double red[16];
+  double num = 0.0, den = 0.0;
+  for (int w = threadIdx.x; w < W; w += blockDim.x) {
+    const double x = weight[w];
+    num += x * eloc_re[w];
+    den += x;
+  }
+  num = block_sum(num, red);
+  den = block_sum(den, red);
+  if (threadIdx.x == 0) {
+    if (emix_out) emix_out[0] = num / den;
+    if (den_out) den_out[0] = den;
+  }
+}
+
+hipError_t mixed_energy(hipStream_t st, int W, const double* weight, const double* eloc_re,
+                        double* emix_out, double* den_out) {
+  hipLaunchKernelGGL(k_mixed_energy, dim3(1), dim3(1024), 0, st, W, weight, eloc_re, emix_out,
+                     den_out);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Modified Gram-Schmidt per (walker, spin), FP64, in place in global memory
+// (Sec. IV.A: periodic orthonormalisation of walker orbitals).
+// ===========================================================================
+__global__ __launch_bounds__(256) void k_mgs(int M, int Nt, int n_up, int n_dn,
+                                             double* __restrict__ phr, double* __restrict__ phi) {
+  __shared__ double red[4];
+  const int w = blockIdx.x, s = blockIdx.y;
+  const int N = s ? n_dn : n_up, off = s ? n_up : 0;
+  const long wb = (long)w * M * Nt;
+  const int wv = wave_id(), l = lane_id();
+  for (int j = 0; j < N; ++j) {
+    double nrm = 0.0;
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+      const double a = phr[wb + (long)m * Nt + off + j], b = phi[wb + (long)m * Nt + off + j];
+      nrm += a * a + b * b;
+    }
+    nrm = block_sum(nrm, red);
+    const double r = sqrt(nrm);
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+      phr[wb + (long)m * Nt + off + j] /= r;
+      phi[wb + (long)m * Nt + off + j] /= r;
+    }
+    __syncthreads();
+    for (int k = j + 1 + wv; k < N; k += 4) {
+      double dr = 0.0, di = 0.0;
+      for (int m = l; m < M; m += AFQ_WAVE) {
+        const double qr = phr[wb + (long)m * Nt + off + j], qi = phi[wb + (long)m * Nt + off + j];
+        const double ar = phr[wb + (long)m * Nt + off + k], ai = phi[wb + (long)m * Nt + off + k];
+        dr += qr * ar + qi * ai;   // conj(q) a
+        di += qr * ai - qi * ar;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      for (int m = l; m < M; m += AFQ_WAVE) {
+        const double qr = phr[wb + (long)m * Nt + off + j], qi = phi[wb + (long)m * Nt + off + j];
+        phr[wb + (long)m * Nt + off + k] -= dr * qr - di * qi;
+        phi[wb + (long)m * Nt + off + k] -= dr * qi + di * qr;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double* phr, double* phi) {
+  hipLaunchKernelGGL(k_mgs, dim3(W, 2), dim3(256), 0, st, M, Nt, n_up, n_dn, phr, phi);
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Comb (population control).  Prefix sums and tooth positions are
+// sequential in one thread so that every rounding step is the same as a
+// plain left-to-right loop.
+// ===========================================================================
+__global__ void k_comb_parents(int W, const double* __restrict__ weight, uint64_t seed,
+                               uint64_t pc_index, int system_id, double* cbuf, int* parent,
+                               double* norm_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc = 0.0;
+  int last = W - 1;
+  bool any = false;
+  for (int k = 0; k < W; ++k) {
+    acc = acc + weight[k];
+    cbuf[k] = acc;
+  }
+  for (int k = W - 1; k >= 0; --k)
+    if (weight[k] > 0.0) { last = k; any = true; break; }
+  (void)any;
+  const double wtot = acc;
+  const PhiloxOut r = philox4x64_10(pc_index, 0ull, 0ull, (uint64_t)system_id, seed, AFQ_STREAM_COMB);
+  const double xi = u64_to_unit(r.w[0]);
+  int k = 0;
+  for (int j = 0; j < W; ++j) {
+    const double zj = (((double)j + xi) * wtot) / (double)W;
+    while (k < W && !(cbuf[k] > zj)) ++k;
+    parent[j] = (k < W) ? k : last;
+  }
+  if (norm_out) norm_out[0] = wtot / (double)W;
+}
+
+hipError_t comb_parents(hipStream_t st, int W, const double* weight, uint64_t seed,
+                        uint64_t pc_index, int system_id, double* cbuf, int* parent,
+                        double* norm_out) {
+  hipLaunchKernelGGL(k_comb_parents, dim3(1), dim3(64), 0, st, W, weight, seed, pc_index,
+                     system_id, cbuf, parent, norm_out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_gather_rows(long row, const int* __restrict__ parent,
+                                                     const double* __restrict__ src,
+                                                     double* __restrict__ dst) {
+  const int j = blockIdx.x;
+  const long p = parent[j];
+  for (long e = threadIdx.x; e < row; e += blockDim.x) dst[(long)j * row + e] = src[p * row + e];
+}
+
+hipError_t gather_rows(hipStream_t st, int W, long row, const int* parent, const double* src,
+                       double* dst) {
+  hipLaunchKernelGGL(k_gather_rows, dim3(W), dim3(256), 0, st, row, parent, src, dst);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* p, long n, double value) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+hipError_t fill(hipStream_t st, double* p, long n, double value) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, value);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_broadcast_rows(long row, const double* __restrict__ src,
+                                                        double* __restrict__ dst) {
+  const int j = blockIdx.x;
+  for (long e = threadIdx.x; e < row; e += blockDim.x) dst[(long)j * row + e] = src[e];
+}
+
+hipError_t broadcast_rows(hipStream_t st, int W, long row, const double* src, double* dst) {
+  hipLaunchKernelGGL(k_broadcast_rows, dim3(W), dim3(256), 0, st, row, src, dst);
+  return hipGetLastError();
+}
+
+// lbar_g += sum_{m < M, a < N} Lt[g][m][a] C[m][a]   (one block per g)
+__global__ __launch_bounds__(256) void k_lbar(int M, int MP4, int N, int NP,
+                                              const double* __restrict__ Lt,
+                                              const double* __restrict__ C, double* lbar) {
+  __shared__ double red[4];
+  const int q = blockIdx.x;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < M * N; e += blockDim.x) {
+    const int m = e / N, a = e % N;
+    s += Lt[(long)q * MP4 * NP + (long)m * NP + a] * C[(long)m * M + a];
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) lbar[q] += s;
+}
+
+hipError_t lbar_accumulate(hipStream_t st, int G, int M, int MP4, int N, int NP, const double* Lt,
+                           const double* C, double* lbar) {
+  if (G == 0 || N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lbar, dim3(G), dim3(256), 0, st, M, MP4, N, NP, Lt, C, lbar);
+  return hipGetLastError();
+}
+
+__global__ void k_convert(const double* src, float* dst, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
+hipError_t convert_f64_f32(hipStream_t st, const double* src, float* dst, long n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_convert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace afq

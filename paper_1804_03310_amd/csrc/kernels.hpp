@@ -1,0 +1,97 @@
+// Launchers of the gfx950 kernels (host side).  Every launcher enqueues on
+// `st` and returns the hipError_t of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace afq {
+
+// Per-spin parameters of one system, shared by several kernels.
+struct SpinGeom {
+  int N;              // electrons of this spin
+  int off;            // first column of this spin in a walker matrix
+  int NP;             // N rounded up to a multiple of 16
+  const double* C;    // [M][M] orbitals, D_0 = columns 0..N-1
+  const double* htil; // [N][M] = D_0^T h
+  const void* Lt;     // [G][MP4][NP] half-rotated Cholesky, D_0^T L_g, transposed, zero padded
+};
+
+// C[z] = alpha * A[z] B[z]; A(m,k) = A_KMAJ ? A[k*lda+m] : A[m*lda+k], B(k,n) = B[k*ldb+n].
+template <typename TIn, typename TOut, bool A_KMAJ>
+hipError_t gemm_real(hipStream_t st, int Mr, int Nc, int K, const TIn* A, int lda, long sA,
+                     const TIn* B, int ldb, long sB, TOut* C, int ldc, long sC, int batch,
+                     double alpha);
+
+// Walker-batched complex product of an M x K operator with K x Nc walker columns.
+// mode 0: D1 = In + A In (and D2 = D1 if D2 != null); A real, shared.
+// mode 1: Out = alpha A In (type T), D1 += alpha A In; A complex per walker.
+template <typename T, typename TIn, bool A_CPLX, int MODE>
+hipError_t cgemm_walkers(hipStream_t st, int W, int Mr, int Nc, int K, const T* Ar, const T* Ai,
+                         int lda, long sA, const TIn* Inr, const TIn* Ini, int ldin, long sIn,
+                         T* Outr, T* Outi, double* D1r, double* D1i, double* D2r, double* D2i,
+                         int ldo, long sO, double alpha);
+
+// Fields x, shifted propagator coefficients coefT[g][2w + {0,1}] = i sqrt(dt)(x - xbar)
+// (re, im) and the mean-field log factor mf[w].
+template <typename T>
+hipError_t fields_coeff(hipStream_t st, int W, int G, uint64_t seed, uint64_t t, int system_id,
+                        double dt, const double* v_re, const double* v_im, const double* lbar,
+                        T* coefT, double* mf_re, double* mf_im, double* xdump);
+
+// Per (walker, spin): S = D_0^T phi, LU/Gauss-Jordan inverse, log det, Theta = phi S^-1,
+// E1 = Tr(htil Theta).
+hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, SpinGeom s1,
+                         const double* phr, const double* phi, double* thr, double* thi,
+                         double* ld_re, double* ld_im, double* e1_re, double* e1_im,
+                         size_t max_lds);
+
+// Per (walker, spin): X_g = Ltil_g Theta; v[w][s][g] = Tr X_g; exx[w][s] = sum_g Tr(X_g X_g).
+template <typename T>
+hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGeom s0, SpinGeom s1,
+                    const double* thr, const double* thi, double* vs_re, double* vs_im,
+                    double* exx_re, double* exx_im, size_t max_lds);
+
+// Per walker: v = v_up + v_dn, E_L, log S_new (single determinant).
+hipError_t combine_single(hipStream_t st, int W, int G, double e_core, const double* vs_re,
+                          const double* vs_im, const double* exx_re, const double* exx_im,
+                          const double* e1_re, const double* e1_im, const double* ld_re,
+                          const double* ld_im, double* v_re, double* v_im, double* lsn_re,
+                          double* lsn_im, double* eln_re, double* eln_im, int* vfin);
+
+// mode 0: logS, eloc <- new values.  mode 1: phaseless weight update.  mode 2: logS only.
+hipError_t weight_update(hipStream_t st, int W, int mode, double dt, double e_trial,
+                         const double* lsn_re, const double* lsn_im, const double* eln_re,
+                         const double* eln_im, const double* mf_re, const double* mf_im,
+                         const int* vfin, double* weight, double* logS_re, double* logS_im,
+                         double* eloc_re, double* eloc_im, int* dead);
+
+// Dead walkers back to the reference determinant and its state.
+hipError_t reset_dead(hipStream_t st, int W, int M, int Nt, int G, const int* dead,
+                      const double* D0, double ref_ls_re, double ref_ls_im, double ref_el_re,
+                      double ref_el_im, const double* vref_re, const double* vref_im,
+                      double* phr, double* phi, double* logS_re, double* logS_im,
+                      double* eloc_re, double* eloc_im, double* v_re, double* v_im);
+
+// emix_out[0] = sum W Re E_L / sum W; den_out (nullable) = sum W.
+hipError_t mixed_energy(hipStream_t st, int W, const double* weight, const double* eloc_re,
+                        double* emix_out, double* den_out);
+
+// Modified Gram-Schmidt of both spin blocks of every walker, in place.
+hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double* phr, double* phi);
+
+// Comb: parents and norm factor (single thread, left-to-right sums).
+hipError_t comb_parents(hipStream_t st, int W, const double* weight, uint64_t seed,
+                        uint64_t pc_index, int system_id, double* cbuf, int* parent,
+                        double* norm_out);
+// Gather rows of length `row` doubles from src[parent[j]] to dst[j], for `nbuf` buffers.
+hipError_t gather_rows(hipStream_t st, int W, long row, const int* parent, const double* src,
+                       double* dst);
+hipError_t fill(hipStream_t st, double* p, long n, double value);
+hipError_t broadcast_rows(hipStream_t st, int W, long row, const double* src, double* dst);
+
+// lbar[g] += sum_{m,a} Lt[g][m][a] C[m][a]
+hipError_t lbar_accumulate(hipStream_t st, int G, int M, int MP4, int N, int NP, const double* Lt,
+                           const double* C, double* lbar);
+hipError_t convert_f64_f32(hipStream_t st, const double* src, float* dst, long n);
+
+}  // namespace afq

@@ -1,0 +1,277 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every case prints its name before running so that a failing GPU step can be
+identified from the log.  FP64 bar: mixed energy within 1e-9 Ha over 100
+steps; per-walker E_L within 1e-11 relative.  FP32 contractions: stated
+per-case tolerances in Ha.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import afqmc_synth as syn
+from oracle import Oracle, Options as OOptions, gaussian_fields
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def afq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1804_03310_amd as afq
+    return afq
+
+
+def _make(afq, inp, W, mf=True):
+    ham = afq.Hamiltonian(inp.h, inp.L, inp.e_core)
+    coeff = inp.coeff if inp.n_det > 1 else None
+    exc = inp.exc if inp.n_det > 1 else None
+    trial = afq.Trial(ham, inp.n_up, inp.n_dn, inp.C_up, inp.C_dn, coeff, exc, mf_subtract=mf)
+    w = afq.Walkers(trial, W)
+    return ham, trial, w
+
+
+def _set_phi(w, phi):
+    w.phi_re.copy_(torch.from_numpy(np.ascontiguousarray(phi.real)))
+    w.phi_im.copy_(torch.from_numpy(np.ascontiguousarray(phi.imag)))
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _wrap(a):
+    return (a + np.pi) % (2 * np.pi) - np.pi
+
+
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,G,t,sys_id", [(37, 41, 0, 0), (5, 250, 17, 3), (64, 1, 99, 0)])
+def test_fields_match_oracle(afq, W, G, t, sys_id):
+    _say(f"fields W={W} G={G} t={t} sys={sys_id}")
+    x = _np(afq.fields(11, t, W, G, sys_id))
+    ref = gaussian_fields(11, t, np.arange(W), G, sys_id)
+    assert np.max(np.abs(x - ref)) < 1e-13
+
+
+def test_local_energy_at_trial_equals_oracle(afq):
+    _say("local energy at trial, plain-M10")
+    inp = syn.workload_system(syn.WORKLOADS["plain-M10"])
+    ham, trial, w = _make(afq, inp, 8)
+    afq.walkers_from_trial(ham, trial, w)
+    e = afq.local_energy(ham, trial, w)
+    o = Oracle.from_inputs(inp)
+    ref = o.init_walkers(1).eloc[0].real
+    assert abs(e - ref) < 1e-11 * abs(ref)
+    assert np.allclose(_np(w.eloc[0]), ref, rtol=1e-11, atol=0)
+
+
+@pytest.mark.parametrize("M,n_up,n_dn,G,W", [(10, 5, 5, 40, 16), (23, 7, 4, 37, 9),
+                                               (50, 25, 25, 250, 6), (40, 17, 0, 30, 5)])
+def test_local_energy_random_walkers_fp64(afq, M, n_up, n_dn, G, W):
+    _say(f"local energy random walkers M={M} N={n_up}/{n_dn} G={G} W={W}")
+    inp = syn.make_system(M, n_up, n_dn, G, 8.0, seed=M + G, e_core=0.75)
+    ham, trial, w = _make(afq, inp, W)
+    re, im = syn.random_walkers(M, n_up, n_dn, W, seed=3, scale=0.3)
+    D0 = np.concatenate([inp.C_up[:, :n_up], inp.C_dn[:, :n_dn]], axis=1)
+    phi = D0[None] + re + 1j * im
+    _set_phi(w, phi)
+    afq.local_energy(ham, trial, w)
+    o = Oracle.from_inputs(inp)
+    m = o.measure(phi)
+    el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
+    ls = _np(w.logovlp[0]) + 1j * _np(w.logovlp[1])
+    assert np.allclose(el, m["eloc"], rtol=1e-10, atol=1e-10)
+    assert np.allclose(ls.real, m["logS"].real, atol=1e-10)
+    assert np.allclose(_wrap(ls.imag - m["logS"].imag), 0.0, atol=1e-10)
+
+
+def _run_both(afq, inp, W, n_steps, dt, opt_kw, prec=("fp64", "fp64"), seed=0, oracle_walkers=None):
+    ham, trial, w = _make(afq, inp, W)
+    afq.walkers_from_trial(ham, trial, w)
+    et = afq.local_energy(ham, trial, w)
+    opt = afq.Options(e_trial=et, chol_prec=prec[0], taylor_prec=prec[1], **opt_kw)
+    em = _np(afq.propagate(ham, trial, w, n_steps, dt, seed, 0, opt))
+    o = Oracle.from_inputs(inp)
+    st = o.init_walkers(W)
+    oe = o.propagate(st, n_steps, dt, seed, 0, OOptions(e_trial=et, **opt_kw))
+    return em, oe, w, st
+
+
+def test_propagate_plain_fp64_parity_100_steps(afq):
+    """Plain FP64 workload (M=10, 5/5, 40 vectors, 64 walkers, 100 steps)."""
+    _say("propagate plain-M10 fp64 100 steps")
+    wl = syn.WORKLOADS["plain-M10"]
+    inp = syn.workload_system(wl)
+    em, oe, w, st = _run_both(afq, inp, wl.n_walkers, wl.n_steps, wl.dt,
+                              dict(taylor_order=6, ortho_every=wl.ortho_every, pc_every=0))
+    print("max |dE_mix| =", np.max(np.abs(em - oe)), "alive", int(np.sum(st.weight > 0)))
+    assert np.max(np.abs(em - oe)) <= 1e-9
+    assert np.allclose(_np(w.weight), st.weight, rtol=1e-9, atol=1e-12)
+    el = _np(w.eloc[0])
+    assert np.allclose(el[st.weight > 0], st.eloc.real[st.weight > 0], rtol=1e-9)
+
+
+def test_propagate_with_comb_fp64_parity(afq):
+    _say("propagate plain-M10 fp64 with comb every 5")
+    wl = syn.WORKLOADS["plain-M10"]
+    inp = syn.workload_system(wl)
+    em, oe, w, st = _run_both(afq, inp, 64, 30, wl.dt, dict(taylor_order=6, ortho_every=2, pc_every=5))
+    assert np.max(np.abs(em - oe)) <= 1e-9
+    assert np.allclose(_np(w.weight), st.weight, rtol=1e-9)
+
+
+def test_propagate_is_deterministic(afq):
+    _say("determinism")
+    wl = syn.WORKLOADS["plain-M10"]
+    inp = syn.workload_system(wl)
+    outs = []
+    for _ in range(2):
+        ham, trial, w = _make(afq, inp, 32)
+        afq.walkers_from_trial(ham, trial, w)
+        opt = afq.Options(e_trial=-10.0, ortho_every=2, pc_every=4)
+        outs.append((_np(afq.propagate(ham, trial, w, 12, 0.005, 7, 3, opt)), _np(w.phi_re)))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_split_calls_equal_one_call(afq):
+    _say("split propagate calls")
+    inp = syn.workload_system(syn.WORKLOADS["plain-M10"])
+    ham, trial, w = _make(afq, inp, 16)
+    afq.walkers_from_trial(ham, trial, w)
+    opt = afq.Options(e_trial=-10.0, ortho_every=3, pc_every=0)
+    e_all = _np(afq.propagate(ham, trial, w, 10, 0.005, 5, 0, opt))
+    ham2, trial2, w2 = _make(afq, inp, 16)
+    afq.walkers_from_trial(ham2, trial2, w2)
+    e1 = _np(afq.propagate(ham2, trial2, w2, 4, 0.005, 5, 0, opt))
+    e2 = _np(afq.propagate(ham2, trial2, w2, 6, 0.005, 5, 4, opt))
+    assert np.allclose(np.concatenate([e1, e2]), e_all, rtol=0, atol=1e-11)
+
+
+def test_orthonormalize_parity(afq):
+    _say("orthonormalize")
+    inp = syn.make_system(30, 9, 6, 20, 8.0, seed=4)
+    ham, trial, w = _make(afq, inp, 7)
+    re, im = syn.random_walkers(30, 9, 6, 7, seed=5, scale=0.4)
+    phi = np.concatenate([inp.C_up[:, :9], inp.C_dn[:, :6]], axis=1)[None] + re + 1j * im
+    _set_phi(w, phi)
+    afq.local_energy(ham, trial, w)
+    e0 = _np(w.eloc[0]).copy()
+    afq.orthonormalize(ham, trial, w)
+    o = Oracle.from_inputs(inp)
+    st = o.init_walkers(7, phi=phi)
+    o.orthonormalize(st)
+    got = _np(w.phi_re) + 1j * _np(w.phi_im)
+    assert np.allclose(got, st.phi, atol=1e-12)
+    ls = _np(w.logovlp[0]) + 1j * _np(w.logovlp[1])
+    assert np.allclose(ls.real, st.logS.real, atol=1e-10)
+    assert np.allclose(_wrap(ls.imag - st.logS.imag), 0, atol=1e-10)
+    afq.local_energy(ham, trial, w)
+    assert np.allclose(_np(w.eloc[0]), e0, rtol=1e-11)
+
+
+@pytest.mark.parametrize("W", [1, 7, 64, 1000])
+def test_reconfigure_parity(afq, W):
+    _say(f"reconfigure W={W}")
+    inp = syn.make_system(6, 2, 2, 4, 8.0, seed=6)
+    ham, trial, w = _make(afq, inp, W)
+    rng = np.random.default_rng(W)
+    re, im = syn.random_walkers(6, 2, 2, W, seed=W, scale=0.3)
+    D0 = np.concatenate([inp.C_up[:, :2], inp.C_dn[:, :2]], axis=1)
+    phi = D0[None] + re + 1j * im
+    _set_phi(w, phi)
+    wts = rng.exponential(size=W)
+    wts[rng.random(W) < 0.25] = 0.0
+    if not np.any(wts > 0):
+        wts[0] = 1.0
+    w.weight.copy_(torch.from_numpy(wts))
+    afq.local_energy(ham, trial, w)
+    el_before = _np(w.eloc[0]).copy()
+    norm = afq.reconfigure(trial, w, 13, 4)
+    o = Oracle.from_inputs(inp)
+    st = o.init_walkers(W, phi=phi)
+    st.weight = wts.copy()
+    onorm = o.reconfigure(st, 13, 4)
+    assert norm == pytest.approx(onorm, rel=1e-14)
+    got = _np(w.phi_re) + 1j * _np(w.phi_im)
+    assert np.array_equal(got, st.phi)   # bit-exact copies of the same parents
+    assert np.array_equal(_np(w.weight), np.ones(W))
+    # parents are unique: E_L were copied along
+    assert np.all(np.isin(_np(w.eloc[0]), el_before))
+
+
+def _one_step_sampled(afq, inp, W, sample, dt, prec, taylor_order=6):
+    """One step of all W walkers from the reference on the GPU; the oracle
+    repeats the step for the sampled walkers alone (counter-based fields)."""
+    ham, trial, w = _make(afq, inp, W)
+    afq.walkers_from_trial(ham, trial, w)
+    et = afq.local_energy(ham, trial, w)
+    opt = afq.Options(taylor_order=taylor_order, e_trial=et, chol_prec=prec[0], taylor_prec=prec[1])
+    afq.propagate(ham, trial, w, 1, dt, 3, 0, opt)
+    el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
+    wt = _np(w.weight)
+    o = Oracle.from_inputs(inp)
+    st = o.init_walkers(len(sample), index=np.asarray(sample))
+    o.propagate(st, 1, dt, 3, 0, OOptions(taylor_order=taylor_order, e_trial=et))
+    return el[sample], wt[sample], st
+
+
+@pytest.mark.parametrize("prec,tol", [(("fp64", "fp64"), 1e-9), (("fp32", "fp32"), None)])
+def test_hchain_full_size_one_step_sampled(afq, prec, tol):
+    """hchain-M50 at its full size (1024 walkers, the benchmark's launch
+    configuration): per-walker E_L and weight after one step on 8 sampled
+    walkers vs the oracle.  FP64: relative 1e-9.  FP32 contractions: the
+    error is printed and bounded by 2e-6 relative (|E_L| ~ 1e4 Ha here)."""
+    wl = syn.WORKLOADS["hchain-M50"]
+    inp = syn.workload_system(wl)
+    sample = [0, 1, 255, 256, 511, 700, 1022, 1023]
+    _say(f"hchain full size one step {prec}")
+    el, wt, st = _one_step_sampled(afq, inp, wl.n_walkers, sample, wl.dt, prec)
+    alive = st.weight > 0
+    rel = np.abs(el - st.eloc)[alive] / np.abs(st.eloc[alive])
+    print(f"{prec}: alive {int(alive.sum())}/8, max |dE_L| = {np.max(np.abs(el - st.eloc)[alive]):.3e} Ha,"
+          f" max rel {np.max(rel):.3e}")
+    assert np.array_equal(wt > 0, alive)
+    bound = tol if tol is not None else 2e-6
+    assert np.max(rel) <= bound
+    assert np.allclose(wt[alive], st.weight[alive], rtol=50 * bound)
+
+
+def test_fp32_trajectory_tamed_hchain(afq):
+    """hchain shapes (M=50, 25/25, 250 vectors) with L scaled by 0.25 so that
+    walkers survive (the generator as specified kills every walker within a
+    few steps): 32 walkers, 20 steps, FP32 contractions and Taylor vs the FP64
+    oracle's mixed energy."""
+    _say("fp32 tamed hchain 32 walkers 20 steps")
+    wl = syn.WORKLOADS["hchain-M50"]
+    inp = syn.workload_system(wl)
+    inp.L = 0.25 * inp.L
+    em, oe, w, st = _run_both(afq, inp, 32, 20, wl.dt,
+                              dict(taylor_order=6, ortho_every=10, pc_every=0), prec=("fp32", "fp32"))
+    err = np.max(np.abs(em - oe))
+    print("fp32 tamed: max |dE_mix| (Ha) =", err, " |E| ~", abs(oe[-1]), "alive", int(np.sum(st.weight > 0)))
+    assert np.all(np.isfinite(oe))
+    assert err <= 1e-3 * abs(oe[-1])
+
+
+def test_fp64_trajectory_tamed_hchain(afq):
+    _say("fp64 tamed hchain 32 walkers 20 steps")
+    wl = syn.WORKLOADS["hchain-M50"]
+    inp = syn.workload_system(wl)
+    inp.L = 0.25 * inp.L
+    em, oe, w, st = _run_both(afq, inp, 32, 20, wl.dt, dict(taylor_order=6, ortho_every=10, pc_every=0))
+    err = np.max(np.abs(em - oe))
+    print("fp64 tamed: max |dE_mix| (Ha) =", err)
+    assert err <= 1e-9 * abs(oe[-1])
