@@ -209,6 +209,12 @@ struct afqmc_trial {
   int n_det = 1;
   std::vector<double> coeff;
   std::vector<int32_t> exc;
+  // multi-determinant trial: [n_det][2][5] (E, hole0, hole1, particle0, particle1),
+  // coefficients, and per spin (L_g C) for g < G plus (h C) at g = G, [G+1][M][M]
+  int* d_exc = nullptr;
+  double* d_coeff = nullptr;
+  double* LC64[2] = {nullptr, nullptr};
+  float* LC32[2] = {nullptr, nullptr};
   double ref_ls[2] = {0, 0}, ref_el[2] = {0, 0};
   double* vref_re = nullptr;
   double* vref_im = nullptr;
@@ -226,6 +232,7 @@ struct WS {
   double *lsn_re, *lsn_im, *eln_re, *eln_im, *mf_re, *mf_im;
   int *vfin, *dead, *parent;
   double *cbuf, *scal;
+  double *c0_re, *c0_im, *tot_re, *tot_im;
   void* coefT;
   void* A;
   double *P_re, *P_im, *ACC_re, *ACC_im;
@@ -279,6 +286,11 @@ WS layout(const afqmc_trial* tr, int W, void* base) {
   ws.Tb_re = take(wm);
   ws.Tb_im = take(wm);
   ws.snap = (double*)take(wm * 2 + (size_t)W * (4 + 2 * G) * sizeof(double));
+  const size_t nd = tr->n_det > 1 ? (size_t)tr->n_det : 0;
+  ws.c0_re = (double*)take((size_t)W * 2 * nd * sizeof(double));
+  ws.c0_im = (double*)take((size_t)W * 2 * nd * sizeof(double));
+  ws.tot_re = (double*)take(W * sizeof(double));
+  ws.tot_im = (double*)take(W * sizeof(double));
   ws.total = off;
   return ws;
 }
@@ -307,6 +319,25 @@ afq::SpinGeom spin_geom(const afqmc_trial* tr, int s, bool fp32) {
   return g;
 }
 
+afq::MDParams md_params(const afqmc_trial* tr, bool fp32) {
+  afq::MDParams p;
+  p.M = tr->ham->M;
+  p.Nt = tr->Nt;
+  p.G = tr->ham->G;
+  p.n_det = tr->n_det;
+  p.MP4 = tr->MP4;
+  p.e_core = tr->ham->e_core;
+  for (int s = 0; s < 2; ++s) {
+    p.sp[s].N = tr->nel[s];
+    p.sp[s].off = s ? tr->nel[0] : 0;
+    p.sp[s].C = tr->C[s];
+    p.sp[s].LC = fp32 ? (const void*)tr->LC32[s] : (const void*)tr->LC64[s];
+  }
+  p.exc = tr->d_exc;
+  p.coeff = tr->d_coeff;
+  return p;
+}
+
 // Overlap / Theta / exchange / combination for the current phi; leaves the new
 // log overlap and E_L in ws.lsn / ws.eln and the force-bias traces in ws.v.
 afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqmc_prec chol,
@@ -319,6 +350,25 @@ afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqm
     TimedLaunch tl(&hm->timer, KC_OVERLAP, st);
     AFQ_CK(afq::overlap_theta(st, W, M, Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re, ws.th_im,
                               ws.ld_re, ws.ld_im, ws.e1_re, ws.e1_im, hm->max_lds));
+  }
+  if (tr->n_det > 1) {
+    const afq::MDParams mp = md_params(tr, f32);
+    {
+      TimedLaunch tl(&hm->timer, KC_OTHER, st);
+      AFQ_CK(afq::md_overlap(st, W, mp, ws.th_re, ws.th_im, ws.ld_re, ws.ld_im, ws.c0_re, ws.c0_im,
+                             ws.tot_re, ws.tot_im, ws.lsn_re, ws.lsn_im, hm->max_lds));
+    }
+    TimedLaunch tl(&hm->timer, KC_EXCHANGE, st);
+    if (f32) {
+      AFQ_CK(afq::md_energy<float>(st, W, mp, ws.th_re, ws.th_im, ws.c0_re, ws.c0_im, ws.tot_re,
+                                   ws.tot_im, ws.v_re, ws.v_im, ws.eln_re, ws.eln_im, ws.vfin,
+                                   hm->max_lds));
+    } else {
+      AFQ_CK(afq::md_energy<double>(st, W, mp, ws.th_re, ws.th_im, ws.c0_re, ws.c0_im, ws.tot_re,
+                                    ws.tot_im, ws.v_re, ws.v_im, ws.eln_re, ws.eln_im, ws.vfin,
+                                    hm->max_lds));
+    }
+    return AFQMC_OK;
   }
   if (G > 0) {
     TimedLaunch tl(&hm->timer, KC_EXCHANGE, st);
@@ -359,10 +409,16 @@ afqmc_status orthonormalize_impl(afqmc_trial* tr, afqmc_walkers* wk, const WS& w
   const afq::SpinGeom s0 = spin_geom(tr, 0, false), s1 = spin_geom(tr, 1, false);
   AFQ_CK(afq::overlap_theta(st, W, hm->M, tr->Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re,
                             ws.th_im, ws.ld_re, ws.ld_im, ws.e1_re, ws.e1_im, hm->max_lds));
+  if (tr->n_det > 1) {
+    const afq::MDParams mp = md_params(tr, false);
+    AFQ_CK(afq::md_overlap(st, W, mp, ws.th_re, ws.th_im, ws.ld_re, ws.ld_im, ws.c0_re, ws.c0_im,
+                           ws.tot_re, ws.tot_im, ws.lsn_re, ws.lsn_im, hm->max_lds));
+  } else {
   // log S = sum over spins of log det (single determinant)
   AFQ_CK(afq::combine_single(st, W, 0, 0.0, ws.vs_re, ws.vs_im, ws.exx_re, ws.exx_im, ws.e1_re,
                              ws.e1_im, ws.ld_re, ws.ld_im, ws.v_re, ws.v_im, ws.lsn_re,
                              ws.lsn_im, ws.eln_re, ws.eln_im, ws.vfin));
+  }
   AFQ_CK(afq::weight_update(st, W, 2, 0.0, 0.0, ws.lsn_re, ws.lsn_im, ws.eln_re, ws.eln_im,
                             ws.mf_re, ws.mf_im, ws.vfin, wk->weight, wk->logovlp_re,
                             wk->logovlp_im, wk->eloc_re, wk->eloc_im, ws.dead));
@@ -602,7 +658,36 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
   if (n_det > 1 && (!coeff || !exc)) return fail(AFQMC_ERR_ARG, "coeff / exc NULL with n_det > 1");
   if (!all_finite(C_up, (size_t)M * M) || !all_finite(C_dn, (size_t)M * M))
     return fail(AFQMC_ERR_ARG, "C has a non-finite entry");
-  if (n_det > 1) return fail(AFQMC_ERR_UNSUPPORTED, "multi-determinant trials are not built yet");
+  std::vector<int> exc_dev;
+  if (n_det > 1) {
+    const int row = 1 + 2 * AFQMC_MAX_EXC;
+    const int nel_[2] = {n_up, n_dn};
+    exc_dev.assign((size_t)n_det * 10, 0);
+    for (int i = 0; i < n_det; ++i) {
+      if (!std::isfinite(coeff[i])) return fail(AFQMC_ERR_ARG, "coeff has a non-finite entry");
+      for (int s = 0; s < 2; ++s) {
+        const int32_t* ex = exc + ((size_t)i * 2 + s) * row;
+        const int E = ex[0];
+        if (E < 0 || E > AFQMC_MAX_EXC) return fail(AFQMC_ERR_ARG, "excitation count out of range");
+        if (i == 0 && E != 0) return fail(AFQMC_ERR_ARG, "determinant 0 must be the reference");
+        if (E > 2) return fail(AFQMC_ERR_UNSUPPORTED, "more than 2 excitations per spin");
+        for (int e = 0; e < E; ++e) {
+          const int r = ex[1 + e], v = ex[1 + AFQMC_MAX_EXC + e];
+          if (r < 0 || r >= nel_[s] || v < nel_[s] || v >= M)
+            return fail(AFQMC_ERR_ARG, "hole / particle index out of range");
+          for (int f = 0; f < e; ++f)
+            if (ex[1 + f] == r || ex[1 + AFQMC_MAX_EXC + f] == v)
+              return fail(AFQMC_ERR_ARG, "repeated hole or particle");
+        }
+        int* d = &exc_dev[((size_t)i * 2 + s) * 5];
+        d[0] = E;
+        for (int e = 0; e < E; ++e) {
+          d[1 + e] = ex[1 + e];
+          d[3 + e] = ex[1 + AFQMC_MAX_EXC + e];
+        }
+      }
+    }
+  }
   const int nel[2] = {n_up, n_dn};
   const double* Cs[2] = {C_up, C_dn};
   // the reference determinant must have orthonormal orbitals
@@ -702,6 +787,35 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
   }
   if (hipMemcpy(tr->D0, D0h.data(), D0h.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
     return bad(AFQMC_ERR_DEVICE, "D0 upload");
+  if (n_det > 1) {
+    void *pe, *pc;
+    if (tr->arena.alloc(&pe, exc_dev.size() * sizeof(int)) || tr->arena.alloc(&pc, (size_t)n_det * 8))
+      return bad(AFQMC_ERR_OOM, "trial allocation failed");
+    tr->d_exc = (int*)pe;
+    tr->d_coeff = (double*)pc;
+    tr->coeff.assign(coeff, coeff + n_det);
+    if (hipMemcpy(tr->d_exc, exc_dev.data(), exc_dev.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(tr->d_coeff, coeff, (size_t)n_det * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return bad(AFQMC_ERR_DEVICE, "excitation upload");
+    const size_t nlc = (size_t)(G + 1) * mm;
+    for (int s = 0; s < 2; ++s) {
+      void *p64, *p32;
+      if (tr->arena.alloc(&p64, nlc * 8) || tr->arena.alloc(&p32, nlc * 4))
+        return bad(AFQMC_ERR_OOM, "trial allocation failed");
+      tr->LC64[s] = (double*)p64;
+      tr->LC32[s] = (float*)p32;
+      // LC[g][m][p] = (L_g C)[m][p] for g < G, LC[G] = h C
+      if (G > 0 && afq::gemm_real<double, double, false>(st, M, M, M, hm->L, M, (long)mm, tr->C[s], M,
+                                                         0, tr->LC64[s], M, (long)mm, G, 1.0) != hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "L C");
+      if (afq::gemm_real<double, double, false>(st, M, M, M, hm->h, M, 0, tr->C[s], M, 0,
+                                                tr->LC64[s] + (size_t)G * mm, M, 0, 1, 1.0) != hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "h C");
+      if (afq::convert_f64_f32(st, tr->LC64[s], tr->LC32[s], (long)nlc) != hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "convert");
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return bad(AFQMC_ERR_DEVICE, "sync");
+  }
   // reference state: one walker at D_0, measured in FP64
   {
     afqmc_walkers rw;

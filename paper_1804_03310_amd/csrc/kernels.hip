@@ -444,9 +444,10 @@ hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, Spin
 // X_g = Ltil_g Theta (N x N, complex) as 16x16 MFMA tiles, pairing tile
 // (I,J) with (J,I) through a per-wave LDS scratch so that Tr(X X) =
 // sum_ab X_ab X_ba never leaves the CU.  Theta is staged once in LDS in the
-// contraction type T.
+// contraction type T when it fits (THETA_LDS); otherwise the B operand is
+// read from the walker's FP64 Theta in global memory (L2 resident).
 // ===========================================================================
-template <typename T>
+template <typename T, bool THETA_LDS>
 __global__ __launch_bounds__(256) void k_exchange(int M, int MP4, int Nt, int G, SpinGeom s0,
                                                   SpinGeom s1, const double* __restrict__ thr,
                                                   const double* __restrict__ thi,
@@ -470,19 +471,32 @@ __global__ __launch_bounds__(256) void k_exchange(int M, int MP4, int Nt, int G,
     if (threadIdx.x == 0) { exx_re[2 * w + s] = 0.0; exx_im[2 * w + s] = 0.0; }
     return;
   }
-  T* Tr = (T*)lds_raw;              // [MP4][NP]
-  T* Ti = Tr + MP4 * NP;            // [MP4][NP]
-  T* scr = Ti + MP4 * NP;           // 4 waves x 2 x 256
+  T* Tr = (T*)lds_raw;                       // [MP4][NP] (THETA_LDS)
+  T* Ti = Tr + (THETA_LDS ? MP4 * NP : 0);   // [MP4][NP]
+  T* scr = Ti + (THETA_LDS ? MP4 * NP : 0);  // 4 waves x 2 x 256
   T* myr = scr + wv * 512;
   T* myi = myr + 256;
   const long wb = (long)w * M * Nt;
-  for (int e = threadIdx.x; e < MP4 * NP; e += blockDim.x) {
-    const int m = e / NP, b = e % NP;
-    const bool ok = m < M && b < N;
-    Tr[e] = ok ? (T)thr[wb + (long)m * Nt + off + b] : (T)0;
-    Ti[e] = ok ? (T)thi[wb + (long)m * Nt + off + b] : (T)0;
+  if (THETA_LDS) {
+    for (int e = threadIdx.x; e < MP4 * NP; e += blockDim.x) {
+      const int m = e / NP, b = e % NP;
+      const bool ok = m < M && b < N;
+      Tr[e] = ok ? (T)thr[wb + (long)m * Nt + off + b] : (T)0;
+      Ti[e] = ok ? (T)thi[wb + (long)m * Nt + off + b] : (T)0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  // B operand Theta[m][b] (zero outside m < M, b < N)
+  auto theta = [&](int m, int b, T& re, T& im) {
+    if (THETA_LDS) {
+      re = Tr[m * NP + b];
+      im = Ti[m * NP + b];
+    } else {
+      const bool ok = m < M && b < N;
+      re = ok ? (T)thr[wb + (long)m * Nt + off + b] : (T)0;
+      im = ok ? (T)thi[wb + (long)m * Nt + off + b] : (T)0;
+    }
+  };
   const int NT = NP / 16;
   double xx_re = 0.0, xx_im = 0.0;
   for (int q = wv; q < G; q += 4) {
@@ -494,12 +508,14 @@ __global__ __launch_bounds__(256) void k_exchange(int M, int MP4, int Nt, int G,
         for (int k = 0; k < MP4; k += 4) {
           const int kr = (k + lk) * NP;
           const T aI = Lq[kr + 16 * I + li];
-          const T bJr = Tr[kr + 16 * J + li], bJi = Ti[kr + 16 * J + li];
+          T bJr, bJi;
+          theta(k + lk, 16 * J + li, bJr, bJi);
           pr = MM::mma(aI, bJr, pr);
           pi = MM::mma(aI, bJi, pi);
           if (I != J) {
             const T aJ = Lq[kr + 16 * J + li];
-            const T bIr = Tr[kr + 16 * I + li], bIi = Ti[kr + 16 * I + li];
+            T bIr, bIi;
+            theta(k + lk, 16 * I + li, bIr, bIi);
             qr = MM::mma(aJ, bIr, qr);
             qi = MM::mma(aJ, bIi, qi);
           }
@@ -548,9 +564,13 @@ hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGe
                     double* exx_re, double* exx_im, size_t max_lds) {
   const int NP = s0.NP > s1.NP ? s0.NP : s1.NP;
   const size_t lds = (size_t)(2 * MP4 * NP + 4 * 512) * sizeof(T);
-  if (lds > max_lds) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_exchange<T>), dim3(W, 2), dim3(256), lds, st, M, MP4, Nt, G, s0, s1, thr,
-                     thi, vs_re, vs_im, exx_re, exx_im);
+  if (lds <= max_lds) {
+    hipLaunchKernelGGL((k_exchange<T, true>), dim3(W, 2), dim3(256), lds, st, M, MP4, Nt, G, s0, s1,
+                       thr, thi, vs_re, vs_im, exx_re, exx_im);
+  } else {
+    hipLaunchKernelGGL((k_exchange<T, false>), dim3(W, 2), dim3(256), (size_t)4 * 512 * sizeof(T),
+                       st, M, MP4, Nt, G, s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
+  }
   return hipGetLastError();
 }
 template hipError_t exchange<double>(hipStream_t, int, int, int, int, int, SpinGeom, SpinGeom,

@@ -95,3 +95,40 @@ hipError_t lbar_accumulate(hipStream_t st, int G, int M, int MP4, int N, int NP,
 hipError_t convert_f64_f32(hipStream_t st, const double* src, float* dst, long n);
 
 }  // namespace afq
+
+namespace afq {
+
+// Multi-determinant trial (Sec. III).  Per spin: N, column offset, orbitals C
+// [M][M] (FP64) and the rotated Cholesky tensor LC [G+1][M][M] in the
+// contraction type, LC[g][m][p] = (L_g C)[m][p] and LC[G] = h C.
+struct MDSpin {
+  int N;
+  int off;
+  const double* C;
+  const void* LC;
+};
+struct MDParams {
+  int M, Nt, G, n_det, MP4;
+  double e_core;
+  MDSpin sp[2];
+  const int* exc;        // [n_det][2][5] = (E, hole0, hole1, particle0, particle1)
+  const double* coeff;   // [n_det]
+};
+
+// Per walker: Ghat = C^T Theta_0 (FP64), overlap ratio of every determinant
+// c0[w][s][i] = det(Ghat[particles, holes]), the total relative overlap
+// tot[w] = sum_i c_i c0_up c0_dn, and log S = sum_s log det A_s + log tot.
+hipError_t md_overlap(hipStream_t st, int W, const MDParams& p, const double* thr,
+                      const double* thi, const double* ld_re, const double* ld_im,
+                      double* c0_re, double* c0_im, double* tot_re, double* tot_im,
+                      double* lsn_re, double* lsn_im, size_t max_lds);
+
+// Per walker: E_L, force-bias input v and finiteness flag for the
+// multi-determinant trial, from the reference Theta_0 and the ratios above.
+template <typename T>
+hipError_t md_energy(hipStream_t st, int W, const MDParams& p, const double* thr,
+                     const double* thi, const double* c0_re, const double* c0_im,
+                     const double* tot_re, const double* tot_im, double* v_re, double* v_im,
+                     double* eln_re, double* eln_im, int* vfin, size_t max_lds);
+
+}  // namespace afq

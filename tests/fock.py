@@ -14,6 +14,9 @@ import itertools
 
 import numpy as np
 
+MAX_EXC = 4
+EXC_ROW = 1 + 2 * MAX_EXC
+
 
 def basis(M: int, n_up: int, n_dn: int):
     states = []
@@ -123,3 +126,45 @@ def permutation_sign(seq):
             if seq[i] > seq[j]:
                 sign = -sign
     return sign
+
+
+def fci_trial(h, L, e_core, C, n_up, n_dn):
+    """Exact ground state of the Fock-space H, expressed as a multi-determinant
+    trial over the orbitals C with the in-place hole->particle convention."""
+    M = h.shape[0]
+    hmo = C.T @ h @ C
+    Lmo = np.einsum("ip,gij,jq->gpq", C, L, C)
+    H, states, _ = hamiltonian_matrix(hmo, eri_from_chol(Lmo), e_core, M, n_up, n_dn)
+    evals, evecs = np.linalg.eigh(H)
+    # any eigenstate gives zero variance; take the lowest one with a sizeable
+    # reference amplitude (walkers start at the reference determinant)
+    ref_bits = sum(1 << i for i in range(n_up)) | sum(1 << (M + i) for i in range(n_dn))
+    kref = states.index(ref_bits)
+    pick = next(k for k in range(len(evals)) if abs(evecs[kref, k]) > 0.05)
+    c = evecs[:, pick]
+    exc_rows, coeff = [], []
+    for k, b in enumerate(states):
+        if abs(c[k]) < 1e-14:
+            continue
+        row = np.zeros((2, EXC_ROW), dtype=np.int32)
+        sign = 1
+        for s, n in enumerate((n_up, n_dn)):
+            occ = [i for i in range(M) if (b >> (s * M + i)) & 1]
+            holes = sorted(set(range(n)) - set(occ))
+            parts = sorted(set(occ) - set(range(n)))
+            inplace = list(range(n))
+            for r, v in zip(holes, parts):
+                inplace[inplace.index(r)] = v
+            sign *= permutation_sign(inplace)
+            row[s, 0] = len(holes)
+            for e, (r, v) in enumerate(zip(holes, parts)):
+                row[s, 1 + e] = r
+                row[s, 1 + MAX_EXC + e] = v
+        exc_rows.append(row)
+        coeff.append(sign * c[k])
+    # the reference (no excitations) first
+    order = sorted(range(len(exc_rows)), key=lambda i: (exc_rows[i][0, 0] + exc_rows[i][1, 0]) != 0)
+    exc = np.array([exc_rows[i] for i in order])
+    coeff = np.array([coeff[i] for i in order])
+    assert exc[0, 0, 0] == 0 and exc[0, 1, 0] == 0
+    return exc, coeff, evals[pick]

@@ -275,3 +275,98 @@ def test_fp64_trajectory_tamed_hchain(afq):
     err = np.max(np.abs(em - oe))
     print("fp64 tamed: max |dE_mix| (Ha) =", err)
     assert err <= 1e-9 * abs(oe[-1])
+
+
+# --------------------------------------------------------------------------
+# Multi-determinant trial (SMW route on the GPU, direct per-determinant
+# matrix elements in the oracle)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_multidet_local_energy_random_walkers(afq, prec, tol):
+    _say(f"multidet local energy random walkers {prec}")
+    M, nu, nd, G = 14, 4, 3, 9
+    inp = syn.make_system(M, nu, nd, G, 4.0, n_det=40, seed=8, e_core=0.3)
+    ham, trial, w = _make(afq, inp, 6)
+    D0 = np.concatenate([inp.C_up[:, :nu], inp.C_dn[:, :nd]], axis=1)
+    re, im = syn.random_walkers(M, nu, nd, 6, seed=2, scale=0.3)
+    phi = D0[None] + re + 1j * im
+    phi[5] = D0          # on the reference: every excited overlap is zero
+    _set_phi(w, phi)
+    if prec == "fp64":
+        afq.local_energy(ham, trial, w)
+    else:  # the FP32 contraction path is reached through a zero-step propagate
+        afq.propagate(ham, trial, w, 0, 0.01, 0, 0, afq.Options(chol_prec="fp32"))
+    o = Oracle.from_inputs(inp)
+    m = o.measure(phi)
+    el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
+    ls = _np(w.logovlp[0]) + 1j * _np(w.logovlp[1])
+    print(prec, "max rel dE_L", np.max(np.abs(el - m["eloc"]) / np.abs(m["eloc"])))
+    assert np.allclose(el, m["eloc"], rtol=tol, atol=0)
+    assert np.allclose(ls.real, m["logS"].real, atol=1e-10)
+    assert np.allclose(_wrap(ls.imag - m["logS"].imag), 0.0, atol=1e-10)
+
+
+def test_multidet_exact_fci_trial_zero_variance(afq):
+    """Exact ground state as a multi-determinant trial in a rotated orbital
+    basis (M=4, 2+2): every live walker's E_L equals the exact eigenvalue at
+    every step of a real run with MGS and comb."""
+    import fock
+    _say("multidet exact FCI trial zero variance")
+    M, nu, nd = 4, 2, 2
+    inp = syn.make_system(M, nu, nd, 5, 3.0, seed=13, e_core=0.2)
+    rng = np.random.default_rng(17)
+    C = np.linalg.qr(rng.standard_normal((M, M)))[0]
+    exc, coeff, efci = fock.fci_trial(inp.h, inp.L, inp.e_core, C, nu, nd)
+    ham = afq.Hamiltonian(inp.h, inp.L, inp.e_core)
+    trial = afq.Trial(ham, nu, nd, C, C, coeff, exc)
+    w = afq.Walkers(trial, 16)
+    afq.walkers_from_trial(ham, trial, w)
+    e0 = afq.local_energy(ham, trial, w)
+    assert abs(e0 - efci) < 1e-10
+    opt = afq.Options(ortho_every=2, pc_every=3, e_trial=efci)
+    em = _np(afq.propagate(ham, trial, w, 12, 0.02, 2, 0, opt))
+    wt = _np(w.weight)
+    el = _np(w.eloc[0])
+    assert np.all(np.abs(em - efci) < 1e-9)
+    assert np.allclose(el[wt > 0], efci, atol=1e-9)
+
+
+def test_multidet_propagate_fp64_parity(afq):
+    _say("multidet propagate fp64 parity")
+    M, nu, nd, G = 24, 7, 5, 30
+    inp = syn.make_system(M, nu, nd, G, 8.0, n_det=25, seed=31)
+    em, oe, w, st = _run_both(afq, inp, 12, 10, 0.005, dict(taylor_order=6, ortho_every=2, pc_every=5))
+    print("multidet max |dE_mix| =", np.max(np.abs(em - oe)), "alive", int(np.sum(st.weight > 0)))
+    assert np.max(np.abs(em - oe)) <= 1e-9 * max(1.0, np.max(np.abs(oe)))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_tm_multidet_full_size_sampled(afq, prec, tol):
+    """tm-multidet-M120 at full size (2048 walkers, 100 determinants, 600
+    vectors): E_L and log S of walkers perturbed from the reference, from the
+    multi-determinant kernels in the launch shape the step uses; the oracle
+    evaluates 3 sampled walkers directly."""
+    wl = syn.WORKLOADS["tm-multidet-M120"]
+    inp = syn.workload_system(wl)
+    _say(f"tm-multidet full size sampled {prec}")
+    W = wl.n_walkers
+    ham, trial, w = _make(afq, inp, W)
+    D0 = np.concatenate([inp.C_up[:, :wl.n_up], inp.C_dn[:, :wl.n_dn]], axis=1)
+    re, im = syn.random_walkers(wl.M, wl.n_up, wl.n_dn, W, seed=4, scale=0.05)
+    phi = D0[None] + re + 1j * im
+    _set_phi(w, phi)
+    if prec == "fp64":
+        afq.local_energy(ham, trial, w)
+    else:
+        afq.propagate(ham, trial, w, 0, wl.dt, 0, 0, afq.Options(chol_prec="fp32"))
+    el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
+    ls = _np(w.logovlp[0]) + 1j * _np(w.logovlp[1])
+    sample = [0, 1000, 2047]
+    o = Oracle.from_inputs(inp)
+    m = o.measure(phi[sample])
+    rel = np.abs(el[sample] - m["eloc"]) / np.abs(m["eloc"])
+    print(f"{prec}: max rel dE_L {np.max(rel):.3e}")
+    assert np.max(rel) <= tol
+    assert np.allclose(ls.real[sample], m["logS"].real, atol=1e-9)
+    assert np.allclose(_wrap(ls.imag[sample] - m["logS"].imag), 0.0, atol=1e-9)

@@ -334,48 +334,6 @@ def test_zero_variance_one_body_only():
     assert np.allclose(st.eloc, exact, atol=1e-12)
 
 
-def _fci_trial(h, L, e_core, C, n_up, n_dn):
-    """Exact ground state of the Fock-space H, expressed as a multi-determinant
-    trial over the orbitals C with the in-place hole->particle convention."""
-    M = h.shape[0]
-    hmo = C.T @ h @ C
-    Lmo = np.einsum("ip,gij,jq->gpq", C, L, C)
-    H, states, _ = fock.hamiltonian_matrix(hmo, fock.eri_from_chol(Lmo), e_core, M, n_up, n_dn)
-    evals, evecs = np.linalg.eigh(H)
-    # any eigenstate gives zero variance; take the lowest one with a sizeable
-    # reference amplitude (walkers start at the reference determinant)
-    ref_bits = sum(1 << i for i in range(n_up)) | sum(1 << (M + i) for i in range(n_dn))
-    kref = states.index(ref_bits)
-    pick = next(k for k in range(len(evals)) if abs(evecs[kref, k]) > 0.05)
-    c = evecs[:, pick]
-    exc_rows, coeff = [], []
-    for k, b in enumerate(states):
-        if abs(c[k]) < 1e-14:
-            continue
-        row = np.zeros((2, syn.EXC_ROW), dtype=np.int32)
-        sign = 1
-        for s, n in enumerate((n_up, n_dn)):
-            occ = [i for i in range(M) if (b >> (s * M + i)) & 1]
-            holes = sorted(set(range(n)) - set(occ))
-            parts = sorted(set(occ) - set(range(n)))
-            inplace = list(range(n))
-            for r, v in zip(holes, parts):
-                inplace[inplace.index(r)] = v
-            sign *= fock.permutation_sign(inplace)
-            row[s, 0] = len(holes)
-            for e, (r, v) in enumerate(zip(holes, parts)):
-                row[s, 1 + e] = r
-                row[s, 1 + syn.MAX_EXC + e] = v
-        exc_rows.append(row)
-        coeff.append(sign * c[k])
-    # the reference (no excitations) first
-    order = sorted(range(len(exc_rows)), key=lambda i: (exc_rows[i][0, 0] + exc_rows[i][1, 0]) != 0)
-    exc = np.array([exc_rows[i] for i in order])
-    coeff = np.array([coeff[i] for i in order])
-    assert exc[0, 0, 0] == 0 and exc[0, 1, 0] == 0
-    return exc, coeff, evals[pick]
-
-
 def test_zero_variance_exact_fci_trial_whole_step():
     """With the exact ground state as a multi-determinant trial, every
     walker's E_L equals E_FCI at every step of a real random-field run."""
@@ -383,7 +341,7 @@ def test_zero_variance_exact_fci_trial_whole_step():
     inp = syn.make_system(M, n_up, n_dn, 5, 3.0, seed=13, e_core=0.2)
     rng = np.random.default_rng(17)
     C = np.linalg.qr(rng.standard_normal((M, M)))[0]   # rotated orbital basis
-    exc, coeff, efci = _fci_trial(inp.h, inp.L, inp.e_core, C, n_up, n_dn)
+    exc, coeff, efci = fock.fci_trial(inp.h, inp.L, inp.e_core, C, n_up, n_dn)
     assert coeff.size > 10
     o = Oracle(inp.h, inp.L, inp.e_core, C, C, n_up, n_dn, coeff, exc)
     st = o.init_walkers(6)
