@@ -53,8 +53,10 @@ typedef enum {
   AFQMC_ERR_UNSUPPORTED = -7  /* size or precision outside this build's limits */
 } afqmc_status;
 
-/* Arithmetic of a contraction (Sec. III: single- vs double-precision). */
-typedef enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1 } afqmc_prec;
+/* Arithmetic of a contraction (Sec. III: single- vs double-precision).
+ * AFQMC_BF16: bf16 operands with FP32 accumulation on the matrix cores
+ * (contractions only; single-determinant trials). */
+typedef enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16 = 2 } afqmc_prec;
 
 #define AFQMC_MAX_EXC 4      /* excitations per spin in one determinant      */
 #define AFQMC_MAX_NEL 64     /* electrons per spin                           */
@@ -82,7 +84,8 @@ typedef struct {
   size_t workspace_bytes;
 } afqmc_walkers;
 
-/* Run options.  taylor_order: terms of the series for exp(A) (>= 1).
+/* Run options.  taylor_order: terms of the series for exp(A) (>= 1);
+ * chol_prec may be AFQMC_BF16, taylor_prec only AFQMC_FP64 or AFQMC_FP32.
  * ortho_every / pc_every: orthonormalise / comb after global step t when
  * (t+1) is a multiple (0 = never).  e_trial: E_T of the weight factor.
  * chol_prec: arithmetic of sum_g x_g L_g and of Ltil_g Theta;
@@ -124,6 +127,13 @@ afqmc_status afqmc_init_trial(afqmc_trial **out, afqmc_ham *ham, int n_up, int n
 /* Bytes of walker workspace for n_walkers walkers of this trial. */
 afqmc_status afqmc_walker_workspace_bytes(const afqmc_trial *trial, int n_walkers,
                                           size_t *bytes);
+
+/* Device bytes one system of these sizes occupies: Hamiltonian, trial
+ * (including one cached B1), the caller's walker buffers for n_walkers
+ * walkers and their workspace.  For admission decisions before anything is
+ * allocated. */
+afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_det,
+                                   int n_walkers, size_t *bytes);
 
 /* Sets every walker to the reference determinant D_0 with weight 1 and
  * fills logovlp / eloc with the reference values. */

@@ -18,14 +18,14 @@ AFQMC_OK = 0
 STATUS_NAMES = {0: "AFQMC_OK", -1: "AFQMC_ERR_ARG", -2: "AFQMC_ERR_OOM", -3: "AFQMC_ERR_DEVICE",
                 -4: "AFQMC_ERR_STATE", -5: "AFQMC_ERR_SINGULAR", -6: "AFQMC_ERR_NONFINITE",
                 -7: "AFQMC_ERR_UNSUPPORTED"}
-PREC = {"fp64": 0, "fp32": 1}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 MAX_EXC = 4
 
 # Every symbol include/afqmc.h declares.
 EXPORTED = ["afqmc_init_hamiltonian", "afqmc_init_trial", "afqmc_walker_workspace_bytes",
             "afqmc_walkers_from_trial", "afqmc_propagate", "afqmc_local_energy",
             "afqmc_orthonormalize", "afqmc_reconfigure", "afqmc_fields",
-            "afqmc_timing_enable", "afqmc_timing_read",
+            "afqmc_timing_enable", "afqmc_timing_read", "afqmc_footprint_bytes",
             "afqmc_free_hamiltonian", "afqmc_free_trial", "afqmc_last_error"]
 KERNEL_CLASSES = ["exchange", "propagator_build", "taylor_b1", "overlap_theta", "mgs", "comb",
                   "other"]
@@ -75,6 +75,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "afqmc_reconfigure": (c_int, [P, ctypes.POINTER(WalkersStruct), c_uint64, c_uint64, P, P]),
         "afqmc_fields": (c_int, [c_uint64, c_uint64, c_int, c_int, c_int, P, P]),
         "afqmc_timing_enable": (c_int, [P, c_int]),
+        "afqmc_footprint_bytes": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int,
+                                          ctypes.POINTER(c_size_t)]),
         "afqmc_timing_read": (c_int, [P, c_int, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(c_double)]),
         "afqmc_free_hamiltonian": (None, [P]),

@@ -179,6 +179,7 @@ struct afqmc_ham {
   double* h = nullptr;   // [M][M]
   double* L = nullptr;   // [G][M][M]
   float* Lf = nullptr;   // [G][M][M]
+  void* Lbf = nullptr;   // [G][M][M] bf16
   double* L2 = nullptr;  // sum_g L_g L_g
   std::vector<double> h_host;
   Arena arena;
@@ -202,6 +203,8 @@ struct afqmc_trial {
   double* htil[2] = {nullptr, nullptr};
   double* Lt64[2] = {nullptr, nullptr};
   float* Lt32[2] = {nullptr, nullptr};
+  void* Ltbf[2] = {nullptr, nullptr};  // [G][NP][MP32] bf16 (m contiguous)
+  int MP32 = 32;
   double* lbar = nullptr;
   double* D0 = nullptr;
   std::vector<double> H1p;
@@ -241,9 +244,8 @@ struct WS {
   size_t total;
 };
 
-WS layout(const afqmc_trial* tr, int W, void* base) {
+WS layout_dims(long M, long G, long Nt, int n_det, int W, void* base) {
   WS ws;
-  const long M = tr->ham->M, G = tr->ham->G, Nt = tr->Nt;
   size_t off = 0;
   char* b = (char*)base;
   auto take = [&](size_t bytes) -> void* {
@@ -286,13 +288,17 @@ WS layout(const afqmc_trial* tr, int W, void* base) {
   ws.Tb_re = take(wm);
   ws.Tb_im = take(wm);
   ws.snap = (double*)take(wm * 2 + (size_t)W * (4 + 2 * G) * sizeof(double));
-  const size_t nd = tr->n_det > 1 ? (size_t)tr->n_det : 0;
+  const size_t nd = n_det > 1 ? (size_t)n_det : 0;
   ws.c0_re = (double*)take((size_t)W * 2 * nd * sizeof(double));
   ws.c0_im = (double*)take((size_t)W * 2 * nd * sizeof(double));
   ws.tot_re = (double*)take(W * sizeof(double));
   ws.tot_im = (double*)take(W * sizeof(double));
   ws.total = off;
   return ws;
+}
+
+WS layout(const afqmc_trial* tr, int W, void* base) {
+  return layout_dims(tr->ham->M, tr->ham->G, tr->Nt, tr->n_det, W, base);
 }
 
 afqmc_status check_walkers(const afqmc_trial* tr, const afqmc_walkers* wk) {
@@ -308,14 +314,15 @@ afqmc_status check_walkers(const afqmc_trial* tr, const afqmc_walkers* wk) {
   return AFQMC_OK;
 }
 
-afq::SpinGeom spin_geom(const afqmc_trial* tr, int s, bool fp32) {
+afq::SpinGeom spin_geom(const afqmc_trial* tr, int s, afqmc_prec prec) {
+  const bool fp32 = prec == AFQMC_FP32;
   afq::SpinGeom g;
   g.N = tr->nel[s];
   g.off = s ? tr->nel[0] : 0;
   g.NP = tr->NP[s];
   g.C = tr->C[s];
   g.htil = tr->htil[s];
-  g.Lt = fp32 ? (const void*)tr->Lt32[s] : (const void*)tr->Lt64[s];
+  g.Lt = prec == AFQMC_BF16 ? tr->Ltbf[s] : fp32 ? (const void*)tr->Lt32[s] : (const void*)tr->Lt64[s];
   return g;
 }
 
@@ -345,7 +352,7 @@ afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqm
   afqmc_ham* hm = tr->ham;
   const int W = wk->n_walkers, M = hm->M, G = hm->G, Nt = tr->Nt;
   const bool f32 = chol == AFQMC_FP32;
-  const afq::SpinGeom s0 = spin_geom(tr, 0, f32), s1 = spin_geom(tr, 1, f32);
+  const afq::SpinGeom s0 = spin_geom(tr, 0, chol), s1 = spin_geom(tr, 1, chol);
   {
     TimedLaunch tl(&hm->timer, KC_OVERLAP, st);
     AFQ_CK(afq::overlap_theta(st, W, M, Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re, ws.th_im,
@@ -372,7 +379,10 @@ afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqm
   }
   if (G > 0) {
     TimedLaunch tl(&hm->timer, KC_EXCHANGE, st);
-    if (f32) {
+    if (chol == AFQMC_BF16) {
+      AFQ_CK(afq::exchange_bf16(st, W, M, tr->MP32, Nt, G, s0, s1, ws.th_re, ws.th_im, ws.vs_re,
+                                ws.vs_im, ws.exx_re, ws.exx_im, hm->max_lds));
+    } else if (f32) {
       AFQ_CK(afq::exchange<float>(st, W, M, tr->MP4, Nt, G, s0, s1, ws.th_re, ws.th_im, ws.vs_re,
                                   ws.vs_im, ws.exx_re, ws.exx_im, hm->max_lds));
     } else {
@@ -406,7 +416,7 @@ afqmc_status orthonormalize_impl(afqmc_trial* tr, afqmc_walkers* wk, const WS& w
     TimedLaunch tl(&hm->timer, KC_MGS, st);
     AFQ_CK(afq::mgs(st, W, hm->M, tr->Nt, tr->nel[0], tr->nel[1], wk->phi_re, wk->phi_im));
   }
-  const afq::SpinGeom s0 = spin_geom(tr, 0, false), s1 = spin_geom(tr, 1, false);
+  const afq::SpinGeom s0 = spin_geom(tr, 0, AFQMC_FP64), s1 = spin_geom(tr, 1, AFQMC_FP64);
   AFQ_CK(afq::overlap_theta(st, W, hm->M, tr->Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re,
                             ws.th_im, ws.ld_re, ws.ld_im, ws.e1_re, ws.e1_im, hm->max_lds));
   if (tr->n_det > 1) {
@@ -487,6 +497,8 @@ B1Entry* get_b1(afqmc_trial* tr, double dt, hipStream_t st, afqmc_status* err) {
   return &tr->b1.back();
 }
 
+struct Bf16Tag {};
+
 template <typename TC, typename TT>
 afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B1Entry* b1,
                              int n_steps, double dt, uint64_t seed, uint64_t step0,
@@ -495,18 +507,28 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
   const int W = wk->n_walkers, M = hm->M, G = hm->G, Nt = tr->Nt;
   const long mn = (long)M * Nt, mm = (long)M * M;
   const TC* Lc = std::is_same<TC, float>::value ? (const TC*)hm->Lf : (const TC*)hm->L;
+  constexpr bool BF = std::is_same<TC, Bf16Tag>::value;
   const TT* B1m = std::is_same<TT, float>::value ? (const TT*)b1->d32 : (const TT*)b1->d64;
   TC* coefT = (TC*)ws.coefT;
   TT* A = (TT*)ws.A;
   TT* Tbuf[2][2] = {{(TT*)ws.Ta_re, (TT*)ws.Ta_im}, {(TT*)ws.Tb_re, (TT*)ws.Tb_im}};
   for (int s = 0; s < n_steps; ++s) {
     const uint64_t t = step0 + (uint64_t)s;
-    AFQ_CK(afq::fields_coeff<TC>(st, W, G, seed, t, wk->system_id, dt, ws.v_re, ws.v_im, tr->lbar,
-                                 coefT, ws.mf_re, ws.mf_im, nullptr));
+    if constexpr (BF) {
+      AFQ_CK(afq::fields_coeff_bf16(st, W, G, G, seed, t, wk->system_id, dt, ws.v_re, ws.v_im,
+                                    tr->lbar, ws.coefT, ws.mf_re, ws.mf_im));
+    } else {
+      AFQ_CK(afq::fields_coeff<TC>(st, W, G, seed, t, wk->system_id, dt, ws.v_re, ws.v_im, tr->lbar,
+                                   coefT, ws.mf_re, ws.mf_im, nullptr));
+    }
     if (G > 0) {
       TimedLaunch tl(&hm->timer, KC_ABUILD, st);
-      AFQ_CK((afq::gemm_real<TC, TT, true>(st, 2 * W, (int)mm, G, coefT, 2 * W, 0, Lc, (int)mm, 0,
-                                           A, (int)mm, 0, 1, 1.0)));
+      if constexpr (BF) {
+        AFQ_CK(afq::gemm_bf16<TT>(st, 2 * W, (int)mm, G, ws.coefT, G, hm->Lbf, (int)mm, A, (int)mm, 1.0));
+      } else {
+        AFQ_CK((afq::gemm_real<TC, TT, true>(st, 2 * W, (int)mm, G, coefT, 2 * W, 0, Lc, (int)mm, 0,
+                                             A, (int)mm, 0, 1, 1.0)));
+      }
     } else {
       AFQ_CK(hipMemsetAsync(A, 0, (size_t)W * 2 * mm * sizeof(TT), st));
     }
@@ -599,9 +621,10 @@ afqmc_status afqmc_init_hamiltonian(afqmc_ham** out, int device, void* stream, i
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
     hm->max_lds = (size_t)lds;
   const size_t mm = (size_t)M * M, gmm = (size_t)n_chol * mm;
-  void *ph, *pL, *pLf, *pL2;
+  void *ph, *pL, *pLf, *pL2, *pLb;
   if (hm->arena.alloc(&ph, mm * 8) || hm->arena.alloc(&pL, gmm * 8) ||
-      hm->arena.alloc(&pLf, gmm * 4) || hm->arena.alloc(&pL2, mm * 8)) {
+      hm->arena.alloc(&pLf, gmm * 4) || hm->arena.alloc(&pL2, mm * 8) ||
+      hm->arena.alloc(&pLb, gmm * 2)) {
     hm->arena.release();
     delete hm;
     return fail(AFQMC_ERR_OOM, "hamiltonian allocation failed");
@@ -610,6 +633,7 @@ afqmc_status afqmc_init_hamiltonian(afqmc_ham** out, int device, void* stream, i
   hm->L = (double*)pL;
   hm->Lf = (float*)pLf;
   hm->L2 = (double*)pL2;
+  hm->Lbf = pLb;
   auto bad = [&](const char* what) {
     hm->arena.release();
     delete hm;
@@ -619,6 +643,7 @@ afqmc_status afqmc_init_hamiltonian(afqmc_ham** out, int device, void* stream, i
   if (n_chol > 0) {
     if (hipMemcpyAsync(hm->L, L, gmm * 8, hipMemcpyHostToDevice, st) != hipSuccess) return bad("L upload");
     if (afq::convert_f64_f32(st, hm->L, hm->Lf, (long)gmm) != hipSuccess) return bad("L convert");
+    if (afq::convert_f64_bf16(st, hm->L, hm->Lbf, (long)gmm) != hipSuccess) return bad("L convert");
   }
   // sum_g L_g L_g as one GEMM over the stacked index (g, k)
   if (afq::gemm_real<double, double, true>(st, M, M, n_chol * M, hm->L, M, 0, hm->L, M, 0, hm->L2,
@@ -634,6 +659,30 @@ void afqmc_free_hamiltonian(afqmc_ham* hm) {
   (void)hipSetDevice(hm->device);
   hm->arena.release();
   delete hm;
+}
+
+afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_det, int n_walkers,
+                                   size_t* bytes) {
+  if (!bytes || M < 1 || n_chol < 0 || n_up < 0 || n_dn < 0 || n_up + n_dn < 1 || n_det < 1 ||
+      n_walkers < 1)
+    return fail(AFQMC_ERR_ARG, "invalid sizes");
+  const size_t m = M, g = n_chol, mm = m * m, a = 256;
+  auto rnd = [&](size_t b) { return (std::max(b, a) + a - 1) / a * a; };
+  const int nel[2] = {n_up, n_dn};
+  const size_t MP4 = round_up(M, 4), MP32 = round_up(M, 32), Nt = (size_t)n_up + n_dn;
+  size_t tot = rnd(mm * 8) * 2 + rnd(g * mm * 8) + rnd(g * mm * 4) + rnd(g * mm * 2);  // ham
+  for (int s = 0; s < 2; ++s) {                                                        // trial
+    const size_t NP = round_up(std::max(nel[s], 1), 16);
+    tot += rnd(mm * 8) + rnd(std::max(nel[s], 1) * m * 8) + rnd(g * MP4 * NP * 12) +
+           rnd(g * NP * MP32 * 2);
+    if (n_det > 1) tot += rnd((g + 1) * mm * 8) + rnd((g + 1) * mm * 4);
+  }
+  tot += 3 * rnd(std::max<size_t>(g, 1) * 8) + rnd(m * Nt * 8) + rnd(mm * 8) + 2 * rnd(mm * 12);
+  if (n_det > 1) tot += rnd((size_t)n_det * 40) + rnd((size_t)n_det * 8);
+  tot += 2 * rnd((size_t)n_walkers * m * Nt * 8) + 5 * rnd((size_t)n_walkers * 8);  // walkers
+  tot += layout_dims(M, n_chol, (long)Nt, n_det, n_walkers, nullptr).total;
+  *bytes = tot;
+  return AFQMC_OK;
 }
 
 afqmc_status afqmc_walker_workspace_bytes(const afqmc_trial* tr, int n_walkers, size_t* bytes) {
@@ -707,6 +756,7 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
   tr->nel[1] = n_dn;
   tr->Nt = n_up + n_dn;
   tr->MP4 = round_up(M, 4);
+  tr->MP32 = round_up(M, 32);
   tr->n_det = n_det;
   for (int s = 0; s < 2; ++s) tr->NP[s] = round_up(std::max(nel[s], 1), 16);
   auto bad = [&](afqmc_status code, const char* what) {
@@ -737,6 +787,16 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
     }
     if (afq::convert_f64_f32(st, tr->Lt64[s], tr->Lt32[s], (long)nlt) != hipSuccess)
       return bad(AFQMC_ERR_DEVICE, "convert");
+    {
+      void* pb = nullptr;
+      const size_t nb = (size_t)G * tr->NP[s] * tr->MP32;
+      if (tr->arena.alloc(&pb, nb * 2)) return bad(AFQMC_ERR_OOM, "trial allocation failed");
+      tr->Ltbf[s] = pb;
+      if (hipMemsetAsync(pb, 0, nb * 2, st) != hipSuccess) return bad(AFQMC_ERR_DEVICE, "memset");
+      if (G > 0 && afq::transpose_f64_bf16(st, tr->MP4, tr->NP[s], tr->MP32, (long)tr->MP4 * tr->NP[s],
+                                           (long)tr->NP[s] * tr->MP32, G, tr->Lt64[s], pb) != hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "bf16 half-rotation");
+    }
     if (nel[s] > 0) {
       // htil[a][m] = sum_i C[i][a] h[i][m]
       if (afq::gemm_real<double, double, true>(st, nel[s], M, M, tr->C[s], M, 0, hm->h, M, 0,
@@ -954,9 +1014,12 @@ afqmc_status afqmc_propagate(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk, 
   if (opt->taylor_order < 1 || opt->taylor_order > 64) return fail(AFQMC_ERR_ARG, "taylor_order");
   if (opt->ortho_every < 0 || opt->pc_every < 0) return fail(AFQMC_ERR_ARG, "negative interval");
   if (!std::isfinite(opt->e_trial)) return fail(AFQMC_ERR_ARG, "e_trial is not finite");
-  if ((opt->chol_prec != AFQMC_FP64 && opt->chol_prec != AFQMC_FP32) ||
+  if ((opt->chol_prec != AFQMC_FP64 && opt->chol_prec != AFQMC_FP32 &&
+       opt->chol_prec != AFQMC_BF16) ||
       (opt->taylor_prec != AFQMC_FP64 && opt->taylor_prec != AFQMC_FP32))
     return fail(AFQMC_ERR_UNSUPPORTED, "precision");
+  if (opt->chol_prec == AFQMC_BF16 && tr->n_det > 1)
+    return fail(AFQMC_ERR_UNSUPPORTED, "bf16 contractions with a multi-determinant trial");
   AFQ_CK(hipSetDevice(hm->device));
   hipStream_t st = (hipStream_t)stream;
   const WS ws = layout(tr, wk->n_walkers, wk->workspace);
@@ -966,6 +1029,11 @@ afqmc_status afqmc_propagate(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk, 
   s = measure_set(tr, wk, ws, opt->chol_prec, st);
   if (s != AFQMC_OK) return s;
   const bool c32 = opt->chol_prec == AFQMC_FP32, t32 = opt->taylor_prec == AFQMC_FP32;
+  if (opt->chol_prec == AFQMC_BF16) {
+    if (t32)
+      return propagate_typed<Bf16Tag, float>(tr, wk, ws, b1, n_steps, dt, seed, step0, opt, emix_dev, st);
+    return propagate_typed<Bf16Tag, double>(tr, wk, ws, b1, n_steps, dt, seed, step0, opt, emix_dev, st);
+  }
   if (c32 && t32)
     return propagate_typed<float, float>(tr, wk, ws, b1, n_steps, dt, seed, step0, opt, emix_dev, st);
   if (c32 && !t32)

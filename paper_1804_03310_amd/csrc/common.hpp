@@ -134,3 +134,14 @@ __device__ inline zdbl zdiv(zdbl a, zdbl b) {
 __device__ inline zdbl zlog(zdbl a) { return {log(hypot(a.re, a.im)), atan2(a.im, a.re)}; }
 
 template <typename T> __device__ inline T to_t(double x) { return (T)x; }
+
+// ---------------------------------------------------------------------------
+// BF16 16x16x32 MFMA (gfx950): lane l supplies A[i = l%16][k = 8*(l/16) + j]
+// and B[k = 8*(l/16) + j][n = l%16] for j = 0..7 (eight bf16 each, packed in
+// one 16-byte vector); accumulator entry v holds D[4*(l/16) + v][l%16] in FP32.
+// ---------------------------------------------------------------------------
+typedef __bf16 afq_bf8 __attribute__((ext_vector_type(8)));
+__device__ inline afq_f4 mfma_bf16(afq_bf8 a, afq_bf8 b, afq_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline int row_bf16(int lk, int v) { return 4 * lk + v; }

@@ -132,3 +132,19 @@ hipError_t md_energy(hipStream_t st, int W, const MDParams& p, const double* thr
                      double* eln_re, double* eln_im, int* vfin, size_t max_lds);
 
 }  // namespace afq
+
+namespace afq {
+// BF16 contraction path (bf16.hip).
+hipError_t convert_f64_bf16(hipStream_t st, const double* src, void* dst, long n);
+hipError_t transpose_f64_bf16(hipStream_t st, int rows, int cols, int ld_dst, long s_src,
+                              long s_dst, int batch, const double* src, void* dst);
+template <typename TOut>
+hipError_t gemm_bf16(hipStream_t st, int Mr, int Nc, int K, const void* A, int lda, const void* B,
+                     int ldb, TOut* C, int ldc, double alpha);
+hipError_t fields_coeff_bf16(hipStream_t st, int W, int G, int ldg, uint64_t seed, uint64_t t,
+                             int system_id, double dt, const double* v_re, const double* v_im,
+                             const double* lbar, void* coef, double* mf_re, double* mf_im);
+hipError_t exchange_bf16(hipStream_t st, int W, int M, int MP32, int Nt, int G, SpinGeom s0,
+                         SpinGeom s1, const double* thr, const double* thi, double* vs_re,
+                         double* vs_im, double* exx_re, double* exx_im, size_t max_lds);
+}  // namespace afq

@@ -370,3 +370,53 @@ def test_tm_multidet_full_size_sampled(afq, prec, tol):
     assert np.max(rel) <= tol
     assert np.allclose(ls.real[sample], m["logS"].real, atol=1e-9)
     assert np.allclose(_wrap(ls.imag[sample] - m["logS"].imag), 0.0, atol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Precision sweep at the 200-orbital size
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def sweep_case():
+    wl = syn.WORKLOADS["sweep-M200"]
+    inp = syn.workload_system(wl)
+    D0 = np.concatenate([inp.C_up[:, :wl.n_up], inp.C_dn[:, :wl.n_dn]], axis=1)
+    re, im = syn.random_walkers(wl.M, wl.n_up, wl.n_dn, wl.n_walkers, seed=6, scale=0.03)
+    phi = D0[None] + re + 1j * im
+    sample = [0, 1023]
+    o = Oracle.from_inputs(inp)
+    ref = o.measure(phi[sample])
+    return wl, inp, phi, sample, ref
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16", 2e-2)])
+def test_sweep_full_size_local_energy(afq, sweep_case, prec, tol):
+    """sweep-M200 (M=200, 50/50, 1000 vectors, 1024 walkers): E_L of perturbed
+    walkers with the exchange contraction in FP64 / FP32 / BF16 (FP32
+    accumulation) against the FP64 oracle on 2 sampled walkers; the error in
+    Ha is printed."""
+    wl, inp, phi, sample, ref = sweep_case
+    _say(f"sweep full size local energy {prec}")
+    ham, trial, w = _make(afq, inp, wl.n_walkers)
+    _set_phi(w, phi)
+    afq.propagate(ham, trial, w, 0, wl.dt, 0, 0, afq.Options(chol_prec=prec))
+    el = (_np(w.eloc[0]) + 1j * _np(w.eloc[1]))[sample]
+    err = np.abs(el - ref["eloc"])
+    print(f"sweep {prec}: |E_L| ~ {np.abs(ref['eloc']).max():.1f} Ha, max |dE_L| = {err.max():.3e} Ha,"
+          f" rel {np.max(err / np.abs(ref['eloc'])):.3e}")
+    assert np.max(err / np.abs(ref["eloc"])) <= tol
+
+
+def test_bf16_propagate_runs_and_tracks_fp64(afq):
+    """BF16 contractions over 10 steps of the tamed hydrogen-chain variant:
+    finite, and the mixed energy within 2% of the FP64 oracle."""
+    _say("bf16 tamed hchain 16 walkers 10 steps")
+    wl = syn.WORKLOADS["hchain-M50"]
+    inp = syn.workload_system(wl)
+    inp.L = 0.25 * inp.L
+    em, oe, w, st = _run_both(afq, inp, 16, 10, wl.dt, dict(taylor_order=6, ortho_every=10, pc_every=0),
+                              prec=("bf16", "fp32"))
+    err = np.max(np.abs(em - oe))
+    print("bf16 tamed: max |dE_mix| (Ha) =", err, " |E| ~", abs(oe[-1]))
+    assert np.all(np.isfinite(em))
+    assert err <= 2e-2 * abs(oe[-1])
