@@ -535,6 +535,10 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
     // phi -> P = B1 phi, ACC = P
     {
     TimedLaunch tl_t(&hm->timer, KC_TAYLOR, st);
+    if (afq::propagate_fused_fits(M, Nt, sizeof(TT), hm->max_lds)) {
+      AFQ_CK(afq::propagate_fused<TT>(st, W, M, Nt, opt->taylor_order, A, B1m, wk->phi_re,
+                                      wk->phi_im, hm->max_lds));
+    } else {
     AFQ_CK((afq::cgemm_walkers<TT, double, false, 0>(st, W, M, Nt, M, B1m, nullptr, M, 0,
                                                      wk->phi_re, wk->phi_im, Nt, mn, nullptr,
                                                      nullptr, ws.P_re, ws.P_im, ws.ACC_re,
@@ -561,6 +565,7 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
                                                      ws.ACC_re, ws.ACC_im, Nt, mn, nullptr,
                                                      nullptr, wk->phi_re, wk->phi_im, nullptr,
                                                      nullptr, Nt, mn, 1.0)));
+    }
     }
     afqmc_status rs = measure_core(tr, wk, ws, opt->chol_prec, st);
     if (rs != AFQMC_OK) return rs;

@@ -558,11 +558,158 @@ __global__ __launch_bounds__(256) void k_exchange(int M, int MP4, int Nt, int G,
   }
 }
 
+// Exchange kernel for N <= 16*NT (NT <= 2): per Cholesky index all NT x NT
+// tiles of X_g (re and im) are accumulated together, so each k step loads NT
+// A values (global, L2 resident) and 2 NT B values (LDS) for 2 NT^2 MFMAs; the
+// A operand of the next four k steps is prefetched into registers while the
+// current four run.  The Theta rows in LDS are padded to a stride of 16 mod
+// 32 elements against bank conflicts; X is stashed once per g in a per-wave
+// LDS tile (odd row stride) to pair X_ab with X_ba.
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, int G, SpinGeom s0,
+                                                       SpinGeom s1, const double* __restrict__ thr,
+                                                       const double* __restrict__ thi,
+                                                       double* __restrict__ vs_re,
+                                                       double* __restrict__ vs_im, double* exx_re,
+                                                       double* exx_im) {
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ double red[8];
+  typedef Mfma<T> MM;
+  typedef typename MM::acc_t acc_t;
+  constexpr int NPM = 16 * NT;
+  constexpr int LDB = (NPM % 32 == 0) ? NPM + 16 : NPM;
+  constexpr int LDX = NPM + 1;
+  const int w = blockIdx.x, s = blockIdx.y;
+  const SpinGeom g = s ? s1 : s0;
+  const int N = g.N, NP = g.NP, off = g.off, nt = NP / 16;
+  const T* __restrict__ Lt = (const T*)g.Lt;
+  const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
+  if (N == 0) {
+    for (int q = threadIdx.x; q < G; q += blockDim.x) {
+      vs_re[((long)w * 2 + s) * G + q] = 0.0;
+      vs_im[((long)w * 2 + s) * G + q] = 0.0;
+    }
+    if (threadIdx.x == 0) { exx_re[2 * w + s] = 0.0; exx_im[2 * w + s] = 0.0; }
+    return;
+  }
+  T* Br = (T*)lds_raw;
+  T* Bi = Br + MP4 * LDB;
+  T* Xr = Bi + MP4 * LDB + wv * 2 * NPM * LDX;
+  T* Xi = Xr + NPM * LDX;
+  const long wb = (long)w * M * Nt;
+  for (int e = threadIdx.x; e < MP4 * NPM; e += blockDim.x) {
+    const int m = e / NPM, b = e % NPM;
+    const bool ok = m < M && b < N;
+    Br[m * LDB + b] = ok ? (T)thr[wb + (long)m * Nt + off + b] : (T)0;
+    Bi[m * LDB + b] = ok ? (T)thi[wb + (long)m * Nt + off + b] : (T)0;
+  }
+  __syncthreads();
+  const int KS = MP4 / 4;
+  double xx_re = 0.0, xx_im = 0.0;
+  for (int q = wv; q < G; q += 4) {
+    const T* __restrict__ Lq = Lt + (long)q * MP4 * NP;
+    acc_t cr[NT][NT], ci[NT][NT];
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+      for (int J = 0; J < NT; ++J) { cr[I][J] = MM::zero(); ci[I][J] = MM::zero(); }
+    T a0[4][NT], a1[4][NT];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+        a0[j][I] = (j < KS && I < nt) ? Lq[(4 * j + lk) * NP + 16 * I + li] : (T)0;
+    for (int kb = 0; kb < KS; kb += 4) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int I = 0; I < NT; ++I)
+          a1[j][I] = (kb + 4 + j < KS && I < nt) ? Lq[(4 * (kb + 4 + j) + lk) * NP + 16 * I + li] : (T)0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (kb + j < KS) {
+          const int m = 4 * (kb + j) + lk;
+          T br[NT], bi[NT];
+#pragma unroll
+          for (int J = 0; J < NT; ++J) {
+            br[J] = Br[m * LDB + 16 * J + li];
+            bi[J] = Bi[m * LDB + 16 * J + li];
+          }
+#pragma unroll
+          for (int I = 0; I < NT; ++I)
+#pragma unroll
+            for (int J = 0; J < NT; ++J) {
+              cr[I][J] = MM::mma(a0[j][I], br[J], cr[I][J]);
+              ci[I][J] = MM::mma(a0[j][I], bi[J], ci[I][J]);
+            }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int I = 0; I < NT; ++I) a0[j][I] = a1[j][I];
+    }
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+      for (int J = 0; J < NT; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * I + MM::row(lk, v), c = 16 * J + li;
+          Xr[r * LDX + c] = cr[I][J][v];
+          Xi[r * LDX + c] = ci[I][J][v];
+        }
+    wave_lds_sync();
+    double tr_re = 0.0, tr_im = 0.0;
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+      for (int J = 0; J < NT; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * I + MM::row(lk, v), b = 16 * J + li;
+          const double xr = (double)cr[I][J][v], xi = (double)ci[I][J][v];
+          const double yr = (double)Xr[b * LDX + a], yi = (double)Xi[b * LDX + a];
+          xx_re += xr * yr - xi * yi;
+          xx_im += xr * yi + xi * yr;
+          if (a == b) { tr_re += xr; tr_im += xi; }
+        }
+    wave_lds_sync();
+    tr_re = wave_sum(tr_re);
+    tr_im = wave_sum(tr_im);
+    if (l == 0) {
+      vs_re[((long)w * 2 + s) * G + q] = tr_re;
+      vs_im[((long)w * 2 + s) * G + q] = tr_im;
+    }
+  }
+  xx_re = wave_sum(xx_re);
+  xx_im = wave_sum(xx_im);
+  if (l == 0) { red[wv] = xx_re; red[4 + wv] = xx_im; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    exx_re[2 * w + s] = (red[0] + red[1]) + (red[2] + red[3]);
+    exx_im[2 * w + s] = (red[4] + red[5]) + (red[6] + red[7]);
+  }
+}
+
 template <typename T>
 hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGeom s0, SpinGeom s1,
                     const double* thr, const double* thi, double* vs_re, double* vs_im,
                     double* exx_re, double* exx_im, size_t max_lds) {
   const int NP = s0.NP > s1.NP ? s0.NP : s1.NP;
+  if (NP <= 32) {
+    const int NPM = NP, LDB = (NPM % 32 == 0) ? NPM + 16 : NPM, LDX = NPM + 1;
+    const size_t ldsf = (size_t)(2 * MP4 * LDB + 4 * 2 * NPM * LDX) * sizeof(T);
+    if (ldsf <= max_lds) {
+      if (NP == 16)
+        hipLaunchKernelGGL((k_exchange_full<T, 1>), dim3(W, 2), dim3(256), ldsf, st, M, MP4, Nt, G,
+                           s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
+      else
+        hipLaunchKernelGGL((k_exchange_full<T, 2>), dim3(W, 2), dim3(256), ldsf, st, M, MP4, Nt, G,
+                           s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
+      return hipGetLastError();
+    }
+  }
   const size_t lds = (size_t)(2 * MP4 * NP + 4 * 512) * sizeof(T);
   if (lds <= max_lds) {
     hipLaunchKernelGGL((k_exchange<T, true>), dim3(W, 2), dim3(256), lds, st, M, MP4, Nt, G, s0, s1,
@@ -903,5 +1050,200 @@ hipError_t convert_f64_f32(hipStream_t st, const double* src, float* dst, long n
   hipLaunchKernelGGL(k_convert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }
+
+}  // namespace afq
+
+namespace afq {
+
+// ===========================================================================
+// Fused one-body propagation for small M (Eq. 3 with Thouless: matrix
+// products on the orbitals).  One block per walker:
+//   phi1 = phi + (B1 - I) phi,  S = phi1,  T_0 = phi1,
+//   T_n = A T_{n-1} / n,  S += T_n  (n = 1..order),  phi = S + (B1 - I) S.
+// A (complex symmetric, so its rows serve as MFMA A-operand columns) and the
+// current term live in LDS in the contraction type T; the running sum S stays
+// in FP64 registers of the lanes that own each output element; B1 - I
+// (symmetric) is read from global memory (L2 resident, shared by all walkers).
+// Terms are rounded to T and the sums accumulate the unrounded FP64 products,
+// exactly as in the unfused chain.  MT = output tiles per wave.
+// ===========================================================================
+template <typename T, int MT>
+__global__ __launch_bounds__(256) void k_propagate_fused(int M, int Nt, int MP4, int order,
+                                                         const T* __restrict__ A,
+                                                         const T* __restrict__ B1m,
+                                                         double* __restrict__ phr,
+                                                         double* __restrict__ phi) {
+  extern __shared__ unsigned char lds_raw[];
+  typedef Mfma<T> MM;
+  typedef typename MM::acc_t acc_t;
+  const int w = blockIdx.x;
+  const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
+  const long mm = (long)M * M, mn = (long)M * Nt;
+  T* Asr = (T*)lds_raw;          // [MP4][M]  Asr[k][i] = A[k][i] = A[i][k]
+  T* Asi = Asr + MP4 * M;
+  T* Tb[2][2];                   // ping-pong term buffers [MP4][Nt] (re, im)
+  Tb[0][0] = Asi + MP4 * M;
+  Tb[0][1] = Tb[0][0] + MP4 * Nt;
+  Tb[1][0] = Tb[0][1] + MP4 * Nt;
+  Tb[1][1] = Tb[1][0] + MP4 * Nt;
+  const T* Ag = A + (long)w * 2 * mm;
+  for (int e = threadIdx.x; e < MP4 * M; e += blockDim.x) {
+    const int k = e / M, i = e % M;
+    Asr[e] = k < M ? Ag[(long)k * M + i] : (T)0;
+    Asi[e] = k < M ? Ag[mm + (long)k * M + i] : (T)0;
+  }
+  const long wb = (long)w * mn;
+  for (int e = threadIdx.x; e < MP4 * Nt; e += blockDim.x) {
+    const int k = e / Nt, c = e % Nt;
+    Tb[0][0][e] = k < M ? (T)phr[wb + (long)k * Nt + c] : (T)0;
+    Tb[0][1][e] = k < M ? (T)phi[wb + (long)k * Nt + c] : (T)0;
+    Tb[1][0][e] = (T)0;
+    Tb[1][1][e] = (T)0;
+  }
+  const int RT = (M + 15) / 16, CT = (Nt + 15) / 16, ntile = RT * CT;
+  double sr[MT][4], si[MT][4];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const int tile = wv + 4 * t;
+    const int rt = tile / CT, ct = tile % CT;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * rt + MM::row(lk, v), c = 16 * ct + li;
+      const bool ok = tile < ntile && r < M && c < Nt;
+      sr[t][v] = ok ? phr[wb + (long)r * Nt + c] : 0.0;
+      si[t][v] = ok ? phi[wb + (long)r * Nt + c] : 0.0;
+    }
+  }
+  __syncthreads();
+  int cur = 0;
+  // one product of an M x M operator with the current term; real (B1 - I) from
+  // global memory or complex A from LDS
+  auto product = [&](bool cplx, acc_t (&cr)[MT], acc_t (&ci)[MT]) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t) { cr[t] = MM::zero(); ci[t] = MM::zero(); }
+    const T* br_ = Tb[cur][0];
+    const T* bi_ = Tb[cur][1];
+    for (int k0 = 0; k0 < MP4; k0 += 4) {
+      const int k = k0 + lk;
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const int tile = wv + 4 * t;
+        if (tile >= ntile) continue;
+        const int rt = tile / CT, ct = tile % CT;
+        const int i = 16 * rt + li, c = 16 * ct + li;
+        const T b_r = c < Nt ? br_[k * Nt + c] : (T)0;
+        const T b_i = c < Nt ? bi_[k * Nt + c] : (T)0;
+        if (cplx) {
+          const T a_r = i < M ? Asr[k * M + i] : (T)0;
+          const T a_i = i < M ? Asi[k * M + i] : (T)0;
+          cr[t] = MM::mma(a_r, b_r, cr[t]);
+          cr[t] = MM::mma(-a_i, b_i, cr[t]);
+          ci[t] = MM::mma(a_r, b_i, ci[t]);
+          ci[t] = MM::mma(a_i, b_r, ci[t]);
+        } else {
+          const T a = (i < M && k < M) ? B1m[(long)k * M + i] : (T)0;
+          cr[t] = MM::mma(a, b_r, cr[t]);
+          ci[t] = MM::mma(a, b_i, ci[t]);
+        }
+      }
+    }
+  };
+  auto store_term = [&](int buf, const double (&xr)[MT][4], const double (&xi)[MT][4]) {
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const int tile = wv + 4 * t;
+      const int rt = tile / CT, ct = tile % CT;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * rt + MM::row(lk, v), c = 16 * ct + li;
+        if (tile < ntile && r < M && c < Nt) {
+          Tb[buf][0][r * Nt + c] = (T)xr[t][v];
+          Tb[buf][1][r * Nt + c] = (T)xi[t][v];
+        }
+      }
+    }
+  };
+  acc_t cr[MT], ci[MT];
+  double xr[MT][4], xi[MT][4];
+  // phi1 = phi + (B1 - I) phi
+  product(false, cr, ci);
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      sr[t][v] += (double)cr[t][v];
+      si[t][v] += (double)ci[t][v];
+    }
+  store_term(cur ^ 1, sr, si);
+  __syncthreads();
+  cur ^= 1;
+  // Taylor terms
+  for (int n = 1; n <= order; ++n) {
+    const double alpha = 1.0 / n;
+    product(true, cr, ci);
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        xr[t][v] = alpha * (double)cr[t][v];
+        xi[t][v] = alpha * (double)ci[t][v];
+        sr[t][v] += xr[t][v];
+        si[t][v] += xi[t][v];
+      }
+    if (n < order) {
+      store_term(cur ^ 1, xr, xi);
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+  // phi = S + (B1 - I) S
+  store_term(cur ^ 1, sr, si);
+  __syncthreads();
+  cur ^= 1;
+  product(false, cr, ci);
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const int tile = wv + 4 * t;
+    const int rt = tile / CT, ct = tile % CT;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * rt + MM::row(lk, v), c = 16 * ct + li;
+      if (tile < ntile && r < M && c < Nt) {
+        phr[wb + (long)r * Nt + c] = sr[t][v] + (double)cr[t][v];
+        phi[wb + (long)r * Nt + c] = si[t][v] + (double)ci[t][v];
+      }
+    }
+  }
+}
+
+template <typename T>
+hipError_t propagate_fused(hipStream_t st, int W, int M, int Nt, int order, const T* A,
+                           const T* B1m, double* phr, double* phi, size_t max_lds) {
+  const int MP4 = ((M + 3) / 4) * 4;
+  const int ntile = ((M + 15) / 16) * ((Nt + 15) / 16);
+  const size_t lds = (size_t)(2 * MP4 * M + 4 * MP4 * Nt) * sizeof(T);
+  if (lds > max_lds || ntile > 32) return hipErrorInvalidValue;
+  const int mt = (ntile + 3) / 4;
+#define AFQ_PF(MTV)                                                                             \
+  hipLaunchKernelGGL((k_propagate_fused<T, MTV>), dim3(W), dim3(256), lds, st, M, Nt, MP4, order, \
+                     A, B1m, phr, phi)
+  if (mt <= 1) AFQ_PF(1);
+  else if (mt <= 2) AFQ_PF(2);
+  else if (mt <= 4) AFQ_PF(4);
+  else AFQ_PF(8);
+#undef AFQ_PF
+  return hipGetLastError();
+}
+
+bool propagate_fused_fits(int M, int Nt, size_t elem, size_t max_lds) {
+  const int MP4 = ((M + 3) / 4) * 4;
+  const int ntile = ((M + 15) / 16) * ((Nt + 15) / 16);
+  return (size_t)(2 * MP4 * M + 4 * MP4 * Nt) * elem <= max_lds && ntile <= 32;
+}
+
+template hipError_t propagate_fused<float>(hipStream_t, int, int, int, int, const float*,
+                                           const float*, double*, double*, size_t);
+template hipError_t propagate_fused<double>(hipStream_t, int, int, int, int, const double*,
+                                            const double*, double*, double*, size_t);
 
 }  // namespace afq

@@ -148,3 +148,11 @@ hipError_t exchange_bf16(hipStream_t st, int W, int M, int MP32, int Nt, int G, 
                          SpinGeom s1, const double* thr, const double* thi, double* vs_re,
                          double* vs_im, double* exx_re, double* exx_im, size_t max_lds);
 }  // namespace afq
+
+namespace afq {
+// Fused B1 exp(A) B1 for small M (one block per walker; see kernels.hip).
+template <typename T>
+hipError_t propagate_fused(hipStream_t st, int W, int M, int Nt, int order, const T* A,
+                           const T* B1m, double* phr, double* phi, size_t max_lds);
+bool propagate_fused_fits(int M, int Nt, size_t elem, size_t max_lds);
+}  // namespace afq

@@ -420,3 +420,65 @@ def test_bf16_propagate_runs_and_tracks_fp64(afq):
     print("bf16 tamed: max |dE_mix| (Ha) =", err, " |E| ~", abs(oe[-1]))
     assert np.all(np.isfinite(em))
     assert err <= 2e-2 * abs(oe[-1])
+
+
+# --------------------------------------------------------------------------
+# Edge cases
+# --------------------------------------------------------------------------
+
+def test_zero_variance_one_body_no_cholesky_vectors(afq):
+    """No Cholesky vectors (G = 0) and a trial of eigenvectors of h: E_L is the
+    sum of occupied eigenvalues for every walker at every step."""
+    _say("zero variance one-body, G=0")
+    M, nu, nd = 9, 3, 2
+    inp = syn.make_system(M, nu, nd, 1, 4.0, seed=5, e_core=1.25)
+    L0 = np.zeros((0, M, M))
+    eps = np.linalg.eigvalsh(inp.h)
+    exact = inp.e_core + eps[:nu].sum() + eps[:nd].sum()
+    ham = afq.Hamiltonian(inp.h, L0, inp.e_core)
+    trial = afq.Trial(ham, nu, nd, inp.C_up, inp.C_dn)
+    w = afq.Walkers(trial, 8)
+    afq.walkers_from_trial(ham, trial, w)
+    assert abs(afq.local_energy(ham, trial, w) - exact) < 1e-12
+    em = _np(afq.propagate(ham, trial, w, 10, 0.01, 1, 0, afq.Options(ortho_every=2, pc_every=5,
+                                                                     e_trial=exact)))
+    assert np.allclose(em, exact, atol=1e-12)
+
+
+@pytest.mark.parametrize("W,nu,nd", [(1, 4, 3), (5, 6, 0)])
+def test_propagate_edge_shapes_fp64(afq, W, nu, nd):
+    _say(f"edge shapes W={W} N={nu}/{nd}")
+    inp = syn.make_system(13, nu, nd, 11, 6.0, seed=W + nu)
+    em, oe, w, st = _run_both(afq, inp, W, 8, 0.01, dict(taylor_order=6, ortho_every=3, pc_every=4))
+    assert np.max(np.abs(em - oe)) <= 1e-9 * max(1.0, np.max(np.abs(oe)))
+
+
+def test_multidet_with_only_the_reference_matches_single_det(afq):
+    """A two-determinant trial whose second coefficient is 0 gives the
+    single-determinant energies (exercises the multi-det kernels' reference
+    terms against the single-det kernels)."""
+    _say("multidet degenerate to single det")
+    M, nu, nd, G = 12, 4, 3, 9
+    inp = syn.make_system(M, nu, nd, G, 6.0, n_det=2, seed=4)
+    inp.coeff = np.array([1.0, 0.0])
+    ham = afq.Hamiltonian(inp.h, inp.L, inp.e_core)
+    t1 = afq.Trial(ham, nu, nd, inp.C_up, inp.C_dn)
+    t2 = afq.Trial(ham, nu, nd, inp.C_up, inp.C_dn, inp.coeff, inp.exc)
+    D0 = np.concatenate([inp.C_up[:, :nu], inp.C_dn[:, :nd]], axis=1)
+    re, im = syn.random_walkers(M, nu, nd, 4, seed=1, scale=0.3)
+    out = []
+    for t in (t1, t2):
+        w = afq.Walkers(t, 4)
+        _set_phi(w, D0[None] + re + 1j * im)
+        afq.local_energy(ham, t, w)
+        out.append(_np(w.eloc[0]) + 1j * _np(w.eloc[1]))
+    assert np.allclose(out[0], out[1], rtol=1e-11)
+
+
+def test_propagate_large_m_unfused_chain_fp64(afq):
+    """M=100, 20/20 electrons (the fused small-M propagation does not fit in
+    LDS here, so the walker-batched GEMM chain runs): mixed-energy parity."""
+    _say("propagate M=100 unfused chain fp64")
+    inp = syn.make_system(100, 20, 20, 40, 20.0, seed=9)
+    em, oe, w, st = _run_both(afq, inp, 4, 4, 0.005, dict(taylor_order=6, ortho_every=2, pc_every=0))
+    assert np.max(np.abs(em - oe)) <= 1e-9 * max(1.0, np.max(np.abs(oe)))
