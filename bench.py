@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--walkers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--tte-repeats", type=int, default=5)
     ap.add_argument("--tte-steps", type=int, default=50)
     args = ap.parse_args()
