@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--tte-repeats", type=int, default=5)
     ap.add_argument("--tte-steps", type=int, default=50)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain elementwise copy of 256 MiB (reads 256 MiB, writes "
+                         "256 MiB) so that HBM byte counters can be scaled")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -159,6 +162,14 @@ def main():
                              "p99": float(np.percentile(tte, 99)) if tte else None,
                              "repeats": len(tte), "steps": args.tte_steps},
     }
+    if args.calibrate_copy:
+        x = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"kernel": "torch elementwise mul (x * 1.0 -> y)",
+                                   "bytes_read": x.numel() * 8, "bytes_written": y.numel() * 8}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, inp, args.cpu_walkers, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -54,6 +54,13 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+__device__ inline float wave_sum_t(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, AFQ_WAVE);
+  return v;
+}
+__device__ inline double wave_sum_t(double v) { return wave_sum(v); }
+
 // Fixed-order block sum of one double per thread (blockDim.x <= 1024,
 // a multiple of 64).  `red` is LDS scratch of blockDim.x/64 doubles.  All
 // threads return the total.

@@ -285,9 +285,13 @@ template hipError_t fields_coeff<float>(hipStream_t, int, int, uint64_t, uint64_
 // ===========================================================================
 // Overlap, inverse, log det and Theta, FP64 (Sec. II mixed estimates; the
 // reference determinant's A and A^-1 of Sec. III).  One block per (walker,
-// spin).  S = D_0^T phi in LDS, in-place Gauss-Jordan inversion with row
-// pivoting, Theta = phi S^-1, E1 = Tr(htil Theta).
+// spin).  The walker's spin block phi and the occupied trial orbitals D_0 are
+// staged in LDS when they fit (STAGE), S = D_0^T phi is formed there and
+// inverted in place by Gauss-Jordan elimination with row pivoting (the scaled
+// pivot row goes to a side buffer so one column costs four barriers), then
+// Theta = phi S^-1 and E1 = Tr(htil Theta).
 // ===========================================================================
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s0, SpinGeom s1,
                                                        const double* __restrict__ phr,
                                                        const double* __restrict__ phi,
@@ -311,17 +315,34 @@ __global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s
   }
   const int ld = N + 1;
   double* Sr = lds;
-  double* Si = lds + N * ld;
+  double* Si = Sr + N * ld;
   double* fr = Si + N * ld;
   double* fi = fr + N;
-  // S[a][b] = sum_m C[m][a] phi[m][off+b]
+  double* rr = fi + N;     // scaled pivot row
+  double* ri = rr + N;
+  double* Pr = ri + N;     // staged phi block [M][N] (STAGE)
+  double* Pi = Pr + (STAGE ? M * N : 0);
+  double* Dm = Pi + (STAGE ? M * N : 0);   // staged D_0 [M][N] (STAGE)
+  if (STAGE) {
+    for (int e = threadIdx.x; e < M * N; e += blockDim.x) {
+      const int m = e / N, b = e % N;
+      Pr[e] = phr[wb + (long)m * Nt + off + b];
+      Pi[e] = phi[wb + (long)m * Nt + off + b];
+      Dm[e] = g.C[(long)m * M + b];
+    }
+    __syncthreads();
+  }
+  auto PHr = [&](int m, int b) { return STAGE ? Pr[m * N + b] : phr[wb + (long)m * Nt + off + b]; };
+  auto PHi = [&](int m, int b) { return STAGE ? Pi[m * N + b] : phi[wb + (long)m * Nt + off + b]; };
+  auto D0 = [&](int m, int a) { return STAGE ? Dm[m * N + a] : g.C[(long)m * M + a]; };
+  // S[a][b] = sum_m D0[m][a] phi[m][b]
   for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
     const int a = e / N, b = e % N;
     double sr = 0.0, si = 0.0;
     for (int m = 0; m < M; ++m) {
-      const double c = g.C[(long)m * M + a];
-      sr += c * phr[wb + (long)m * Nt + off + b];
-      si += c * phi[wb + (long)m * Nt + off + b];
+      const double c = D0(m, a);
+      sr += c * PHr(m, b);
+      si += c * PHi(m, b);
     }
     Sr[a * ld + b] = sr;
     Si[a * ld + b] = si;
@@ -335,18 +356,16 @@ __global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s
       double mag = -1.0;
       int idx = i;
       if (i < N) mag = Sr[i * ld + k] * Sr[i * ld + k] + Si[i * ld + k] * Si[i * ld + k];
-      // wave argmax, ties to the lowest row
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) {
         const double om = __shfl_xor(mag, o, AFQ_WAVE);
         const int oi = __shfl_xor(idx, o, AFQ_WAVE);
         if (om > mag || (om == mag && oi < idx)) { mag = om; idx = oi; }
       }
-      if (threadIdx.x == 0) pk_sh = idx;
+      if (threadIdx.x == 0) { pk_sh = idx; piv[k] = idx; }
     }
     __syncthreads();
     const int p = pk_sh;
-    if (threadIdx.x == 0) piv[k] = p;
     if (p != k) {
       for (int j = threadIdx.x; j < N; j += blockDim.x) {
         double t = Sr[k * ld + j]; Sr[k * ld + j] = Sr[p * ld + j]; Sr[p * ld + j] = t;
@@ -360,26 +379,23 @@ __global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s
     ldr += lg.re;
     ldi += lg.im;
     const zdbl pinv = zdiv(zdbl{1.0, 0.0}, pv);
-    // column k factors of the other rows
-    for (int i = threadIdx.x; i < N; i += blockDim.x) { fr[i] = Sr[i * ld + k]; fi[i] = Si[i * ld + k]; }
-    __syncthreads();
-    // scale pivot row
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
-      zdbl v = (j == k) ? pinv : zmul(zdbl{Sr[k * ld + j], Si[k * ld + j]}, pinv);
-      Sr[k * ld + j] = v.re;
-      Si[k * ld + j] = v.im;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      fr[i] = Sr[i * ld + k];
+      fi[i] = Si[i * ld + k];
+      const zdbl v = (i == k) ? pinv : zmul(zdbl{Sr[k * ld + i], Si[k * ld + i]}, pinv);
+      rr[i] = v.re;
+      ri[i] = v.im;
     }
     __syncthreads();
-    // eliminate
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
       const int i = e / N, j = e % N;
-      if (i == k) continue;
-      const zdbl f = {fr[i], fi[i]};
       zdbl v;
-      if (j == k) {
-        v = zmul(zdbl{-f.re, -f.im}, pinv);
+      if (i == k) {
+        v = zdbl{rr[j], ri[j]};
+      } else if (j == k) {
+        v = zmul(zdbl{-fr[i], -fi[i]}, pinv);
       } else {
-        v = zsub(zdbl{Sr[i * ld + j], Si[i * ld + j]}, zmul(f, zdbl{Sr[k * ld + j], Si[k * ld + j]}));
+        v = zsub(zdbl{Sr[i * ld + j], Si[i * ld + j]}, zmul(zdbl{fr[i], fi[i]}, zdbl{rr[j], ri[j]}));
       }
       Sr[i * ld + j] = v.re;
       Si[i * ld + j] = v.im;
@@ -394,16 +410,16 @@ __global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s
         double t = Sr[i * ld + k]; Sr[i * ld + k] = Sr[i * ld + p]; Sr[i * ld + p] = t;
         t = Si[i * ld + k]; Si[i * ld + k] = Si[i * ld + p]; Si[i * ld + p] = t;
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  // Theta[m][b] = sum_a phi[m][off+a] Sinv[a][b];  E1 = sum htil[b][m] Theta[m][b]
+  // Theta[m][b] = sum_a phi[m][a] Sinv[a][b];  E1 = sum htil[b][m] Theta[m][b]
   double er = 0.0, ei = 0.0;
   for (int e = threadIdx.x; e < M * N; e += blockDim.x) {
     const int m = e / N, b = e % N;
     double tr = 0.0, ti = 0.0;
     for (int a = 0; a < N; ++a) {
-      const double pr = phr[wb + (long)m * Nt + off + a], pi = phi[wb + (long)m * Nt + off + a];
+      const double pr = PHr(m, a), pi = PHi(m, a);
       const double qr = Sr[a * ld + b], qi = Si[a * ld + b];
       tr += pr * qr - pi * qi;
       ti += pr * qi + pi * qr;
@@ -430,10 +446,16 @@ hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, Spin
                          double* ld_re, double* ld_im, double* e1_re, double* e1_im,
                          size_t max_lds) {
   const int N = s0.N > s1.N ? s0.N : s1.N;
-  const size_t lds = (size_t)(2 * N * (N + 1) + 2 * N) * sizeof(double);
-  if (lds > max_lds) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_overlap_theta, dim3(W, 2), dim3(256), lds, st, M, Nt, s0, s1, phr, phi,
-                     thr, thi, ld_re, ld_im, e1_re, e1_im);
+  const size_t base = (size_t)(2 * N * (N + 1) + 4 * N) * sizeof(double);
+  const size_t staged = base + (size_t)3 * M * N * sizeof(double);
+  if (staged <= 65536 && staged <= max_lds) {
+    hipLaunchKernelGGL(k_overlap_theta<true>, dim3(W, 2), dim3(256), staged, st, M, Nt, s0, s1, phr,
+                       phi, thr, thi, ld_re, ld_im, e1_re, e1_im);
+  } else {
+    if (base > max_lds) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_overlap_theta<false>, dim3(W, 2), dim3(256), base, st, M, Nt, s0, s1, phr,
+                       phi, thr, thi, ld_re, ld_im, e1_re, e1_im);
+  }
   return hipGetLastError();
 }
 
@@ -558,13 +580,20 @@ __global__ __launch_bounds__(256) void k_exchange(int M, int MP4, int Nt, int G,
   }
 }
 
-// Exchange kernel for N <= 16*NT (NT <= 2): per Cholesky index all NT x NT
-// tiles of X_g (re and im) are accumulated together, so each k step loads NT
-// A values (global, L2 resident) and 2 NT B values (LDS) for 2 NT^2 MFMAs; the
-// A operand of the next four k steps is prefetched into registers while the
-// current four run.  The Theta rows in LDS are padded to a stride of 16 mod
-// 32 elements against bank conflicts; X is stashed once per g in a per-wave
-// LDS tile (odd row stride) to pair X_ab with X_ba.
+// Exchange kernel for N <= 16*NT (NT <= 2), one walker and spin per block:
+// per Cholesky index all NT x NT tiles of X_g (re and im) are accumulated
+// together, so each k step loads NT A values (global, L2 resident) and 2 NT B
+// values (LDS) for 2 NT^2 MFMAs; the A operand of the next four k steps (and,
+// during the epilogue, of the first four steps of the next g) is prefetched
+// into registers.  Theta rows in LDS are padded to a stride of 16 mod 32
+// elements against bank conflicts.  X is stashed row-major once per g in a
+// per-wave LDS tile whose rows are 16-byte aligned, so the four X_ba values a
+// lane pairs with its four X_ab come back in one 128-bit read.  Per-g partial
+// sums are formed in the contraction type and added to FP64 totals.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef afq_f4 type; };
+template <> struct Vec4<double> { typedef afq_d4 type; };
+
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, int G, SpinGeom s0,
                                                        SpinGeom s1, const double* __restrict__ thr,
@@ -572,13 +601,14 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
                                                        double* __restrict__ vs_re,
                                                        double* __restrict__ vs_im, double* exx_re,
                                                        double* exx_im) {
-  extern __shared__ unsigned char lds_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   __shared__ double red[8];
   typedef Mfma<T> MM;
   typedef typename MM::acc_t acc_t;
+  typedef typename Vec4<T>::type v4_t;
   constexpr int NPM = 16 * NT;
   constexpr int LDB = (NPM % 32 == 0) ? NPM + 16 : NPM;
-  constexpr int LDX = NPM + 1;
+  constexpr int LDX = NPM + 4;
   const int w = blockIdx.x, s = blockIdx.y;
   const SpinGeom g = s ? s1 : s0;
   const int N = g.N, NP = g.NP, off = g.off, nt = NP / 16;
@@ -606,25 +636,25 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
   __syncthreads();
   const int KS = MP4 / 4;
   double xx_re = 0.0, xx_im = 0.0;
-  for (int q = wv; q < G; q += 4) {
+  T a0[4][NT], a1[4][NT];
+  auto load_a = [&](T (&a)[4][NT], int q, int kb) {
     const T* __restrict__ Lq = Lt + (long)q * MP4 * NP;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+        a[j][I] = (q < G && kb + j < KS && I < nt) ? Lq[(4 * (kb + j) + lk) * NP + 16 * I + li] : (T)0;
+  };
+  load_a(a0, wv, 0);
+  for (int q = wv; q < G; q += 4) {
     acc_t cr[NT][NT], ci[NT][NT];
 #pragma unroll
     for (int I = 0; I < NT; ++I)
 #pragma unroll
       for (int J = 0; J < NT; ++J) { cr[I][J] = MM::zero(); ci[I][J] = MM::zero(); }
-    T a0[4][NT], a1[4][NT];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int I = 0; I < NT; ++I)
-        a0[j][I] = (j < KS && I < nt) ? Lq[(4 * j + lk) * NP + 16 * I + li] : (T)0;
     for (int kb = 0; kb < KS; kb += 4) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int I = 0; I < NT; ++I)
-          a1[j][I] = (kb + 4 + j < KS && I < nt) ? Lq[(4 * (kb + 4 + j) + lk) * NP + 16 * I + li] : (T)0;
+      if (kb + 4 < KS) load_a(a1, q, kb + 4);
+      else load_a(a1, q + 4, 0);   // first batch of this wave's next g
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (kb + j < KS) {
@@ -649,6 +679,7 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
 #pragma unroll
         for (int I = 0; I < NT; ++I) a0[j][I] = a1[j][I];
     }
+    // stash X row-major: lane (li, lk) holds X[16I + row(lk, v)][16J + li]
 #pragma unroll
     for (int I = 0; I < NT; ++I)
 #pragma unroll
@@ -660,23 +691,38 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
           Xi[r * LDX + c] = ci[I][J][v];
         }
     wave_lds_sync();
-    double tr_re = 0.0, tr_im = 0.0;
+    T pxr = (T)0, pxi = (T)0, ptr = (T)0, pti = (T)0;
 #pragma unroll
     for (int I = 0; I < NT; ++I)
 #pragma unroll
-      for (int J = 0; J < NT; ++J)
+      for (int J = 0; J < NT; ++J) {
+        // partners X_ba, b = 16J + li, a = 16I + row(lk, v): for the f32 layout the
+        // four a of a lane are consecutive, so one 128-bit read per tile
+        T yr[4], yi[4];
+        if (MM::row(0, 1) == 1) {
+          const v4_t vr = *(const v4_t*)&Xr[(16 * J + li) * LDX + 16 * I + MM::row(lk, 0)];
+          const v4_t vi = *(const v4_t*)&Xi[(16 * J + li) * LDX + 16 * I + MM::row(lk, 0)];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) { yr[v] = vr[v]; yi[v] = vi[v]; }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            yr[v] = Xr[(16 * J + li) * LDX + 16 * I + MM::row(lk, v)];
+            yi[v] = Xi[(16 * J + li) * LDX + 16 * I + MM::row(lk, v)];
+          }
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int a = 16 * I + MM::row(lk, v), b = 16 * J + li;
-          const double xr = (double)cr[I][J][v], xi = (double)ci[I][J][v];
-          const double yr = (double)Xr[b * LDX + a], yi = (double)Xi[b * LDX + a];
-          xx_re += xr * yr - xi * yi;
-          xx_im += xr * yi + xi * yr;
-          if (a == b) { tr_re += xr; tr_im += xi; }
+          const T xr = cr[I][J][v], xi = ci[I][J][v];
+          pxr += xr * yr[v] - xi * yi[v];
+          pxi += xr * yi[v] + xi * yr[v];
+          if (I == J && MM::row(lk, v) == li) { ptr += xr; pti += xi; }
         }
+      }
     wave_lds_sync();
-    tr_re = wave_sum(tr_re);
-    tr_im = wave_sum(tr_im);
+    xx_re += (double)pxr;
+    xx_im += (double)pxi;
+    const double tr_re = (double)wave_sum_t(ptr), tr_im = (double)wave_sum_t(pti);
     if (l == 0) {
       vs_re[((long)w * 2 + s) * G + q] = tr_re;
       vs_im[((long)w * 2 + s) * G + q] = tr_im;
@@ -698,7 +744,7 @@ hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGe
                     double* exx_re, double* exx_im, size_t max_lds) {
   const int NP = s0.NP > s1.NP ? s0.NP : s1.NP;
   if (NP <= 32) {
-    const int NPM = NP, LDB = (NPM % 32 == 0) ? NPM + 16 : NPM, LDX = NPM + 1;
+    const int NPM = NP, LDB = (NPM % 32 == 0) ? NPM + 16 : NPM, LDX = NPM + 4;
     const size_t ldsf = (size_t)(2 * MP4 * LDB + 4 * 2 * NPM * LDX) * sizeof(T);
     if (ldsf <= max_lds) {
       if (NP == 16)
@@ -895,90 +941,137 @@ hipError_t mixed_energy(hipStream_t st, int W, const double* weight, const doubl
 }
 
 // ===========================================================================
-// Modified Gram-Schmidt per (walker, spin), FP64, in place in global memory
-// (Sec. IV.A: periodic orthonormalisation of walker orbitals).
+// Modified Gram-Schmidt per (walker, spin), FP64 (Sec. IV.A: periodic
+// orthonormalisation of walker orbitals).  The spin block is staged in LDS
+// when it fits (STAGE) and written back at the end; otherwise it is updated
+// in place in global memory.
 // ===========================================================================
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_mgs(int M, int Nt, int n_up, int n_dn,
                                              double* __restrict__ phr, double* __restrict__ phi) {
+  extern __shared__ double qs[];
   __shared__ double red[4];
   const int w = blockIdx.x, s = blockIdx.y;
   const int N = s ? n_dn : n_up, off = s ? n_up : 0;
   const long wb = (long)w * M * Nt;
   const int wv = wave_id(), l = lane_id();
+  double* Qr = qs;
+  double* Qi = qs + (STAGE ? M * N : 0);
+  if (STAGE) {
+    for (int e = threadIdx.x; e < M * N; e += blockDim.x) {
+      const int m = e / N, b = e % N;
+      Qr[e] = phr[wb + (long)m * Nt + off + b];
+      Qi[e] = phi[wb + (long)m * Nt + off + b];
+    }
+    __syncthreads();
+  }
+  auto R = [&](int m, int c) -> double& { return STAGE ? Qr[m * N + c] : phr[wb + (long)m * Nt + off + c]; };
+  auto I = [&](int m, int c) -> double& { return STAGE ? Qi[m * N + c] : phi[wb + (long)m * Nt + off + c]; };
   for (int j = 0; j < N; ++j) {
     double nrm = 0.0;
     for (int m = threadIdx.x; m < M; m += blockDim.x) {
-      const double a = phr[wb + (long)m * Nt + off + j], b = phi[wb + (long)m * Nt + off + j];
+      const double a = R(m, j), b = I(m, j);
       nrm += a * a + b * b;
     }
     nrm = block_sum(nrm, red);
     const double r = sqrt(nrm);
     for (int m = threadIdx.x; m < M; m += blockDim.x) {
-      phr[wb + (long)m * Nt + off + j] /= r;
-      phi[wb + (long)m * Nt + off + j] /= r;
+      R(m, j) /= r;
+      I(m, j) /= r;
     }
     __syncthreads();
     for (int k = j + 1 + wv; k < N; k += 4) {
       double dr = 0.0, di = 0.0;
       for (int m = l; m < M; m += AFQ_WAVE) {
-        const double qr = phr[wb + (long)m * Nt + off + j], qi = phi[wb + (long)m * Nt + off + j];
-        const double ar = phr[wb + (long)m * Nt + off + k], ai = phi[wb + (long)m * Nt + off + k];
+        const double qr = R(m, j), qi = I(m, j);
+        const double ar = R(m, k), ai = I(m, k);
         dr += qr * ar + qi * ai;   // conj(q) a
         di += qr * ai - qi * ar;
       }
       dr = wave_sum(dr);
       di = wave_sum(di);
       for (int m = l; m < M; m += AFQ_WAVE) {
-        const double qr = phr[wb + (long)m * Nt + off + j], qi = phi[wb + (long)m * Nt + off + j];
-        phr[wb + (long)m * Nt + off + k] -= dr * qr - di * qi;
-        phi[wb + (long)m * Nt + off + k] -= dr * qi + di * qr;
+        const double qr = R(m, j), qi = I(m, j);
+        R(m, k) -= dr * qr - di * qi;
+        I(m, k) -= dr * qi + di * qr;
       }
     }
     __syncthreads();
   }
+  if (STAGE) {
+    for (int e = threadIdx.x; e < M * N; e += blockDim.x) {
+      const int m = e / N, b = e % N;
+      phr[wb + (long)m * Nt + off + b] = Qr[e];
+      phi[wb + (long)m * Nt + off + b] = Qi[e];
+    }
+  }
 }
 
 hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double* phr, double* phi) {
-  hipLaunchKernelGGL(k_mgs, dim3(W, 2), dim3(256), 0, st, M, Nt, n_up, n_dn, phr, phi);
+  const int N = n_up > n_dn ? n_up : n_dn;
+  const size_t lds = (size_t)2 * M * N * sizeof(double);
+  if (lds <= 65536)
+    hipLaunchKernelGGL(k_mgs<true>, dim3(W, 2), dim3(256), lds, st, M, Nt, n_up, n_dn, phr, phi);
+  else
+    hipLaunchKernelGGL(k_mgs<false>, dim3(W, 2), dim3(256), 0, st, M, Nt, n_up, n_dn, phr, phi);
   return hipGetLastError();
 }
 
 // ===========================================================================
-// Comb (population control).  Prefix sums and tooth positions are
-// sequential in one thread so that every rounding step is the same as a
-// plain left-to-right loop.
+// Comb (population control).  The inclusive prefix sums are formed by one
+// thread, left to right, so every rounding step is that of a plain loop; each
+// tooth z_j = ((j + xi) W_tot) / W then finds the first k with C_k > z_j by a
+// binary search over the same prefix array (the result of a left-to-right
+// sweep).  The prefix array lives in LDS when W fits, else in global scratch.
 // ===========================================================================
-__global__ void k_comb_parents(int W, const double* __restrict__ weight, uint64_t seed,
-                               uint64_t pc_index, int system_id, double* cbuf, int* parent,
-                               double* norm_out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double acc = 0.0;
-  int last = W - 1;
-  bool any = false;
-  for (int k = 0; k < W; ++k) {
-    acc = acc + weight[k];
-    cbuf[k] = acc;
+__global__ __launch_bounds__(1024) void k_comb_parents(int W, const double* __restrict__ weight,
+                                                       uint64_t seed, uint64_t pc_index,
+                                                       int system_id, double* cbuf, int* parent,
+                                                       double* norm_out, int use_lds) {
+  extern __shared__ double cs[];
+  __shared__ double sh[2];
+  __shared__ int last_sh;
+  double* C = use_lds ? cs : cbuf;
+  if (use_lds)
+    for (int k = threadIdx.x; k < W; k += blockDim.x) C[k] = weight[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    int last = W - 1;
+    for (int k = 0; k < W; ++k) {
+      const double wk = use_lds ? C[k] : weight[k];
+      if (wk > 0.0) last = k;
+      acc = acc + wk;
+      C[k] = acc;
+    }
+    const PhiloxOut r =
+        philox4x64_10(pc_index, 0ull, 0ull, (uint64_t)system_id, seed, AFQ_STREAM_COMB);
+    sh[0] = acc;
+    sh[1] = u64_to_unit(r.w[0]);
+    last_sh = last;
   }
-  for (int k = W - 1; k >= 0; --k)
-    if (weight[k] > 0.0) { last = k; any = true; break; }
-  (void)any;
-  const double wtot = acc;
-  const PhiloxOut r = philox4x64_10(pc_index, 0ull, 0ull, (uint64_t)system_id, seed, AFQ_STREAM_COMB);
-  const double xi = u64_to_unit(r.w[0]);
-  int k = 0;
-  for (int j = 0; j < W; ++j) {
+  __syncthreads();
+  const double wtot = sh[0], xi = sh[1];
+  const int last = last_sh;
+  for (int j = threadIdx.x; j < W; j += blockDim.x) {
     const double zj = (((double)j + xi) * wtot) / (double)W;
-    while (k < W && !(cbuf[k] > zj)) ++k;
-    parent[j] = (k < W) ? k : last;
+    int lo = 0, hi = W;  // first index with C[k] > zj in [lo, hi]
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (C[mid] > zj) hi = mid; else lo = mid + 1;
+    }
+    parent[j] = (lo < W) ? lo : last;
   }
-  if (norm_out) norm_out[0] = wtot / (double)W;
+  if (threadIdx.x == 0 && norm_out) norm_out[0] = wtot / (double)W;
 }
 
 hipError_t comb_parents(hipStream_t st, int W, const double* weight, uint64_t seed,
                         uint64_t pc_index, int system_id, double* cbuf, int* parent,
                         double* norm_out) {
-  hipLaunchKernelGGL(k_comb_parents, dim3(1), dim3(64), 0, st, W, weight, seed, pc_index,
-                     system_id, cbuf, parent, norm_out);
+  const size_t lds = (size_t)W * sizeof(double);
+  const int use_lds = lds <= 65536 ? 1 : 0;
+  hipLaunchKernelGGL(k_comb_parents, dim3(1), dim3(1024), use_lds ? lds : 0, st, W, weight, seed,
+                     pc_index, system_id, cbuf, parent, norm_out, use_lds);
   return hipGetLastError();
 }
 
@@ -1060,15 +1153,17 @@ namespace afq {
 // products on the orbitals).  One block per walker:
 //   phi1 = phi + (B1 - I) phi,  S = phi1,  T_0 = phi1,
 //   T_n = A T_{n-1} / n,  S += T_n  (n = 1..order),  phi = S + (B1 - I) S.
-// A (complex symmetric, so its rows serve as MFMA A-operand columns) and the
-// current term live in LDS in the contraction type T; the running sum S stays
-// in FP64 registers of the lanes that own each output element; B1 - I
-// (symmetric) is read from global memory (L2 resident, shared by all walkers).
-// Terms are rounded to T and the sums accumulate the unrounded FP64 products,
-// exactly as in the unfused chain.  MT = output tiles per wave.
+// A and B1 - I (both symmetric, so their rows serve as MFMA A-operand
+// columns) and the current term live in LDS in the contraction type T; the
+// running sum S stays in FP64 registers of the lanes that own each output
+// element.  Eight waves per block.  Terms are rounded to T and the sums
+// accumulate the unrounded FP64 products, exactly as in the unfused chain.
+// MT = output tiles per wave.
 // ===========================================================================
+constexpr int NWAVE = 8;  // waves per block of the fused propagation
+
 template <typename T, int MT>
-__global__ __launch_bounds__(256) void k_propagate_fused(int M, int Nt, int MP4, int order,
+__global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4, int order,
                                                          const T* __restrict__ A,
                                                          const T* __restrict__ B1m,
                                                          double* __restrict__ phr,
@@ -1081,8 +1176,9 @@ __global__ __launch_bounds__(256) void k_propagate_fused(int M, int Nt, int MP4,
   const long mm = (long)M * M, mn = (long)M * Nt;
   T* Asr = (T*)lds_raw;          // [MP4][M]  Asr[k][i] = A[k][i] = A[i][k]
   T* Asi = Asr + MP4 * M;
+  T* Bm = Asi + MP4 * M;         // (B1 - I)[k][i], symmetric
   T* Tb[2][2];                   // ping-pong term buffers [MP4][Nt] (re, im)
-  Tb[0][0] = Asi + MP4 * M;
+  Tb[0][0] = Bm + MP4 * M;
   Tb[0][1] = Tb[0][0] + MP4 * Nt;
   Tb[1][0] = Tb[0][1] + MP4 * Nt;
   Tb[1][1] = Tb[1][0] + MP4 * Nt;
@@ -1091,6 +1187,7 @@ __global__ __launch_bounds__(256) void k_propagate_fused(int M, int Nt, int MP4,
     const int k = e / M, i = e % M;
     Asr[e] = k < M ? Ag[(long)k * M + i] : (T)0;
     Asi[e] = k < M ? Ag[mm + (long)k * M + i] : (T)0;
+    Bm[e] = k < M ? B1m[(long)k * M + i] : (T)0;
   }
   const long wb = (long)w * mn;
   for (int e = threadIdx.x; e < MP4 * Nt; e += blockDim.x) {
@@ -1104,7 +1201,7 @@ __global__ __launch_bounds__(256) void k_propagate_fused(int M, int Nt, int MP4,
   double sr[MT][4], si[MT][4];
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
-    const int tile = wv + 4 * t;
+    const int tile = wv + NWAVE * t;
     const int rt = tile / CT, ct = tile % CT;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1116,8 +1213,8 @@ __global__ __launch_bounds__(256) void k_propagate_fused(int M, int Nt, int MP4,
   }
   __syncthreads();
   int cur = 0;
-  // one product of an M x M operator with the current term; real (B1 - I) from
-  // global memory or complex A from LDS
+  // one product of an M x M operator with the current term: real (B1 - I) or
+  // complex A, both from LDS
   auto product = [&](bool cplx, acc_t (&cr)[MT], acc_t (&ci)[MT]) {
 #pragma unroll
     for (int t = 0; t < MT; ++t) { cr[t] = MM::zero(); ci[t] = MM::zero(); }
@@ -1127,7 +1224,7 @@ __global__ __launch_bounds__(256) void k_propagate_fused(int M, int Nt, int MP4,
       const int k = k0 + lk;
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
-        const int tile = wv + 4 * t;
+        const int tile = wv + NWAVE * t;
         if (tile >= ntile) continue;
         const int rt = tile / CT, ct = tile % CT;
         const int i = 16 * rt + li, c = 16 * ct + li;
@@ -1141,7 +1238,7 @@ __global__ __launch_bounds__(256) void k_propagate_fused(int M, int Nt, int MP4,
           ci[t] = MM::mma(a_r, b_i, ci[t]);
           ci[t] = MM::mma(a_i, b_r, ci[t]);
         } else {
-          const T a = (i < M && k < M) ? B1m[(long)k * M + i] : (T)0;
+          const T a = i < M ? Bm[k * M + i] : (T)0;
           cr[t] = MM::mma(a, b_r, cr[t]);
           ci[t] = MM::mma(a, b_i, ci[t]);
         }
@@ -1151,7 +1248,7 @@ __global__ __launch_bounds__(256) void k_propagate_fused(int M, int Nt, int MP4,
   auto store_term = [&](int buf, const double (&xr)[MT][4], const double (&xi)[MT][4]) {
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      const int tile = wv + 4 * t;
+      const int tile = wv + NWAVE * t;
       const int rt = tile / CT, ct = tile % CT;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -1203,7 +1300,7 @@ __global__ __launch_bounds__(256) void k_propagate_fused(int M, int Nt, int MP4,
   product(false, cr, ci);
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
-    const int tile = wv + 4 * t;
+    const int tile = wv + NWAVE * t;
     const int rt = tile / CT, ct = tile % CT;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1221,11 +1318,11 @@ hipError_t propagate_fused(hipStream_t st, int W, int M, int Nt, int order, cons
                            const T* B1m, double* phr, double* phi, size_t max_lds) {
   const int MP4 = ((M + 3) / 4) * 4;
   const int ntile = ((M + 15) / 16) * ((Nt + 15) / 16);
-  const size_t lds = (size_t)(2 * MP4 * M + 4 * MP4 * Nt) * sizeof(T);
-  if (lds > max_lds || ntile > 32) return hipErrorInvalidValue;
-  const int mt = (ntile + 3) / 4;
+  const size_t lds = (size_t)(3 * MP4 * M + 4 * MP4 * Nt) * sizeof(T);
+  if (lds > max_lds || ntile > 8 * NWAVE) return hipErrorInvalidValue;
+  const int mt = (ntile + NWAVE - 1) / NWAVE;
 #define AFQ_PF(MTV)                                                                             \
-  hipLaunchKernelGGL((k_propagate_fused<T, MTV>), dim3(W), dim3(256), lds, st, M, Nt, MP4, order, \
+  hipLaunchKernelGGL((k_propagate_fused<T, MTV>), dim3(W), dim3(64 * NWAVE), lds, st, M, Nt, MP4, order, \
                      A, B1m, phr, phi)
   if (mt <= 1) AFQ_PF(1);
   else if (mt <= 2) AFQ_PF(2);
@@ -1238,7 +1335,7 @@ hipError_t propagate_fused(hipStream_t st, int W, int M, int Nt, int order, cons
 bool propagate_fused_fits(int M, int Nt, size_t elem, size_t max_lds) {
   const int MP4 = ((M + 3) / 4) * 4;
   const int ntile = ((M + 15) / 16) * ((Nt + 15) / 16);
-  return (size_t)(2 * MP4 * M + 4 * MP4 * Nt) * elem <= max_lds && ntile <= 32;
+  return (size_t)(3 * MP4 * M + 4 * MP4 * Nt) * elem <= max_lds && ntile <= 8 * NWAVE;
 }
 
 template hipError_t propagate_fused<float>(hipStream_t, int, int, int, int, const float*,
