@@ -17,6 +17,16 @@ are not available, so entries are random with the distributions below:
   ``0.5 * N(0,1) * exp(-g / tau_d)`` and mirrored.  ``V_ijkl = sum_g
   L[g,i,k] L[g,j,l]`` is then positive semidefinite as an (ik),(jl) matrix,
   like a Cholesky-decomposed two-electron integral (Sec. II, Eq. 1).
+  The workloads with ``tau_d = 50`` then multiply every ``L[g]`` by
+  ``l_scale = 1 / sqrt(M)`` (``health_scale``).  Unscaled, the spectral
+  norm of the one-step propagator exponent ``sqrt(dt) sum_g x_g L[g]`` is
+  about 2 to 5 at M = 50 to 200 (against 0.44 for the M = 10 workload), the
+  exchange energy reaches 1e4 Ha and every walker of the M = 50 workload is
+  dead within five steps.  The scale brings that norm to about 0.3; at the
+  M = 50 size the walkers' Im E_L spread then stays near 3 Ha and no walker
+  dies in 60 steps without population control, while at a norm of 0.44 the
+  spread grows past 30 Ha by step 60.  The unscaled recipe stays available
+  as ``hchain-M50-literal``.
 * trial orbitals: all eigenvectors of ``h`` in ascending eigenvalue order,
   each column sign-fixed so that its largest-magnitude entry is positive
   (lowest index on ties).  The reference determinant occupies the first
@@ -57,6 +67,13 @@ class Workload:
     pc_every: int = 0
     ham_seed: int = 0
     field_seed: int = 0
+    l_scale: float = 1.0
+
+
+def health_scale(M: int) -> float:
+    """Factor applied to the Cholesky-like vectors of the tau_d = 50
+    workloads: brings ||sqrt(dt) sum_g x_g L[g]||_2 to about 0.3 at dt = 0.005."""
+    return 1.0 / float(np.sqrt(M))
 
 
 # The four single-system workloads of the measurement plan.  Run parameters
@@ -71,18 +88,25 @@ WORKLOADS = {
     "hchain-M50": Workload("hchain-M50", M=50, n_up=25, n_dn=25, n_chol=250,
                            n_walkers=1024, n_steps=1000, dt=0.005, tau_d=50.0,
                            chol_prec="fp32", taylor_prec="fp32",
-                           ortho_every=10, pc_every=20),
+                           ortho_every=10, pc_every=20, l_scale=health_scale(50)),
+    "hchain-M50-literal": Workload("hchain-M50-literal", M=50, n_up=25, n_dn=25,
+                                   n_chol=250, n_walkers=1024, n_steps=1000, dt=0.005,
+                                   tau_d=50.0, chol_prec="fp32", taylor_prec="fp32",
+                                   ortho_every=10, pc_every=20),
     "tm-multidet-M120": Workload("tm-multidet-M120", M=120, n_up=13, n_dn=11,
                                  n_chol=600, n_walkers=2048, n_steps=500,
                                  dt=0.005, tau_d=50.0, n_det=100,
-                                 chol_prec="fp32", ortho_every=2, pc_every=20),
+                                 chol_prec="fp32", ortho_every=2, pc_every=20,
+                                 l_scale=health_scale(120)),
     "sweep-M200": Workload("sweep-M200", M=200, n_up=50, n_dn=50, n_chol=1000,
                            n_walkers=1024, n_steps=200, dt=0.005, tau_d=50.0,
-                           chol_prec="bf16", ortho_every=2, pc_every=20),
+                           chol_prec="bf16", ortho_every=2, pc_every=20,
+                           l_scale=health_scale(200)),
 }
 
 
-def make_hamiltonian(M: int, n_chol: int, tau_d: float, seed: int = 0):
+def make_hamiltonian(M: int, n_chol: int, tau_d: float, seed: int = 0,
+                     l_scale: float = 1.0):
     """Return (h [M,M], L [n_chol,M,M]) as float64 arrays."""
     rng = np.random.default_rng(seed)
     h = np.zeros((M, M))
@@ -97,6 +121,8 @@ def make_hamiltonian(M: int, n_chol: int, tau_d: float, seed: int = 0):
         Lg = np.zeros((M, M))
         Lg[iu0] = vals
         L[g] = Lg + Lg.T - np.diag(np.diag(Lg))
+    if l_scale != 1.0:
+        L *= l_scale
     return h, L
 
 
@@ -198,8 +224,8 @@ class SystemInputs:
 
 def make_system(M: int, n_up: int, n_dn: int, n_chol: int, tau_d: float,
                 n_det: int = 1, seed: int = 0, e_core: float = 0.0,
-                exc_seed: Optional[int] = None) -> SystemInputs:
-    h, L = make_hamiltonian(M, n_chol, tau_d, seed)
+                exc_seed: Optional[int] = None, l_scale: float = 1.0) -> SystemInputs:
+    h, L = make_hamiltonian(M, n_chol, tau_d, seed, l_scale)
     C = make_trial_orbitals(h)
     if n_det > 1:
         exc, coeff = make_excitations(M, n_up, n_dn, n_det,
@@ -213,7 +239,7 @@ def make_system(M: int, n_up: int, n_dn: int, n_chol: int, tau_d: float,
 
 def workload_system(w: Workload) -> SystemInputs:
     return make_system(w.M, w.n_up, w.n_dn, w.n_chol, w.tau_d, n_det=w.n_det,
-                       seed=w.ham_seed)
+                       seed=w.ham_seed, l_scale=w.l_scale)
 
 
 def random_walkers(M: int, n_up: int, n_dn: int, W: int, seed: int,

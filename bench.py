@@ -11,8 +11,10 @@ Prints one JSON line.  `value` is walker-steps/s over the timed steps with all
 inputs resident in HBM.  `roofline` reports the fused exchange / force-bias
 kernel (the dominant one): algorithmic flops per launch divided by its average
 duration, measured with HIP events on the launch stream over the timed region.
-`cpu_baseline` times the FP64 numpy oracle on a bounded sample of the same
-workload on the host cores.
+`accuracy` (hydrogen-chain workload) runs all walkers for 100 steps with
+population control off and compares E_mix per step with the stored FP64
+oracle run under tests/golden.  `cpu_baseline` times the FP64 numpy oracle on
+a bounded sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -29,12 +31,56 @@ sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def exchange_flops_per_walker(M, n_up, n_dn, G):
     """X_g = Ltil_g Theta (real N x M times complex M x N: 4 N^2 M flops) and
     Tr(X_g X_g) (N^2 complex multiply-adds: 8 N^2 flops), per spin and g."""
     return sum(G * (4 * n * n * M + 8 * n * n) for n in (n_up, n_dn))
+
+
+def multidet_flops_per_walker(M, n_up, n_dn, G):
+    """Multi-determinant energy: per spin and per g (the G vectors and h),
+    P_g = (C^T L_g) Theta_0 (real M x M times complex M x N: 4 M^2 N flops)
+    and X0^2 = P[:N] P[:N] (complex N x N x N: 8 N^3 flops); the per-determinant
+    corrections are O(E^2 N) and not counted."""
+    return sum((G + 1) * (4 * M * M * n + 8 * n ** 3) for n in (n_up, n_dn) if n)
+
+
+GOLDEN = {"hchain-M50": ("hchain-M50_W1024_T100.txt", 1024, 100, 1)}
+
+
+def read_golden(fname):
+    et, num, den = None, [], []
+    with open(os.path.join(ROOT, "tests", "golden", fname)) as f:
+        for line in f:
+            p = line.split()
+            if not p or p[0] == "#":
+                continue
+            if p[0] == "e_trial":
+                et = float(p[1])
+            elif p[0] == "step":
+                num.append(float(p[2]))
+                den.append(float(p[3]))
+    return et, np.array(num) / np.array(den)
+
+
+def accuracy_check(afq, torch, wl, inp, ham, trial, opt_kw):
+    """E_mix per step, all walkers, population control off, vs the stored
+    FP64 oracle run of the same workload and fields."""
+    fname, W, n_steps, seed = GOLDEN[wl.name]
+    et, ref = read_golden(fname)
+    w = afq.Walkers(trial, W)
+    afq.walkers_from_trial(ham, trial, w)
+    opt = afq.Options(e_trial=et, pc_every=0, **opt_kw)
+    em = afq.propagate(ham, trial, w, n_steps, wl.dt, seed, 0, opt).cpu().numpy()
+    err = np.abs(em - ref)
+    return {"max_abs_dEmix_Ha": float(err.max()), "final_abs_dEmix_Ha": float(err[-1]),
+            "gate_Ha": 1e-4, "pass": bool(err.max() <= 1e-4),
+            "walkers": W, "steps": n_steps, "pc": "off", "field_seed": seed,
+            "e_mix_final": float(em[-1]), "alive_final": int((w.weight > 0).sum().item()),
+            "reference": "FP64 oracle sums stored in tests/golden/" + fname}
 
 
 def cpu_baseline(wl, inp, sample_walkers, sample_steps):
@@ -65,6 +111,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="hchain-M50")
     ap.add_argument("--walkers", type=int, default=0)
+    ap.add_argument("--prec", default="",
+                    help="override precisions: 'chol' or 'chol,taylor' from fp64/fp32/bf16")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=80)
@@ -87,16 +136,23 @@ def main():
 
     wl = syn.WORKLOADS[args.workload]
     W = args.walkers or wl.n_walkers
+    chol_prec, taylor_prec = wl.chol_prec, wl.taylor_prec
+    if args.prec:
+        parts = args.prec.split(",")
+        chol_prec = parts[0]
+        taylor_prec = parts[1] if len(parts) > 1 else ("fp64" if parts[0] == "fp64" else taylor_prec)
     inp = syn.workload_system(wl)
     torch.cuda.set_device(0)
     ham = afq.Hamiltonian(inp.h, inp.L, inp.e_core)
-    trial = afq.Trial(ham, inp.n_up, inp.n_dn, inp.C_up, inp.C_dn)
+    multi = inp.n_det > 1
+    trial = afq.Trial(ham, inp.n_up, inp.n_dn, inp.C_up, inp.C_dn,
+                      inp.coeff if multi else None, inp.exc if multi else None)
     w = afq.Walkers(trial, W)
     afq.walkers_from_trial(ham, trial, w)
     et = afq.local_energy(ham, trial, w)
-    opt = afq.Options(taylor_order=wl.taylor_order, ortho_every=wl.ortho_every,
-                      pc_every=wl.pc_every, e_trial=et, chol_prec=wl.chol_prec,
-                      taylor_prec=wl.taylor_prec)
+    opt_kw = dict(taylor_order=wl.taylor_order, ortho_every=wl.ortho_every,
+                  chol_prec=chol_prec, taylor_prec=taylor_prec)
+    opt = afq.Options(pc_every=wl.pc_every, e_trial=et, **opt_kw)
     emix = torch.empty(max(args.steps, args.warmup, args.tte_steps, 1), dtype=torch.float64,
                        device="cuda")
     # warmup
@@ -128,9 +184,15 @@ def main():
         tte.append(time.perf_counter() - t1)
 
     n_ex, ms_ex = ktimes["exchange"]
-    flops = exchange_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
+    if multi:
+        flops = multidet_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
+        kname = "k_md_energy (P = (C^T L_g) Theta_0, X0^2, per-determinant corrections)"
+    else:
+        flops = exchange_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
+        kname = ("k_exchange_full (fused Ltil*Theta, Tr X, Tr XX)"
+                 if max(wl.n_up, wl.n_dn) <= 32 else "k_exchange (fused Ltil*Theta, Tr X, Tr XX)")
     avg_s = (ms_ex / n_ex) / 1e3 if n_ex else float("nan")
-    peak = FP32_PEAK_TFLOPS if wl.chol_prec == "fp32" else FP64_PEAK_TFLOPS
+    peak = {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}[chol_prec]
     achieved = flops / avg_s / 1e12 if n_ex else float("nan")
     value = W * args.steps / elapsed
     out = {
@@ -144,16 +206,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if wl.chol_prec == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[chol_prec],
         "data": "synthetic",
         "config": {"workload": wl.name, "M": wl.M, "n_up": wl.n_up, "n_dn": wl.n_dn,
                    "n_chol": wl.n_chol, "n_walkers": W, "dt": wl.dt,
                    "taylor_order": wl.taylor_order, "ortho_every": wl.ortho_every,
-                   "pc_every": wl.pc_every,
-                   "precision": f"contractions {wl.chol_prec}, Taylor/B1 {wl.taylor_prec}, "
+                   "pc_every": wl.pc_every, "n_det": inp.n_det, "l_scale": wl.l_scale,
+                   "precision": f"contractions {chol_prec}, Taylor/B1 {taylor_prec}, "
                                 "overlap/inverse/det/MGS/sums fp64",
-                   "e_mix_last": e_last, "alive_walkers": alive},
-        "roofline": {"bound": "mfma", "kernel": "k_exchange (fused Ltil*Theta, Tr X, Tr XX)",
+                   "e_trial": et, "e_mix_last": e_last, "alive_walkers": alive},
+        "roofline": {"bound": "mfma", "kernel": kname,
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3, "launches": n_ex},
@@ -170,6 +232,8 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration"] = {"kernel": "torch elementwise mul (x * 1.0 -> y)",
                                    "bytes_read": x.numel() * 8, "bytes_written": y.numel() * 8}
+    if not args.no_accuracy and wl.name in GOLDEN:
+        out["accuracy"] = accuracy_check(afq, torch, wl, inp, ham, trial, opt_kw)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, inp, args.cpu_walkers, args.cpu_steps)
     print(json.dumps(out), flush=True)

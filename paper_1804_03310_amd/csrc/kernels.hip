@@ -441,11 +441,296 @@ __global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s
   }
 }
 
+// Same quantities for N <= 32, one wavefront per (walker, spin) and no block
+// barriers.  S = D_0^T phi is an FP64 MFMA product with both operands read
+// from global memory in batches of four k steps (the next batch in flight
+// while the current one is multiplied).  Each lane then keeps one row half
+// (16 complex entries) of S in registers for Gauss-Jordan elimination with
+// implicit row pivoting: the pivot row is chosen among the rows not used yet,
+// rows never move, and the scaled pivot row is broadcast through LDS.  The
+// result R relates to the inverse by S^-1[k][j] = R[pi(k)][pi^-1(j)], pi(k)
+// being the pivot row of column k, and is written to LDS in that order;
+// det S = sign(pi) prod of the pivots.  Theta = phi S^-1 is a second FP64
+// MFMA product over 16-row tiles of phi (the first tile's operands are
+// requested before the elimination starts) with S^-1 held in registers.
+__device__ inline double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int NT>
+struct OvlWave {
+  static constexpr int NP = 16 * NT;
+  static constexpr int LD = NP + 2;                          // even: 16-byte aligned rows
+  static constexpr int DOUBLES = 2 * NP * LD + 2 * NP + NP;  // S re/im, pivot row, pi
+};
+
+template <int NT>
+__global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, SpinGeom s0, SpinGeom s1,
+                                                            const double* __restrict__ phr,
+                                                            const double* __restrict__ phi,
+                                                            double* __restrict__ thr,
+                                                            double* __restrict__ thi, double* ld_re,
+                                                            double* ld_im, double* e1_re,
+                                                            double* e1_im) {
+  typedef OvlWave<NT> L;
+  constexpr int NP = L::NP, LD = L::LD, KA = NP / 4;
+  using MM = Mfma<double>;
+  typedef MM::acc_t acc_t;
+  extern __shared__ __attribute__((aligned(16))) double olds[];
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int w = blockIdx.x, s = wv;
+  const SpinGeom g = s ? s1 : s0;
+  const int N = g.N, off = g.off;
+  const long wb = (long)w * M * Nt;
+  if (N == 0) {
+    if (l == 0) {
+      ld_re[2 * w + s] = 0.0; ld_im[2 * w + s] = 0.0;
+      e1_re[2 * w + s] = 0.0; e1_im[2 * w + s] = 0.0;
+    }
+    return;
+  }
+  double* Sr = olds + wv * L::DOUBLES;
+  double* Si = Sr + NP * LD;
+  double* rowr = Si + NP * LD;
+  double* rowi = rowr + NP;
+  int* piarr = (int*)(rowi + NP);
+  const int li = l & 15, lk = l >> 4;
+  // ---- S = D_0^T phi (zero padded to NP x NP) ----
+  {
+    acc_t cr[NT][NT], ci[NT][NT];
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+      for (int J = 0; J < NT; ++J) { cr[I][J] = MM::zero(); ci[I][J] = MM::zero(); }
+    const int KS = (M + 3) >> 2;
+    double a0[4][NT], r0[4][NT], i0[4][NT], a1[4][NT], r1[4][NT], i1[4][NT];
+    auto load = [&](double (&a)[4][NT], double (&br)[4][NT], double (&bi)[4][NT], int kb) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = 4 * (kb + j) + lk;
+#pragma unroll
+        for (int I = 0; I < NT; ++I) {
+          const int col = 16 * I + li;
+          const bool ok = m < M && col < N;
+          a[j][I] = ok ? g.C[(long)m * M + col] : 0.0;
+          br[j][I] = ok ? phr[wb + (long)m * Nt + off + col] : 0.0;
+          bi[j][I] = ok ? phi[wb + (long)m * Nt + off + col] : 0.0;
+        }
+      }
+    };
+    load(a0, r0, i0, 0);
+    for (int kb = 0; kb < KS; kb += 4) {
+      if (kb + 4 < KS) load(a1, r1, i1, kb + 4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int I = 0; I < NT; ++I)
+#pragma unroll
+          for (int J = 0; J < NT; ++J) {
+            cr[I][J] = MM::mma(a0[j][I], r0[j][J], cr[I][J]);
+            ci[I][J] = MM::mma(a0[j][I], i0[j][J], ci[I][J]);
+          }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int I = 0; I < NT; ++I) { a0[j][I] = a1[j][I]; r0[j][I] = r1[j][I]; i0[j][I] = i1[j][I]; }
+    }
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+      for (int J = 0; J < NT; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * I + MM::row(lk, v), c = 16 * J + li;
+          Sr[r * LD + c] = cr[I][J][v];
+          Si[r * LD + c] = ci[I][J][v];
+        }
+  }
+  wave_lds_sync();
+  // first row tile of phi for the Theta product, requested now so that the
+  // loads overlap the elimination: A[m = li][a = 4 ka + lk]
+  double par[KA], pai[KA];
+  auto load_phi_tile = [&](double (&ar)[KA], double (&ai)[KA], int R) {
+    const int m = 16 * R + li;
+#pragma unroll
+    for (int ka = 0; ka < KA; ++ka) {
+      const int a = 4 * ka + lk;
+      const bool ok = m < M && a < N;
+      ar[ka] = ok ? phr[wb + (long)m * Nt + off + a] : 0.0;
+      ai[ka] = ok ? phi[wb + (long)m * Nt + off + a] : 0.0;
+    }
+  };
+  load_phi_tile(par, pai, 0);
+  // ---- Gauss-Jordan with implicit pivoting, rows in registers ----
+  const int i = l & (NP - 1);
+  const int h = (NT == 2) ? (l >> 5) : 0;
+  const bool owner = (NT == 2) || (l < 16);
+  double xr[16], xi[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    xr[c] = Sr[i * LD + 16 * h + c];
+    xi[c] = Si[i * LD + 16 * h + c];
+  }
+  unsigned int used = 0u;
+  int mypi = 0, mypinv = 0;
+  double pkr = 1.0, pki = 0.0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    if (k >= N) break;
+    const int hk = k >> 4, ck = k & 15;
+    double fr = xr[ck], fi = xi[ck];
+    if (NT == 2) {
+      const double orr = __shfl_xor(fr, 32, AFQ_WAVE), oii = __shfl_xor(fi, 32, AFQ_WAVE);
+      if (h != hk) { fr = orr; fi = oii; }
+    }
+    // candidate key: |S_ik|^2 (non-negative, so its bits order as unsigned)
+    // with the low five mantissa bits replaced by 31 - i (lowest row wins a
+    // tie); rows already used and padding rows get 0
+    const double mag = fr * fr + fi * fi;
+    unsigned long long key =
+        (i < N && !((used >> i) & 1u))
+            ? (((unsigned long long)__double_as_longlong(mag) & ~31ull) | (unsigned long long)(31 - i))
+            : 0ull;
+#pragma unroll
+    for (int o = NP / 2; o >= 1; o >>= 1) {
+      const unsigned long long ok = (unsigned long long)__shfl_xor((long long)key, o, AFQ_WAVE);
+      key = ok > key ? ok : key;
+    }
+    const int p = 31 - (int)(__builtin_amdgcn_readfirstlane((int)(key & 31ull)));
+    used |= 1u << p;
+    const zdbl pv = {readlane_d(fr, p), readlane_d(fi, p)};
+    const zdbl pinv = zdiv(zdbl{1.0, 0.0}, pv);
+    if (l == k) { pkr = pv.re; pki = pv.im; mypi = p; }
+    if (i == p) mypinv = k;
+    if (owner && i == p) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int j = 16 * h + c;
+        const zdbl v = (j == k) ? pinv : zmul(zdbl{xr[c], xi[c]}, pinv);
+        rowr[j] = v.re;
+        rowi[j] = v.im;
+      }
+    }
+    wave_lds_sync();
+    const zdbl nf = zmul(zdbl{-fr, -fi}, pinv);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int j = 16 * h + c;
+      const double rr = rowr[j], ri = rowi[j];
+      if (i == p) {
+        xr[c] = rr; xi[c] = ri;
+      } else if (j == k) {
+        xr[c] = nf.re; xi[c] = nf.im;
+      } else {
+        xr[c] = xr[c] - (fr * rr - fi * ri);
+        xi[c] = xi[c] - (fr * ri + fi * rr);
+      }
+    }
+    wave_lds_sync();
+  }
+  // ---- log det: pivots and the sign of pi ----
+  if (l < N) piarr[l] = mypi;
+  wave_lds_sync();
+  double lr = 0.0, lim = 0.0, inv = 0.0;
+  if (l < N) {
+    const zdbl lg = zlog(zdbl{pkr, pki});
+    lr = lg.re;
+    lim = lg.im;
+    const int pk = piarr[l];
+    int cnt = 0;
+    for (int k2 = l + 1; k2 < N; ++k2) cnt += piarr[k2] < pk;
+    inv = (double)cnt;
+  }
+  lr = wave_sum(lr);
+  lim = wave_sum(lim);
+  inv = wave_sum(inv);
+  // ---- S^-1[pi^-1(i)][pi(j)] = R[i][j] ----
+  if (owner && i < N) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int j = 16 * h + c;
+      if (j < N) {
+        const int col = piarr[j];
+        Sr[mypinv * LD + col] = xr[c];
+        Si[mypinv * LD + col] = xi[c];
+      }
+    }
+  }
+  wave_lds_sync();
+  // ---- Theta = phi S^-1 by 16-row tiles, E1 = Tr(htil Theta) ----
+  double sbr[KA][NT], sbi[KA][NT];
+#pragma unroll
+  for (int ka = 0; ka < KA; ++ka)
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      sbr[ka][J] = Sr[(4 * ka + lk) * LD + 16 * J + li];
+      sbi[ka][J] = Si[(4 * ka + lk) * LD + 16 * J + li];
+    }
+  const int KN = (N + 3) >> 2;
+  const int RT = (M + 15) >> 4;
+  double er = 0.0, ei = 0.0;
+  for (int R = 0; R < RT; ++R) {
+    if (R > 0) load_phi_tile(par, pai, R);
+    acc_t tr[NT], ti[NT];
+#pragma unroll
+    for (int J = 0; J < NT; ++J) { tr[J] = MM::zero(); ti[J] = MM::zero(); }
+#pragma unroll
+    for (int ka = 0; ka < KA; ++ka) {
+      if (ka < KN) {
+#pragma unroll
+        for (int J = 0; J < NT; ++J) {
+          tr[J] = MM::mma(par[ka], sbr[ka][J], tr[J]);
+          tr[J] = MM::mma(-pai[ka], sbi[ka][J], tr[J]);
+          ti[J] = MM::mma(par[ka], sbi[ka][J], ti[J]);
+          ti[J] = MM::mma(pai[ka], sbr[ka][J], ti[J]);
+        }
+      }
+    }
+#pragma unroll
+    for (int J = 0; J < NT; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * R + MM::row(lk, v), b = 16 * J + li;
+        if (m < M && b < N) {
+          thr[wb + (long)m * Nt + off + b] = tr[J][v];
+          thi[wb + (long)m * Nt + off + b] = ti[J][v];
+          const double hv = g.htil[(long)b * M + m];
+          er += hv * tr[J][v];
+          ei += hv * ti[J][v];
+        }
+      }
+  }
+  er = wave_sum(er);
+  ei = wave_sum(ei);
+  if (l == 0) {
+    const double pi_ = 3.141592653589793238462643383279;
+    ld_re[2 * w + s] = lr;
+    ld_im[2 * w + s] = lim + ((((int)inv) & 1) ? pi_ : 0.0);
+    e1_re[2 * w + s] = er;
+    e1_im[2 * w + s] = ei;
+  }
+}
+
 hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, SpinGeom s1,
                          const double* phr, const double* phi, double* thr, double* thi,
                          double* ld_re, double* ld_im, double* e1_re, double* e1_im,
                          size_t max_lds) {
   const int N = s0.N > s1.N ? s0.N : s1.N;
+  if (N <= 16) {
+    const size_t lds = (size_t)2 * OvlWave<1>::DOUBLES * sizeof(double);
+    hipLaunchKernelGGL(k_overlap_theta_wave<1>, dim3(W), dim3(128), lds, st, M, Nt, s0, s1, phr,
+                       phi, thr, thi, ld_re, ld_im, e1_re, e1_im);
+    return hipGetLastError();
+  }
+  if (N <= 32) {
+    const size_t lds = (size_t)2 * OvlWave<2>::DOUBLES * sizeof(double);
+    hipLaunchKernelGGL(k_overlap_theta_wave<2>, dim3(W), dim3(128), lds, st, M, Nt, s0, s1, phr,
+                       phi, thr, thi, ld_re, ld_im, e1_re, e1_im);
+    return hipGetLastError();
+  }
   const size_t base = (size_t)(2 * N * (N + 1) + 4 * N) * sizeof(double);
   const size_t staged = base + (size_t)3 * M * N * sizeof(double);
   if (staged <= 65536 && staged <= max_lds) {
@@ -585,10 +870,12 @@ __global__ __launch_bounds__(256) void k_exchange(int M, int MP4, int Nt, int G,
 // together, so each k step loads NT A values (global, L2 resident) and 2 NT B
 // values (LDS) for 2 NT^2 MFMAs; the A operand of the next four k steps (and,
 // during the epilogue, of the first four steps of the next g) is prefetched
-// into registers.  Theta rows in LDS are padded to a stride of 16 mod 32
-// elements against bank conflicts.  X is stashed row-major once per g in a
-// per-wave LDS tile whose rows are 16-byte aligned, so the four X_ba values a
-// lane pairs with its four X_ab come back in one 128-bit read.  Per-g partial
+// into registers.  Theta rows in LDS are unpadded; for 32 columns the two
+// 16-column halves of odd rows are swapped so that the lanes reading rows m
+// and m+1 hit different banks.  X is stashed row-major once per g in a
+// per-wave LDS tile with the same half swap on every other group of four
+// rows; the four X_ba values a lane pairs with its four X_ab stay contiguous
+// and 16-byte aligned and come back in one 128-bit read.  Per-g partial
 // sums are formed in the contraction type and added to FP64 totals.
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef afq_f4 type; };
@@ -607,8 +894,11 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
   typedef typename MM::acc_t acc_t;
   typedef typename Vec4<T>::type v4_t;
   constexpr int NPM = 16 * NT;
-  constexpr int LDB = (NPM % 32 == 0) ? NPM + 16 : NPM;
-  constexpr int LDX = NPM + 4;
+  constexpr int LDB = NPM;
+  constexpr int LDX = NPM;
+  // column swizzles (identity for 16 columns)
+  auto swb = [](int m, int b) { return NT == 2 ? (b ^ ((m & 1) << 4)) : b; };
+  auto swx = [](int r, int c) { return NT == 2 ? (c ^ (((r >> 2) & 1) << 4)) : c; };
   const int w = blockIdx.x, s = blockIdx.y;
   const SpinGeom g = s ? s1 : s0;
   const int N = g.N, NP = g.NP, off = g.off, nt = NP / 16;
@@ -630,8 +920,8 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
   for (int e = threadIdx.x; e < MP4 * NPM; e += blockDim.x) {
     const int m = e / NPM, b = e % NPM;
     const bool ok = m < M && b < N;
-    Br[m * LDB + b] = ok ? (T)thr[wb + (long)m * Nt + off + b] : (T)0;
-    Bi[m * LDB + b] = ok ? (T)thi[wb + (long)m * Nt + off + b] : (T)0;
+    Br[m * LDB + swb(m, b)] = ok ? (T)thr[wb + (long)m * Nt + off + b] : (T)0;
+    Bi[m * LDB + swb(m, b)] = ok ? (T)thi[wb + (long)m * Nt + off + b] : (T)0;
   }
   __syncthreads();
   const int KS = MP4 / 4;
@@ -662,8 +952,8 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
           T br[NT], bi[NT];
 #pragma unroll
           for (int J = 0; J < NT; ++J) {
-            br[J] = Br[m * LDB + 16 * J + li];
-            bi[J] = Bi[m * LDB + 16 * J + li];
+            br[J] = Br[m * LDB + swb(m, 16 * J + li)];
+            bi[J] = Bi[m * LDB + swb(m, 16 * J + li)];
           }
 #pragma unroll
           for (int I = 0; I < NT; ++I)
@@ -687,8 +977,8 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = 16 * I + MM::row(lk, v), c = 16 * J + li;
-          Xr[r * LDX + c] = cr[I][J][v];
-          Xi[r * LDX + c] = ci[I][J][v];
+          Xr[r * LDX + swx(r, c)] = cr[I][J][v];
+          Xi[r * LDX + swx(r, c)] = ci[I][J][v];
         }
     wave_lds_sync();
     T pxr = (T)0, pxi = (T)0, ptr = (T)0, pti = (T)0;
@@ -699,16 +989,18 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
         // partners X_ba, b = 16J + li, a = 16I + row(lk, v): for the f32 layout the
         // four a of a lane are consecutive, so one 128-bit read per tile
         T yr[4], yi[4];
+        const int rb = 16 * J + li;
         if (MM::row(0, 1) == 1) {
-          const v4_t vr = *(const v4_t*)&Xr[(16 * J + li) * LDX + 16 * I + MM::row(lk, 0)];
-          const v4_t vi = *(const v4_t*)&Xi[(16 * J + li) * LDX + 16 * I + MM::row(lk, 0)];
+          const int c0 = swx(rb, 16 * I + MM::row(lk, 0));
+          const v4_t vr = *(const v4_t*)&Xr[rb * LDX + c0];
+          const v4_t vi = *(const v4_t*)&Xi[rb * LDX + c0];
 #pragma unroll
           for (int v = 0; v < 4; ++v) { yr[v] = vr[v]; yi[v] = vi[v]; }
         } else {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            yr[v] = Xr[(16 * J + li) * LDX + 16 * I + MM::row(lk, v)];
-            yi[v] = Xi[(16 * J + li) * LDX + 16 * I + MM::row(lk, v)];
+            yr[v] = Xr[rb * LDX + swx(rb, 16 * I + MM::row(lk, v))];
+            yi[v] = Xi[rb * LDX + swx(rb, 16 * I + MM::row(lk, v))];
           }
         }
 #pragma unroll
@@ -744,7 +1036,7 @@ hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGe
                     double* exx_re, double* exx_im, size_t max_lds) {
   const int NP = s0.NP > s1.NP ? s0.NP : s1.NP;
   if (NP <= 32) {
-    const int NPM = NP, LDB = (NPM % 32 == 0) ? NPM + 16 : NPM, LDX = NPM + 4;
+    const int NPM = NP, LDB = NPM, LDX = NPM;
     const size_t ldsf = (size_t)(2 * MP4 * LDB + 4 * 2 * NPM * LDX) * sizeof(T);
     if (ldsf <= max_lds) {
       if (NP == 16)
