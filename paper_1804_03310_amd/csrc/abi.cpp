@@ -678,7 +678,8 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
   size_t tot = rnd(mm * 8) * 2 + rnd(g * mm * 8) + rnd(g * mm * 4) + rnd(g * mm * 2);  // ham
   for (int s = 0; s < 2; ++s) {                                                        // trial
     const size_t NP = round_up(std::max(nel[s], 1), 16);
-    tot += rnd(mm * 8) + rnd(std::max(nel[s], 1) * m * 8) + rnd(g * MP4 * NP * 12) +
+    const size_t nlt = (g * MP4 + 16) * NP;
+    tot += rnd(mm * 8) + rnd(std::max(nel[s], 1) * m * 8) + rnd(nlt * 8) + rnd(nlt * 4) +
            rnd(g * NP * MP32 * 2);
     if (n_det > 1) tot += rnd((g + 1) * mm * 8) + rnd((g + 1) * mm * 4);
   }
@@ -772,7 +773,9 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
   const size_t mm = (size_t)M * M;
   for (int s = 0; s < 2; ++s) {
     void *pc, *ph, *p64, *p32;
-    const size_t nlt = (size_t)G * tr->MP4 * tr->NP[s];
+    // 16 zero rows after the last slab: the exchange kernel reads its A
+    // operand in batches of four k steps without bounds checks
+    const size_t nlt = (size_t)G * tr->MP4 * tr->NP[s] + (size_t)16 * tr->NP[s];
     if (tr->arena.alloc(&pc, mm * 8) || tr->arena.alloc(&ph, (size_t)std::max(nel[s], 1) * M * 8) ||
         tr->arena.alloc(&p64, nlt * 8) || tr->arena.alloc(&p32, nlt * 4))
       return bad(AFQMC_ERR_OOM, "trial allocation failed");

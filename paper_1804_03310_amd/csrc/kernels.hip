@@ -577,11 +577,17 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
   unsigned int used = 0u;
   int mypi = 0, mypinv = 0;
   double pkr = 1.0, pki = 0.0;
-#pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    if (k >= N) break;
+  // a runtime loop over the pivot columns: an unrolled one does not fit the
+  // instruction cache
+#pragma unroll 1
+  for (int k = 0; k < N; ++k) {
     const int hk = k >> 4, ck = k & 15;
-    double fr = xr[ck], fi = xi[ck];
+    double fr = 0.0, fi = 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      fr = (c == ck) ? xr[c] : fr;
+      fi = (c == ck) ? xi[c] : fi;
+    }
     if (NT == 2) {
       const double orr = __shfl_xor(fr, 32, AFQ_WAVE), oii = __shfl_xor(fi, 32, AFQ_WAVE);
       if (h != hk) { fr = orr; fi = oii; }
@@ -901,7 +907,11 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
   auto swx = [](int r, int c) { return NT == 2 ? (c ^ (((r >> 2) & 1) << 4)) : c; };
   const int w = blockIdx.x, s = blockIdx.y;
   const SpinGeom g = s ? s1 : s0;
-  const int N = g.N, NP = g.NP, off = g.off, nt = NP / 16;
+  const int N = g.N, off = g.off;
+  // Lt row stride of this spin; the block's tile count NT covers the larger
+  // spin, so a 16-column spin in an NT = 2 launch has no second row tile
+  const int NP = g.NP;
+  const bool one_tile = (NT == 2) && (NP == 16);
   const T* __restrict__ Lt = (const T*)g.Lt;
   const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
   if (N == 0) {
@@ -927,14 +937,22 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
   const int KS = MP4 / 4;
   double xx_re = 0.0, xx_im = 0.0;
   T a0[4][NT], a1[4][NT];
+  // A operand, four k steps from k step kb of slab q (clamped to the last
+  // slab).  Rows past the slab are the next slab's or the zero rows that
+  // follow the last one; the MFMAs of k steps >= KS are skipped.
+  const T* __restrict__ Llane = Lt + lk * NP + li;
   auto load_a = [&](T (&a)[4][NT], int q, int kb) {
-    const T* __restrict__ Lq = Lt + (long)q * MP4 * NP;
+    const T* __restrict__ Lq = Llane + (long)(q < G ? q : G - 1) * MP4 * NP + 4 * kb * NP;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int I = 0; I < NT; ++I)
-        a[j][I] = (q < G && kb + j < KS && I < nt) ? Lq[(4 * (kb + j) + lk) * NP + 16 * I + li] : (T)0;
+      for (int I = 0; I < NT; ++I) a[j][I] = (I == 0 || !one_tile) ? Lq[4 * j * NP + 16 * I] : (T)0;
   };
+  // this lane's B elements (row lk of each group of four, column swizzle of
+  // an odd/even row fixed by lk)
+  const int bsw = (NT == 2) ? ((lk & 1) << 4) : 0;
+  const T* __restrict__ Brl = Br + lk * LDB;
+  const T* __restrict__ Bil = Bi + lk * LDB;
   load_a(a0, wv, 0);
   for (int q = wv; q < G; q += 4) {
     acc_t cr[NT][NT], ci[NT][NT];
@@ -948,12 +966,12 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (kb + j < KS) {
-          const int m = 4 * (kb + j) + lk;
+          const int mo = 4 * (kb + j) * LDB;
           T br[NT], bi[NT];
 #pragma unroll
           for (int J = 0; J < NT; ++J) {
-            br[J] = Br[m * LDB + swb(m, 16 * J + li)];
-            bi[J] = Bi[m * LDB + swb(m, 16 * J + li)];
+            br[J] = Brl[mo + ((16 * J + li) ^ bsw)];
+            bi[J] = Bil[mo + ((16 * J + li) ^ bsw)];
           }
 #pragma unroll
           for (int I = 0; I < NT; ++I)

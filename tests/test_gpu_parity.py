@@ -78,7 +78,8 @@ def test_local_energy_at_trial_equals_oracle(afq):
 
 
 @pytest.mark.parametrize("M,n_up,n_dn,G,W", [(10, 5, 5, 40, 16), (23, 7, 4, 37, 9),
-                                               (50, 25, 25, 250, 6), (40, 17, 0, 30, 5)])
+                                               (50, 25, 25, 250, 6), (40, 17, 0, 30, 5),
+                                               (29, 20, 9, 33, 7), (70, 31, 32, 41, 3)])
 def test_local_energy_random_walkers_fp64(afq, M, n_up, n_dn, G, W):
     _say(f"local energy random walkers M={M} N={n_up}/{n_dn} G={G} W={W}")
     inp = syn.make_system(M, n_up, n_dn, G, 8.0, seed=M + G, e_core=0.75)
@@ -95,6 +96,28 @@ def test_local_energy_random_walkers_fp64(afq, M, n_up, n_dn, G, W):
     assert np.allclose(el, m["eloc"], rtol=1e-10, atol=1e-10)
     assert np.allclose(ls.real, m["logS"].real, atol=1e-10)
     assert np.allclose(_wrap(ls.imag - m["logS"].imag), 0.0, atol=1e-10)
+
+
+@pytest.mark.parametrize("M,n_up,n_dn,G,W", [(23, 7, 4, 37, 9), (29, 20, 9, 33, 7),
+                                               (50, 25, 25, 250, 6), (40, 17, 0, 30, 5)])
+def test_local_energy_random_walkers_fp32(afq, M, n_up, n_dn, G, W):
+    """FP32 contractions (reached through a zero-step propagate, which
+    refreshes E_L with the step's precision): relative 1e-5.  The walkers
+    are 0.1-scale perturbations of D_0 (overlap condition numbers below 10):
+    the FP32 error of E_L grows with cond(S) since Theta carries S^-1."""
+    _say(f"local energy random walkers fp32 M={M} N={n_up}/{n_dn} G={G} W={W}")
+    inp = syn.make_system(M, n_up, n_dn, G, 8.0, seed=M + G, e_core=0.75)
+    ham, trial, w = _make(afq, inp, W)
+    re, im = syn.random_walkers(M, n_up, n_dn, W, seed=3, scale=0.1)
+    D0 = np.concatenate([inp.C_up[:, :n_up], inp.C_dn[:, :n_dn]], axis=1)
+    phi = D0[None] + re + 1j * im
+    _set_phi(w, phi)
+    afq.propagate(ham, trial, w, 0, 0.01, 0, 0, afq.Options(chol_prec="fp32", taylor_prec="fp32"))
+    m = Oracle.from_inputs(inp).measure(phi)
+    el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
+    err = np.abs(el - m["eloc"]) / np.abs(m["eloc"])
+    print(f"fp32 max rel dE_L = {err.max():.3e}")
+    assert err.max() <= 1e-5
 
 
 def _run_both(afq, inp, W, n_steps, dt, opt_kw, prec=("fp64", "fp64"), seed=0, oracle_walkers=None):
