@@ -888,8 +888,9 @@ template <> struct Vec4<float> { typedef afq_f4 type; };
 template <> struct Vec4<double> { typedef afq_d4 type; };
 
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, int G, SpinGeom s0,
-                                                       SpinGeom s1, const double* __restrict__ thr,
+__global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, int G, int s_base,
+                                                       SpinGeom s0, SpinGeom s1,
+                                                       const double* __restrict__ thr,
                                                        const double* __restrict__ thi,
                                                        double* __restrict__ vs_re,
                                                        double* __restrict__ vs_im, double* exx_re,
@@ -900,18 +901,13 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
   typedef typename MM::acc_t acc_t;
   typedef typename Vec4<T>::type v4_t;
   constexpr int NPM = 16 * NT;
-  constexpr int LDB = NPM;
   constexpr int LDX = NPM;
-  // column swizzles (identity for 16 columns)
-  auto swb = [](int m, int b) { return NT == 2 ? (b ^ ((m & 1) << 4)) : b; };
+  // X stash column swizzle (identity for 16 columns)
   auto swx = [](int r, int c) { return NT == 2 ? (c ^ (((r >> 2) & 1) << 4)) : c; };
-  const int w = blockIdx.x, s = blockIdx.y;
+  const int w = blockIdx.x, s = s_base + blockIdx.y;
   const SpinGeom g = s ? s1 : s0;
   const int N = g.N, off = g.off;
-  // Lt row stride of this spin; the block's tile count NT covers the larger
-  // spin, so a 16-column spin in an NT = 2 launch has no second row tile
-  const int NP = g.NP;
-  const bool one_tile = (NT == 2) && (NP == 16);
+  constexpr int NP = NPM;  // the launch matches NT to this spin's padded width
   const T* __restrict__ Lt = (const T*)g.Lt;
   const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
   if (N == 0) {
@@ -922,16 +918,18 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
     if (threadIdx.x == 0) { exx_re[2 * w + s] = 0.0; exx_im[2 * w + s] = 0.0; }
     return;
   }
-  T* Br = (T*)lds_raw;
-  T* Bi = Br + MP4 * LDB;
-  T* Xr = Bi + MP4 * LDB + wv * 2 * NPM * LDX;
+  // Theta staged as [m][b mod 16][b / 16][re, im]: the 2 NT B values a lane
+  // needs for one k step are contiguous (one 128-bit read for NT = 2)
+  T* Bc = (T*)lds_raw;
+  T* Xr = Bc + MP4 * 2 * NPM + wv * 2 * NPM * LDX;
   T* Xi = Xr + NPM * LDX;
   const long wb = (long)w * M * Nt;
   for (int e = threadIdx.x; e < MP4 * NPM; e += blockDim.x) {
     const int m = e / NPM, b = e % NPM;
     const bool ok = m < M && b < N;
-    Br[m * LDB + swb(m, b)] = ok ? (T)thr[wb + (long)m * Nt + off + b] : (T)0;
-    Bi[m * LDB + swb(m, b)] = ok ? (T)thi[wb + (long)m * Nt + off + b] : (T)0;
+    T* d = Bc + ((m * 16 + (b & 15)) * NT + (b >> 4)) * 2;
+    d[0] = ok ? (T)thr[wb + (long)m * Nt + off + b] : (T)0;
+    d[1] = ok ? (T)thi[wb + (long)m * Nt + off + b] : (T)0;
   }
   __syncthreads();
   const int KS = MP4 / 4;
@@ -946,13 +944,11 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int I = 0; I < NT; ++I) a[j][I] = (I == 0 || !one_tile) ? Lq[4 * j * NP + 16 * I] : (T)0;
+      for (int I = 0; I < NT; ++I) a[j][I] = Lq[4 * j * NP + 16 * I];
   };
-  // this lane's B elements (row lk of each group of four, column swizzle of
-  // an odd/even row fixed by lk)
-  const int bsw = (NT == 2) ? ((lk & 1) << 4) : 0;
-  const T* __restrict__ Brl = Br + lk * LDB;
-  const T* __restrict__ Bil = Bi + lk * LDB;
+  // this lane's B elements: row 4 k + lk, columns li and 16 + li
+  typedef T bvec_t __attribute__((ext_vector_type(2 * NT)));
+  const bvec_t* __restrict__ Bl = (const bvec_t*)(Bc + (lk * 16 + li) * 2 * NT);
   load_a(a0, wv, 0);
   for (int q = wv; q < G; q += 4) {
     acc_t cr[NT][NT], ci[NT][NT];
@@ -963,22 +959,20 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
     for (int kb = 0; kb < KS; kb += 4) {
       if (kb + 4 < KS) load_a(a1, q, kb + 4);
       else load_a(a1, q + 4, 0);   // first batch of this wave's next g
+      // the four k steps' B values are requested together
+      bvec_t bq[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (kb + j < KS) bq[j] = Bl[4 * (kb + j) * 16];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (kb + j < KS) {
-          const int mo = 4 * (kb + j) * LDB;
-          T br[NT], bi[NT];
-#pragma unroll
-          for (int J = 0; J < NT; ++J) {
-            br[J] = Brl[mo + ((16 * J + li) ^ bsw)];
-            bi[J] = Bil[mo + ((16 * J + li) ^ bsw)];
-          }
 #pragma unroll
           for (int I = 0; I < NT; ++I)
 #pragma unroll
             for (int J = 0; J < NT; ++J) {
-              cr[I][J] = MM::mma(a0[j][I], br[J], cr[I][J]);
-              ci[I][J] = MM::mma(a0[j][I], bi[J], ci[I][J]);
+              cr[I][J] = MM::mma(a0[j][I], bq[j][2 * J], cr[I][J]);
+              ci[I][J] = MM::mma(a0[j][I], bq[j][2 * J + 1], ci[I][J]);
             }
         }
       }
@@ -1054,15 +1048,26 @@ hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGe
                     double* exx_re, double* exx_im, size_t max_lds) {
   const int NP = s0.NP > s1.NP ? s0.NP : s1.NP;
   if (NP <= 32) {
-    const int NPM = NP, LDB = NPM, LDX = NPM;
-    const size_t ldsf = (size_t)(2 * MP4 * LDB + 4 * 2 * NPM * LDX) * sizeof(T);
-    if (ldsf <= max_lds) {
-      if (NP == 16)
-        hipLaunchKernelGGL((k_exchange_full<T, 1>), dim3(W, 2), dim3(256), ldsf, st, M, MP4, Nt, G,
-                           s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
-      else
-        hipLaunchKernelGGL((k_exchange_full<T, 2>), dim3(W, 2), dim3(256), ldsf, st, M, MP4, Nt, G,
-                           s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
+    // one launch per distinct padded width (both spins in one launch when
+    // they agree); the kernel's tile count must equal the spin's NP / 16
+    // Theta (re, im) [MP4][NPM] plus four waves' X stash (re, im) [NPM][NPM]
+    auto lds_of = [&](int npm) { return (size_t)(2 * MP4 * npm + 4 * 2 * npm * npm) * sizeof(T); };
+    const size_t ld32 = lds_of(32), ld16 = lds_of(16);
+    if (ld32 <= max_lds) {
+      auto launch = [&](int npm, int s_base, int ny) {
+        if (npm == 16)
+          hipLaunchKernelGGL((k_exchange_full<T, 1>), dim3(W, ny), dim3(256), ld16, st, M, MP4, Nt,
+                             G, s_base, s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
+        else
+          hipLaunchKernelGGL((k_exchange_full<T, 2>), dim3(W, ny), dim3(256), ld32, st, M, MP4, Nt,
+                             G, s_base, s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
+      };
+      if (s0.NP == s1.NP) {
+        launch(s0.NP, 0, 2);
+      } else {
+        launch(s0.NP, 0, 1);
+        launch(s1.NP, 1, 1);
+      }
       return hipGetLastError();
     }
   }

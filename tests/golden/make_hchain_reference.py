@@ -22,9 +22,10 @@ import argparse
 import os
 import sys
 
-# one BLAS thread per worker process (set before numpy is first imported)
+# one BLAS thread per worker process unless the caller says otherwise (set
+# before numpy is first imported)
 for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-    os.environ[_v] = "1"
+    os.environ.setdefault(_v, "1")
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
