@@ -61,6 +61,24 @@ __device__ inline float wave_sum_t(float v) {
 }
 __device__ inline double wave_sum_t(double v) { return wave_sum(v); }
 
+// Sum over the lanes {0..3, 20..23, 40..43, 60..63}, which hold the diagonal
+// of a 16x16 f32 MFMA result tile (lane (li, lk) holds rows 4 lk .. 4 lk + 3
+// of column li); returned in every lane.  Quad sums by DPP, then the four
+// quads by lane reads, in a fixed order.
+__device__ inline float quad_sum_dpp(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+  return x;
+}
+__device__ inline float diag16_sum(float x) {
+  const int q = __float_as_int(quad_sum_dpp(x));
+  const float a = __int_as_float(__builtin_amdgcn_readlane(q, 0));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(q, 20));
+  const float c = __int_as_float(__builtin_amdgcn_readlane(q, 40));
+  const float d = __int_as_float(__builtin_amdgcn_readlane(q, 60));
+  return (a + b) + (c + d);
+}
+
 // Fixed-order block sum of one double per thread (blockDim.x <= 1024,
 // a multiple of 64).  `red` is LDS scratch of blockDim.x/64 doubles.  All
 // threads return the total.

@@ -1020,13 +1020,34 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
           const T xr = cr[I][J][v], xi = ci[I][J][v];
           pxr += xr * yr[v] - xi * yi[v];
           pxi += xr * yi[v] + xi * yr[v];
-          if (I == J && MM::row(lk, v) == li) { ptr += xr; pti += xi; }
+          if (MM::row(0, 1) != 1 && I == J && MM::row(lk, v) == li) { ptr += xr; pti += xi; }
         }
       }
     wave_lds_sync();
     xx_re += (double)pxr;
     xx_im += (double)pxi;
-    const double tr_re = (double)wave_sum_t(ptr), tr_im = (double)wave_sum_t(pti);
+    double tr_re, tr_im;
+    if (MM::row(0, 1) == 1) {
+      // f32 layout: in the lanes that diag16_sum reads, element li & 3 of a
+      // diagonal tile is on the diagonal
+      const int vd = li & 3;
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        T dr = cr[I][I][0], di = ci[I][I][0];
+#pragma unroll
+        for (int v = 1; v < 4; ++v) {
+          dr = (vd == v) ? cr[I][I][v] : dr;
+          di = (vd == v) ? ci[I][I][v] : di;
+        }
+        ptr += dr;
+        pti += di;
+      }
+      tr_re = (double)diag16_sum((float)ptr);
+      tr_im = (double)diag16_sum((float)pti);
+    } else {
+      tr_re = (double)wave_sum_t(ptr);
+      tr_im = (double)wave_sum_t(pti);
+    }
     if (l == 0) {
       vs_re[((long)w * 2 + s) * G + q] = tr_re;
       vs_im[((long)w * 2 + s) * G + q] = tr_im;
