@@ -50,6 +50,26 @@ def multidet_flops_per_walker(M, n_up, n_dn, G):
 
 GOLDEN = {"hchain-M50": ("hchain-M50_W1024_T100.txt", 1024, 100, 1)}
 
+TRAFFIC = {"hchain-M50": "hchain-M50_exchange_traffic.json"}
+
+
+def measured_traffic(wl_name, chol_prec):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the copy-kernel
+    calibration), or None when there is none for this workload and precision
+    or the kernel source has changed since the counters were taken."""
+    import hashlib
+    name = TRAFFIC.get(wl_name)
+    if name is None:
+        return None
+    with open(os.path.join(ROOT, "profiles", name)) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if rec["chol_prec"] != chol_prec or rec["source_sha256"] != digest:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
 
 def read_golden(fname):
     et, num, den = None, [], []
@@ -217,7 +237,8 @@ def main():
                    "e_trial": et, "e_mix_last": e_last, "alive_walkers": alive},
         "roofline": {"bound": "mfma", "kernel": kname,
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(wl.name, chol_prec),
                      "flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3, "launches": n_ex},
         "kernel_ms_per_step": {k: (v[1] / max(args.steps, 1)) for k, v in ktimes.items() if v[0]},
         "time_to_energy_s": {"p50": float(np.percentile(tte, 50)) if tte else None,
