@@ -60,9 +60,10 @@ def measured_traffic(wl_name, chol_prec):
     or the kernel source has changed since the counters were taken."""
     import hashlib
     name = TRAFFIC.get(wl_name)
-    if name is None:
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if path is None or not os.path.exists(path):
         return None
-    with open(os.path.join(ROOT, "profiles", name)) as f:
+    with open(path) as f:
         rec = json.load(f)
     with open(os.path.join(ROOT, rec["source"]), "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()

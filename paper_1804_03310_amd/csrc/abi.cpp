@@ -203,6 +203,8 @@ struct afqmc_trial {
   double* htil[2] = {nullptr, nullptr};
   double* Lt64[2] = {nullptr, nullptr};
   float* Lt32[2] = {nullptr, nullptr};
+  double* Apk64[2] = {nullptr, nullptr};  // NP <= 32: exchange A operand, repacked
+  float* Apk32[2] = {nullptr, nullptr};
   void* Ltbf[2] = {nullptr, nullptr};  // [G][NP][MP32] bf16 (m contiguous)
   int MP32 = 32;
   double* lbar = nullptr;
@@ -314,6 +316,12 @@ afqmc_status check_walkers(const afqmc_trial* tr, const afqmc_walkers* wk) {
   return AFQMC_OK;
 }
 
+// Elements of the exchange kernel's repacked A operand for one spin (NP <= 32).
+size_t pack_exchange_elems(size_t G, size_t MP4, size_t NP) {
+  const size_t KB = (MP4 / 4 + 3) / 4;
+  return G * KB * 64 * 4 * (NP / 16);
+}
+
 afq::SpinGeom spin_geom(const afqmc_trial* tr, int s, afqmc_prec prec) {
   const bool fp32 = prec == AFQMC_FP32;
   afq::SpinGeom g;
@@ -323,6 +331,7 @@ afq::SpinGeom spin_geom(const afqmc_trial* tr, int s, afqmc_prec prec) {
   g.C = tr->C[s];
   g.htil = tr->htil[s];
   g.Lt = prec == AFQMC_BF16 ? tr->Ltbf[s] : fp32 ? (const void*)tr->Lt32[s] : (const void*)tr->Lt64[s];
+  g.Apk = fp32 ? (const void*)tr->Apk32[s] : (const void*)tr->Apk64[s];
   return g;
 }
 
@@ -681,6 +690,10 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
     const size_t nlt = (g * MP4 + 16) * NP;
     tot += rnd(mm * 8) + rnd(std::max(nel[s], 1) * m * 8) + rnd(nlt * 8) + rnd(nlt * 4) +
            rnd(g * NP * MP32 * 2);
+    if (NP <= 32 && g > 0) {
+      const size_t npk = pack_exchange_elems(g, MP4, NP);
+      tot += rnd(npk * 8) + rnd(npk * 4);
+    }
     if (n_det > 1) tot += rnd((g + 1) * mm * 8) + rnd((g + 1) * mm * 4);
   }
   tot += 3 * rnd(std::max<size_t>(g, 1) * 8) + rnd(m * Nt * 8) + rnd(mm * 8) + 2 * rnd(mm * 12);
@@ -795,6 +808,19 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
     }
     if (afq::convert_f64_f32(st, tr->Lt64[s], tr->Lt32[s], (long)nlt) != hipSuccess)
       return bad(AFQMC_ERR_DEVICE, "convert");
+    if (tr->NP[s] <= 32 && G > 0) {
+      const size_t npk = pack_exchange_elems(G, tr->MP4, tr->NP[s]);
+      void *q64, *q32;
+      if (tr->arena.alloc(&q64, npk * 8) || tr->arena.alloc(&q32, npk * 4))
+        return bad(AFQMC_ERR_OOM, "trial allocation failed");
+      tr->Apk64[s] = (double*)q64;
+      tr->Apk32[s] = (float*)q32;
+      if (afq::pack_exchange_a<double>(st, G, tr->MP4, tr->NP[s], tr->Lt64[s], tr->Apk64[s]) !=
+              hipSuccess ||
+          afq::pack_exchange_a<float>(st, G, tr->MP4, tr->NP[s], tr->Lt32[s], tr->Apk32[s]) !=
+              hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "exchange operand repack");
+    }
     {
       void* pb = nullptr;
       const size_t nb = (size_t)G * tr->NP[s] * tr->MP32;

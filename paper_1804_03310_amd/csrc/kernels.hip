@@ -936,15 +936,19 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
   double xx_re = 0.0, xx_im = 0.0;
   T a0[4][NT], a1[4][NT];
   // A operand, four k steps from k step kb of slab q (clamped to the last
-  // slab).  Rows past the slab are the next slab's or the zero rows that
-  // follow the last one; the MFMAs of k steps >= KS are skipped.
-  const T* __restrict__ Llane = Lt + lk * NP + li;
+  // slab), from the repacked copy: a lane's 4 NT values are contiguous, so
+  // they arrive in NT (FP32) or 2 NT (FP64) 128-bit loads
+  const int KB = (KS + 3) / 4;
+  const T* __restrict__ Apl = (const T*)g.Apk + (long)l * 4 * NT;
   auto load_a = [&](T (&a)[4][NT], int q, int kb) {
-    const T* __restrict__ Lq = Llane + (long)(q < G ? q : G - 1) * MP4 * NP + 4 * kb * NP;
+    const v4_t* __restrict__ p =
+        (const v4_t*)(Apl + ((long)(q < G ? q : G - 1) * KB + kb / 4) * 64 * 4 * NT);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int h = 0; h < NT; ++h) {
+      const v4_t v = p[h];
 #pragma unroll
-      for (int I = 0; I < NT; ++I) a[j][I] = Lq[4 * j * NP + 16 * I];
+      for (int e = 0; e < 4; ++e) a[(4 * h + e) / NT][(4 * h + e) % NT] = v[e];
+    }
   };
   // this lane's B elements: row 4 k + lk, columns li and 16 + li
   typedef T bvec_t __attribute__((ext_vector_type(2 * NT)));
@@ -1062,6 +1066,34 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
     exx_im[2 * w + s] = (red[4] + red[5]) + (red[6] + red[7]);
   }
 }
+
+template <typename T>
+__global__ void k_pack_exchange_a(long n, int MP4, int NP, int KB, const T* __restrict__ Lt,
+                                  T* __restrict__ Apk) {
+  const int NT = NP / 16;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int I = (int)(e % NT);
+    const int j = (int)((e / NT) % 4);
+    const int l = (int)((e / (4 * NT)) % 64);
+    const long gkb = e / (4 * NT * 64);
+    const int kb = (int)(gkb % KB);
+    const long g = gkb / KB;
+    const int m = 4 * (4 * kb + j) + (l >> 4), a = 16 * I + (l & 15);
+    Apk[e] = m < MP4 ? Lt[(g * MP4 + m) * NP + a] : (T)0;
+  }
+}
+
+template <typename T>
+hipError_t pack_exchange_a(hipStream_t st, int G, int MP4, int NP, const T* Lt, T* Apk) {
+  const int KB = (MP4 / 4 + 3) / 4;
+  const long n = (long)G * KB * 64 * 4 * (NP / 16);
+  if (n == 0) return hipSuccess;
+  const int blocks = (int)std::min<long>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_pack_exchange_a<T>), dim3(blocks), dim3(256), 0, st, n, MP4, NP, KB, Lt, Apk);
+  return hipGetLastError();
+}
+template hipError_t pack_exchange_a<double>(hipStream_t, int, int, int, const double*, double*);
+template hipError_t pack_exchange_a<float>(hipStream_t, int, int, int, const float*, float*);
 
 template <typename T>
 hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGeom s0, SpinGeom s1,

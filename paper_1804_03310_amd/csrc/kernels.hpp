@@ -14,6 +14,8 @@ struct SpinGeom {
   const double* C;    // [M][M] orbitals, D_0 = columns 0..N-1
   const double* htil; // [N][M] = D_0^T h
   const void* Lt;     // [G][MP4][NP] half-rotated Cholesky, D_0^T L_g, transposed, zero padded
+  const void* Apk;    // NP <= 32: Lt repacked as the exchange kernel's A operand
+                      // [G][KB][64 lanes][4 k steps][NP / 16], KB = ceil(MP4 / 16)
 };
 
 // C[z] = alpha * A[z] B[z]; A(m,k) = A_KMAJ ? A[k*lda+m] : A[m*lda+k], B(k,n) = B[k*ldb+n].
@@ -46,6 +48,13 @@ hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, Spin
                          size_t max_lds);
 
 // Per (walker, spin): X_g = Ltil_g Theta; v[w][s][g] = Tr X_g; exx[w][s] = sum_g Tr(X_g X_g).
+// Repack Lt [G][MP4][NP] (NP = 16 NT <= 32) into the A-operand order of the
+// exchange kernel: for slab g, batch kb of four k steps and lane l = li + 16 lk,
+// the 4 NT values Lt[g][4 (4 kb + j) + lk][16 I + li] (j < 4, I < NT)
+// contiguous; rows past MP4 are zero.
+template <typename T>
+hipError_t pack_exchange_a(hipStream_t st, int G, int MP4, int NP, const T* Lt, T* Apk);
+
 template <typename T>
 hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGeom s0, SpinGeom s1,
                     const double* thr, const double* thi, double* vs_re, double* vs_im,
