@@ -888,7 +888,7 @@ template <> struct Vec4<float> { typedef afq_f4 type; };
 template <> struct Vec4<double> { typedef afq_d4 type; };
 
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, int G, int s_base,
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_exchange_full(int M, int MP4, int Nt, int G, int s_base,
                                                        SpinGeom s0, SpinGeom s1,
                                                        const double* __restrict__ thr,
                                                        const double* __restrict__ thi,
@@ -901,9 +901,16 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
   typedef typename MM::acc_t acc_t;
   typedef typename Vec4<T>::type v4_t;
   constexpr int NPM = 16 * NT;
-  constexpr int LDX = NPM;
-  // X stash column swizzle (identity for 16 columns)
-  auto swx = [](int r, int c) { return NT == 2 ? (c ^ (((r >> 2) & 1) << 4)) : c; };
+  // X stash: the tiles (I, J) with I >= J, row-major; for NT = 2 rows 0-15
+  // hold only tile (0, 0) (16 wide), rows 16-31 tiles (1, 0) and (1, 1).
+  // Column groups are XOR-swizzled by row group against bank conflicts; a
+  // group of four consecutive columns stays contiguous and 16-byte aligned.
+  constexpr int XS = NT == 2 ? 768 : 256;  // elements per plane
+  auto xaddr = [](int r, int c) {
+    if (NT == 1) return r * 16 + c;
+    return r < 16 ? r * 16 + (c ^ (((r >> 2) & 3) << 2))
+                  : 256 + (r - 16) * 32 + (c ^ (((r >> 2) & 1) << 4));
+  };
   const int w = blockIdx.x, s = s_base + blockIdx.y;
   const SpinGeom g = s ? s1 : s0;
   const int N = g.N, off = g.off;
@@ -921,8 +928,8 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
   // Theta staged as [m][b mod 16][b / 16][re, im]: the 2 NT B values a lane
   // needs for one k step are contiguous (one 128-bit read for NT = 2)
   T* Bc = (T*)lds_raw;
-  T* Xr = Bc + MP4 * 2 * NPM + wv * 2 * NPM * LDX;
-  T* Xi = Xr + NPM * LDX;
+  T* Xr = Bc + MP4 * 2 * NPM + wv * 2 * XS;
+  T* Xi = Xr + XS;
   const long wb = (long)w * M * Nt;
   for (int e = threadIdx.x; e < MP4 * NPM; e += blockDim.x) {
     const int m = e / NPM, b = e % NPM;
@@ -985,43 +992,48 @@ __global__ __launch_bounds__(256) void k_exchange_full(int M, int MP4, int Nt, i
 #pragma unroll
         for (int I = 0; I < NT; ++I) a0[j][I] = a1[j][I];
     }
-    // stash X row-major: lane (li, lk) holds X[16I + row(lk, v)][16J + li]
+    // stash X row-major: lane (li, lk) holds X[16I + row(lk, v)][16J + li].
+    // Tr(XX) sums X_ab X_ba over all (a, b); the tile block (I, J), I < J,
+    // gives the same sum as (J, I), so only tiles with I >= J are read as
+    // partners and only tiles with I <= J are paired (twice for I < J).
 #pragma unroll
     for (int I = 0; I < NT; ++I)
 #pragma unroll
       for (int J = 0; J < NT; ++J)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          if (I < J) continue;
           const int r = 16 * I + MM::row(lk, v), c = 16 * J + li;
-          Xr[r * LDX + swx(r, c)] = cr[I][J][v];
-          Xi[r * LDX + swx(r, c)] = ci[I][J][v];
+          Xr[xaddr(r, c)] = cr[I][J][v];
+          Xi[xaddr(r, c)] = ci[I][J][v];
         }
     wave_lds_sync();
     T pxr = (T)0, pxi = (T)0, ptr = (T)0, pti = (T)0;
 #pragma unroll
     for (int I = 0; I < NT; ++I)
 #pragma unroll
-      for (int J = 0; J < NT; ++J) {
+      for (int J = I; J < NT; ++J) {
         // partners X_ba, b = 16J + li, a = 16I + row(lk, v): for the f32 layout the
         // four a of a lane are consecutive, so one 128-bit read per tile
         T yr[4], yi[4];
         const int rb = 16 * J + li;
         if (MM::row(0, 1) == 1) {
-          const int c0 = swx(rb, 16 * I + MM::row(lk, 0));
-          const v4_t vr = *(const v4_t*)&Xr[rb * LDX + c0];
-          const v4_t vi = *(const v4_t*)&Xi[rb * LDX + c0];
+          const int x0 = xaddr(rb, 16 * I + MM::row(lk, 0));
+          const v4_t vr = *(const v4_t*)&Xr[x0];
+          const v4_t vi = *(const v4_t*)&Xi[x0];
 #pragma unroll
           for (int v = 0; v < 4; ++v) { yr[v] = vr[v]; yi[v] = vi[v]; }
         } else {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            yr[v] = Xr[rb * LDX + swx(rb, 16 * I + MM::row(lk, v))];
-            yi[v] = Xi[rb * LDX + swx(rb, 16 * I + MM::row(lk, v))];
+            yr[v] = Xr[xaddr(rb, 16 * I + MM::row(lk, v))];
+            yi[v] = Xi[xaddr(rb, 16 * I + MM::row(lk, v))];
           }
         }
+        const T f = (I == J) ? (T)1 : (T)2;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const T xr = cr[I][J][v], xi = ci[I][J][v];
+          const T xr = f * cr[I][J][v], xi = f * ci[I][J][v];
           pxr += xr * yr[v] - xi * yi[v];
           pxi += xr * yi[v] + xi * yr[v];
           if (MM::row(0, 1) != 1 && I == J && MM::row(lk, v) == li) { ptr += xr; pti += xi; }
@@ -1103,8 +1115,11 @@ hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGe
   if (NP <= 32) {
     // one launch per distinct padded width (both spins in one launch when
     // they agree); the kernel's tile count must equal the spin's NP / 16
-    // Theta (re, im) [MP4][NPM] plus four waves' X stash (re, im) [NPM][NPM]
-    auto lds_of = [&](int npm) { return (size_t)(2 * MP4 * npm + 4 * 2 * npm * npm) * sizeof(T); };
+    // Theta (re, im) [MP4][NPM] plus four waves' X stash (re, im), three
+    // 16x16 tiles for NPM = 32 and one for NPM = 16
+    auto lds_of = [&](int npm) {
+      return (size_t)(2 * MP4 * npm + 4 * 2 * (npm == 32 ? 768 : 256)) * sizeof(T);
+    };
     const size_t ld32 = lds_of(32), ld16 = lds_of(16);
     if (ld32 <= max_lds) {
       auto launch = [&](int npm, int s_base, int ny) {
