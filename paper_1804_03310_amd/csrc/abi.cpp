@@ -316,7 +316,7 @@ afqmc_status check_walkers(const afqmc_trial* tr, const afqmc_walkers* wk) {
   return AFQMC_OK;
 }
 
-// Elements of the exchange kernel's repacked A operand for one spin (NP <= 32).
+// Elements of the exchange kernels' repacked A operand for one spin (NP <= 64).
 size_t pack_exchange_elems(size_t G, size_t MP4, size_t NP) {
   const size_t KB = (MP4 / 4 + 3) / 4;
   return G * KB * 64 * 4 * (NP / 16);
@@ -423,7 +423,8 @@ afqmc_status orthonormalize_impl(afqmc_trial* tr, afqmc_walkers* wk, const WS& w
   const int W = wk->n_walkers;
   {
     TimedLaunch tl(&hm->timer, KC_MGS, st);
-    AFQ_CK(afq::mgs(st, W, hm->M, tr->Nt, tr->nel[0], tr->nel[1], wk->phi_re, wk->phi_im));
+    AFQ_CK(afq::mgs(st, W, hm->M, tr->Nt, tr->nel[0], tr->nel[1], wk->phi_re, wk->phi_im,
+                    hm->max_lds));
   }
   const afq::SpinGeom s0 = spin_geom(tr, 0, AFQMC_FP64), s1 = spin_geom(tr, 1, AFQMC_FP64);
   AFQ_CK(afq::overlap_theta(st, W, hm->M, tr->Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re,
@@ -693,6 +694,8 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
     if (NP <= 32 && g > 0) {
       const size_t npk = pack_exchange_elems(g, MP4, NP);
       tot += rnd(npk * 8) + rnd(npk * 4);
+    } else if (NP <= 64 && g > 0) {
+      tot += rnd(pack_exchange_elems(g, MP4, NP) * 4);
     }
     if (n_det > 1) tot += rnd((g + 1) * mm * 8) + rnd((g + 1) * mm * 4);
   }
@@ -819,6 +822,15 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
               hipSuccess ||
           afq::pack_exchange_a<float>(st, G, tr->MP4, tr->NP[s], tr->Lt32[s], tr->Apk32[s]) !=
               hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "exchange operand repack");
+    } else if (tr->NP[s] <= 64 && G > 0) {
+      // FP32 only: the wide exchange kernel's layout (one row tile per wavefront)
+      const size_t npk = pack_exchange_elems(G, tr->MP4, tr->NP[s]);
+      void* q32;
+      if (tr->arena.alloc(&q32, npk * 4)) return bad(AFQMC_ERR_OOM, "trial allocation failed");
+      tr->Apk32[s] = (float*)q32;
+      if (afq::pack_exchange_a<float>(st, G, tr->MP4, tr->NP[s], tr->Lt32[s], tr->Apk32[s]) !=
+          hipSuccess)
         return bad(AFQMC_ERR_DEVICE, "exchange operand repack");
     }
     {

@@ -1079,6 +1079,22 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_exchange_full(i
   }
 }
 
+// Repack Lt for k_exchange_wide: [g][I][kb][lane][4 k steps], rows past MP4 zero.
+template <typename T>
+__global__ void k_pack_exchange_a_wide(long n, int MP4, int NP, int KB, const T* __restrict__ Lt,
+                                       T* __restrict__ Apk) {
+  const int NT = NP / 16;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e % 4);
+    const int l = (int)((e / 4) % 64);
+    const int kb = (int)((e / 256) % KB);
+    const int I = (int)((e / (256L * KB)) % NT);
+    const long g = e / (256L * KB * NT);
+    const int m = 4 * (4 * kb + j) + (l >> 4), a = 16 * I + (l & 15);
+    Apk[e] = m < MP4 ? Lt[(g * MP4 + m) * NP + a] : (T)0;
+  }
+}
+
 template <typename T>
 __global__ void k_pack_exchange_a(long n, int MP4, int NP, int KB, const T* __restrict__ Lt,
                                   T* __restrict__ Apk) {
@@ -1101,11 +1117,187 @@ hipError_t pack_exchange_a(hipStream_t st, int G, int MP4, int NP, const T* Lt, 
   const long n = (long)G * KB * 64 * 4 * (NP / 16);
   if (n == 0) return hipSuccess;
   const int blocks = (int)std::min<long>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL((k_pack_exchange_a<T>), dim3(blocks), dim3(256), 0, st, n, MP4, NP, KB, Lt, Apk);
+  if (NP <= 32)
+    hipLaunchKernelGGL((k_pack_exchange_a<T>), dim3(blocks), dim3(256), 0, st, n, MP4, NP, KB, Lt, Apk);
+  else
+    hipLaunchKernelGGL((k_pack_exchange_a_wide<T>), dim3(blocks), dim3(256), 0, st, n, MP4, NP, KB, Lt,
+                       Apk);
   return hipGetLastError();
 }
 template hipError_t pack_exchange_a<double>(hipStream_t, int, int, int, const double*, double*);
 template hipError_t pack_exchange_a<float>(hipStream_t, int, int, int, const float*, float*);
+
+// Exchange kernel for 32 < N <= 16 NT (NT = 3, 4), FP32: one walker and spin
+// per block of two groups of NT wavefronts; a group takes every other
+// Cholesky index and wavefront I of the group computes the row tile I of X_g
+// (NT tiles of 16x16, re and im), so its A operand is one value per k step
+// (from the repacked copy [g][I][kb][lane][4]) and its B operand the 2 NT
+// staged Theta values of the k step.  Tr(XX) pairs the tiles (I, J), J >= I,
+// with the stashed tile (J, I) (twice for J > I); each wavefront stashes its
+// tiles (I, J), J <= I, and the diagonal trace of tile (I, I) for the group's
+// sum.  Two block barriers per pair of Cholesky indices.
+template <int NT>
+__global__ __launch_bounds__(128 * NT) void k_exchange_wide(int M, int MP4, int Nt, int G,
+                                                            int s_base, SpinGeom s0, SpinGeom s1,
+                                                            const double* __restrict__ thr,
+                                                            const double* __restrict__ thi,
+                                                            double* __restrict__ vs_re,
+                                                            double* __restrict__ vs_im,
+                                                            double* exx_re, double* exx_im) {
+  typedef Mfma<float> MM;
+  typedef MM::acc_t acc_t;
+  constexpr int NPM = 16 * NT, NTRI = NT * (NT + 1) / 2, NW = 2 * NT;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  __shared__ double red[2 * NW];
+  __shared__ float trs[2][2][NT];
+  const int w = blockIdx.x, s = s_base + blockIdx.y;
+  const SpinGeom g = s ? s1 : s0;
+  const int N = g.N, off = g.off;
+  const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
+  const int grp = wv / NT, I = wv % NT;
+  if (N == 0) {
+    for (int q = threadIdx.x; q < G; q += blockDim.x) {
+      vs_re[((long)w * 2 + s) * G + q] = 0.0;
+      vs_im[((long)w * 2 + s) * G + q] = 0.0;
+    }
+    if (threadIdx.x == 0) { exx_re[2 * w + s] = 0.0; exx_im[2 * w + s] = 0.0; }
+    return;
+  }
+  // Theta as [m][b mod 16][b / 16][re, im]; per group a stash of the NTRI
+  // tiles (r, c), r >= c, each 16x16 row-major with column groups swizzled
+  float* Bc = (float*)lds_raw;
+  float* Xr = Bc + MP4 * 2 * NPM + grp * 2 * NTRI * 256;
+  float* Xi = Xr + NTRI * 256;
+  const long wb = (long)w * M * Nt;
+  for (int e = threadIdx.x; e < MP4 * NPM; e += blockDim.x) {
+    const int m = e / NPM, b = e % NPM;
+    const bool ok = m < M && b < N;
+    float* d = Bc + ((m * 16 + (b & 15)) * NT + (b >> 4)) * 2;
+    d[0] = ok ? (float)thr[wb + (long)m * Nt + off + b] : 0.f;
+    d[1] = ok ? (float)thi[wb + (long)m * Nt + off + b] : 0.f;
+  }
+  __syncthreads();
+  auto tile = [](int tr, int tc) { return (tr * (tr + 1) / 2 + tc) * 256; };
+  auto xsw = [](int r, int c) { return r * 16 + (c ^ (((r >> 2) & 3) << 2)); };
+  const int KS = MP4 / 4, KB = (KS + 3) / 4;
+  const float* __restrict__ Apl = (const float*)g.Apk + (long)l * 4;
+  auto load_a = [&](float (&a)[4], int q, int kb) {
+    const afq_f4 v =
+        *(const afq_f4*)(Apl + ((((long)(q < G ? q : G - 1) * NT + I) * KB + kb / 4) * 64) * 4);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[j] = v[j];
+  };
+  const float* __restrict__ Bl = Bc + (lk * 16 + li) * 2 * NT;
+  double xx_re = 0.0, xx_im = 0.0;
+  float a0[4], a1[4];
+  load_a(a0, grp, 0);
+  for (int q0 = 0; q0 < G; q0 += 2) {
+    const int q = q0 + grp;
+    const bool act = q < G;  // uniform over the group; idle groups still meet the barriers
+    acc_t cr[NT], ci[NT];
+#pragma unroll
+    for (int J = 0; J < NT; ++J) { cr[J] = MM::zero(); ci[J] = MM::zero(); }
+    if (act) {
+      for (int kb = 0; kb < KS; kb += 4) {
+        if (kb + 4 < KS) load_a(a1, q, kb + 4);
+        else load_a(a1, q + 2, 0);  // first batch of this group's next g
+        float bq[4][2 * NT];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (kb + j < KS) {
+            const float* p = Bl + 4 * (kb + j) * 16 * 2 * NT;
+#pragma unroll
+            for (int h = 0; h < NT / 2; ++h) {
+              const afq_f4 v = *(const afq_f4*)(p + 4 * h);
+              bq[j][4 * h] = v[0]; bq[j][4 * h + 1] = v[1];
+              bq[j][4 * h + 2] = v[2]; bq[j][4 * h + 3] = v[3];
+            }
+            if (NT & 1) {
+              const float2 v = *(const float2*)(p + 2 * NT - 2);
+              bq[j][2 * NT - 2] = v.x; bq[j][2 * NT - 1] = v.y;
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (kb + j < KS) {
+#pragma unroll
+            for (int J = 0; J < NT; ++J) {
+              cr[J] = MM::mma(a0[j], bq[j][2 * J], cr[J]);
+              ci[J] = MM::mma(a0[j], bq[j][2 * J + 1], ci[J]);
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a0[j] = a1[j];
+      }
+      // stash tiles (I, J), J <= I: lane (li, lk) holds rows 4 lk + v, column li
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+        if (J <= I) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Xr[tile(I, J) + xsw(4 * lk + v, li)] = cr[J][v];
+            Xi[tile(I, J) + xsw(4 * lk + v, li)] = ci[J][v];
+          }
+        }
+      }
+      // diagonal of tile (I, I): element li & 3 in the lanes diag16_sum reads
+      float dr = 0.f, di = 0.f;
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool hit = (J == I) && (v == (li & 3));
+          dr = hit ? cr[J][v] : dr;
+          di = hit ? ci[J][v] : di;
+        }
+      }
+      const float tr = diag16_sum(dr), ti = diag16_sum(di);
+      if (l == 0) { trs[grp][0][I] = tr; trs[grp][1][I] = ti; }
+    }
+    __syncthreads();
+    if (act) {
+      float pxr = 0.f, pxi = 0.f;
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+        if (J >= I) {
+          // partner X_ba: row 16 J + li, columns 16 I + 4 lk + v = tile (J, I),
+          // local row li, columns 4 lk .. 4 lk + 3
+          const int x0 = tile(J, I) + xsw(li, 4 * lk);
+          const afq_f4 yr = *(const afq_f4*)&Xr[x0];
+          const afq_f4 yi = *(const afq_f4*)&Xi[x0];
+          const float f = (J == I) ? 1.f : 2.f;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float xr = f * cr[J][v], xi = f * ci[J][v];
+            pxr += xr * yr[v] - xi * yi[v];
+            pxi += xr * yi[v] + xi * yr[v];
+          }
+        }
+      }
+      xx_re += (double)pxr;
+      xx_im += (double)pxi;
+      if (I == 0 && l == 0) {
+        double sr = 0.0, si = 0.0;
+        for (int t = 0; t < NT; ++t) { sr += (double)trs[grp][0][t]; si += (double)trs[grp][1][t]; }
+        vs_re[((long)w * 2 + s) * G + q] = sr;
+        vs_im[((long)w * 2 + s) * G + q] = si;
+      }
+    }
+    __syncthreads();
+  }
+  xx_re = wave_sum(xx_re);
+  xx_im = wave_sum(xx_im);
+  if (l == 0) { red[wv] = xx_re; red[NW + wv] = xx_im; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sr = 0.0, si = 0.0;
+    for (int t = 0; t < NW; ++t) { sr += red[t]; si += red[NW + t]; }
+    exx_re[2 * w + s] = sr;
+    exx_im[2 * w + s] = si;
+  }
+}
 
 template <typename T>
 hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGeom s0, SpinGeom s1,
@@ -1128,6 +1320,30 @@ hipError_t exchange(hipStream_t st, int W, int M, int MP4, int Nt, int G, SpinGe
                              G, s_base, s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
         else
           hipLaunchKernelGGL((k_exchange_full<T, 2>), dim3(W, ny), dim3(256), ld32, st, M, MP4, Nt,
+                             G, s_base, s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
+      };
+      if (s0.NP == s1.NP) {
+        launch(s0.NP, 0, 2);
+      } else {
+        launch(s0.NP, 0, 1);
+        launch(s1.NP, 1, 1);
+      }
+      return hipGetLastError();
+    }
+  }
+  if (sizeof(T) == 4 && NP <= 64 && s0.NP > 32 && s1.NP > 32) {
+    // Theta (re, im) [MP4][NP] plus two groups' stashes of NT (NT + 1) / 2 tiles
+    auto lds_w = [&](int np) {
+      const int nt = np / 16;
+      return (size_t)(2 * MP4 * np + 2 * 2 * (nt * (nt + 1) / 2) * 256) * sizeof(float);
+    };
+    if (lds_w(NP) <= max_lds) {
+      auto launch = [&](int np, int s_base, int ny) {
+        if (np == 48)
+          hipLaunchKernelGGL((k_exchange_wide<3>), dim3(W, ny), dim3(384), lds_w(48), st, M, MP4, Nt,
+                             G, s_base, s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
+        else
+          hipLaunchKernelGGL((k_exchange_wide<4>), dim3(W, ny), dim3(512), lds_w(64), st, M, MP4, Nt,
                              G, s_base, s0, s1, thr, thi, vs_re, vs_im, exx_re, exx_im);
       };
       if (s0.NP == s1.NP) {
@@ -1326,8 +1542,9 @@ hipError_t mixed_energy(hipStream_t st, int W, const double* weight, const doubl
 // ===========================================================================
 // Modified Gram-Schmidt per (walker, spin), FP64 (Sec. IV.A: periodic
 // orthonormalisation of walker orbitals).  The spin block is staged in LDS
-// when it fits (STAGE) and written back at the end; otherwise it is updated
-// in place in global memory.
+// when it fits in the block's LDS (STAGE; up to 160 KB on gfx950, e.g. 200
+// orbitals x 50 electrons) and written back at the end; otherwise it is
+// updated in place in global memory.
 // ===========================================================================
 template <bool STAGE>
 __global__ __launch_bounds__(256) void k_mgs(int M, int Nt, int n_up, int n_dn,
@@ -1390,10 +1607,11 @@ __global__ __launch_bounds__(256) void k_mgs(int M, int Nt, int n_up, int n_dn,
   }
 }
 
-hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double* phr, double* phi) {
+hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double* phr, double* phi,
+               size_t max_lds) {
   const int N = n_up > n_dn ? n_up : n_dn;
   const size_t lds = (size_t)2 * M * N * sizeof(double);
-  if (lds <= 65536)
+  if (lds <= max_lds)
     hipLaunchKernelGGL(k_mgs<true>, dim3(W, 2), dim3(256), lds, st, M, Nt, n_up, n_dn, phr, phi);
   else
     hipLaunchKernelGGL(k_mgs<false>, dim3(W, 2), dim3(256), 0, st, M, Nt, n_up, n_dn, phr, phi);

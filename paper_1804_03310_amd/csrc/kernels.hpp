@@ -14,8 +14,9 @@ struct SpinGeom {
   const double* C;    // [M][M] orbitals, D_0 = columns 0..N-1
   const double* htil; // [N][M] = D_0^T h
   const void* Lt;     // [G][MP4][NP] half-rotated Cholesky, D_0^T L_g, transposed, zero padded
-  const void* Apk;    // NP <= 32: Lt repacked as the exchange kernel's A operand
-                      // [G][KB][64 lanes][4 k steps][NP / 16], KB = ceil(MP4 / 16)
+  const void* Apk;    // Lt repacked as the exchange kernels' A operand, KB = ceil(MP4 / 16):
+                      // NP <= 32: [G][KB][64 lanes][4 k steps][NP / 16] (FP64 and FP32);
+                      // 32 < NP <= 64: [G][NP / 16][KB][64 lanes][4 k steps] (FP32)
 };
 
 // C[z] = alpha * A[z] B[z]; A(m,k) = A_KMAJ ? A[k*lda+m] : A[m*lda+k], B(k,n) = B[k*ldb+n].
@@ -48,10 +49,11 @@ hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, Spin
                          size_t max_lds);
 
 // Per (walker, spin): X_g = Ltil_g Theta; v[w][s][g] = Tr X_g; exx[w][s] = sum_g Tr(X_g X_g).
-// Repack Lt [G][MP4][NP] (NP = 16 NT <= 32) into the A-operand order of the
-// exchange kernel: for slab g, batch kb of four k steps and lane l = li + 16 lk,
-// the 4 NT values Lt[g][4 (4 kb + j) + lk][16 I + li] (j < 4, I < NT)
-// contiguous; rows past MP4 are zero.
+// Repack Lt [G][MP4][NP] (NP = 16 NT) into the A-operand order of the
+// exchange kernels: for slab g, batch kb of four k steps and lane
+// l = li + 16 lk, the values Lt[g][4 (4 kb + j) + lk][16 I + li] (j < 4,
+// I < NT) with j and I innermost for NP <= 32 and I outermost (after g) for
+// 32 < NP <= 64; rows past MP4 are zero.
 template <typename T>
 hipError_t pack_exchange_a(hipStream_t st, int G, int MP4, int NP, const T* Lt, T* Apk);
 
@@ -86,7 +88,8 @@ hipError_t mixed_energy(hipStream_t st, int W, const double* weight, const doubl
                         double* emix_out, double* den_out);
 
 // Modified Gram-Schmidt of both spin blocks of every walker, in place.
-hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double* phr, double* phi);
+hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double* phr, double* phi,
+               size_t max_lds);
 
 // Comb: parents and norm factor (single thread, left-to-right sums).
 hipError_t comb_parents(hipStream_t st, int W, const double* weight, uint64_t seed,

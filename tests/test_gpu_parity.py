@@ -79,7 +79,8 @@ def test_local_energy_at_trial_equals_oracle(afq):
 
 @pytest.mark.parametrize("M,n_up,n_dn,G,W", [(10, 5, 5, 40, 16), (23, 7, 4, 37, 9),
                                                (50, 25, 25, 250, 6), (40, 17, 0, 30, 5),
-                                               (29, 20, 9, 33, 7), (70, 31, 32, 41, 3)])
+                                               (29, 20, 9, 33, 7), (70, 31, 32, 41, 3),
+                                               (70, 40, 33, 23, 3)])
 def test_local_energy_random_walkers_fp64(afq, M, n_up, n_dn, G, W):
     _say(f"local energy random walkers M={M} N={n_up}/{n_dn} G={G} W={W}")
     inp = syn.make_system(M, n_up, n_dn, G, 8.0, seed=M + G, e_core=0.75)
@@ -99,7 +100,9 @@ def test_local_energy_random_walkers_fp64(afq, M, n_up, n_dn, G, W):
 
 
 @pytest.mark.parametrize("M,n_up,n_dn,G,W", [(23, 7, 4, 37, 9), (29, 20, 9, 33, 7),
-                                               (50, 25, 25, 250, 6), (40, 17, 0, 30, 5)])
+                                               (50, 25, 25, 250, 6), (40, 17, 0, 30, 5),
+                                               (70, 40, 33, 23, 3), (90, 50, 64, 19, 2),
+                                               (80, 40, 20, 21, 3), (75, 49, 0, 17, 2)])
 def test_local_energy_random_walkers_fp32(afq, M, n_up, n_dn, G, W):
     """FP32 contractions (reached through a zero-step propagate, which
     refreshes E_L with the step's precision): relative 1e-5.  The walkers
