@@ -104,6 +104,94 @@ def accuracy_check(afq, torch, wl, inp, ham, trial, opt_kw):
             "reference": "FP64 oracle sums stored in tests/golden/" + fname}
 
 
+def serving_bench(args):
+    """Mixed request stream through the serving loop (paper_1804_03310_amd.serving):
+    Poisson arrivals at 20 requests/s, M uniform over {20, 40, 80, 120, 160}
+    with N = M/4 electrons per spin and 5M Cholesky vectors (health-scaled
+    tau_d = 50 generator), W uniform over {128, 512, 2048}, FP32 contractions,
+    comb every 20 steps; half the requests are neutral/cation correlated-sampling
+    pairs (cation: one down electron fewer) sharing the Hamiltonian, field seed
+    and system id, without population control.  Two distinct systems per M.
+    Reports walker-steps/s over the whole stream, p50/p99 arrival-to-result
+    latency, and whether a few requests rerun alone reproduce their mixed
+    results bitwise."""
+    import torch
+
+    import afqmc_synth as syn
+    from paper_1804_03310_amd.serving import Request, Server
+
+    rng = np.random.default_rng(args.serve_seed)
+    n = args.requests
+    systems = {}
+
+    def system(M, k):
+        if (M, k) not in systems:
+            systems[(M, k)] = syn.make_system(M, M // 4, M // 4, 5 * M, 50.0, seed=1000 * M + k,
+                                              l_scale=syn.health_scale(M))
+        return systems[(M, k)]
+
+    gaps = rng.exponential(1.0 / args.rate, n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    reqs = []
+    i = 0
+    sys_id = 0
+    while i < n:
+        M = int(rng.choice([20, 40, 80, 120, 160]))
+        W = int(rng.choice([128, 512, 2048]))
+        inp = system(M, int(rng.integers(2)))
+        pair = (i + 1 < n) and (i % 4 < 2)  # half of the requests, in pairs
+        seed = int(rng.integers(1 << 30))
+        base = dict(h=inp.h, L=inp.L, e_core=0.0, C_up=inp.C_up, C_dn=inp.C_dn, n_walkers=W,
+                    n_steps=args.serve_steps, dt=0.005, seed=seed, chol_prec="fp32",
+                    taylor_prec="fp32", ortho_every=2)
+        if pair:
+            sys_id += 1
+            for n_dn in (inp.n_dn, inp.n_dn - 1):
+                reqs.append(Request(n_up=inp.n_up, n_dn=n_dn, system_id=sys_id, pc_every=0,
+                                    arrival=float(arrivals[i]), tag=("pair", sys_id, n_dn), **base))
+                i += 1
+        else:
+            reqs.append(Request(n_up=inp.n_up, n_dn=inp.n_dn, system_id=0, pc_every=20,
+                                arrival=float(arrivals[i]), tag=("single", i), **base))
+            i += 1
+    torch.cuda.set_device(0)
+    srv = Server(args.serve_budget_gb << 30, max_active=args.serve_slots,
+                 chunk_steps=args.serve_chunk)
+    ids = [srv.submit(r) for r in reqs]
+    t0 = time.perf_counter()
+    srv.run()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    res = [srv.poll(k) for k in ids]
+    # alone vs mix: the first pair's two members and the largest single request
+    check = [k for k, r in enumerate(reqs) if r.tag[0] == "pair"][:2]
+    singles = [k for k, r in enumerate(reqs) if r.tag[0] == "single"]
+    if singles:
+        check.append(max(singles, key=lambda k: reqs[k].M * reqs[k].n_walkers))
+    same = True
+    for k in check:
+        r = reqs[k]
+        r1 = Request(**{f: getattr(r, f) for f in r.__dataclass_fields__})
+        r1.arrival = 0.0
+        s1 = Server(args.serve_budget_gb << 30, max_active=1, chunk_steps=args.serve_chunk)
+        rid = s1.submit(r1)
+        s1.run()
+        same = same and res[k] is not None and np.array_equal(s1.poll(rid).emix, res[k].emix)
+    ws = sum(r.n_walkers * r.n_steps for r, x in zip(reqs, res) if x is not None and x.error is None)
+    out = {"metric": "serving: walker-steps/s over a mixed request stream; p50/p99 arrival-to-result latency",
+           "value": ws / wall, "unit": "walker-steps/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "serving-mix", "requests": n, "rate_per_s": args.rate,
+                      "steps_per_request": args.serve_steps, "M": [20, 40, 80, 120, 160],
+                      "walkers": [128, 512, 2048], "cs_pairs": sum(1 for r in reqs if r.tag[0] == "pair") // 2,
+                      "budget_gib": args.serve_budget_gb, "max_active": args.serve_slots,
+                      "chunk_steps": args.serve_chunk},
+           "wall_s": wall, "completed": st.get("completed"), "rejected": st.get("rejected"),
+           "p50_s": st.get("p50_s"), "p99_s": st.get("p99_s"), "peak_bytes": st.get("peak_bytes"),
+           "alone_vs_mix_bitwise": bool(same), "alone_vs_mix_checked": len(check)}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(wl, inp, sample_walkers, sample_steps):
     from oracle import Oracle, Options as OOptions
     try:
@@ -140,6 +228,15 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--tte-repeats", type=int, default=5)
     ap.add_argument("--tte-steps", type=int, default=50)
+    ap.add_argument("--serving", action="store_true",
+                    help="run the mixed request stream through the serving loop instead")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--serve-steps", type=int, default=50)
+    ap.add_argument("--serve-seed", type=int, default=0)
+    ap.add_argument("--serve-budget-gb", type=int, default=64)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-chunk", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise copy of 256 MiB (reads 256 MiB, writes "
                          "256 MiB) so that HBM byte counters can be scaled")
@@ -149,6 +246,10 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(walker sharding is described in DESIGN.md but not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.serving:
+        serving_bench(args)
+        return
 
     import torch
 

@@ -141,33 +141,32 @@ struct MdLds {
 };
 
 // t^1 and t^2 coefficients of det(Ghat[occ] + t P[occ]) for one determinant
-// and spin (relative to det A), from the reference quantities in LDS.
-template <typename T>
-__device__ inline void md_det_coeffs(int N, int Nmax, int E, const int* hole, const int* part,
-                                     const T* gr, const T* gi, const T* pr, const T* pi,
-                                     const double* x2r, const double* x2i, Cx trx0, Cx trx2,
-                                     Cx& c1, Cx& c2) {
+// and spin (relative to det A), from the reference quantities in LDS.  E (the
+// excitation rank, 1 or 2) is a template parameter so that every small E x E
+// array lives in registers; holes (h0, h1) and particles (v0, v1).
+template <int E, typename T>
+__device__ inline void md_det_coeffs_e(int N, int Nmax, int h0, int h1, int v0, int v1,
+                                       const T* gr, const T* gi, const T* pr, const T* pi,
+                                       const double* x2r, const double* x2i, Cx trx0, Cx trx2,
+                                       Cx& c1, Cx& c2) {
   const Cx e2 = 0.5 * (trx0 * trx0 - trx2);
-  if (E == 0) {
-    c1 = trx0;
-    c2 = e2;
-    return;
-  }
+  const int hole[2] = {h0, h1}, part[2] = {v0, v1};
   auto X0 = [&](int a, int b) { return cx((double)pr[a * Nmax + b], (double)pi[a * Nmax + b]); };
   auto X2 = [&](int a, int b) { return cx(x2r[a * Nmax + b], x2i[a * Nmax + b]); };
   auto Gv = [&](int v, int c) { return cx((double)gr[v * N + c], (double)gi[v * N + c]); };
-  auto Pv = [&](int v, int c) { return X0(v, c); };
   Cx S0[2][2], Q[2][2], GX[2][2], PX[2][2], GXX[2][2], XR[2][2], X2R[2][2];
+#pragma unroll
   for (int e = 0; e < E; ++e)
+#pragma unroll
     for (int f = 0; f < E; ++f) {
       const int v = part[e], r = hole[f];
       S0[e][f] = Gv(v, r);
-      Q[e][f] = Pv(v, r);
+      Q[e][f] = X0(v, r);
       Cx gx = cx(0, 0), px = cx(0, 0), gxx = cx(0, 0);
       for (int c = 0; c < N; ++c) {
-        const Cx g = Gv(v, c), pc = Pv(v, c);
-        gx = gx + g * X0(c, r);
-        px = px + pc * X0(c, r);
+        const Cx g = Gv(v, c), pc = X0(v, c), xcr = X0(c, r);
+        gx = gx + g * xcr;
+        px = px + pc * xcr;
         gxx = gxx + g * X2(c, r);
       }
       GX[e][f] = gx;
@@ -177,9 +176,12 @@ __device__ inline void md_det_coeffs(int N, int Nmax, int E, const int* hole, co
       X2R[e][f] = X2(hole[e], r);
     }
   Cx S1[2][2], S2[2][2];
+#pragma unroll
   for (int e = 0; e < E; ++e)
+#pragma unroll
     for (int f = 0; f < E; ++f) {
-      Cx bq = GX[e][f], qq = PX[e][f], gxx = GXX[e][f] ;
+      Cx bq = GX[e][f], qq = PX[e][f], gxx = GXX[e][f];
+#pragma unroll
       for (int g = 0; g < E; ++g) {
         bq = bq - S0[e][g] * XR[g][f];
         qq = qq - Q[e][g] * XR[g][f];
@@ -188,14 +190,17 @@ __device__ inline void md_det_coeffs(int N, int Nmax, int E, const int* hole, co
       S1[e][f] = Q[e][f] - bq;
       Cx bqq = gxx;
       // U_R X0[R,R] with U_R = bq (row e)
+#pragma unroll
       for (int g = 0; g < E; ++g) {
         Cx ueg = GX[e][g];
+#pragma unroll
         for (int h = 0; h < E; ++h) ueg = ueg - S0[e][h] * XR[h][g];
         bqq = bqq - ueg * XR[g][f];
       }
       S2[e][f] = bqq - qq;
     }
   Cx t1 = trx0, touch = cx(0, 0);
+#pragma unroll
   for (int e = 0; e < E; ++e) {
     t1 = t1 - XR[e][e];
     touch = touch + (XR[e][e] * trx0 - X2R[e][e]);
@@ -214,6 +219,21 @@ __device__ inline void md_det_coeffs(int N, int Nmax, int E, const int* hole, co
   }
   c1 = d1 + t1 * d0;
   c2 = d2 + t1 * d1 + t2 * d0;
+}
+
+template <typename T>
+__device__ inline void md_det_coeffs(int N, int Nmax, int E, int h0, int h1, int v0, int v1,
+                                     const T* gr, const T* gi, const T* pr, const T* pi,
+                                     const double* x2r, const double* x2i, Cx trx0, Cx trx2,
+                                     Cx& c1, Cx& c2) {
+  if (E == 0) {
+    c1 = trx0;
+    c2 = 0.5 * (trx0 * trx0 - trx2);
+  } else if (E == 1) {
+    md_det_coeffs_e<1>(N, Nmax, h0, h1, v0, v1, gr, gi, pr, pi, x2r, x2i, trx0, trx2, c1, c2);
+  } else {
+    md_det_coeffs_e<2>(N, Nmax, h0, h1, v0, v1, gr, gi, pr, pi, x2r, x2i, trx0, trx2, c1, c2);
+  }
 }
 
 template <typename T, int DPT>
@@ -298,8 +318,8 @@ __global__ __launch_bounds__(256) void k_md_energy(MDParams p, int Nmax, int NPm
       if (N == 0) {
 #pragma unroll
         for (int k = 0; k < DPT; ++k) {
-          c1[k][s] = cx(0, 0);
-          c2[k][s] = cx(0, 0);
+          if (s) { c1[k][1] = cx(0, 0); c2[k][1] = cx(0, 0); }
+          else { c1[k][0] = cx(0, 0); c2[k][0] = cx(0, 0); }
         }
         continue;
       }
@@ -310,13 +330,27 @@ __global__ __launch_bounds__(256) void k_md_energy(MDParams p, int Nmax, int NPm
         const int rt = t / CT, ct = t % CT;
         acc_t ar = MM::zero(), ai = MM::zero();
         const int prow = 16 * rt + li;
-        for (int k0 = 0; k0 < MP4; k0 += 4) {
-          const int m = k0 + lk;
-          const T a = (m < M && prow < M) ? A[(long)m * M + prow] : (T)0;
-          const T br = tb[s][m * NPmax + 16 * ct + li];
-          const T bi = tb[s][MP4 * NPmax + m * NPmax + 16 * ct + li];
-          ar = MM::mma(a, br, ar);
-          ai = MM::mma(a, bi, ai);
+        // A (L_g C, L2 or memory resident) in batches of eight k steps, all
+        // eight loads in flight before the first MFMA of the batch
+        const int KSt = MP4 / 4;
+        for (int kb = 0; kb < KSt; kb += 8) {
+          T a[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int m = 4 * (kb + j) + lk;
+            a[j] = (kb + j < KSt && m < M && prow < M) ? A[(long)m * M + prow] : (T)0;
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (kb + j < KSt) {
+              const int m = 4 * (kb + j) + lk;
+              const T* tbs = s ? tb[1] : tb[0];
+              const T br = tbs[m * NPmax + 16 * ct + li];
+              const T bi = tbs[MP4 * NPmax + m * NPmax + 16 * ct + li];
+              ar = MM::mma(a[j], br, ar);
+              ai = MM::mma(a[j], bi, ai);
+            }
+          }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -357,13 +391,18 @@ __global__ __launch_bounds__(256) void k_md_energy(MDParams p, int Nmax, int NPm
 #pragma unroll
       for (int k = 0; k < DPT; ++k) {
         const int i = threadIdx.x + k * blockDim.x;
+        // spin-indexed per-determinant values by select, so that no array is
+        // indexed with the runtime spin (which would place it in scratch memory)
+        Cx o1 = cx(0, 0), o2 = cx(0, 0);
         if (i < p.n_det) {
-          md_det_coeffs<T>(N, Nmax, myE[k][s], myH[k][s], myP[k][s], gt[s], gt[s] + M * N, pb,
-                           pb + M * Nmax, x2, x2 + Nmax * Nmax, trx0, trx2, c1[k][s], c2[k][s]);
-        } else {
-          c1[k][s] = cx(0, 0);
-          c2[k][s] = cx(0, 0);
+          const int E = s ? myE[k][1] : myE[k][0];
+          const int h0 = s ? myH[k][1][0] : myH[k][0][0], h1 = s ? myH[k][1][1] : myH[k][0][1];
+          const int v0 = s ? myP[k][1][0] : myP[k][0][0], v1 = s ? myP[k][1][1] : myP[k][0][1];
+          const T* gs = s ? gt[1] : gt[0];
+          md_det_coeffs<T>(N, Nmax, E, h0, h1, v0, v1, gs, gs + M * N, pb, pb + M * Nmax, x2,
+                           x2 + Nmax * Nmax, trx0, trx2, o1, o2);
         }
+        if (s) { c1[k][1] = o1; c2[k][1] = o2; } else { c1[k][0] = o1; c2[k][0] = o2; }
       }
       __syncthreads();
     }

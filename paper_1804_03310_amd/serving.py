@@ -88,20 +88,44 @@ def footprint_bytes(req: Request) -> int:
 
 
 class GpuExecutor:
-    """Runs requests through the HIP library, one torch stream per run."""
+    """Runs requests through the HIP library, one torch stream per run.
+
+    Requests that carry the same h and L arrays (the same Python objects, e.g.
+    the neutral and cation of a correlated-sampling pair) share one device
+    Hamiltonian, which is read-only once built; it is freed when its last run
+    finishes.
+    """
 
     def __init__(self, device: int = 0):
         self.device = device
+        self._hams = {}
 
     def footprint(self, req: Request) -> int:
         return footprint_bytes(req)
 
+    def _hamiltonian(self, req: Request):
+        import torch
+
+        from . import Hamiltonian
+        key = (id(req.h), id(req.L), float(req.e_core))
+        ent = self._hams.get(key)
+        if ent is None:
+            # set-up work (this Hamiltonian's and its trials' initialisation) goes
+            # to a stream of its own, not behind a running request's steps
+            if getattr(self, "_init_stream", None) is None:
+                self._init_stream = torch.cuda.Stream(device=self.device)
+            ham = Hamiltonian(req.h, req.L, req.e_core, device=self.device, stream=self._init_stream)
+            self._init_stream.synchronize()
+            ent = self._hams[key] = [ham, 0, req.h, req.L]  # keep the arrays alive with the key
+        ent[1] += 1
+        return key, ent[0]
+
     def start(self, req: Request):
         import torch
 
-        from . import (Hamiltonian, Options, Trial, Walkers, local_energy, walkers_from_trial)
+        from . import (Options, Trial, Walkers, local_energy, walkers_from_trial)
         stream = torch.cuda.Stream(device=self.device)
-        ham = Hamiltonian(req.h, req.L, req.e_core, device=self.device, stream=stream)
+        ham_key, ham = self._hamiltonian(req)
         trial = Trial(ham, req.n_up, req.n_dn, req.C_up, req.C_dn, req.coeff, req.exc)
         w = Walkers(trial, req.n_walkers, system_id=req.system_id)
         emix = torch.empty(max(req.n_steps, 1), dtype=torch.float64,
@@ -112,8 +136,8 @@ class GpuExecutor:
         opt = Options(taylor_order=req.taylor_order, ortho_every=req.ortho_every,
                       pc_every=req.pc_every, e_trial=et, chol_prec=req.chol_prec,
                       taylor_prec=req.taylor_prec)
-        return {"ham": ham, "trial": trial, "w": w, "stream": stream, "emix": emix, "opt": opt,
-                "e_trial": et, "done_steps": 0, "event": None}
+        return {"ham": ham, "ham_key": ham_key, "trial": trial, "w": w, "stream": stream,
+                "emix": emix, "opt": opt, "e_trial": et, "done_steps": 0, "event": None}
 
     def enqueue(self, h, req: Request, n: int) -> None:
         import torch
@@ -136,6 +160,11 @@ class GpuExecutor:
         et = h["e_trial"]
         for k in ("w", "trial", "ham", "emix"):
             h[k] = None
+        ent = self._hams.get(h["ham_key"])
+        if ent is not None:
+            ent[1] -= 1
+            if ent[1] == 0:
+                del self._hams[h["ham_key"]]
         return out, et
 
 
