@@ -192,6 +192,63 @@ def serving_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def precision_report(args):
+    """Per-step E_L error of the reduced-precision contraction modes on the
+    FP64 trajectory's walkers (kernel error) and E_mix drift over a short
+    trajectory with the same fields (includes the trajectories' divergence),
+    both against the FP64 path, which the parity tests pin to the FP64 oracle
+    at this size.  Only the contraction precision varies; Taylor, B1,
+    overlaps, inverses, determinants and MGS stay FP64."""
+    import torch
+
+    import afqmc_synth as syn
+    import paper_1804_03310_amd as afq
+
+    wl = syn.WORKLOADS[args.workload]
+    W = args.walkers or wl.n_walkers
+    inp = syn.workload_system(wl)
+    torch.cuda.set_device(0)
+    ham = afq.Hamiltonian(inp.h, inp.L, inp.e_core)
+    trial = afq.Trial(ham, inp.n_up, inp.n_dn, inp.C_up, inp.C_dn)
+    w = afq.Walkers(trial, W)
+    afq.walkers_from_trial(ham, trial, w)
+    et = afq.local_energy(ham, trial, w)
+    base = dict(taylor_order=wl.taylor_order, ortho_every=wl.ortho_every, pc_every=0, e_trial=et,
+                taylor_prec="fp64")
+    steps = args.steps
+    # FP64 reference trajectory; keep the walkers after `steps` steps
+    em64 = afq.propagate(ham, trial, w, steps, wl.dt, 7, 0, afq.Options(chol_prec="fp64", **base))
+    em64 = em64.cpu().numpy()
+    phi_re, phi_im = w.phi_re.clone(), w.phi_im.clone()
+    wt = w.weight.clone()
+    el64 = w.eloc[0].cpu().numpy().copy()
+    alive = (wt > 0).cpu().numpy()
+    out = {"metric": "per-step E_L error and E_mix drift of the contraction precisions vs FP64",
+           "unit": "Ha", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": wl.name, "M": wl.M, "n_up": wl.n_up, "n_dn": wl.n_dn,
+                      "n_chol": wl.n_chol, "n_walkers": W, "steps": steps, "l_scale": wl.l_scale,
+                      "varied": "propagator build and L~ Theta contractions",
+                      "fixed_fp64": "Taylor, B1, overlaps, inverses, determinants, MGS, sums"},
+           "e_mix_fp64_last": float(em64[-1]), "modes": {}}
+    for prec in args.sweep_precs.split(","):
+        # (i) kernel error: E_L on the FP64 trajectory's walkers
+        w.phi_re.copy_(phi_re)
+        w.phi_im.copy_(phi_im)
+        w.weight.copy_(wt)
+        afq.propagate(ham, trial, w, 0, wl.dt, 7, steps, afq.Options(chol_prec=prec, **base))
+        el = w.eloc[0].cpu().numpy()
+        d = np.abs(el - el64)[alive]
+        # (ii) trajectory drift from the same start and fields
+        afq.walkers_from_trial(ham, trial, w)
+        em = afq.propagate(ham, trial, w, steps, wl.dt, 7, 0,
+                           afq.Options(chol_prec=prec, **base)).cpu().numpy()
+        out["modes"][prec] = {"el_max_abs_err": float(d.max()), "el_mean_abs_err": float(d.mean()),
+                              "el_max_rel_err": float((d / np.abs(el64[alive])).max()),
+                              "emix_max_abs_drift": float(np.abs(em - em64).max()),
+                              "emix_drift_last": float(abs(em[-1] - em64[-1]))}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(wl, inp, sample_walkers, sample_steps):
     from oracle import Oracle, Options as OOptions
     try:
@@ -228,6 +285,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--tte-repeats", type=int, default=5)
     ap.add_argument("--tte-steps", type=int, default=50)
+    ap.add_argument("--precision-report", action="store_true",
+                    help="E_L error and E_mix drift of the contraction precisions vs FP64")
+    ap.add_argument("--sweep-precs", default="fp32,bf16,fp64")
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed request stream through the serving loop instead")
     ap.add_argument("--requests", type=int, default=64)
@@ -249,6 +309,9 @@ def main():
 
     if args.serving:
         serving_bench(args)
+        return
+    if args.precision_report:
+        precision_report(args)
         return
 
     import torch
