@@ -29,7 +29,12 @@ notes):
   with v_gamma = <L_gamma>_mix (Sec. II: chosen to minimise weight fluctuations).
 * weights in the local-energy form W <- W exp(-dt (Re E_L - E_T)) max(0, cos dtheta)
   (Sec. II), E_L evaluated at the propagated walker; dtheta = Im log of the
-  overlap ratio.
+  overlap ratio.  Optionally the hybrid form the production runs use (Sec.
+  IV.A, after Purwanto et al.): W <- W |I| exp(-dt (E_0 - E_T)) max(0, cos dtheta)
+  with the importance function I = (<Psi_T|phi'>/<Psi_T|phi>) (mean-field phase
+  included) exp(sum_gamma (x_gamma xbar_gamma - xbar_gamma^2 / 2)) and
+  E_0 = e_core - 1/2 sum_gamma lbar_gamma^2, the constant the propagator drops;
+  E_L is then only measured every meas_every steps.
 * exp of the one-body operator by a Taylor series of fixed order.
 * walkers that die (weight 0 or any non-finite quantity) are reset to the
   reference determinant with weight 0; they keep being propagated and are
@@ -255,6 +260,8 @@ class Options:
     e_trial: float = 0.0
     mf_subtract: bool = True
     system_id: int = 0
+    weight_mode: int = 0      # 0: local-energy form; 1: hybrid form
+    meas_every: int = 1       # hybrid: E_mix measured after steps t with (t+1) % meas_every == 0
 
 
 @dataclasses.dataclass
@@ -332,6 +339,9 @@ class Oracle:
         # H1' = h - 1/2 sum_gamma L_gamma L_gamma + sum_gamma lbar_gamma L_gamma.
         self.H1p = (self.h - 0.5 * np.einsum("gik,gkj->ij", self.L, self.L, optimize=True)
                     + np.einsum("g,gij->ij", self.lbar, self.L, optimize=True))
+        # The scalar the propagator leaves out: with 1/2 sum L^2 = 1/2 sum (L - lbar)^2
+        # + sum lbar L - 1/2 sum lbar^2, e^{-dt H} = B(x-integral) e^{-dt E_0}.
+        self.e0_shift = self.e_core - 0.5 * float(np.dot(self.lbar, self.lbar))
         self._b1 = {}
 
     @classmethod
@@ -507,6 +517,23 @@ class Oracle:
         phi = B1 @ phi
         return phi, mf
 
+    def shifted_step(self, st: WalkerState, x: np.ndarray, dt: float, order: int):
+        """Propagate every walker with fields x shifted by the force bias.
+
+        Returns (phi', measure(phi'), log r, log I): r = <Psi_T|phi'>/<Psi_T|phi>
+        with the mean-field phase factor, and the hybrid importance function
+        I = r exp(sum_gamma (x_gamma xbar_gamma - xbar_gamma^2 / 2)), whose
+        Gaussian average over x is <Psi_T|B1 exp(-dt/2 sum (L - lbar)^2) B1|phi>
+        / <Psi_T|phi> for any complex shift xbar (Eq. 2 after x -> x - xbar).
+        """
+        xbar = -1j * np.sqrt(dt) * (st.v - self.lbar[None, :])
+        phi, mf = self.apply_propagator(st.phi, x - xbar, dt, order)
+        with np.errstate(all="ignore"):
+            m = self.measure(phi)
+            logr = m["logS"] - st.logS + mf
+            logI = logr + np.sum(x * xbar - 0.5 * xbar * xbar, axis=1)
+        return phi, m, logr, logI
+
     def step(self, st: WalkerState, t: int, seed: int, dt: float, opt: Options):
         """One timestep for every walker; returns the mixed energy after it.
 
@@ -516,22 +543,25 @@ class Oracle:
         update with dtheta = Im log(<Psi_T|phi'>/<Psi_T|phi>) including the
         mean-field phase factor (Sec. II).
         """
-        sq = np.sqrt(dt)
         x = gaussian_fields(seed, t, st.index, self.n_chol, opt.system_id)
-        xbar = -1j * sq * (st.v - self.lbar[None, :])
-        phi, mf = self.apply_propagator(st.phi, x - xbar, dt, opt.taylor_order)
+        phi, m, logr, logI = self.shifted_step(st, x, dt, opt.taylor_order)
+        measuring = opt.weight_mode == 0 or (t + 1) % max(opt.meas_every, 1) == 0
         with np.errstate(all="ignore"):
-            m = self.measure(phi)
-            logr = m["logS"] - st.logS + mf
             cosd = np.cos(logr.imag)
-            wnew = st.weight * np.exp(-dt * (m["eloc"].real - opt.e_trial)) * np.maximum(0.0, cosd)
-        ok = (np.isfinite(wnew) & np.isfinite(m["eloc"]) & np.isfinite(m["logS"])
+            if opt.weight_mode == 0:
+                wnew = st.weight * np.exp(-dt * (m["eloc"].real - opt.e_trial)) * np.maximum(0.0, cosd)
+            else:
+                wnew = (st.weight * np.exp(logI.real - dt * (self.e0_shift - opt.e_trial))
+                        * np.maximum(0.0, cosd))
+        ok = (np.isfinite(wnew) & np.isfinite(m["logS"])
               & np.all(np.isfinite(m["v"]), axis=1) & (wnew > 0))
+        if measuring:
+            ok &= np.isfinite(m["eloc"])
         st.phi = phi
         st.weight = np.where(ok, wnew, 0.0)
         st.logS, st.eloc, st.v = m["logS"], m["eloc"], m["v"]
         self._reset_dead(st, ~ok)
-        return self.mixed_energy(st)
+        return self.mixed_energy(st) if measuring else float("nan")
 
     def _reset_dead(self, st: WalkerState, dead: np.ndarray):
         if not np.any(dead):

@@ -453,6 +453,65 @@ def test_trotter_split_is_second_order_in_dt():
     assert errs[2] < 1e-4
 
 
+def test_hybrid_importance_function_average_matches_fock_space():
+    """Hybrid weights (Sec. IV.A): the Gaussian average over x of the
+    oracle's importance function I(x) for a walker away from the trial (so
+    that the force bias is complex) equals <Psi_T|B1 e^{-dt/2 (L - lbar)^2}
+    B1|phi>/<Psi_T|phi> from Fock space; restoring e^{-dt E_0} gives
+    <Psi_T|e^{-dt H}|phi>/<Psi_T|phi> up to the O(dt^3) split error.  A wrong
+    sign of x xbar or xbar^2/2, a dropped mean-field phase or a wrong E_0 fails."""
+    M, n_up, n_dn = 4, 2, 1
+    inp = _small_system(M, n_up, n_dn, 1, seed=91)
+    o = Oracle.from_inputs(inp)
+    V = fock.eri_from_chol(inp.L)
+    H, states, index = fock.hamiltonian_matrix(inp.h, V, inp.e_core, M, n_up, n_dn)
+    Lop = fock.one_body_matrix(inp.L[0], M, states, index)
+    H1f = fock.one_body_matrix(o.H1p, M, states, index)
+    dt = 0.01
+    re, im = syn.random_walkers(M, n_up, n_dn, 1, seed=4, scale=0.4)
+    D0 = np.concatenate([inp.C_up[:, :n_up], inp.C_dn[:, :n_dn]], axis=1)
+    st = o.init_walkers(1, phi=D0[None] + re + 1j * im)
+    assert abs((st.v[0, 0] - o.lbar[0]).imag) > 1e-3   # complex force bias
+    cT = fock.det_amplitudes(inp.C_up[:, :n_up], inp.C_dn[:, :n_dn], M, states)
+    c0 = fock.det_amplitudes(st.phi[0][:, :n_up], st.phi[0][:, n_up:], M, states)
+    ovl0 = cT @ c0
+    xs, ws = np.polynomial.hermite_e.hermegauss(80)
+    ws = ws / np.sqrt(2 * np.pi)
+    avg = 0.0
+    for x, wgt in zip(xs, ws):
+        _, _, _, logI = o.shifted_step(st, np.array([[x]]), dt, 40)
+        avg += wgt * np.exp(logI[0])
+    B1f = scipy.linalg.expm(-0.5 * dt * H1f)
+    K = Lop - o.lbar[0] * np.eye(len(states))
+    split = cT @ (B1f @ scipy.linalg.expm(-0.5 * dt * (K @ K)) @ B1f @ c0) / ovl0
+    assert abs(avg - split) < 1e-10 * abs(split)
+    full = cT @ (scipy.linalg.expm(-dt * H) @ c0) / ovl0
+    assert abs(avg * np.exp(-dt * o.e0_shift) - full) < 1e-6 * abs(full)
+
+
+def test_hybrid_weights_zero_variance_one_body():
+    """L = 0 and a trial of eigenvectors of h: the hybrid importance function
+    is exp(-dt E_1body) exactly, so hybrid and local-energy weights coincide
+    and the measured E_mix is exact."""
+    M, n_up, n_dn = 8, 3, 2
+    inp = syn.make_system(M, n_up, n_dn, 6, 4.0, seed=5, e_core=1.25)
+    L0 = np.zeros_like(inp.L)
+    o = Oracle(inp.h, L0, inp.e_core, inp.C_up, inp.C_dn, n_up, n_dn)
+    eps = np.linalg.eigvalsh(inp.h)
+    exact = inp.e_core + eps[:n_up].sum() + eps[:n_dn].sum()
+    re, im = syn.random_walkers(M, n_up, n_dn, 8, seed=2, scale=0.3)
+    D0 = np.concatenate([inp.C_up[:, :n_up], inp.C_dn[:, :n_dn]], axis=1)
+    sa = o.init_walkers(8, phi=D0[None] + re + 1j * im)
+    sb = sa.copy()
+    et = exact + 0.7
+    ea = o.propagate(sa, 9, 0.02, seed=1, step0=0, opt=Options(ortho_every=2, e_trial=et))
+    eb = o.propagate(sb, 9, 0.02, seed=1, step0=0,
+                     opt=Options(ortho_every=2, e_trial=et, weight_mode=1, meas_every=3))
+    assert np.allclose(sa.weight, sb.weight, rtol=1e-12)
+    assert np.allclose(eb[2::3], ea[2::3], atol=1e-12)
+    assert np.all(np.isnan(eb[0::3])) and np.all(np.isnan(eb[1::3]))
+
+
 def test_weight_update_matches_fock_space():
     """One oracle step (exact exponential) against Fock space: new overlap
     ratio incl. the mean-field phase, E_L at the new walker, phaseless weight."""
