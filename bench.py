@@ -280,6 +280,10 @@ def main():
     ap.add_argument("--prec", default="",
                     help="override precisions: 'chol' or 'chol,taylor' from fp64/fp32/bf16")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--weight-mode", choices=["local", "hybrid"], default="local",
+                    help="local-energy weights every step (default) or the hybrid form")
+    ap.add_argument("--meas-every", type=int, default=20,
+                    help="hybrid form: steps between E_L measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=80)
@@ -336,8 +340,11 @@ def main():
     afq.walkers_from_trial(ham, trial, w)
     et = afq.local_energy(ham, trial, w)
     opt_kw = dict(taylor_order=wl.taylor_order, ortho_every=wl.ortho_every,
-                  chol_prec=chol_prec, taylor_prec=taylor_prec)
+                  chol_prec=chol_prec, taylor_prec=taylor_prec, weight_mode=args.weight_mode,
+                  meas_every=args.meas_every)
     opt = afq.Options(pc_every=wl.pc_every, e_trial=et, **opt_kw)
+    if args.weight_mode == "hybrid":  # the time-to-energy runs end on a measured step
+        args.tte_steps = -(-args.tte_steps // args.meas_every) * args.meas_every
     emix = torch.empty(max(args.steps, args.warmup, args.tte_steps, 1), dtype=torch.float64,
                        device="cuda")
     # warmup
@@ -355,7 +362,9 @@ def main():
     elapsed = time.perf_counter() - t0
     afq.timing_enable(ham, False)
     ktimes = {k: afq.timing_read(ham, k) for k in afq._abi.KERNEL_CLASSES}
-    e_last = float(emix[args.steps - 1].item()) if args.steps else float("nan")
+    em_host = emix[:args.steps].cpu().numpy() if args.steps else np.zeros(0)
+    finite = em_host[np.isfinite(em_host)]
+    e_last = float(finite[-1]) if finite.size else float("nan")
     alive = int((w.weight > 0).sum().item())
 
     # time to energy: propagate start -> final E_mix on the host
@@ -397,6 +406,8 @@ def main():
                    "n_chol": wl.n_chol, "n_walkers": W, "dt": wl.dt,
                    "taylor_order": wl.taylor_order, "ortho_every": wl.ortho_every,
                    "pc_every": wl.pc_every, "n_det": inp.n_det, "l_scale": wl.l_scale,
+                   "weight_mode": args.weight_mode,
+                   "meas_every": args.meas_every if args.weight_mode == "hybrid" else 1,
                    "precision": f"contractions {chol_prec}, Taylor/B1 {taylor_prec}, "
                                 "overlap/inverse/det/MGS/sums fp64",
                    "e_trial": et, "e_mix_last": e_last, "alive_walkers": alive},
@@ -418,7 +429,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration"] = {"kernel": "torch elementwise mul (x * 1.0 -> y)",
                                    "bytes_read": x.numel() * 8, "bytes_written": y.numel() * 8}
-    if not args.no_accuracy and wl.name in GOLDEN:
+    if not args.no_accuracy and wl.name in GOLDEN and args.weight_mode == "local":
         out["accuracy"] = accuracy_check(afq, torch, wl, inp, ham, trial, opt_kw)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, inp, args.cpu_walkers, args.cpu_steps)

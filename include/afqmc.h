@@ -90,7 +90,16 @@ typedef struct {
  * (t+1) is a multiple (0 = never).  e_trial: E_T of the weight factor.
  * chol_prec: arithmetic of sum_g x_g L_g and of Ltil_g Theta;
  * taylor_prec: arithmetic of the Taylor products and of B1 phi.
- * Overlaps, inverses, determinants, MGS and all final sums are FP64. */
+ * Overlaps, inverses, determinants, MGS and all final sums are FP64.
+ * weight_mode: AFQMC_WEIGHT_LOCAL_ENERGY (Sec. II; the default, 0) or
+ * AFQMC_WEIGHT_HYBRID (Sec. IV.A: W <- W |I| exp(-dt (E_0 - e_trial))
+ * max(0, cos dtheta), I = (<Psi_T|phi'>/<Psi_T|phi>) exp(sum_g
+ * (x_g xbar_g - xbar_g^2 / 2)), E_0 = e_core - 1/2 sum_g lbar_g^2); in the
+ * hybrid form E_L and E_mix are only evaluated after steps t with
+ * (t+1) % meas_every == 0 (meas_every >= 1; ignored in the local-energy
+ * form), the other entries of emix_dev are NaN and walkers' eloc keep the
+ * last measured value. */
+typedef enum { AFQMC_WEIGHT_LOCAL_ENERGY = 0, AFQMC_WEIGHT_HYBRID = 1 } afqmc_weight_mode;
 typedef struct {
   int32_t taylor_order;
   int32_t ortho_every;
@@ -98,6 +107,8 @@ typedef struct {
   double e_trial;
   afqmc_prec chol_prec;
   afqmc_prec taylor_prec;
+  int32_t weight_mode;
+  int32_t meas_every;
 } afqmc_options;
 
 /* Hamiltonian of Eq. 1: one-body h [M][M] (symmetric), Cholesky vectors
@@ -189,10 +200,11 @@ afqmc_status afqmc_fields(uint64_t seed, uint64_t t, int n_walkers, int n_chol,
  * recorded on the launch stream.  Classes: 0 fused exchange / force bias
  * (L~ Theta contraction), 1 propagator build sum_g c_g L_g, 2 Taylor and
  * B1 products, 3 overlap / inverse / Theta, 4 MGS, 5 comb, 6 other
- * per-walker kernels.  afqmc_timing_read synchronises on the recorded
+ * per-walker kernels, 7 force bias alone (the hybrid form's steps without
+ * an E_L measurement).  afqmc_timing_read synchronises on the recorded
  * events, returns the number of timed launches and their summed duration in
  * milliseconds for one class, and clears that class. */
-#define AFQMC_NUM_KERNEL_CLASSES 7
+#define AFQMC_NUM_KERNEL_CLASSES 8
 afqmc_status afqmc_timing_enable(afqmc_ham *ham, int enable);
 afqmc_status afqmc_timing_read(afqmc_ham *ham, int kernel_class, int64_t *launches,
                                double *total_ms);

@@ -133,10 +133,13 @@ class Options:
     e_trial: float = 0.0
     chol_prec: str = "fp64"
     taylor_prec: str = "fp64"
+    weight_mode: str = "local"   # "local" (local-energy form) or "hybrid"
+    meas_every: int = 1          # hybrid: E_L / E_mix after steps t with (t+1) % meas_every == 0
 
     def struct(self) -> OptionsStruct:
         return OptionsStruct(self.taylor_order, self.ortho_every, self.pc_every, float(self.e_trial),
-                             _abi.PREC[self.chol_prec], _abi.PREC[self.taylor_prec])
+                             _abi.PREC[self.chol_prec], _abi.PREC[self.taylor_prec],
+                             _abi.WEIGHT_MODES[self.weight_mode], int(self.meas_every))
 
 
 def walkers_from_trial(ham: Hamiltonian, trial: Trial, w: Walkers, stream=None) -> None:

@@ -28,7 +28,7 @@ EXPORTED = ["afqmc_init_hamiltonian", "afqmc_init_trial", "afqmc_walker_workspac
             "afqmc_timing_enable", "afqmc_timing_read", "afqmc_footprint_bytes",
             "afqmc_free_hamiltonian", "afqmc_free_trial", "afqmc_last_error"]
 KERNEL_CLASSES = ["exchange", "propagator_build", "taylor_b1", "overlap_theta", "mgs", "comb",
-                  "other"]
+                  "other", "force_bias"]
 
 
 class WalkersStruct(ctypes.Structure):
@@ -41,7 +41,11 @@ class WalkersStruct(ctypes.Structure):
 
 class OptionsStruct(ctypes.Structure):
     _fields_ = [("taylor_order", c_int32), ("ortho_every", c_int32), ("pc_every", c_int32),
-                ("e_trial", c_double), ("chol_prec", c_int), ("taylor_prec", c_int)]
+                ("e_trial", c_double), ("chol_prec", c_int), ("taylor_prec", c_int),
+                ("weight_mode", c_int32), ("meas_every", c_int32)]
+
+
+WEIGHT_MODES = {"local": 0, "hybrid": 1}
 
 
 class AfqmcError(RuntimeError):

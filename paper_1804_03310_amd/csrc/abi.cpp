@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -168,7 +169,8 @@ struct TimedLaunch {
   }
 };
 
-enum { KC_EXCHANGE = 0, KC_ABUILD = 1, KC_TAYLOR = 2, KC_OVERLAP = 3, KC_MGS = 4, KC_COMB = 5, KC_OTHER = 6 };
+enum { KC_EXCHANGE = 0, KC_ABUILD = 1, KC_TAYLOR = 2, KC_OVERLAP = 3, KC_MGS = 4, KC_COMB = 5, KC_OTHER = 6,
+       KC_FBIAS = 7 };
 
 struct afqmc_ham {
   KernelTimer timer;
@@ -209,6 +211,11 @@ struct afqmc_trial {
   int MP32 = 32;
   double* lbar = nullptr;
   double* D0 = nullptr;
+  // hybrid weights: E_0 = e_core - 1/2 sum lbar^2, and (single determinant)
+  // Lcat[(m Nt + b)][g] = Lt_{spin of b}[g][m][a] for the force bias v = Theta Lcat
+  double e0_shift = 0.0;
+  double* Lcat64 = nullptr;
+  float* Lcat32 = nullptr;
   std::vector<double> H1p;
   std::vector<B1Entry> b1;
   int n_det = 1;
@@ -234,7 +241,7 @@ struct WS {
   double *ld_re, *ld_im, *e1_re, *e1_im, *exx_re, *exx_im;
   double *vs_re, *vs_im;
   double *v_re, *v_im;
-  double *lsn_re, *lsn_im, *eln_re, *eln_im, *mf_re, *mf_im;
+  double *lsn_re, *lsn_im, *eln_re, *eln_im, *mf_re, *mf_im, *hy_re, *hy_im;
   int *vfin, *dead, *parent;
   double *cbuf, *scal;
   double *c0_re, *c0_im, *tot_re, *tot_im;
@@ -270,6 +277,8 @@ WS layout_dims(long M, long G, long Nt, int n_det, int W, void* base) {
   ws.v_im = (double*)take((size_t)W * G * sizeof(double));
   ws.lsn_re = (double*)take(W * sizeof(double));
   ws.lsn_im = (double*)take(W * sizeof(double));
+  ws.hy_re = (double*)take(W * sizeof(double));
+  ws.hy_im = (double*)take(W * sizeof(double));
   ws.eln_re = (double*)take(W * sizeof(double));
   ws.eln_im = (double*)take(W * sizeof(double));
   ws.mf_re = (double*)take(W * sizeof(double));
@@ -509,6 +518,46 @@ B1Entry* get_b1(afqmc_trial* tr, double dt, hipStream_t st, afqmc_status* err) {
 
 struct Bf16Tag {};
 
+// Hybrid steps without a measurement (single determinant): overlap, Theta and
+// log S', then the force bias v_g = sum_(m,b) Theta[m][b] Lcat[(m,b)][g] as a
+// GEMM over all walkers, split over K = M Nt into nz partials (in the Taylor
+// accumulators, free at this point) summed in a fixed order.
+afqmc_status hybrid_force_bias(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bool fp32,
+                               hipStream_t st) {
+  afqmc_ham* hm = tr->ham;
+  const int W = wk->n_walkers, M = hm->M, G = hm->G, Nt = tr->Nt;
+  const afq::SpinGeom s0 = spin_geom(tr, 0, AFQMC_FP64), s1 = spin_geom(tr, 1, AFQMC_FP64);
+  {
+    TimedLaunch tl(&hm->timer, KC_OVERLAP, st);
+    AFQ_CK(afq::overlap_theta(st, W, M, Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re, ws.th_im,
+                              ws.ld_re, ws.ld_im, ws.e1_re, ws.e1_im, hm->max_lds));
+  }
+  const long K = (long)M * Nt;
+  int nz = 1;
+  for (int c : {8, 4, 2})
+    if (K % c == 0 && (long)c * G <= K) { nz = c; break; }
+  const int Kc = (int)(K / nz);
+  {
+    TimedLaunch tl(&hm->timer, KC_FBIAS, st);
+    for (int part = 0; part < 2; ++part) {
+      const double* th = part ? ws.th_im : ws.th_re;
+      double* out = part ? ws.ACC_im : ws.ACC_re;
+      if (fp32) {
+        float* a32 = (float*)(part ? ws.P_im : ws.P_re);
+        AFQ_CK(afq::convert_f64_f32(st, th, a32, (long)W * K));
+        AFQ_CK((afq::gemm_real<float, double, false>(st, W, G, Kc, a32, (int)K, Kc, tr->Lcat32, G,
+                                                     (long)Kc * G, out, G, (long)W * G, nz, 1.0)));
+      } else {
+        AFQ_CK((afq::gemm_real<double, double, false>(st, W, G, Kc, th, (int)K, Kc, tr->Lcat64, G,
+                                                      (long)Kc * G, out, G, (long)W * G, nz, 1.0)));
+      }
+    }
+  }
+  AFQ_CK(afq::hybrid_force_bias_finish(st, W, G, nz, ws.ACC_re, ws.ACC_im, ws.v_re, ws.v_im, ws.ld_re,
+                                       ws.ld_im, ws.lsn_re, ws.lsn_im, ws.vfin));
+  return AFQMC_OK;
+}
+
 template <typename TC, typename TT>
 afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B1Entry* b1,
                              int n_steps, double dt, uint64_t seed, uint64_t step0,
@@ -522,14 +571,18 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
   TC* coefT = (TC*)ws.coefT;
   TT* A = (TT*)ws.A;
   TT* Tbuf[2][2] = {{(TT*)ws.Ta_re, (TT*)ws.Ta_im}, {(TT*)ws.Tb_re, (TT*)ws.Tb_im}};
+  const bool hybrid = opt->weight_mode == AFQMC_WEIGHT_HYBRID;
+  double* hyr = hybrid ? ws.hy_re : nullptr;
+  double* hyi = hybrid ? ws.hy_im : nullptr;
   for (int s = 0; s < n_steps; ++s) {
     const uint64_t t = step0 + (uint64_t)s;
+    const bool measuring = !hybrid || (t + 1) % (uint64_t)opt->meas_every == 0;
     if constexpr (BF) {
       AFQ_CK(afq::fields_coeff_bf16(st, W, G, G, seed, t, wk->system_id, dt, ws.v_re, ws.v_im,
-                                    tr->lbar, ws.coefT, ws.mf_re, ws.mf_im));
+                                    tr->lbar, ws.coefT, ws.mf_re, ws.mf_im, hyr, hyi));
     } else {
       AFQ_CK(afq::fields_coeff<TC>(st, W, G, seed, t, wk->system_id, dt, ws.v_re, ws.v_im, tr->lbar,
-                                   coefT, ws.mf_re, ws.mf_im, nullptr));
+                                   coefT, ws.mf_re, ws.mf_im, nullptr, hyr, hyi));
     }
     if (G > 0) {
       TimedLaunch tl(&hm->timer, KC_ABUILD, st);
@@ -577,17 +630,26 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
                                                      nullptr, Nt, mn, 1.0)));
     }
     }
-    afqmc_status rs = measure_core(tr, wk, ws, opt->chol_prec, st);
+    afqmc_status rs;
+    if (hybrid && !measuring && tr->n_det == 1 && G > 0)
+      rs = hybrid_force_bias(tr, wk, ws, opt->chol_prec != AFQMC_FP64, st);
+    else
+      rs = measure_core(tr, wk, ws, opt->chol_prec, st);
     if (rs != AFQMC_OK) return rs;
-    AFQ_CK(afq::weight_update(st, W, 1, dt, opt->e_trial, ws.lsn_re, ws.lsn_im, ws.eln_re,
-                              ws.eln_im, ws.mf_re, ws.mf_im, ws.vfin, wk->weight, wk->logovlp_re,
-                              wk->logovlp_im, wk->eloc_re, wk->eloc_im, ws.dead));
+    AFQ_CK(afq::weight_update(st, W, hybrid ? (measuring ? 3 : 4) : 1, dt, opt->e_trial, ws.lsn_re,
+                              ws.lsn_im, ws.eln_re, ws.eln_im, ws.mf_re, ws.mf_im, ws.vfin,
+                              wk->weight, wk->logovlp_re, wk->logovlp_im, wk->eloc_re, wk->eloc_im,
+                              ws.dead, ws.hy_re, ws.hy_im, tr->e0_shift));
     AFQ_CK(afq::reset_dead(st, W, M, Nt, G, ws.dead, tr->D0, tr->ref_ls[0], tr->ref_ls[1],
                            tr->ref_el[0], tr->ref_el[1], tr->vref_re, tr->vref_im, wk->phi_re,
                            wk->phi_im, wk->logovlp_re, wk->logovlp_im, wk->eloc_re, wk->eloc_im,
                            ws.v_re, ws.v_im));
-    AFQ_CK(afq::mixed_energy(st, W, wk->weight, wk->eloc_re, emix_dev ? emix_dev + s : ws.scal,
-                             ws.scal + 1));
+    if (measuring) {
+      AFQ_CK(afq::mixed_energy(st, W, wk->weight, wk->eloc_re, emix_dev ? emix_dev + s : ws.scal,
+                               ws.scal + 1));
+    } else if (emix_dev) {
+      AFQ_CK(afq::fill(st, emix_dev + s, 1, std::numeric_limits<double>::quiet_NaN()));
+    }
     if (opt->ortho_every > 0 && (t + 1) % (uint64_t)opt->ortho_every == 0) {
       rs = orthonormalize_impl(tr, wk, ws, st);
       if (rs != AFQMC_OK) return rs;
@@ -701,6 +763,7 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
   }
   tot += 3 * rnd(std::max<size_t>(g, 1) * 8) + rnd(m * Nt * 8) + rnd(mm * 8) + 2 * rnd(mm * 12);
   if (n_det > 1) tot += rnd((size_t)n_det * 40) + rnd((size_t)n_det * 8);
+  if (n_det == 1 && g > 0) tot += rnd(m * Nt * g * 8) + rnd(m * Nt * g * 4);  // Lcat
   tot += 2 * rnd((size_t)n_walkers * m * Nt * 8) + 5 * rnd((size_t)n_walkers * 8);  // walkers
   tot += layout_dims(M, n_chol, (long)Nt, n_det, n_walkers, nullptr).total;
   *bytes = tot;
@@ -893,6 +956,26 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
   }
   if (hipMemcpy(tr->D0, D0h.data(), D0h.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
     return bad(AFQMC_ERR_DEVICE, "D0 upload");
+  {
+    std::vector<double> lb((size_t)std::max(G, 1));
+    if (hipMemcpy(lb.data(), tr->lbar, lb.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return bad(AFQMC_ERR_DEVICE, "lbar download");
+    double s2 = 0.0;
+    for (int g = 0; g < G; ++g) s2 += lb[g] * lb[g];
+    tr->e0_shift = hm->e_core - 0.5 * s2;
+  }
+  if (n_det == 1 && G > 0) {
+    const size_t nk = (size_t)M * tr->Nt * G;
+    void *q64, *q32;
+    if (tr->arena.alloc(&q64, nk * 8) || tr->arena.alloc(&q32, nk * 4))
+      return bad(AFQMC_ERR_OOM, "trial allocation failed");
+    tr->Lcat64 = (double*)q64;
+    tr->Lcat32 = (float*)q32;
+    if (afq::build_lcat(st, G, M, tr->MP4, tr->Nt, n_up, n_dn, tr->NP[0], tr->NP[1], tr->Lt64[0],
+                        tr->Lt64[1], tr->Lcat64) != hipSuccess ||
+        afq::convert_f64_f32(st, tr->Lcat64, tr->Lcat32, (long)nk) != hipSuccess)
+      return bad(AFQMC_ERR_DEVICE, "Lcat");
+  }
   if (n_det > 1) {
     void *pe, *pc;
     if (tr->arena.alloc(&pe, exc_dev.size() * sizeof(int)) || tr->arena.alloc(&pc, (size_t)n_det * 8))
@@ -1060,6 +1143,10 @@ afqmc_status afqmc_propagate(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk, 
   if (opt->taylor_order < 1 || opt->taylor_order > 64) return fail(AFQMC_ERR_ARG, "taylor_order");
   if (opt->ortho_every < 0 || opt->pc_every < 0) return fail(AFQMC_ERR_ARG, "negative interval");
   if (!std::isfinite(opt->e_trial)) return fail(AFQMC_ERR_ARG, "e_trial is not finite");
+  if (opt->weight_mode != AFQMC_WEIGHT_LOCAL_ENERGY && opt->weight_mode != AFQMC_WEIGHT_HYBRID)
+    return fail(AFQMC_ERR_ARG, "weight_mode must be AFQMC_WEIGHT_LOCAL_ENERGY or AFQMC_WEIGHT_HYBRID");
+  if (opt->weight_mode == AFQMC_WEIGHT_HYBRID && opt->meas_every < 1)
+    return fail(AFQMC_ERR_ARG, "meas_every must be >= 1 in the hybrid form");
   if ((opt->chol_prec != AFQMC_FP64 && opt->chol_prec != AFQMC_FP32 &&
        opt->chol_prec != AFQMC_BF16) ||
       (opt->taylor_prec != AFQMC_FP64 && opt->taylor_prec != AFQMC_FP32))

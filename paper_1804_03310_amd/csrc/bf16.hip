@@ -105,11 +105,12 @@ __global__ __launch_bounds__(256) void k_fields_coeff_bf16(int W, int G, int ldg
                                                            const double* __restrict__ v_im,
                                                            const double* __restrict__ lbar,
                                                            __bf16* __restrict__ coef, double* mf_re,
-                                                           double* mf_im) {
+                                                           double* mf_im, double* hy_re,
+                                                           double* hy_im) {
   __shared__ double red[4];
   const int w = blockIdx.x;
   const double sq = sqrt(dt);
-  double sre = 0.0, sim = 0.0;
+  double sre = 0.0, sim = 0.0, hre = 0.0, him = 0.0;
   const int nq = (G + 3) / 4;
   for (int q = threadIdx.x; q < nq; q += blockDim.x) {
     double z[4];
@@ -124,18 +125,27 @@ __global__ __launch_bounds__(256) void k_fields_coeff_bf16(int W, int G, int ldg
       coef[(long)(2 * w + 1) * ldg + g] = (__bf16)(float)(sq * xsr);
       sre += sq * xsi * lb;
       sim += -sq * xsr * lb;
+      const double br = sq * vi, bi = -sq * (vr - lb);
+      hre += z[j] * br - 0.5 * (br * br - bi * bi);
+      him += z[j] * bi - br * bi;
     }
   }
   sre = block_sum(sre, red);
   sim = block_sum(sim, red);
   if (threadIdx.x == 0) { mf_re[w] = sre; mf_im[w] = sim; }
+  if (hy_re) {
+    hre = block_sum(hre, red);
+    him = block_sum(him, red);
+    if (threadIdx.x == 0) { hy_re[w] = hre; hy_im[w] = him; }
+  }
 }
 
 hipError_t fields_coeff_bf16(hipStream_t st, int W, int G, int ldg, uint64_t seed, uint64_t t,
                              int system_id, double dt, const double* v_re, const double* v_im,
-                             const double* lbar, void* coef, double* mf_re, double* mf_im) {
+                             const double* lbar, void* coef, double* mf_re, double* mf_im,
+                             double* hy_re, double* hy_im) {
   hipLaunchKernelGGL(k_fields_coeff_bf16, dim3(W), dim3(256), 0, st, W, G, ldg, seed, t, system_id,
-                     dt, v_re, v_im, lbar, (__bf16*)coef, mf_re, mf_im);
+                     dt, v_re, v_im, lbar, (__bf16*)coef, mf_re, mf_im, hy_re, hy_im);
   return hipGetLastError();
 }
 

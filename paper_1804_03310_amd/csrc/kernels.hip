@@ -96,6 +96,9 @@ template hipError_t gemm_real<double, float, true>(hipStream_t, int, int, int, c
 template hipError_t gemm_real<float, double, true>(hipStream_t, int, int, int, const float*, int,
                                                    long, const float*, int, long, double*, int,
                                                    long, int, double);
+template hipError_t gemm_real<float, double, false>(hipStream_t, int, int, int, const float*, int,
+                                                    long, const float*, int, long, double*, int,
+                                                    long, int, double);
 
 // ===========================================================================
 // Walker-batched complex GEMM for the one-body factors B1 and the Taylor
@@ -231,11 +234,12 @@ __global__ __launch_bounds__(256) void k_fields_coeff(int W, int G, uint64_t see
                                                       const double* __restrict__ v_im,
                                                       const double* __restrict__ lbar,
                                                       T* __restrict__ coefT, double* mf_re,
-                                                      double* mf_im, double* xdump) {
+                                                      double* mf_im, double* xdump, double* hy_re,
+                                                      double* hy_im) {
   __shared__ double red[4];
   const int w = blockIdx.x;
   const double sq = sqrt(dt);
-  double sre = 0.0, sim = 0.0;
+  double sre = 0.0, sim = 0.0, hre = 0.0, him = 0.0;
   const int nq = (G + 3) / 4;
   for (int q = threadIdx.x; q < nq; q += blockDim.x) {
     double z[4];
@@ -259,28 +263,38 @@ __global__ __launch_bounds__(256) void k_fields_coeff(int W, int G, uint64_t see
       // -i sq xs lbar = sq*xsi*lb - i sq*xsr*lb
       sre += sq * xsi * lb;
       sim += -sq * xsr * lb;
+      // hybrid importance term x xbar - xbar^2 / 2, xbar = sq vi - i sq (vr - lb)
+      const double br = sq * vi, bi = -sq * (vr - lb);
+      hre += x * br - 0.5 * (br * br - bi * bi);
+      him += x * bi - br * bi;
       if (xdump) xdump[(long)w * G + g] = x;
     }
   }
   sre = block_sum(sre, red);
   sim = block_sum(sim, red);
   if (threadIdx.x == 0 && mf_re) { mf_re[w] = sre; mf_im[w] = sim; }
+  if (hy_re) {
+    hre = block_sum(hre, red);
+    him = block_sum(him, red);
+    if (threadIdx.x == 0) { hy_re[w] = hre; hy_im[w] = him; }
+  }
 }
 
 template <typename T>
 hipError_t fields_coeff(hipStream_t st, int W, int G, uint64_t seed, uint64_t t, int system_id,
                         double dt, const double* v_re, const double* v_im, const double* lbar,
-                        T* coefT, double* mf_re, double* mf_im, double* xdump) {
+                        T* coefT, double* mf_re, double* mf_im, double* xdump, double* hy_re,
+                        double* hy_im) {
   hipLaunchKernelGGL((k_fields_coeff<T>), dim3(W), dim3(256), 0, st, W, G, seed, t, system_id, dt,
-                     v_re, v_im, lbar, coefT, mf_re, mf_im, xdump);
+                     v_re, v_im, lbar, coefT, mf_re, mf_im, xdump, hy_re, hy_im);
   return hipGetLastError();
 }
 template hipError_t fields_coeff<double>(hipStream_t, int, int, uint64_t, uint64_t, int, double,
                                          const double*, const double*, const double*, double*,
-                                         double*, double*, double*);
+                                         double*, double*, double*, double*, double*);
 template hipError_t fields_coeff<float>(hipStream_t, int, int, uint64_t, uint64_t, int, double,
                                         const double*, const double*, const double*, float*,
-                                        double*, double*, double*);
+                                        double*, double*, double*, double*, double*);
 
 // ===========================================================================
 // Overlap, inverse, log det and Theta, FP64 (Sec. II mixed estimates; the
@@ -1432,9 +1446,32 @@ __global__ void k_weight_update(int W, int mode, double dt, double e_trial,
                                 const double* __restrict__ eln_re, const double* __restrict__ eln_im,
                                 const double* __restrict__ mf_re, const double* __restrict__ mf_im,
                                 const int* __restrict__ vfin, double* weight, double* logS_re,
-                                double* logS_im, double* eloc_re, double* eloc_im, int* dead) {
+                                double* logS_im, double* eloc_re, double* eloc_im, int* dead,
+                                const double* __restrict__ hy_re, const double* __restrict__ hy_im,
+                                double e0) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
+  if (mode == 3 || mode == 4) {
+    // hybrid: W |I| exp(-dt (E_0 - E_T)) max(0, cos dtheta), log I = log r + hy;
+    // mode 3 also takes the new E_L (a measurement step)
+    const double lr = lsn_re[w] - logS_re[w] + mf_re[w];
+    const double li = lsn_im[w] - logS_im[w] + mf_im[w];
+    const double c = cos(li);
+    const double wn = weight[w] * exp(lr + hy_re[w] - dt * (e0 - e_trial)) * (c > 0.0 ? c : 0.0);
+    bool ok = isfinite(wn) && isfinite(lr) && isfinite(li) && isfinite(hy_re[w]) &&
+              isfinite(hy_im[w]) && isfinite(lsn_re[w]) && isfinite(lsn_im[w]) && vfin[w] &&
+              wn > 0.0;
+    if (mode == 3) {
+      ok = ok && isfinite(eln_re[w]) && isfinite(eln_im[w]);
+      eloc_re[w] = eln_re[w];
+      eloc_im[w] = eln_im[w];
+    }
+    weight[w] = ok ? wn : 0.0;
+    logS_re[w] = lsn_re[w];
+    logS_im[w] = lsn_im[w];
+    dead[w] = ok ? 0 : 1;
+    return;
+  }
   if (mode == 2) {
     logS_re[w] = lsn_re[w];
     logS_im[w] = lsn_im[w];
@@ -1466,10 +1503,75 @@ hipError_t weight_update(hipStream_t st, int W, int mode, double dt, double e_tr
                          const double* lsn_re, const double* lsn_im, const double* eln_re,
                          const double* eln_im, const double* mf_re, const double* mf_im,
                          const int* vfin, double* weight, double* logS_re, double* logS_im,
-                         double* eloc_re, double* eloc_im, int* dead) {
+                         double* eloc_re, double* eloc_im, int* dead, const double* hy_re,
+                         const double* hy_im, double e0) {
   hipLaunchKernelGGL(k_weight_update, dim3((W + 255) / 256), dim3(256), 0, st, W, mode, dt,
                      e_trial, lsn_re, lsn_im, eln_re, eln_im, mf_re, mf_im, vfin, weight, logS_re,
-                     logS_im, eloc_re, eloc_im, dead);
+                     logS_im, eloc_re, eloc_im, dead, hy_re, hy_im, e0);
+  return hipGetLastError();
+}
+
+__global__ void k_hybrid_finish(int W, int G, int nz, const double* __restrict__ part_re,
+                                const double* __restrict__ part_im, double* v_re, double* v_im,
+                                const double* __restrict__ ld_re, const double* __restrict__ ld_im,
+                                double* lsn_re, double* lsn_im, int* vfin) {
+  // one block per walker: v_g = sum_z part[z][w][g] (fixed order), flags
+  __shared__ int ok_sh;
+  const int w = blockIdx.x;
+  if (threadIdx.x == 0) ok_sh = 1;
+  __syncthreads();
+  int ok = 1;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    double sr = 0.0, si = 0.0;
+    for (int z = 0; z < nz; ++z) {
+      sr += part_re[((long)z * W + w) * G + g];
+      si += part_im[((long)z * W + w) * G + g];
+    }
+    v_re[(long)w * G + g] = sr;
+    v_im[(long)w * G + g] = si;
+    if (!isfinite(sr) || !isfinite(si)) ok = 0;
+  }
+  if (!ok) ok_sh = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    lsn_re[w] = ld_re[2 * w] + ld_re[2 * w + 1];
+    lsn_im[w] = ld_im[2 * w] + ld_im[2 * w + 1];
+    vfin[w] = ok_sh;
+  }
+}
+
+hipError_t hybrid_force_bias_finish(hipStream_t st, int W, int G, int nz, const double* part_re,
+                                    const double* part_im, double* v_re, double* v_im,
+                                    const double* ld_re, const double* ld_im, double* lsn_re,
+                                    double* lsn_im, int* vfin) {
+  hipLaunchKernelGGL(k_hybrid_finish, dim3(W), dim3(256), 0, st, W, G, nz, part_re, part_im, v_re,
+                     v_im, ld_re, ld_im, lsn_re, lsn_im, vfin);
+  return hipGetLastError();
+}
+
+__global__ void k_build_lcat(long n, int G, int M, int MP4, int Nt, int n_up, int NP0, int NP1,
+                             const double* __restrict__ Lt0, const double* __restrict__ Lt1,
+                             double* __restrict__ Lcat) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int g = (int)(e % G);
+    const long k = e / G;
+    const int m = (int)(k / Nt), b = (int)(k % Nt);
+    const bool up = b < n_up;
+    const int a = up ? b : b - n_up;
+    const int NP = up ? NP0 : NP1;
+    const double* Lt = up ? Lt0 : Lt1;
+    Lcat[e] = Lt[((long)g * MP4 + m) * NP + a];
+  }
+}
+
+hipError_t build_lcat(hipStream_t st, int G, int M, int MP4, int Nt, int n_up, int n_dn, int NP0,
+                      int NP1, const double* Lt0, const double* Lt1, double* Lcat) {
+  (void)n_dn;
+  const long n = (long)M * Nt * G;
+  if (n == 0) return hipSuccess;
+  const int blocks = (int)std::min<long>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_build_lcat, dim3(blocks), dim3(256), 0, st, n, G, M, MP4, Nt, n_up, NP0, NP1,
+                     Lt0, Lt1, Lcat);
   return hipGetLastError();
 }
 

@@ -39,7 +39,8 @@ hipError_t cgemm_walkers(hipStream_t st, int W, int Mr, int Nc, int K, const T* 
 template <typename T>
 hipError_t fields_coeff(hipStream_t st, int W, int G, uint64_t seed, uint64_t t, int system_id,
                         double dt, const double* v_re, const double* v_im, const double* lbar,
-                        T* coefT, double* mf_re, double* mf_im, double* xdump);
+                        T* coefT, double* mf_re, double* mf_im, double* xdump,
+                        double* hy_re = nullptr, double* hy_im = nullptr);
 
 // Per (walker, spin): S = D_0^T phi, LU/Gauss-Jordan inverse, log det, Theta = phi S^-1,
 // E1 = Tr(htil Theta).
@@ -69,12 +70,16 @@ hipError_t combine_single(hipStream_t st, int W, int G, double e_core, const dou
                           const double* ld_im, double* v_re, double* v_im, double* lsn_re,
                           double* lsn_im, double* eln_re, double* eln_im, int* vfin);
 
-// mode 0: logS, eloc <- new values.  mode 1: phaseless weight update.  mode 2: logS only.
+// mode 0: logS, eloc <- new values.  mode 1: phaseless weight update in the local-energy
+// form.  mode 2: logS only.  modes 3 / 4: hybrid form (hy = sum_g (x xbar - xbar^2/2),
+// e0 = E_0) with / without taking the new E_L.
 hipError_t weight_update(hipStream_t st, int W, int mode, double dt, double e_trial,
                          const double* lsn_re, const double* lsn_im, const double* eln_re,
                          const double* eln_im, const double* mf_re, const double* mf_im,
                          const int* vfin, double* weight, double* logS_re, double* logS_im,
-                         double* eloc_re, double* eloc_im, int* dead);
+                         double* eloc_re, double* eloc_im, int* dead,
+                         const double* hy_re = nullptr, const double* hy_im = nullptr,
+                         double e0 = 0.0);
 
 // Dead walkers back to the reference determinant and its state.
 hipError_t reset_dead(hipStream_t st, int W, int M, int Nt, int G, const int* dead,
@@ -153,9 +158,19 @@ hipError_t transpose_f64_bf16(hipStream_t st, int rows, int cols, int ld_dst, lo
 template <typename TOut>
 hipError_t gemm_bf16(hipStream_t st, int Mr, int Nc, int K, const void* A, int lda, const void* B,
                      int ldb, TOut* C, int ldc, double alpha);
+// Hybrid weights: v = Theta_flat Lcat by split-K GEMM partials summed here;
+// lsn = ld_up + ld_dn and vfin = all v finite per walker.
+hipError_t hybrid_force_bias_finish(hipStream_t st, int W, int G, int nz, const double* part_re,
+                                    const double* part_im, double* v_re, double* v_im,
+                                    const double* ld_re, const double* ld_im, double* lsn_re,
+                                    double* lsn_im, int* vfin);
+// Lcat[(m Nt + off_s + a)][g] = Lt_s[g][m][a] for both spins (single determinant).
+hipError_t build_lcat(hipStream_t st, int G, int M, int MP4, int Nt, int n_up, int n_dn, int NP0,
+                      int NP1, const double* Lt0, const double* Lt1, double* Lcat);
 hipError_t fields_coeff_bf16(hipStream_t st, int W, int G, int ldg, uint64_t seed, uint64_t t,
                              int system_id, double dt, const double* v_re, const double* v_im,
-                             const double* lbar, void* coef, double* mf_re, double* mf_im);
+                             const double* lbar, void* coef, double* mf_re, double* mf_im,
+                             double* hy_re = nullptr, double* hy_im = nullptr);
 hipError_t exchange_bf16(hipStream_t st, int W, int M, int MP32, int Nt, int G, SpinGeom s0,
                          SpinGeom s1, const double* thr, const double* thi, double* vs_re,
                          double* vs_im, double* exx_re, double* exx_im, size_t max_lds);

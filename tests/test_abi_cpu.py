@@ -72,9 +72,10 @@ def test_struct_layouts_match_header():
     _abi, _ = _lib()
     # int32, int32, 8 pointers, size_t
     assert ctypes.sizeof(_abi.WalkersStruct) == 8 + 8 * 8 + 8
-    # 3 x int32 (+4 pad), double, 2 x enum(int)
-    assert ctypes.sizeof(_abi.OptionsStruct) == 32
+    # 3 x int32 (+4 pad), double, 2 x enum(int), 2 x int32
+    assert ctypes.sizeof(_abi.OptionsStruct) == 40
     assert _abi.OptionsStruct.e_trial.offset == 16
+    assert _abi.OptionsStruct.weight_mode.offset == 32
 
 
 def test_package_fails_loudly_without_library(tmp_path):

@@ -591,3 +591,87 @@ def test_hchain_subset_1000_steps(afq, prec, n_pin, tol):
           f" runs part (|dE_mix| > 1e-6 Ha) at step {int(part[0]) if part.size else None}")
     assert np.all(np.isfinite(ref)) and np.all(np.isfinite(em))
     assert err[:n_pin].max() <= tol
+
+
+# --------------------------------------------------------------------------
+# Hybrid weight form (Sec. IV.A): E_L measured every meas_every steps
+# --------------------------------------------------------------------------
+
+def _run_both_hybrid(afq, inp, W, n_steps, dt, opt_kw, prec=("fp64", "fp64"), seed=0):
+    ham, trial, w = _make(afq, inp, W)
+    afq.walkers_from_trial(ham, trial, w)
+    et = afq.local_energy(ham, trial, w)
+    opt = afq.Options(e_trial=et, chol_prec=prec[0], taylor_prec=prec[1], weight_mode="hybrid",
+                      **opt_kw)
+    em = _np(afq.propagate(ham, trial, w, n_steps, dt, seed, 0, opt))
+    o = Oracle.from_inputs(inp)
+    st = o.init_walkers(W)
+    oe = o.propagate(st, n_steps, dt, seed, 0, OOptions(e_trial=et, weight_mode=1, **opt_kw))
+    return em, oe, w, st
+
+
+def test_hybrid_plain_fp64_parity(afq):
+    """10-orbital workload, 64 walkers, 40 steps, E_L every 5 steps, comb every
+    10: E_mix at the measured steps and the final weights within 1e-9 of the
+    oracle; the other steps report NaN on both sides."""
+    _say("hybrid plain-M10 fp64 40 steps")
+    wl = syn.WORKLOADS["plain-M10"]
+    inp = syn.workload_system(wl)
+    em, oe, w, st = _run_both_hybrid(afq, inp, 64, 40, wl.dt,
+                                     dict(taylor_order=6, ortho_every=2, pc_every=10, meas_every=5))
+    meas = np.arange(40) % 5 == 4
+    assert np.all(np.isnan(em[~meas])) and np.all(np.isnan(oe[~meas]))
+    print("hybrid fp64: max |dE_mix| =", np.max(np.abs(em[meas] - oe[meas])))
+    assert np.max(np.abs(em[meas] - oe[meas])) <= 1e-9
+    assert np.allclose(_np(w.weight), st.weight, rtol=1e-9, atol=1e-12)
+
+
+def test_hybrid_hchain_fp32(afq):
+    """Hydrogen-chain workload, 32 walkers, 40 steps, FP32 contractions and
+    Taylor, E_L every 10 steps: E_mix at the measured steps within the
+    0.1 mHa gate of the FP64 oracle."""
+    _say("hybrid hchain fp32 32 walkers 40 steps")
+    wl = syn.WORKLOADS["hchain-M50"]
+    inp = syn.workload_system(wl)
+    em, oe, w, st = _run_both_hybrid(afq, inp, 32, 40, wl.dt,
+                                     dict(taylor_order=6, ortho_every=10, pc_every=0, meas_every=10),
+                                     prec=("fp32", "fp32"))
+    meas = np.arange(40) % 10 == 9
+    err = np.max(np.abs(em[meas] - oe[meas]))
+    print("hybrid fp32 hchain: max |dE_mix| =", err, "E_mix", oe[meas])
+    assert np.all(np.isfinite(oe[meas]))
+    assert err <= 1e-4
+
+
+def test_hybrid_multidet_fp64_parity(afq):
+    """Multi-determinant trial in the hybrid form (every step measured on the
+    GPU's multi-determinant route, weights from the importance function)."""
+    _say("hybrid multidet fp64")
+    M, nu, nd, G = 10, 3, 2, 12
+    inp = syn.make_system(M, nu, nd, G, 8.0, n_det=12, seed=41)
+    em, oe, w, st = _run_both_hybrid(afq, inp, 16, 12, 0.01,
+                                     dict(taylor_order=6, ortho_every=2, pc_every=0, meas_every=4))
+    meas = np.arange(12) % 4 == 3
+    print("hybrid multidet: max |dE_mix| =", np.max(np.abs(em[meas] - oe[meas])))
+    assert np.max(np.abs(em[meas] - oe[meas])) <= 1e-9
+    assert np.allclose(_np(w.weight), st.weight, rtol=1e-9, atol=1e-12)
+
+
+def test_hybrid_zero_variance_one_body(afq):
+    """L = 0, eigenvector trial: measured E_mix exact, hybrid weights equal
+    the local-energy form's."""
+    _say("hybrid zero variance one-body")
+    M, nu, nd = 9, 3, 2
+    inp = syn.make_system(M, nu, nd, 4, 4.0, seed=5, e_core=1.25)
+    inp.L = np.zeros_like(inp.L)
+    eps = np.linalg.eigvalsh(inp.h)
+    exact = inp.e_core + eps[:nu].sum() + eps[:nd].sum()
+    res = []
+    for mode in ("local", "hybrid"):
+        ham, trial, w = _make(afq, inp, 8)
+        afq.walkers_from_trial(ham, trial, w)
+        opt = afq.Options(e_trial=exact + 0.5, ortho_every=2, weight_mode=mode, meas_every=3)
+        em = _np(afq.propagate(ham, trial, w, 9, 0.02, 1, 0, opt))
+        res.append((em, _np(w.weight)))
+    assert np.allclose(res[1][0][2::3], exact, atol=1e-12)
+    assert np.allclose(res[0][1], res[1][1], rtol=1e-12)
