@@ -40,6 +40,19 @@ def exchange_flops_per_walker(M, n_up, n_dn, G):
     return sum(G * (4 * n * n * M + 8 * n * n) for n in (n_up, n_dn))
 
 
+def qform_flops_per_walker(M, n_up, n_dn):
+    """Q route exchange: per spin theta^T Q theta over the K = M N_sigma index
+    with Q symmetric (K (K + 1) / 2 distinct entries, each a complex-by-real
+    multiply-add: 2 K (K + 1) flops)."""
+    return sum(2 * (M * n) * (M * n + 1) for n in (n_up, n_dn))
+
+
+def fbias_flops_per_walker(M, n_up, n_dn, G):
+    """Force bias v_g = sum_k theta_k Lq[k][g] (complex 1 x M Nt times real
+    M Nt x G: 4 M Nt G flops)."""
+    return 4 * M * (n_up + n_dn) * G
+
+
 def multidet_flops_per_walker(M, n_up, n_dn, G):
     """Multi-determinant energy: per spin and per g (the G vectors and h),
     P_g = (C^T L_g) Theta_0 (real M x M times complex M x N: 4 M^2 N flops)
@@ -284,6 +297,8 @@ def main():
                     help="local-energy weights every step (default) or the hybrid form")
     ap.add_argument("--meas-every", type=int, default=20,
                     help="hybrid form: steps between E_L measurements")
+    ap.add_argument("--exchange-route", choices=["auto", "ltilde", "q"], default="auto",
+                    help="exchange route of single-determinant trials (auto: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=80)
@@ -336,6 +351,9 @@ def main():
     multi = inp.n_det > 1
     trial = afq.Trial(ham, inp.n_up, inp.n_dn, inp.C_up, inp.C_dn,
                       inp.coeff if multi else None, inp.exc if multi else None)
+    if args.exchange_route != "auto":
+        trial.exchange_route = args.exchange_route
+    route = trial.exchange_route if chol_prec != "bf16" else "ltilde"
     w = afq.Walkers(trial, W)
     afq.walkers_from_trial(ham, trial, w)
     et = afq.local_energy(ham, trial, w)
@@ -381,11 +399,22 @@ def main():
     if multi:
         flops = multidet_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
         kname = "k_md_energy (P = (C^T L_g) Theta_0, X0^2, per-determinant corrections)"
+    elif route == "q":
+        flops = qform_flops_per_walker(wl.M, wl.n_up, wl.n_dn) * W
+        kname = "k_qform (theta^T Q theta, upper-triangular tile pairs)"
     else:
         flops = exchange_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
         kname = ("k_exchange_full (fused Ltil*Theta, Tr X, Tr XX)"
                  if max(wl.n_up, wl.n_dn) <= 32 else "k_exchange (fused Ltil*Theta, Tr X, Tr XX)")
     avg_s = (ms_ex / n_ex) / 1e3 if n_ex else float("nan")
+    fbias_report = None
+    n_fb, ms_fb = ktimes["force_bias"]
+    if route == "q" and n_fb and not multi:
+        # the force-bias class: Theta split, k_fbias_mm and the partial sum
+        fb_flops = fbias_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
+        fb_s = (ms_fb / n_fb) / 1e3
+        fbias_report = {"flops_per_launch": fb_flops, "avg_launch_ms": fb_s * 1e3,
+                        "achieved_tflops": fb_flops / fb_s / 1e12, "launches": n_fb}
     peak = {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}[chol_prec]
     achieved = flops / avg_s / 1e12 if n_ex else float("nan")
     value = W * args.steps / elapsed
@@ -406,7 +435,7 @@ def main():
                    "n_chol": wl.n_chol, "n_walkers": W, "dt": wl.dt,
                    "taylor_order": wl.taylor_order, "ortho_every": wl.ortho_every,
                    "pc_every": wl.pc_every, "n_det": inp.n_det, "l_scale": wl.l_scale,
-                   "weight_mode": args.weight_mode,
+                   "weight_mode": args.weight_mode, "exchange_route": route,
                    "meas_every": args.meas_every if args.weight_mode == "hybrid" else 1,
                    "precision": f"contractions {chol_prec}, Taylor/B1 {taylor_prec}, "
                                 "overlap/inverse/det/MGS/sums fp64",
@@ -417,6 +446,7 @@ def main():
                      "traffic": measured_traffic(wl.name, chol_prec),
                      "flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3, "launches": n_ex},
         "kernel_ms_per_step": {k: (v[1] / max(args.steps, 1)) for k, v in ktimes.items() if v[0]},
+        "force_bias_class": fbias_report,
         "time_to_energy_s": {"p50": float(np.percentile(tte, 50)) if tte else None,
                              "p99": float(np.percentile(tte, 99)) if tte else None,
                              "repeats": len(tte), "steps": args.tte_steps},

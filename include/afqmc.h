@@ -146,6 +146,21 @@ afqmc_status afqmc_walker_workspace_bytes(const afqmc_trial *trial, int n_walker
 afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_det,
                                    int n_walkers, size_t *bytes);
 
+/* How the trial evaluates the exchange energy sum_g Tr(X_g X_g), X_g = Ltil_g
+ * Theta (the contraction inside the paper's Eq. Ys): *route = 0 through the
+ * half-rotated vectors Ltil_g per Cholesky index, or 1 through the
+ * precomputed two-index tensor Q[(n a)][(m b)] = sum_g Ltil_g[a][m]
+ * Ltil_g[b][n] per spin, as the quadratic form theta^T Q theta (chosen at
+ * set-up for single-determinant trials with n_chol >= 2 M and M N_sigma <=
+ * 16384; the BF16 contraction mode always takes route 0). */
+afqmc_status afqmc_trial_exchange_route(const afqmc_trial *trial, int *route);
+
+/* Select the exchange route of later measurements: 0 (Ltil) is always
+ * available; 1 (Q) only where set-up built Q, else AFQMC_ERR_UNSUPPORTED and
+ * the route is left as it was.  Not to be called while work that uses the
+ * trial is in flight on any stream. */
+afqmc_status afqmc_trial_set_exchange_route(afqmc_trial *trial, int route);
+
 /* Sets every walker to the reference determinant D_0 with weight 1 and
  * fills logovlp / eloc with the reference values. */
 afqmc_status afqmc_walkers_from_trial(afqmc_ham *ham, afqmc_trial *trial,

@@ -91,6 +91,20 @@ class Trial:
         check(_lib.afqmc_walker_workspace_bytes(self._t, int(n_walkers), ctypes.byref(b)))
         return int(b.value)
 
+    @property
+    def exchange_route(self) -> str:
+        """"ltilde" (per-vector X_g = Ltil_g Theta) or "q" (two-index tensor Q)."""
+        r = ctypes.c_int()
+        check(_lib.afqmc_trial_exchange_route(self._t, ctypes.byref(r)))
+        return "q" if r.value == 1 else "ltilde"
+
+    @exchange_route.setter
+    def exchange_route(self, route: str) -> None:
+        codes = {"ltilde": 0, "q": 1}
+        if route not in codes:
+            raise ValueError(f"exchange route must be one of {sorted(codes)}")
+        check(_lib.afqmc_trial_set_exchange_route(self._t, codes[route]))
+
     def __del__(self):
         t = getattr(self, "_t", None)
         if t and _lib is not None:

@@ -212,10 +212,21 @@ struct afqmc_trial {
   double* lbar = nullptr;
   double* D0 = nullptr;
   // hybrid weights: E_0 = e_core - 1/2 sum lbar^2, and (single determinant)
-  // Lcat[(m Nt + b)][g] = Lt_{spin of b}[g][m][a] for the force bias v = Theta Lcat
+  // the force-bias operand Lq[k][g] = Ltil_g[a][m] at the split index k of
+  // (spin, m, a): spin 0's (m a) -> m N_up + a padded to Kp[0], then spin 1's
   double e0_shift = 0.0;
-  double* Lcat64 = nullptr;
-  float* Lcat32 = nullptr;
+  int Kp[2] = {0, 0};
+  int Gp = 0;
+  double* Lq64 = nullptr;  // [Kp0 + Kp1][Gp], zero padded
+  float* Lq32 = nullptr;
+  // exchange through Q[(n a)][(m b)] = sum_g Ltil_g[a][m] Ltil_g[b][n] per spin
+  // (single determinant, when the Cholesky count makes it the cheaper route)
+  bool qroute = false;  // measurements take the Q route
+  bool qbuilt = false;  // Q64 / Q32 / qsegs are set up
+  double* Q64[2] = {nullptr, nullptr};  // [Kp][Kp], zero padded
+  float* Q32[2] = {nullptr, nullptr};
+  int4* qsegs = nullptr;  // (spin, I, J0, J1) tile-pair segments, spin 0 first
+  int nseg[2] = {0, 0};
   std::vector<double> H1p;
   std::vector<B1Entry> b1;
   int n_det = 1;
@@ -252,6 +263,9 @@ struct WS {
   double* snap;
   size_t total;
 };
+
+// Doubles per walker in each of ws.ACC_re / ws.ACC_im.
+long acc_cap(long M, long G, long Nt) { return std::max(M * Nt, G); }
 
 WS layout_dims(long M, long G, long Nt, int n_det, int W, void* base) {
   WS ws;
@@ -290,10 +304,14 @@ WS layout_dims(long M, long G, long Nt, int n_det, int W, void* base) {
   ws.scal = (double*)take(16 * sizeof(double));
   ws.coefT = take((size_t)G * 2 * W * sizeof(double));
   ws.A = take((size_t)W * 2 * M * M * sizeof(double));
-  ws.P_re = (double*)take(wm);
-  ws.P_im = (double*)take(wm);
-  ws.ACC_re = (double*)take(wm);
-  ws.ACC_im = (double*)take(wm);
+  // P_*: also the split Theta of the Q route (M Nt + 128 per walker);
+  // ACC_*: also the force-bias and quadratic-form partials
+  const size_t wq = (size_t)W * (M * Nt + 128) * sizeof(double);
+  const size_t wa = (size_t)W * acc_cap(M, G, Nt) * sizeof(double);
+  ws.P_re = (double*)take(wq);
+  ws.P_im = (double*)take(wq);
+  ws.ACC_re = (double*)take(wa);
+  ws.ACC_im = (double*)take(wa);
   ws.Ta_re = take(wm);
   ws.Ta_im = take(wm);
   ws.Tb_re = take(wm);
@@ -323,6 +341,47 @@ afqmc_status check_walkers(const afqmc_trial* tr, const afqmc_walkers* wk) {
   if (wk->workspace_bytes < ws.total)
     return fail(AFQMC_ERR_ARG, "workspace_bytes smaller than afqmc_walker_workspace_bytes");
   return AFQMC_OK;
+}
+
+// The Q route for the exchange energy: single determinant, at least twice as
+// many Cholesky vectors as orbitals (it then needs G / M times fewer flops
+// than the Ltil route) and Q (M N x M N per spin) of at most 16384^2 entries.
+int qpad(long K) { return (int)((K + 63) / 64 * 64); }
+
+// Segments of the upper-triangular 64 x 64 tile pairs (I <= J) of both
+// spins: row I of spin s split into runs of at most S column tiles.  S is
+// chosen so that the partials (2 doubles per segment and walker) fit the
+// workspace; returns the segment count per spin or false.
+bool q_plan(int M, int G, int n_up, int n_dn, std::vector<int4>* segs, int nseg[2]) {
+  const int nel[2] = {n_up, n_dn};
+  int nt[2];
+  for (int s = 0; s < 2; ++s) nt[s] = qpad((long)M * nel[s]) / 64;
+  const long cap = acc_cap(M, G, n_up + n_dn);
+  for (int S = std::max(4, std::min(16, (std::max(nt[0], nt[1]) + 4) / 5)); ; S *= 2) {
+    long tot = 0;
+    for (int s = 0; s < 2; ++s) {
+      nseg[s] = 0;
+      for (int I = 0; I < nt[s]; ++I) nseg[s] += (nt[s] - I + S - 1) / S;
+      tot += nseg[s];
+    }
+    if (2 * tot <= cap) {
+      if (segs) {
+        segs->clear();
+        for (int s = 0; s < 2; ++s)
+          for (int I = 0; I < nt[s]; ++I)
+            for (int J = I; J < nt[s]; J += S) segs->push_back(make_int4(s, I, J, std::min(J + S, nt[s])));
+      }
+      return true;
+    }
+    if (S >= std::max(nt[0], nt[1])) return false;
+  }
+}
+
+bool use_qroute(int M, int G, int n_up, int n_dn, int n_det) {
+  if (n_det != 1 || G < 2 * M) return false;
+  if ((long)M * std::max(n_up, n_dn) > 16384) return false;
+  int ns[2];
+  return q_plan(M, G, n_up, n_dn, nullptr, ns);
 }
 
 // Elements of the exchange kernels' repacked A operand for one spin (NP <= 64).
@@ -363,18 +422,42 @@ afq::MDParams md_params(const afqmc_trial* tr, bool fp32) {
   return p;
 }
 
+// Theta as the FP64 matrix in ws.th_*, or as the Q route's split rows in
+// ws.P_* (contraction type).
+afq::ThetaOut fp64_out(const WS& ws) {
+  afq::ThetaOut o;
+  o.thr = ws.th_re;
+  o.thi = ws.th_im;
+  return o;
+}
+
+afq::ThetaOut split_out(const afqmc_trial* tr, const WS& ws, bool f32) {
+  afq::ThetaOut o;
+  o.sr = ws.P_re;
+  o.si = ws.P_im;
+  o.Ktot = tr->Kp[0] + tr->Kp[1];
+  o.Kp0 = tr->Kp[0];
+  o.f32 = f32;
+  return o;
+}
+
 // Overlap / Theta / exchange / combination for the current phi; leaves the new
 // log overlap and E_L in ws.lsn / ws.eln and the force-bias traces in ws.v.
+afqmc_status measure_qroute(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bool fp32,
+                            hipStream_t st);
+
 afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqmc_prec chol,
                           hipStream_t st) {
   afqmc_ham* hm = tr->ham;
   const int W = wk->n_walkers, M = hm->M, G = hm->G, Nt = tr->Nt;
   const bool f32 = chol == AFQMC_FP32;
   const afq::SpinGeom s0 = spin_geom(tr, 0, chol), s1 = spin_geom(tr, 1, chol);
+  const bool qr = tr->n_det == 1 && G > 0 && tr->qroute && chol != AFQMC_BF16;
   {
     TimedLaunch tl(&hm->timer, KC_OVERLAP, st);
-    AFQ_CK(afq::overlap_theta(st, W, M, Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re, ws.th_im,
-                              ws.ld_re, ws.ld_im, ws.e1_re, ws.e1_im, hm->max_lds));
+    AFQ_CK(afq::overlap_theta(st, W, M, Nt, s0, s1, wk->phi_re, wk->phi_im,
+                              qr ? split_out(tr, ws, f32) : fp64_out(ws), ws.ld_re, ws.ld_im,
+                              ws.e1_re, ws.e1_im, hm->max_lds));
   }
   if (tr->n_det > 1) {
     const afq::MDParams mp = md_params(tr, f32);
@@ -395,7 +478,10 @@ afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqm
     }
     return AFQMC_OK;
   }
-  if (G > 0) {
+  if (qr) {
+    afqmc_status rq = measure_qroute(tr, wk, ws, f32, st);
+    if (rq != AFQMC_OK) return rq;
+  } else if (G > 0) {
     TimedLaunch tl(&hm->timer, KC_EXCHANGE, st);
     if (chol == AFQMC_BF16) {
       AFQ_CK(afq::exchange_bf16(st, W, M, tr->MP32, Nt, G, s0, s1, ws.th_re, ws.th_im, ws.vs_re,
@@ -436,8 +522,10 @@ afqmc_status orthonormalize_impl(afqmc_trial* tr, afqmc_walkers* wk, const WS& w
                     hm->max_lds));
   }
   const afq::SpinGeom s0 = spin_geom(tr, 0, AFQMC_FP64), s1 = spin_geom(tr, 1, AFQMC_FP64);
-  AFQ_CK(afq::overlap_theta(st, W, hm->M, tr->Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re,
-                            ws.th_im, ws.ld_re, ws.ld_im, ws.e1_re, ws.e1_im, hm->max_lds));
+  // log det and E1 only: Theta is not stored (multi-determinant trials need it)
+  AFQ_CK(afq::overlap_theta(st, W, hm->M, tr->Nt, s0, s1, wk->phi_re, wk->phi_im,
+                            tr->n_det > 1 ? fp64_out(ws) : afq::ThetaOut(), ws.ld_re, ws.ld_im,
+                            ws.e1_re, ws.e1_im, hm->max_lds));
   if (tr->n_det > 1) {
     const afq::MDParams mp = md_params(tr, false);
     AFQ_CK(afq::md_overlap(st, W, mp, ws.th_re, ws.th_im, ws.ld_re, ws.ld_im, ws.c0_re, ws.c0_im,
@@ -518,10 +606,54 @@ B1Entry* get_b1(afqmc_trial* tr, double dt, hipStream_t st, afqmc_status* err) {
 
 struct Bf16Tag {};
 
-// Hybrid steps without a measurement (single determinant): overlap, Theta and
-// log S', then the force bias v_g = sum_(m,b) Theta[m][b] Lcat[(m,b)][g] as a
-// GEMM over all walkers, split over K = M Nt into nz partials (in the Taylor
-// accumulators, free at this point) summed in a fixed order.
+// Force bias v_g = sum_k ts[k] Lq[k][g] for all walkers (single determinant)
+// from the split Theta rows in ws.P_* (contraction type), as a GEMM split over
+// k into nz partials in ws.ACC_* (free outside the propagation); returns nz.
+int force_bias_partials(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bool fp32,
+                        hipStream_t st, hipError_t* err) {
+  afqmc_ham* hm = tr->ham;
+  const int W = wk->n_walkers, M = hm->M, G = hm->G, Nt = tr->Nt;
+  const int Ktot = tr->Kp[0] + tr->Kp[1];
+  const int nz = afq::fbias_nz(W, Ktot, G, fp32 ? 4 : 8, acc_cap(M, G, Nt));
+  if (fp32)
+    *err = afq::fbias_mm<float>(st, W, Ktot, G, tr->Gp, nz, (const float*)ws.P_re,
+                                (const float*)ws.P_im, tr->Lq32, ws.ACC_re, ws.ACC_im);
+  else
+    *err = afq::fbias_mm<double>(st, W, Ktot, G, tr->Gp, nz, ws.P_re, ws.P_im, tr->Lq64, ws.ACC_re,
+                                 ws.ACC_im);
+  return nz;
+}
+
+// E_L ingredients by the Q route (single determinant): the force bias into
+// the per-spin trace layout, then per spin theta^T Q theta over the split
+// Theta that the force bias left in ws.P_* (partials in ws.ACC_re).
+afqmc_status measure_qroute(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bool fp32,
+                            hipStream_t st) {
+  afqmc_ham* hm = tr->ham;
+  const int W = wk->n_walkers, G = hm->G;
+  {
+    TimedLaunch tl(&hm->timer, KC_FBIAS, st);
+    hipError_t e;
+    const int nz = force_bias_partials(tr, wk, ws, fp32, st, &e);
+    AFQ_CK(e);
+    AFQ_CK(afq::fbias_to_vs(st, W, G, nz, ws.ACC_re, ws.ACC_im, ws.vs_re, ws.vs_im));
+  }
+  const int nseg = tr->nseg[0] + tr->nseg[1];
+  {
+    TimedLaunch tl(&hm->timer, KC_EXCHANGE, st);
+    if (fp32) {
+      AFQ_CK(afq::qform<float>(st, W, tr->Kp[0], tr->Kp[1], nseg, tr->qsegs, (const float*)ws.P_re,
+                               (const float*)ws.P_im, tr->Q32[0], tr->Q32[1], ws.ACC_re));
+    } else {
+      AFQ_CK(afq::qform<double>(st, W, tr->Kp[0], tr->Kp[1], nseg, tr->qsegs, ws.P_re, ws.P_im,
+                                tr->Q64[0], tr->Q64[1], ws.ACC_re));
+    }
+  }
+  TimedLaunch tl(&hm->timer, KC_OTHER, st);
+  AFQ_CK(afq::qform_reduce(st, W, tr->nseg[0], tr->nseg[1], ws.ACC_re, ws.exx_re, ws.exx_im));
+  return AFQMC_OK;
+}
+
 afqmc_status hybrid_force_bias(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bool fp32,
                                hipStream_t st) {
   afqmc_ham* hm = tr->ham;
@@ -529,29 +661,16 @@ afqmc_status hybrid_force_bias(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws,
   const afq::SpinGeom s0 = spin_geom(tr, 0, AFQMC_FP64), s1 = spin_geom(tr, 1, AFQMC_FP64);
   {
     TimedLaunch tl(&hm->timer, KC_OVERLAP, st);
-    AFQ_CK(afq::overlap_theta(st, W, M, Nt, s0, s1, wk->phi_re, wk->phi_im, ws.th_re, ws.th_im,
-                              ws.ld_re, ws.ld_im, ws.e1_re, ws.e1_im, hm->max_lds));
+    AFQ_CK(afq::overlap_theta(st, W, M, Nt, s0, s1, wk->phi_re, wk->phi_im,
+                              split_out(tr, ws, fp32), ws.ld_re, ws.ld_im, ws.e1_re, ws.e1_im,
+                              hm->max_lds));
   }
-  const long K = (long)M * Nt;
-  int nz = 1;
-  for (int c : {8, 4, 2})
-    if (K % c == 0 && (long)c * G <= K) { nz = c; break; }
-  const int Kc = (int)(K / nz);
+  int nz;
   {
     TimedLaunch tl(&hm->timer, KC_FBIAS, st);
-    for (int part = 0; part < 2; ++part) {
-      const double* th = part ? ws.th_im : ws.th_re;
-      double* out = part ? ws.ACC_im : ws.ACC_re;
-      if (fp32) {
-        float* a32 = (float*)(part ? ws.P_im : ws.P_re);
-        AFQ_CK(afq::convert_f64_f32(st, th, a32, (long)W * K));
-        AFQ_CK((afq::gemm_real<float, double, false>(st, W, G, Kc, a32, (int)K, Kc, tr->Lcat32, G,
-                                                     (long)Kc * G, out, G, (long)W * G, nz, 1.0)));
-      } else {
-        AFQ_CK((afq::gemm_real<double, double, false>(st, W, G, Kc, th, (int)K, Kc, tr->Lcat64, G,
-                                                      (long)Kc * G, out, G, (long)W * G, nz, 1.0)));
-      }
-    }
+    hipError_t e;
+    nz = force_bias_partials(tr, wk, ws, fp32, st, &e);
+    AFQ_CK(e);
   }
   AFQ_CK(afq::hybrid_force_bias_finish(st, W, G, nz, ws.ACC_re, ws.ACC_im, ws.v_re, ws.v_im, ws.ld_re,
                                        ws.ld_im, ws.lsn_re, ws.lsn_im, ws.vfin));
@@ -763,7 +882,15 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
   }
   tot += 3 * rnd(std::max<size_t>(g, 1) * 8) + rnd(m * Nt * 8) + rnd(mm * 8) + 2 * rnd(mm * 12);
   if (n_det > 1) tot += rnd((size_t)n_det * 40) + rnd((size_t)n_det * 8);
-  if (n_det == 1 && g > 0) tot += rnd(m * Nt * g * 8) + rnd(m * Nt * g * 4);  // Lcat
+  const size_t kq[2] = {(size_t)qpad((long)M * n_up), (size_t)qpad((long)M * n_dn)};
+  if (n_det == 1 && g > 0) tot += rnd((kq[0] + kq[1]) * qpad(g) * 12);  // Lq
+  if (use_qroute(M, n_chol, n_up, n_dn, n_det)) {
+    int ns[2];
+    q_plan(M, n_chol, n_up, n_dn, nullptr, ns);
+    tot += rnd((size_t)(ns[0] + ns[1]) * 16);
+    for (int s = 0; s < 2; ++s)
+      if (nel[s]) tot += rnd(kq[s] * kq[s] * 8) + rnd(kq[s] * kq[s] * 4);
+  }
   tot += 2 * rnd((size_t)n_walkers * m * Nt * 8) + 5 * rnd((size_t)n_walkers * 8);  // walkers
   tot += layout_dims(M, n_chol, (long)Nt, n_det, n_walkers, nullptr).total;
   *bytes = tot;
@@ -964,17 +1091,56 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
     for (int g = 0; g < G; ++g) s2 += lb[g] * lb[g];
     tr->e0_shift = hm->e_core - 0.5 * s2;
   }
+  for (int s = 0; s < 2; ++s) tr->Kp[s] = qpad((long)M * nel[s]);
+  tr->Gp = qpad(G);
   if (n_det == 1 && G > 0) {
-    const size_t nk = (size_t)M * tr->Nt * G;
+    const size_t nk = (size_t)(tr->Kp[0] + tr->Kp[1]) * tr->Gp;
     void *q64, *q32;
     if (tr->arena.alloc(&q64, nk * 8) || tr->arena.alloc(&q32, nk * 4))
       return bad(AFQMC_ERR_OOM, "trial allocation failed");
-    tr->Lcat64 = (double*)q64;
-    tr->Lcat32 = (float*)q32;
-    if (afq::build_lcat(st, G, M, tr->MP4, tr->Nt, n_up, n_dn, tr->NP[0], tr->NP[1], tr->Lt64[0],
-                        tr->Lt64[1], tr->Lcat64) != hipSuccess ||
-        afq::convert_f64_f32(st, tr->Lcat64, tr->Lcat32, (long)nk) != hipSuccess)
-      return bad(AFQMC_ERR_DEVICE, "Lcat");
+    tr->Lq64 = (double*)q64;
+    tr->Lq32 = (float*)q32;
+    if (afq::build_lsplit(st, G, tr->Gp, M, tr->MP4, n_up, n_dn, tr->NP[0], tr->NP[1], tr->Kp[0],
+                          tr->Kp[1], tr->Lt64[0], tr->Lt64[1], tr->Lq64) != hipSuccess ||
+        afq::convert_f64_f32(st, tr->Lq64, tr->Lq32, (long)nk) != hipSuccess)
+      return bad(AFQMC_ERR_DEVICE, "force-bias operand");
+  }
+  if (use_qroute(M, G, n_up, n_dn, n_det)) {
+    std::vector<int4> segs;
+    q_plan(M, G, n_up, n_dn, &segs, tr->nseg);
+    void* ps;
+    if (tr->arena.alloc(&ps, segs.size() * sizeof(int4)))
+      return bad(AFQMC_ERR_OOM, "trial allocation failed");
+    tr->qsegs = (int4*)ps;
+    if (hipMemcpy(tr->qsegs, segs.data(), segs.size() * sizeof(int4), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return bad(AFQMC_ERR_DEVICE, "segment upload");
+    for (int s = 0; s < 2; ++s) {
+      if (nel[s] == 0) continue;
+      const long Kq = tr->Kp[s], Kp = (long)tr->MP4 * tr->NP[s];
+      void *q64, *q32;
+      if (tr->arena.alloc(&q64, (size_t)Kq * Kq * 8) || tr->arena.alloc(&q32, (size_t)Kq * Kq * 4))
+        return bad(AFQMC_ERR_OOM, "trial allocation failed");
+      tr->Q64[s] = (double*)q64;
+      tr->Q32[s] = (float*)q32;
+      // P = R^T R over the padded index (m NP + a), then the index permutation
+      double* P = nullptr;
+      if (hipMalloc(&P, (size_t)Kp * Kp * 8) != hipSuccess)
+        return bad(AFQMC_ERR_OOM, "Q set-up allocation failed");
+      const bool ok =
+          afq::gemm_real<double, double, true>(st, (int)Kp, (int)Kp, G, tr->Lt64[s], (int)Kp, 0,
+                                               tr->Lt64[s], (int)Kp, 0, P, (int)Kp, 0, 1, 1.0) ==
+              hipSuccess &&
+          afq::perm_qpad<double>(st, M, nel[s], tr->NP[s], tr->MP4, (int)Kq, P, tr->Q64[s]) ==
+              hipSuccess &&
+          afq::perm_qpad<float>(st, M, nel[s], tr->NP[s], tr->MP4, (int)Kq, P, tr->Q32[s]) ==
+              hipSuccess &&
+          hipStreamSynchronize(st) == hipSuccess;
+      (void)hipFree(P);
+      if (!ok) return bad(AFQMC_ERR_DEVICE, "Q set-up");
+    }
+    tr->qbuilt = true;
+    tr->qroute = true;
   }
   if (n_det > 1) {
     void *pe, *pc;
@@ -1179,6 +1345,21 @@ afqmc_status afqmc_propagate(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk, 
 afqmc_status afqmc_timing_enable(afqmc_ham* hm, int enable) {
   if (!hm) return fail(AFQMC_ERR_ARG, "NULL ham");
   hm->timer.enabled = enable != 0;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_trial_exchange_route(const afqmc_trial* tr, int* route) {
+  if (!tr || !route) return fail(AFQMC_ERR_ARG, "NULL trial or route");
+  *route = tr->qroute ? 1 : 0;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_trial_set_exchange_route(afqmc_trial* tr, int route) {
+  if (!tr) return fail(AFQMC_ERR_ARG, "NULL trial");
+  if (route != 0 && route != 1) return fail(AFQMC_ERR_ARG, "route must be 0 (Ltil) or 1 (Q)");
+  if (route == 1 && !tr->qbuilt)
+    return fail(AFQMC_ERR_UNSUPPORTED, "this trial has no Q tensor (see use conditions)");
+  tr->qroute = route == 1;
   return AFQMC_OK;
 }
 

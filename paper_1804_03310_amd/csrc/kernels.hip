@@ -305,12 +305,46 @@ template hipError_t fields_coeff<float>(hipStream_t, int, int, uint64_t, uint64_
 // pivot row goes to a side buffer so one column costs four barriers), then
 // Theta = phi S^-1 and E1 = Tr(htil Theta).
 // ===========================================================================
+__device__ inline void theta_store(const ThetaOut& to, long w, int M, int Nt, int off, int s, int N,
+                                   int m, int b, double vr, double vi) {
+  if (to.thr) {
+    const long o = (w * M + m) * Nt + off + b;
+    to.thr[o] = vr;
+    to.thi[o] = vi;
+  }
+  if (to.sr) {
+    const long o = w * to.Ktot + (s ? to.Kp0 : 0) + (long)m * N + b;
+    if (to.f32) {
+      ((float*)to.sr)[o] = (float)vr;
+      ((float*)to.si)[o] = (float)vi;
+    } else {
+      ((double*)to.sr)[o] = vr;
+      ((double*)to.si)[o] = vi;
+    }
+  }
+}
+
+// zeros in the split row's padding of spin s, threads t0, t0 + nt, ...
+__device__ inline void theta_pad(const ThetaOut& to, long w, int M, int s, int N, int t0, int nt) {
+  if (!to.sr) return;
+  const int kp = s ? to.Ktot - to.Kp0 : to.Kp0;
+  const long o = w * to.Ktot + (s ? to.Kp0 : 0);
+  for (int e = M * N + t0; e < kp; e += nt) {
+    if (to.f32) {
+      ((float*)to.sr)[o + e] = 0.f;
+      ((float*)to.si)[o + e] = 0.f;
+    } else {
+      ((double*)to.sr)[o + e] = 0.0;
+      ((double*)to.si)[o + e] = 0.0;
+    }
+  }
+}
+
 template <bool STAGE>
 __global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s0, SpinGeom s1,
                                                        const double* __restrict__ phr,
                                                        const double* __restrict__ phi,
-                                                       double* __restrict__ thr,
-                                                       double* __restrict__ thi, double* ld_re,
+                                                       ThetaOut to, double* ld_re,
                                                        double* ld_im, double* e1_re, double* e1_im) {
   extern __shared__ double lds[];
   __shared__ double red[4];
@@ -438,12 +472,12 @@ __global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s
       tr += pr * qr - pi * qi;
       ti += pr * qi + pi * qr;
     }
-    thr[wb + (long)m * Nt + off + b] = tr;
-    thi[wb + (long)m * Nt + off + b] = ti;
+    theta_store(to, w, M, Nt, off, s, N, m, b, tr, ti);
     const double hv = g.htil[(long)b * M + m];
     er += hv * tr;
     ei += hv * ti;
   }
+  theta_pad(to, w, M, s, N, threadIdx.x, blockDim.x);
   er = block_sum(er, red);
   ei = block_sum(ei, red);
   if (threadIdx.x == 0) {
@@ -485,8 +519,7 @@ template <int NT>
 __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, SpinGeom s0, SpinGeom s1,
                                                             const double* __restrict__ phr,
                                                             const double* __restrict__ phi,
-                                                            double* __restrict__ thr,
-                                                            double* __restrict__ thi, double* ld_re,
+                                                            ThetaOut to, double* ld_re,
                                                             double* ld_im, double* e1_re,
                                                             double* e1_im) {
   typedef OvlWave<NT> L;
@@ -715,14 +748,14 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
       for (int v = 0; v < 4; ++v) {
         const int m = 16 * R + MM::row(lk, v), b = 16 * J + li;
         if (m < M && b < N) {
-          thr[wb + (long)m * Nt + off + b] = tr[J][v];
-          thi[wb + (long)m * Nt + off + b] = ti[J][v];
+          theta_store(to, w, M, Nt, off, s, N, m, b, tr[J][v], ti[J][v]);
           const double hv = g.htil[(long)b * M + m];
           er += hv * tr[J][v];
           ei += hv * ti[J][v];
         }
       }
   }
+  theta_pad(to, w, M, s, N, l, AFQ_WAVE);
   er = wave_sum(er);
   ei = wave_sum(ei);
   if (l == 0) {
@@ -735,31 +768,30 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
 }
 
 hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, SpinGeom s1,
-                         const double* phr, const double* phi, double* thr, double* thi,
-                         double* ld_re, double* ld_im, double* e1_re, double* e1_im,
-                         size_t max_lds) {
+                         const double* phr, const double* phi, ThetaOut to, double* ld_re,
+                         double* ld_im, double* e1_re, double* e1_im, size_t max_lds) {
   const int N = s0.N > s1.N ? s0.N : s1.N;
   if (N <= 16) {
     const size_t lds = (size_t)2 * OvlWave<1>::DOUBLES * sizeof(double);
     hipLaunchKernelGGL(k_overlap_theta_wave<1>, dim3(W), dim3(128), lds, st, M, Nt, s0, s1, phr,
-                       phi, thr, thi, ld_re, ld_im, e1_re, e1_im);
+                       phi, to, ld_re, ld_im, e1_re, e1_im);
     return hipGetLastError();
   }
   if (N <= 32) {
     const size_t lds = (size_t)2 * OvlWave<2>::DOUBLES * sizeof(double);
     hipLaunchKernelGGL(k_overlap_theta_wave<2>, dim3(W), dim3(128), lds, st, M, Nt, s0, s1, phr,
-                       phi, thr, thi, ld_re, ld_im, e1_re, e1_im);
+                       phi, to, ld_re, ld_im, e1_re, e1_im);
     return hipGetLastError();
   }
   const size_t base = (size_t)(2 * N * (N + 1) + 4 * N) * sizeof(double);
   const size_t staged = base + (size_t)3 * M * N * sizeof(double);
   if (staged <= 65536 && staged <= max_lds) {
     hipLaunchKernelGGL(k_overlap_theta<true>, dim3(W, 2), dim3(256), staged, st, M, Nt, s0, s1, phr,
-                       phi, thr, thi, ld_re, ld_im, e1_re, e1_im);
+                       phi, to, ld_re, ld_im, e1_re, e1_im);
   } else {
     if (base > max_lds) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_overlap_theta<false>, dim3(W, 2), dim3(256), base, st, M, Nt, s0, s1, phr,
-                       phi, thr, thi, ld_re, ld_im, e1_re, e1_im);
+                       phi, to, ld_re, ld_im, e1_re, e1_im);
   }
   return hipGetLastError();
 }
@@ -1549,29 +1581,32 @@ hipError_t hybrid_force_bias_finish(hipStream_t st, int W, int G, int nz, const 
   return hipGetLastError();
 }
 
-__global__ void k_build_lcat(long n, int G, int M, int MP4, int Nt, int n_up, int NP0, int NP1,
-                             const double* __restrict__ Lt0, const double* __restrict__ Lt1,
-                             double* __restrict__ Lcat) {
+// force bias of the Q route into the per-spin trace layout: vs[w][0][g] =
+// sum_z part[z][w][g], vs[w][1][g] = 0 (the combination adds the two)
+__global__ void k_fbias_to_vs(int W, int G, int nz, const double* __restrict__ part_re,
+                              const double* __restrict__ part_im, double* vs_re, double* vs_im) {
+  const long n = (long)W * G;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    const int g = (int)(e % G);
-    const long k = e / G;
-    const int m = (int)(k / Nt), b = (int)(k % Nt);
-    const bool up = b < n_up;
-    const int a = up ? b : b - n_up;
-    const int NP = up ? NP0 : NP1;
-    const double* Lt = up ? Lt0 : Lt1;
-    Lcat[e] = Lt[((long)g * MP4 + m) * NP + a];
+    const long w = e / G, g = e % G;
+    double sr = 0.0, si = 0.0;
+    for (int z = 0; z < nz; ++z) {
+      sr += part_re[(long)z * n + e];
+      si += part_im[(long)z * n + e];
+    }
+    vs_re[(w * 2) * G + g] = sr;
+    vs_im[(w * 2) * G + g] = si;
+    vs_re[(w * 2 + 1) * G + g] = 0.0;
+    vs_im[(w * 2 + 1) * G + g] = 0.0;
   }
 }
 
-hipError_t build_lcat(hipStream_t st, int G, int M, int MP4, int Nt, int n_up, int n_dn, int NP0,
-                      int NP1, const double* Lt0, const double* Lt1, double* Lcat) {
-  (void)n_dn;
-  const long n = (long)M * Nt * G;
+hipError_t fbias_to_vs(hipStream_t st, int W, int G, int nz, const double* part_re,
+                       const double* part_im, double* vs_re, double* vs_im) {
+  const long n = (long)W * G;
   if (n == 0) return hipSuccess;
   const int blocks = (int)std::min<long>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_build_lcat, dim3(blocks), dim3(256), 0, st, n, G, M, MP4, Nt, n_up, NP0, NP1,
-                     Lt0, Lt1, Lcat);
+  hipLaunchKernelGGL(k_fbias_to_vs, dim3(blocks), dim3(256), 0, st, W, G, nz, part_re, part_im,
+                     vs_re, vs_im);
   return hipGetLastError();
 }
 

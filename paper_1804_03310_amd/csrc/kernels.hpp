@@ -42,12 +42,24 @@ hipError_t fields_coeff(hipStream_t st, int W, int G, uint64_t seed, uint64_t t,
                         T* coefT, double* mf_re, double* mf_im, double* xdump,
                         double* hy_re = nullptr, double* hy_im = nullptr);
 
+// Where the overlap kernels put Theta: the FP64 matrix th[w][m][Nt] (thr
+// non-null) and/or the split rows of the Q route ts[w][Ktot] (sr non-null;
+// float when f32, else double), spin 0's (m b) at m N_up + b, spin 1's from
+// Kp0, the padding up to each spin's 64-multiple written as zeros.
+struct ThetaOut {
+  double* thr = nullptr;
+  double* thi = nullptr;
+  void* sr = nullptr;
+  void* si = nullptr;
+  int Ktot = 0, Kp0 = 0;
+  bool f32 = true;
+};
+
 // Per (walker, spin): S = D_0^T phi, LU/Gauss-Jordan inverse, log det, Theta = phi S^-1,
 // E1 = Tr(htil Theta).
 hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, SpinGeom s1,
-                         const double* phr, const double* phi, double* thr, double* thi,
-                         double* ld_re, double* ld_im, double* e1_re, double* e1_im,
-                         size_t max_lds);
+                         const double* phr, const double* phi, ThetaOut to, double* ld_re,
+                         double* ld_im, double* e1_re, double* e1_im, size_t max_lds);
 
 // Per (walker, spin): X_g = Ltil_g Theta; v[w][s][g] = Tr X_g; exx[w][s] = sum_g Tr(X_g X_g).
 // Repack Lt [G][MP4][NP] (NP = 16 NT) into the A-operand order of the
@@ -164,9 +176,32 @@ hipError_t hybrid_force_bias_finish(hipStream_t st, int W, int G, int nz, const 
                                     const double* part_im, double* v_re, double* v_im,
                                     const double* ld_re, const double* ld_im, double* lsn_re,
                                     double* lsn_im, int* vfin);
-// Lcat[(m Nt + off_s + a)][g] = Lt_s[g][m][a] for both spins (single determinant).
-hipError_t build_lcat(hipStream_t st, int G, int M, int MP4, int Nt, int n_up, int n_dn, int NP0,
-                      int NP1, const double* Lt0, const double* Lt1, double* Lcat);
+// Q route (qroute.hip), over the split Theta rows ts[w][Ktot] that the
+// overlap kernels write (ThetaOut).
+// Lq[k][g] ([Ktot][Gp], zero padded): Ltil_g[a][m] at the split index of (s, m, a).
+hipError_t build_lsplit(hipStream_t st, int G, int Gp, int M, int MP4, int n_up, int n_dn, int NP0,
+                        int NP1, int Kp0, int Kp1, const double* Lt0, const double* Lt1,
+                        double* Lq);
+// Q[(n a)][(m b)] = P[(m NP + a)][(n NP + b)] into [Kp][Kp], zero padded.
+template <typename T>
+hipError_t perm_qpad(hipStream_t st, int M, int N, int NP, int MP4, int Kp, const double* P, T* Q);
+// Number of k ranges of the force-bias GEMM (partials of nz W G doubles must
+// fit cap_per_walker W doubles).
+int fbias_nz(int W, int Ktot, int G, int elem_size, long cap_per_walker);
+// part[z][w][g] = sum over range z of ts[w][k] Lq[k][g], re and im.
+template <typename T>
+hipError_t fbias_mm(hipStream_t st, int W, int Ktot, int G, int Gp, int nz, const T* tsr,
+                    const T* tsi, const T* Lq, double* part_re, double* part_im);
+// part[w][seg] (re, im) of theta^T Q theta over the segment's tile pairs.
+template <typename T>
+hipError_t qform(hipStream_t st, int W, int Kp0, int Kp1, int nseg, const int4* segs, const T* tsr,
+                 const T* tsi, const T* Q0, const T* Q1, double* part);
+// exx[2 w + s] = sum over spin s's segments of part[w][seg]
+hipError_t qform_reduce(hipStream_t st, int W, int nseg0, int nseg1, const double* part,
+                        double* exx_re, double* exx_im);
+// vs[w][0][g] = sum_z part[z][w][g] (both spins' traces together), vs[w][1][g] = 0
+hipError_t fbias_to_vs(hipStream_t st, int W, int G, int nz, const double* part_re,
+                       const double* part_im, double* vs_re, double* vs_im);
 hipError_t fields_coeff_bf16(hipStream_t st, int W, int G, int ldg, uint64_t seed, uint64_t t,
                              int system_id, double dt, const double* v_re, const double* v_im,
                              const double* lbar, void* coef, double* mf_re, double* mf_im,

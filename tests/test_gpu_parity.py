@@ -41,6 +41,11 @@ def _make(afq, inp, W, mf=True):
     return ham, trial, w
 
 
+def _routes(trial):
+    """Exchange routes the trial offers: the Ltil route always, Q where built."""
+    return ["ltilde", "q"] if trial.exchange_route == "q" else ["ltilde"]
+
+
 def _set_phi(w, phi):
     w.phi_re.copy_(torch.from_numpy(np.ascontiguousarray(phi.real)))
     w.phi_im.copy_(torch.from_numpy(np.ascontiguousarray(phi.imag)))
@@ -88,15 +93,17 @@ def test_local_energy_random_walkers_fp64(afq, M, n_up, n_dn, G, W):
     re, im = syn.random_walkers(M, n_up, n_dn, W, seed=3, scale=0.3)
     D0 = np.concatenate([inp.C_up[:, :n_up], inp.C_dn[:, :n_dn]], axis=1)
     phi = D0[None] + re + 1j * im
-    _set_phi(w, phi)
-    afq.local_energy(ham, trial, w)
     o = Oracle.from_inputs(inp)
     m = o.measure(phi)
-    el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
-    ls = _np(w.logovlp[0]) + 1j * _np(w.logovlp[1])
-    assert np.allclose(el, m["eloc"], rtol=1e-10, atol=1e-10)
-    assert np.allclose(ls.real, m["logS"].real, atol=1e-10)
-    assert np.allclose(_wrap(ls.imag - m["logS"].imag), 0.0, atol=1e-10)
+    for route in _routes(trial):
+        trial.exchange_route = route
+        _set_phi(w, phi)
+        afq.local_energy(ham, trial, w)
+        el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
+        ls = _np(w.logovlp[0]) + 1j * _np(w.logovlp[1])
+        assert np.allclose(el, m["eloc"], rtol=1e-10, atol=1e-10), route
+        assert np.allclose(ls.real, m["logS"].real, atol=1e-10)
+        assert np.allclose(_wrap(ls.imag - m["logS"].imag), 0.0, atol=1e-10)
 
 
 @pytest.mark.parametrize("M,n_up,n_dn,G,W", [(23, 7, 4, 37, 9), (29, 20, 9, 33, 7),
@@ -114,13 +121,15 @@ def test_local_energy_random_walkers_fp32(afq, M, n_up, n_dn, G, W):
     re, im = syn.random_walkers(M, n_up, n_dn, W, seed=3, scale=0.1)
     D0 = np.concatenate([inp.C_up[:, :n_up], inp.C_dn[:, :n_dn]], axis=1)
     phi = D0[None] + re + 1j * im
-    _set_phi(w, phi)
-    afq.propagate(ham, trial, w, 0, 0.01, 0, 0, afq.Options(chol_prec="fp32", taylor_prec="fp32"))
     m = Oracle.from_inputs(inp).measure(phi)
-    el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
-    err = np.abs(el - m["eloc"]) / np.abs(m["eloc"])
-    print(f"fp32 max rel dE_L = {err.max():.3e}")
-    assert err.max() <= 1e-5
+    for route in _routes(trial):
+        trial.exchange_route = route
+        _set_phi(w, phi)
+        afq.propagate(ham, trial, w, 0, 0.01, 0, 0, afq.Options(chol_prec="fp32", taylor_prec="fp32"))
+        el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
+        err = np.abs(el - m["eloc"]) / np.abs(m["eloc"])
+        print(f"fp32 {route}: max rel dE_L = {err.max():.3e}")
+        assert err.max() <= 1e-5
 
 
 def _run_both(afq, inp, W, n_steps, dt, opt_kw, prec=("fp64", "fp64"), seed=0, oracle_walkers=None):
@@ -238,10 +247,12 @@ def test_reconfigure_parity(afq, W):
     assert np.all(np.isin(_np(w.eloc[0]), el_before))
 
 
-def _one_step_sampled(afq, inp, W, sample, dt, prec, taylor_order=6):
+def _one_step_sampled(afq, inp, W, sample, dt, prec, taylor_order=6, route=None):
     """One step of all W walkers from the reference on the GPU; the oracle
     repeats the step for the sampled walkers alone (counter-based fields)."""
     ham, trial, w = _make(afq, inp, W)
+    if route is not None:
+        trial.exchange_route = route
     afq.walkers_from_trial(ham, trial, w)
     et = afq.local_energy(ham, trial, w)
     opt = afq.Options(taylor_order=taylor_order, e_trial=et, chol_prec=prec[0], taylor_prec=prec[1])
@@ -254,12 +265,15 @@ def _one_step_sampled(afq, inp, W, sample, dt, prec, taylor_order=6):
     return el[sample], wt[sample], st
 
 
-@pytest.mark.parametrize("name,prec,rel_tol,abs_tol", [
-    ("hchain-M50", ("fp64", "fp64"), 1e-12, 1e-9),
-    ("hchain-M50", ("fp32", "fp32"), None, 1e-4),
-    ("hchain-M50-literal", ("fp64", "fp64"), 1e-9, None),
-    ("hchain-M50-literal", ("fp32", "fp32"), 2e-6, None)])
-def test_hchain_full_size_one_step_sampled(afq, name, prec, rel_tol, abs_tol):
+@pytest.mark.parametrize("name,prec,rel_tol,abs_tol,route", [
+    ("hchain-M50", ("fp64", "fp64"), 1e-12, 1e-9, "q"),
+    ("hchain-M50", ("fp64", "fp64"), 1e-12, 1e-9, "ltilde"),
+    ("hchain-M50", ("fp32", "fp32"), None, 1e-4, "q"),
+    ("hchain-M50", ("fp32", "fp32"), None, 1e-4, "ltilde"),
+    ("hchain-M50-literal", ("fp64", "fp64"), 1e-9, None, "q"),
+    ("hchain-M50-literal", ("fp32", "fp32"), 2e-6, None, "q"),
+    ("hchain-M50-literal", ("fp32", "fp32"), 2e-6, None, "ltilde")])
+def test_hchain_full_size_one_step_sampled(afq, name, prec, rel_tol, abs_tol, route):
     """Hydrogen-chain shapes at full size (1024 walkers, the benchmark's
     launch configuration): per-walker E_L and weight after one step on 8
     sampled walkers vs the oracle.  With the health-scaled vectors the FP32
@@ -268,8 +282,8 @@ def test_hchain_full_size_one_step_sampled(afq, name, prec, rel_tol, abs_tol):
     wl = syn.WORKLOADS[name]
     inp = syn.workload_system(wl)
     sample = [0, 1, 255, 256, 511, 700, 1022, 1023]
-    _say(f"{name} full size one step {prec}")
-    el, wt, st = _one_step_sampled(afq, inp, wl.n_walkers, sample, wl.dt, prec)
+    _say(f"{name} full size one step {prec} route {route}")
+    el, wt, st = _one_step_sampled(afq, inp, wl.n_walkers, sample, wl.dt, prec, route=route)
     alive = st.weight > 0
     err = np.abs(el - st.eloc)[alive]
     rel = err / np.abs(st.eloc[alive])
@@ -471,20 +485,23 @@ def sweep_case():
     return wl, inp, phi, sample, ref
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16", 2e-2)])
-def test_sweep_full_size_local_energy(afq, sweep_case, prec, tol):
+@pytest.mark.parametrize("prec,tol,route", [("fp64", 1e-10, "q"), ("fp64", 1e-10, "ltilde"),
+                                            ("fp32", 1e-5, "q"), ("fp32", 1e-5, "ltilde"),
+                                            ("bf16", 2e-2, "ltilde")])
+def test_sweep_full_size_local_energy(afq, sweep_case, prec, tol, route):
     """sweep-M200 (M=200, 50/50, 1000 vectors, 1024 walkers): E_L of perturbed
     walkers with the exchange contraction in FP64 / FP32 / BF16 (FP32
     accumulation) against the FP64 oracle on 2 sampled walkers; the error in
     Ha is printed."""
     wl, inp, phi, sample, ref = sweep_case
-    _say(f"sweep full size local energy {prec}")
+    _say(f"sweep full size local energy {prec} route {route}")
     ham, trial, w = _make(afq, inp, wl.n_walkers)
+    trial.exchange_route = route
     _set_phi(w, phi)
     afq.propagate(ham, trial, w, 0, wl.dt, 0, 0, afq.Options(chol_prec=prec))
     el = (_np(w.eloc[0]) + 1j * _np(w.eloc[1]))[sample]
     err = np.abs(el - ref["eloc"])
-    print(f"sweep {prec}: |E_L| ~ {np.abs(ref['eloc']).max():.1f} Ha, max |dE_L| = {err.max():.3e} Ha,"
+    print(f"sweep {prec} {route}: |E_L| ~ {np.abs(ref['eloc']).max():.1f} Ha, max |dE_L| = {err.max():.3e} Ha,"
           f" rel {np.max(err / np.abs(ref['eloc'])):.3e}")
     assert np.max(err / np.abs(ref["eloc"])) <= tol
 
@@ -675,3 +692,25 @@ def test_hybrid_zero_variance_one_body(afq):
         res.append((em, _np(w.weight)))
     assert np.allclose(res[1][0][2::3], exact, atol=1e-12)
     assert np.allclose(res[0][1], res[1][1], rtol=1e-12)
+
+
+def test_exchange_route_selection(afq):
+    """The Q route is built for single-determinant trials with n_chol >= 2 M
+    and can be switched off and on; asking for it where it was not built is
+    an error and leaves the route unchanged."""
+    _say("exchange route selection")
+    inp = syn.make_system(10, 5, 5, 40, 8.0, seed=50, e_core=0.75)
+    ham, trial, w = _make(afq, inp, 2)
+    assert trial.exchange_route == "q"
+    trial.exchange_route = "ltilde"
+    assert trial.exchange_route == "ltilde"
+    trial.exchange_route = "q"
+    assert trial.exchange_route == "q"
+    inp2 = syn.make_system(23, 7, 4, 37, 8.0, seed=60, e_core=0.75)
+    ham2, trial2, w2 = _make(afq, inp2, 2)
+    assert trial2.exchange_route == "ltilde"
+    with pytest.raises(afq.AfqmcError):
+        trial2.exchange_route = "q"
+    assert trial2.exchange_route == "ltilde"
+    with pytest.raises(ValueError):
+        trial2.exchange_route = "other"
