@@ -40,6 +40,23 @@ def exchange_flops_per_walker(M, n_up, n_dn, G):
     return sum(G * (4 * n * n * M + 8 * n * n) for n in (n_up, n_dn))
 
 
+def taylor_flops_per_walker(M, Nt, order):
+    """B1 exp(A) B1 phi with the Taylor series: two real M x M times complex
+    M x Nt products (4 M^2 Nt flops each) and `order` complex M x M times
+    complex M x Nt products (8 M^2 Nt flops each)."""
+    return (8 * order + 8) * M * M * Nt
+
+
+def taylor_fused(M, Nt, prec, lds_bytes=160 * 1024):
+    """Whether the propagation runs as the one fused kernel per step (its LDS
+    operands fit one CU, at most 64 output tiles)."""
+    mp4 = (M + 3) // 4 * 4
+    ldk = mp4 if (mp4 // 4) % 2 else mp4 + 4
+    elem = 4 if prec == "fp32" else 8
+    ntile = ((M + 15) // 16) * ((Nt + 15) // 16)
+    return (3 * M + 4 * Nt) * ldk * elem <= lds_bytes and ntile <= 64
+
+
 def qform_flops_per_walker(M, n_up, n_dn):
     """Q route exchange: per spin theta^T Q theta over the K = M N_sigma index
     with Q symmetric (K (K + 1) / 2 distinct entries, each a complex-by-real
@@ -63,16 +80,17 @@ def multidet_flops_per_walker(M, n_up, n_dn, G):
 
 GOLDEN = {"hchain-M50": ("hchain-M50_W1024_T100.txt", 1024, 100, 1)}
 
-TRAFFIC = {"hchain-M50": "hchain-M50_exchange_traffic.json"}
+TRAFFIC = {("hchain-M50", "exchange"): "hchain-M50_qform_traffic.json",
+           ("hchain-M50", "taylor_b1"): "hchain-M50_taylor_traffic.json"}
 
 
-def measured_traffic(wl_name, chol_prec):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the copy-kernel
-    calibration), or None when there is none for this workload and precision
-    or the kernel source has changed since the counters were taken."""
+def measured_traffic(wl_name, cls, chol_prec, taylor_prec):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (scaled by the copy-kernel calibration), or
+    None when there is none for this workload and precision or the kernel
+    source has changed since the counters were taken."""
     import hashlib
-    name = TRAFFIC.get(wl_name)
+    name = TRAFFIC.get((wl_name, cls))
     path = os.path.join(ROOT, "profiles", name) if name else None
     if path is None or not os.path.exists(path):
         return None
@@ -80,7 +98,8 @@ def measured_traffic(wl_name, chol_prec):
         rec = json.load(f)
     with open(os.path.join(ROOT, rec["source"]), "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()
-    if rec["chol_prec"] != chol_prec or rec["source_sha256"] != digest:
+    prec = taylor_prec if cls == "taylor_b1" else chol_prec
+    if rec["prec"] != prec or rec["source_sha256"] != digest:
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -395,18 +414,38 @@ def main():
         _ = float(e[args.tte_steps - 1].item())
         tte.append(time.perf_counter() - t1)
 
-    n_ex, ms_ex = ktimes["exchange"]
+    # candidate kernels for the roofline line: the exchange contraction and,
+    # where it runs as one fused launch, the Taylor propagation; the one with
+    # the larger time per step is reported, the other under "roofline_other"
     if multi:
-        flops = multidet_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
-        kname = "k_md_energy (P = (C^T L_g) Theta_0, X0^2, per-determinant corrections)"
+        ex_flops = multidet_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
+        ex_name = "k_md_energy (P = (C^T L_g) Theta_0, X0^2, per-determinant corrections)"
     elif route == "q":
-        flops = qform_flops_per_walker(wl.M, wl.n_up, wl.n_dn) * W
-        kname = "k_qform (theta^T Q theta, upper-triangular tile pairs)"
+        ex_flops = qform_flops_per_walker(wl.M, wl.n_up, wl.n_dn) * W
+        ex_name = "k_qform (theta^T Q theta, upper-triangular tile pairs)"
     else:
-        flops = exchange_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
-        kname = ("k_exchange_full (fused Ltil*Theta, Tr X, Tr XX)"
-                 if max(wl.n_up, wl.n_dn) <= 32 else "k_exchange (fused Ltil*Theta, Tr X, Tr XX)")
-    avg_s = (ms_ex / n_ex) / 1e3 if n_ex else float("nan")
+        ex_flops = exchange_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
+        ex_name = ("k_exchange_full (fused Ltil*Theta, Tr X, Tr XX)"
+                   if max(wl.n_up, wl.n_dn) <= 32 else "k_exchange (fused Ltil*Theta, Tr X, Tr XX)")
+    ex_peak = {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}[chol_prec]
+    cands = [("exchange", ex_name, ex_flops, ex_peak)]
+    if taylor_fused(wl.M, wl.n_up + wl.n_dn, taylor_prec):
+        cands.append(("taylor_b1",
+                      "k_propagate_fused (B1 exp(A) B1 phi, Taylor order %d)" % wl.taylor_order,
+                      taylor_flops_per_walker(wl.M, wl.n_up + wl.n_dn, wl.taylor_order) * W,
+                      {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS}[taylor_prec]))
+    lines = []
+    for cls, nm, fl, pk in cands:
+        n_l, ms_l = ktimes[cls]
+        a_s = (ms_l / n_l) / 1e3 if n_l else float("nan")
+        ach = fl / a_s / 1e12 if n_l else float("nan")
+        lines.append({"class": cls, "bound": "mfma", "kernel": nm, "achieved": ach, "peak": pk,
+                      "unit": "TFLOP/s", "frac": ach / pk,
+                      "traffic": measured_traffic(wl.name, cls, chol_prec, taylor_prec),
+                      "flops_per_launch": fl, "avg_launch_ms": a_s * 1e3, "launches": n_l,
+                      "ms_per_step": ms_l / max(args.steps, 1)})
+    lines.sort(key=lambda d: -(d["ms_per_step"] if d["launches"] else 0.0))
+    roof, roof_other = lines[0], lines[1:]
     fbias_report = None
     n_fb, ms_fb = ktimes["force_bias"]
     if route == "q" and n_fb and not multi:
@@ -415,8 +454,6 @@ def main():
         fb_s = (ms_fb / n_fb) / 1e3
         fbias_report = {"flops_per_launch": fb_flops, "avg_launch_ms": fb_s * 1e3,
                         "achieved_tflops": fb_flops / fb_s / 1e12, "launches": n_fb}
-    peak = {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}[chol_prec]
-    achieved = flops / avg_s / 1e12 if n_ex else float("nan")
     value = W * args.steps / elapsed
     out = {
         "metric": "walker-steps/sec on 1 MI355X at <=0.1 mHa vs FP64 oracle; p50/p99 time-to-energy",
@@ -440,11 +477,8 @@ def main():
                    "precision": f"contractions {chol_prec}, Taylor/B1 {taylor_prec}, "
                                 "overlap/inverse/det/MGS/sums fp64",
                    "e_trial": et, "e_mix_last": e_last, "alive_walkers": alive},
-        "roofline": {"bound": "mfma", "kernel": kname,
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": measured_traffic(wl.name, chol_prec),
-                     "flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3, "launches": n_ex},
+        "roofline": roof,
+        "roofline_other": roof_other,
         "kernel_ms_per_step": {k: (v[1] / max(args.steps, 1)) for k, v in ktimes.items() if v[0]},
         "force_bias_class": fbias_report,
         "time_to_energy_s": {"p50": float(np.percentile(tte, 50)) if tte else None,

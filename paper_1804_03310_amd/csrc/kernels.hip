@@ -1891,49 +1891,58 @@ namespace afq {
 // products on the orbitals).  One block per walker:
 //   phi1 = phi + (B1 - I) phi,  S = phi1,  T_0 = phi1,
 //   T_n = A T_{n-1} / n,  S += T_n  (n = 1..order),  phi = S + (B1 - I) S.
-// A and B1 - I (both symmetric, so their rows serve as MFMA A-operand
-// columns) and the current term live in LDS in the contraction type T; the
-// running sum S stays in FP64 registers of the lanes that own each output
-// element.  Eight waves per block.  Terms are rounded to T and the sums
-// accumulate the unrounded FP64 products, exactly as in the unfused chain.
-// MT = output tiles per wave.
+// A and B1 - I (both symmetric) are held in LDS as [i][k] and the current
+// term transposed as [c][k], both with k contiguous and row stride LDK (an
+// odd multiple of 4), so a lane fetches the four k values of its MFMA steps
+// (k = 16 u + 4 lk + j, j = 0..3) with one 16-byte read and eight
+// consecutive lanes cover all 32 banks.  The running sum S stays in FP64
+// registers of the lanes that own each output element.  Eight waves per
+// block.  Terms are rounded to T and the sums accumulate the unrounded FP64
+// products, exactly as in the unfused chain.  MT = output tiles per wave;
+// SB: every tile of a wave has the same column tile (B fetched once).
 // ===========================================================================
 constexpr int NWAVE = 8;  // waves per block of the fused propagation
 
-template <typename T, int MT>
-__global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4, int order,
+namespace {
+// smallest LDK >= MP4 with LDK / 4 odd
+inline int taylor_ldk(int MP4) { return ((MP4 / 4) & 1) ? MP4 : MP4 + 4; }
+}  // namespace
+
+template <typename T, int MT, bool SB>
+__global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4, int LDK, int order,
                                                          const T* __restrict__ A,
                                                          const T* __restrict__ B1m,
                                                          double* __restrict__ phr,
                                                          double* __restrict__ phi) {
-  extern __shared__ unsigned char lds_raw[];
+  extern __shared__ __attribute__((aligned(32))) unsigned char lds_raw[];
   typedef Mfma<T> MM;
   typedef typename MM::acc_t acc_t;
+  typedef typename Vec4<T>::type t4;
   const int w = blockIdx.x;
   const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
   const long mm = (long)M * M, mn = (long)M * Nt;
-  T* Asr = (T*)lds_raw;          // [MP4][M]  Asr[k][i] = A[k][i] = A[i][k]
-  T* Asi = Asr + MP4 * M;
-  T* Bm = Asi + MP4 * M;         // (B1 - I)[k][i], symmetric
-  T* Tb[2][2];                   // ping-pong term buffers [MP4][Nt] (re, im)
-  Tb[0][0] = Bm + MP4 * M;
-  Tb[0][1] = Tb[0][0] + MP4 * Nt;
-  Tb[1][0] = Tb[0][1] + MP4 * Nt;
-  Tb[1][1] = Tb[1][0] + MP4 * Nt;
+  T* Ar = (T*)lds_raw;  // [M][LDK]  A[i][k], zero for k >= M
+  T* Ai = Ar + M * LDK;
+  T* Bm = Ai + M * LDK;  // (B1 - I)[i][k]
+  T* TT = Bm + M * LDK;  // ping-pong term buffers, transposed [Nt][LDK] (re, im)
+  auto tt = [&](int buf, int part) { return TT + (2 * buf + part) * Nt * LDK; };
   const T* Ag = A + (long)w * 2 * mm;
-  for (int e = threadIdx.x; e < MP4 * M; e += blockDim.x) {
-    const int k = e / M, i = e % M;
-    Asr[e] = k < M ? Ag[(long)k * M + i] : (T)0;
-    Asi[e] = k < M ? Ag[mm + (long)k * M + i] : (T)0;
-    Bm[e] = k < M ? B1m[(long)k * M + i] : (T)0;
+  for (int e = threadIdx.x; e < M * LDK; e += blockDim.x) {
+    const int i = e / LDK, k = e % LDK;
+    const bool ok = k < M;
+    Ar[e] = ok ? Ag[(long)i * M + k] : (T)0;
+    Ai[e] = ok ? Ag[mm + (long)i * M + k] : (T)0;
+    Bm[e] = ok ? B1m[(long)i * M + k] : (T)0;
   }
   const long wb = (long)w * mn;
+  // phi read row-major (coalesced), stored transposed; padding k >= M zero
   for (int e = threadIdx.x; e < MP4 * Nt; e += blockDim.x) {
     const int k = e / Nt, c = e % Nt;
-    Tb[0][0][e] = k < M ? (T)phr[wb + (long)k * Nt + c] : (T)0;
-    Tb[0][1][e] = k < M ? (T)phi[wb + (long)k * Nt + c] : (T)0;
-    Tb[1][0][e] = (T)0;
-    Tb[1][1][e] = (T)0;
+    const bool ok = k < M;
+    tt(0, 0)[c * LDK + k] = ok ? (T)phr[wb + (long)k * Nt + c] : (T)0;
+    tt(0, 1)[c * LDK + k] = ok ? (T)phi[wb + (long)k * Nt + c] : (T)0;
+    tt(1, 0)[c * LDK + k] = (T)0;
+    tt(1, 1)[c * LDK + k] = (T)0;
   }
   const int RT = (M + 15) / 16, CT = (Nt + 15) / 16, ntile = RT * CT;
   double sr[MT][4], si[MT][4];
@@ -1951,49 +1960,103 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
   }
   __syncthreads();
   int cur = 0;
+  const t4 z4 = {0, 0, 0, 0};
   // one product of an M x M operator with the current term: real (B1 - I) or
   // complex A, both from LDS
   auto product = [&](bool cplx, acc_t (&cr)[MT], acc_t (&ci)[MT]) {
 #pragma unroll
     for (int t = 0; t < MT; ++t) { cr[t] = MM::zero(); ci[t] = MM::zero(); }
-    const T* br_ = Tb[cur][0];
-    const T* bi_ = Tb[cur][1];
-    for (int k0 = 0; k0 < MP4; k0 += 4) {
+    const T* br_ = tt(cur, 0);
+    const T* bi_ = tt(cur, 1);
+    int k0 = 0;
+    for (; k0 + 16 <= MP4; k0 += 16) {
+      const int kk = k0 + 4 * lk;
+      t4 b_r[MT], b_i[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const int tile = wv + NWAVE * t;
+        const int c = 16 * (tile % CT) + li;
+        if (SB && t > 0) { b_r[t] = b_r[0]; b_i[t] = b_i[0]; continue; }
+        const bool ok = tile < ntile && c < Nt;
+        b_r[t] = ok ? *(const t4*)(br_ + c * LDK + kk) : z4;
+        b_i[t] = ok ? *(const t4*)(bi_ + c * LDK + kk) : z4;
+      }
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const int tile = wv + NWAVE * t;
+        if (tile >= ntile) continue;
+        const int i = 16 * (tile / CT) + li;
+        const bool ok = i < M;
+        if (cplx) {
+          const t4 a_r = ok ? *(const t4*)(Ar + i * LDK + kk) : z4;
+          const t4 a_i = ok ? *(const t4*)(Ai + i * LDK + kk) : z4;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            cr[t] = MM::mma(a_r[j], b_r[t][j], cr[t]);
+            cr[t] = MM::mma(-a_i[j], b_i[t][j], cr[t]);
+            ci[t] = MM::mma(a_r[j], b_i[t][j], ci[t]);
+            ci[t] = MM::mma(a_i[j], b_r[t][j], ci[t]);
+          }
+        } else {
+          const t4 a = ok ? *(const t4*)(Bm + i * LDK + kk) : z4;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            cr[t] = MM::mma(a[j], b_r[t][j], cr[t]);
+            ci[t] = MM::mma(a[j], b_i[t][j], ci[t]);
+          }
+        }
+      }
+    }
+    for (; k0 < MP4; k0 += 4) {  // k tail: one step of four, k = k0 + lk
       const int k = k0 + lk;
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
         const int tile = wv + NWAVE * t;
         if (tile >= ntile) continue;
-        const int rt = tile / CT, ct = tile % CT;
-        const int i = 16 * rt + li, c = 16 * ct + li;
-        const T b_r = c < Nt ? br_[k * Nt + c] : (T)0;
-        const T b_i = c < Nt ? bi_[k * Nt + c] : (T)0;
+        const int i = 16 * (tile / CT) + li, c = 16 * (tile % CT) + li;
+        const T b_r = c < Nt ? br_[c * LDK + k] : (T)0;
+        const T b_i = c < Nt ? bi_[c * LDK + k] : (T)0;
         if (cplx) {
-          const T a_r = i < M ? Asr[k * M + i] : (T)0;
-          const T a_i = i < M ? Asi[k * M + i] : (T)0;
+          const T a_r = i < M ? Ar[i * LDK + k] : (T)0;
+          const T a_i = i < M ? Ai[i * LDK + k] : (T)0;
           cr[t] = MM::mma(a_r, b_r, cr[t]);
           cr[t] = MM::mma(-a_i, b_i, cr[t]);
           ci[t] = MM::mma(a_r, b_i, ci[t]);
           ci[t] = MM::mma(a_i, b_r, ci[t]);
         } else {
-          const T a = i < M ? Bm[k * M + i] : (T)0;
+          const T a = i < M ? Bm[i * LDK + k] : (T)0;
           cr[t] = MM::mma(a, b_r, cr[t]);
           ci[t] = MM::mma(a, b_i, ci[t]);
         }
       }
     }
   };
+  // term^T[c][r] for the lane's rows; rows M .. MP4 - 1 receive the zeros
+  // the products give there, rows from MP4 on are not stored
   auto store_term = [&](int buf, const double (&xr)[MT][4], const double (&xi)[MT][4]) {
+    T* outr = tt(buf, 0);
+    T* outi = tt(buf, 1);
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       const int tile = wv + NWAVE * t;
-      const int rt = tile / CT, ct = tile % CT;
+      const int rt = tile / CT, ct = tile % CT, c = 16 * ct + li;
+      if (tile >= ntile || c >= Nt) continue;
+      if (sizeof(T) == 4) {
+        const int r0 = 16 * rt + 4 * lk;  // rows r0 .. r0 + 3 (MP4 is a multiple of 4)
+        if (r0 < MP4) {
+          const t4 vr = {(T)xr[t][0], (T)xr[t][1], (T)xr[t][2], (T)xr[t][3]};
+          const t4 vi = {(T)xi[t][0], (T)xi[t][1], (T)xi[t][2], (T)xi[t][3]};
+          *(t4*)(outr + c * LDK + r0) = vr;
+          *(t4*)(outi + c * LDK + r0) = vi;
+        }
+      } else {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * rt + MM::row(lk, v), c = 16 * ct + li;
-        if (tile < ntile && r < M && c < Nt) {
-          Tb[buf][0][r * Nt + c] = (T)xr[t][v];
-          Tb[buf][1][r * Nt + c] = (T)xi[t][v];
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * rt + MM::row(lk, v);
+          if (r < MP4) {
+            outr[c * LDK + r] = (T)xr[t][v];
+            outi[c * LDK + r] = (T)xi[t][v];
+          }
         }
       }
     }
@@ -2051,29 +2114,37 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
   }
 }
 
+namespace {
+size_t taylor_lds(int M, int Nt, size_t elem) {
+  const int MP4 = ((M + 3) / 4) * 4;
+  return (size_t)(3 * M + 4 * Nt) * taylor_ldk(MP4) * elem;
+}
+}  // namespace
+
 template <typename T>
 hipError_t propagate_fused(hipStream_t st, int W, int M, int Nt, int order, const T* A,
                            const T* B1m, double* phr, double* phi, size_t max_lds) {
-  const int MP4 = ((M + 3) / 4) * 4;
-  const int ntile = ((M + 15) / 16) * ((Nt + 15) / 16);
-  const size_t lds = (size_t)(3 * MP4 * M + 4 * MP4 * Nt) * sizeof(T);
+  const int MP4 = ((M + 3) / 4) * 4, LDK = taylor_ldk(MP4);
+  const int CT = (Nt + 15) / 16;
+  const int ntile = ((M + 15) / 16) * CT;
+  const size_t lds = taylor_lds(M, Nt, sizeof(T));
   if (lds > max_lds || ntile > 8 * NWAVE) return hipErrorInvalidValue;
   const int mt = (ntile + NWAVE - 1) / NWAVE;
-#define AFQ_PF(MTV)                                                                             \
-  hipLaunchKernelGGL((k_propagate_fused<T, MTV>), dim3(W), dim3(64 * NWAVE), lds, st, M, Nt, MP4, order, \
-                     A, B1m, phr, phi)
-  if (mt <= 1) AFQ_PF(1);
-  else if (mt <= 2) AFQ_PF(2);
-  else if (mt <= 4) AFQ_PF(4);
-  else AFQ_PF(8);
+  const bool sb = NWAVE % CT == 0;
+#define AFQ_PF(MTV, SBV)                                                                          \
+  hipLaunchKernelGGL((k_propagate_fused<T, MTV, SBV>), dim3(W), dim3(64 * NWAVE), lds, st, M, Nt,   \
+                     MP4, LDK, order, A, B1m, phr, phi)
+  if (mt <= 1) AFQ_PF(1, false);
+  else if (mt <= 2) { if (sb) AFQ_PF(2, true); else AFQ_PF(2, false); }
+  else if (mt <= 4) { if (sb) AFQ_PF(4, true); else AFQ_PF(4, false); }
+  else AFQ_PF(8, false);
 #undef AFQ_PF
   return hipGetLastError();
 }
 
 bool propagate_fused_fits(int M, int Nt, size_t elem, size_t max_lds) {
-  const int MP4 = ((M + 3) / 4) * 4;
   const int ntile = ((M + 15) / 16) * ((Nt + 15) / 16);
-  return (size_t)(3 * MP4 * M + 4 * MP4 * Nt) * elem <= max_lds && ntile <= 8 * NWAVE;
+  return taylor_lds(M, Nt, elem) <= max_lds && ntile <= 8 * NWAVE;
 }
 
 template hipError_t propagate_fused<float>(hipStream_t, int, int, int, int, const float*,

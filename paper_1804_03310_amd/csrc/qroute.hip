@@ -47,13 +47,23 @@ __device__ inline void tile_fetch(const T* __restrict__ A, long ld, long r0, lon
   }
 }
 
-template <typename T>
+// PAIRS: columns 4 c + jb stored at (jb / 2) 32 + 2 c + jb % 2, so that the
+// two-column passes of the quadratic form read 8 contiguous bytes per lane.
+template <typename T, bool PAIRS>
 __device__ inline void tile_store(T* lds, const typename V4<T>::type (&pre)[4]) {
   typedef typename V4<T>::type t4;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int idx = e * 256 + threadIdx.x, row = idx >> 4, c4 = idx & 15;
-    *(t4*)(lds + row * QLD + 4 * c4) = pre[e];
+    if (PAIRS) {
+      T* p = lds + row * QLD + 2 * c4;
+      p[0] = pre[e][0];
+      p[1] = pre[e][1];
+      p[32] = pre[e][2];
+      p[33] = pre[e][3];
+    } else {
+      *(t4*)(lds + row * QLD + 4 * c4) = pre[e];
+    }
   }
 }
 
@@ -105,9 +115,11 @@ __device__ inline void tile_mma_cols(const T* lds, int jb0, int li, int q, const
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
+      // NJ == 2: the tile was stored with tile_store<T, true> (column pairs)
       T b[NJ];
+      const int base = (16 * u + 4 * q + j) * QLD + (NJ == 2 ? (jb0 >> 1) * 32 + 2 * li : 4 * li + jb0);
 #pragma unroll
-      for (int jj = 0; jj < NJ; ++jj) b[jj] = lds[(16 * u + 4 * q + j) * QLD + 4 * li + jb0 + jj];
+      for (int jj = 0; jj < NJ; ++jj) b[jj] = lds[base + jj];
 #pragma unroll
       for (int g = 0; g < GW; ++g)
 #pragma unroll
@@ -214,7 +226,7 @@ __global__ __launch_bounds__(256) void k_fbias_mm(int W, int Ktot, int G, int Gp
   t4 pre[4];
   if (kt0 < kt1) {  // an empty range (k tiles fewer than ranges) writes zeros
     tile_fetch<T>(Lq, Gp, (long)kt0 * QT, (long)gt * QT, pre);
-    tile_store<T>(lds[0], pre);
+    tile_store<T, false>(lds[0], pre);
 #pragma unroll
     for (int g = 0; g < GW; ++g) {
       afrag_fetch<T>(tsr, Ktot, W, wb + 16 * g, (long)kt0 * QT, li, q, ar[g]);
@@ -228,7 +240,7 @@ __global__ __launch_bounds__(256) void k_fbias_mm(int W, int Ktot, int G, int Gp
     if (more) tile_fetch<T>(Lq, Gp, (long)(kt + 1) * QT, (long)gt * QT, pre);
     tile_mma<T, GW>(lds[buf], li, q, ar, ai, zr, zi);
     if (more) {
-      tile_store<T>(lds[buf ^ 1], pre);
+      tile_store<T, false>(lds[buf ^ 1], pre);
 #pragma unroll
       for (int g = 0; g < GW; ++g) {
         afrag_fetch<T>(tsr, Ktot, W, wb + 16 * g, (long)(kt + 1) * QT, li, q, ar[g]);
@@ -326,7 +338,7 @@ __global__ __launch_bounds__(256, 2) void k_qform(int W, int Ktot, int Kp0, int 
 
   t4 pre[4];
   tile_fetch<T>(Q, Kp, I0, (long)seg.z * QT, pre);
-  tile_store<T>(lds[0], pre);
+  tile_store<T, NJ == 2>(lds[0], pre);
   __syncthreads();
   for (int J = seg.z; J < seg.w; ++J) {
     const int buf = (J - seg.z) & 1;
@@ -360,7 +372,7 @@ __global__ __launch_bounds__(256, 2) void k_qform(int W, int Ktot, int Kp0, int 
           pim[g][v] += f * b;
         }
     }
-    if (more) tile_store<T>(lds[buf ^ 1], pre);
+    if (more) tile_store<T, NJ == 2>(lds[buf ^ 1], pre);
     __syncthreads();
   }
 #pragma unroll
