@@ -302,7 +302,7 @@ WS layout_dims(long M, long G, long Nt, int n_det, int W, void* base) {
   ws.parent = (int*)take(W * sizeof(int));
   ws.cbuf = (double*)take(W * sizeof(double));
   ws.scal = (double*)take(16 * sizeof(double));
-  ws.coefT = take((size_t)G * 2 * W * sizeof(double));
+  ws.coefT = take((size_t)((G + 63) / 64 * 64) * 2 * W * sizeof(double));
   ws.A = take((size_t)W * 2 * M * M * sizeof(double));
   // P_*: also the split Theta of the Q route (M Nt + 128 per walker);
   // ACC_*: also the force-bias and quadratic-form partials
@@ -687,7 +687,8 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
   const TC* Lc = std::is_same<TC, float>::value ? (const TC*)hm->Lf : (const TC*)hm->L;
   constexpr bool BF = std::is_same<TC, Bf16Tag>::value;
   const TT* B1m = std::is_same<TT, float>::value ? (const TT*)b1->d32 : (const TT*)b1->d64;
-  TC* coefT = (TC*)ws.coefT;
+  TC* coefT = (TC*)ws.coefT;  // [2W][Gp] row-major (BF16: the kernels' own layout)
+  const int Gp = (G + 63) / 64 * 64;
   TT* A = (TT*)ws.A;
   TT* Tbuf[2][2] = {{(TT*)ws.Ta_re, (TT*)ws.Ta_im}, {(TT*)ws.Tb_re, (TT*)ws.Tb_im}};
   const bool hybrid = opt->weight_mode == AFQMC_WEIGHT_HYBRID;
@@ -700,16 +701,15 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
       AFQ_CK(afq::fields_coeff_bf16(st, W, G, G, seed, t, wk->system_id, dt, ws.v_re, ws.v_im,
                                     tr->lbar, ws.coefT, ws.mf_re, ws.mf_im, hyr, hyi));
     } else {
-      AFQ_CK(afq::fields_coeff<TC>(st, W, G, seed, t, wk->system_id, dt, ws.v_re, ws.v_im, tr->lbar,
-                                   coefT, ws.mf_re, ws.mf_im, nullptr, hyr, hyi));
+      AFQ_CK(afq::fields_coeff<TC>(st, W, G, Gp, seed, t, wk->system_id, dt, ws.v_re, ws.v_im,
+                                   tr->lbar, coefT, ws.mf_re, ws.mf_im, nullptr, hyr, hyi));
     }
     if (G > 0) {
       TimedLaunch tl(&hm->timer, KC_ABUILD, st);
       if constexpr (BF) {
         AFQ_CK(afq::gemm_bf16<TT>(st, 2 * W, (int)mm, G, ws.coefT, G, hm->Lbf, (int)mm, A, (int)mm, 1.0));
       } else {
-        AFQ_CK((afq::gemm_real<TC, TT, true>(st, 2 * W, (int)mm, G, coefT, 2 * W, 0, Lc, (int)mm, 0,
-                                             A, (int)mm, 0, 1, 1.0)));
+        AFQ_CK((afq::abuild<TC, TT>(st, 2 * W, (int)mm, G, Gp, coefT, Lc, A)));
       }
     } else {
       AFQ_CK(hipMemsetAsync(A, 0, (size_t)W * 2 * mm * sizeof(TT), st));
@@ -1381,8 +1381,9 @@ afqmc_status afqmc_fields(uint64_t seed, uint64_t t, int n_walkers, int n_chol, 
                           double* x_dev, void* stream) {
   if (n_walkers < 1 || n_chol < 1 || system_id < 0 || !x_dev)
     return fail(AFQMC_ERR_ARG, "invalid fields request");
-  AFQ_CK(afq::fields_coeff<double>((hipStream_t)stream, n_walkers, n_chol, seed, t, system_id, 1.0,
-                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, x_dev));
+  AFQ_CK(afq::fields_coeff<double>((hipStream_t)stream, n_walkers, n_chol, 0, seed, t, system_id,
+                                   1.0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   x_dev));
   return AFQMC_OK;
 }
 

@@ -228,12 +228,12 @@ AFQ_INST_CG(float, float, true, 1)
 // mf = -i sqrt(dt) sum_g xs_g lbar_g.
 // ===========================================================================
 template <typename T>
-__global__ __launch_bounds__(256) void k_fields_coeff(int W, int G, uint64_t seed, uint64_t t,
+__global__ __launch_bounds__(256) void k_fields_coeff(int W, int G, int ldc, uint64_t seed, uint64_t t,
                                                       int system_id, double dt,
                                                       const double* __restrict__ v_re,
                                                       const double* __restrict__ v_im,
                                                       const double* __restrict__ lbar,
-                                                      T* __restrict__ coefT, double* mf_re,
+                                                      T* __restrict__ coef, double* mf_re,
                                                       double* mf_im, double* xdump, double* hy_re,
                                                       double* hy_im) {
   __shared__ double red[4];
@@ -256,9 +256,9 @@ __global__ __launch_bounds__(256) void k_fields_coeff(int W, int G, uint64_t see
       const double xsr = x - sq * vi;        // Re(x - xbar)
       const double xsi = sq * (vr - lb);     // Im(x - xbar)
       // i sq xs = -sq*xsi + i sq*xsr
-      if (coefT) {
-        coefT[(long)g * 2 * W + 2 * w] = (T)(-sq * xsi);
-        coefT[(long)g * 2 * W + 2 * w + 1] = (T)(sq * xsr);
+      if (coef) {
+        coef[(long)(2 * w) * ldc + g] = (T)(-sq * xsi);
+        coef[(long)(2 * w + 1) * ldc + g] = (T)(sq * xsr);
       }
       // -i sq xs lbar = sq*xsi*lb - i sq*xsr*lb
       sre += sq * xsi * lb;
@@ -270,6 +270,11 @@ __global__ __launch_bounds__(256) void k_fields_coeff(int W, int G, uint64_t see
       if (xdump) xdump[(long)w * G + g] = x;
     }
   }
+  if (coef)
+    for (int g = G + threadIdx.x; g < ldc; g += blockDim.x) {
+      coef[(long)(2 * w) * ldc + g] = (T)0;
+      coef[(long)(2 * w + 1) * ldc + g] = (T)0;
+    }
   sre = block_sum(sre, red);
   sim = block_sum(sim, red);
   if (threadIdx.x == 0 && mf_re) { mf_re[w] = sre; mf_im[w] = sim; }
@@ -281,18 +286,19 @@ __global__ __launch_bounds__(256) void k_fields_coeff(int W, int G, uint64_t see
 }
 
 template <typename T>
-hipError_t fields_coeff(hipStream_t st, int W, int G, uint64_t seed, uint64_t t, int system_id,
-                        double dt, const double* v_re, const double* v_im, const double* lbar,
-                        T* coefT, double* mf_re, double* mf_im, double* xdump, double* hy_re,
-                        double* hy_im) {
-  hipLaunchKernelGGL((k_fields_coeff<T>), dim3(W), dim3(256), 0, st, W, G, seed, t, system_id, dt,
-                     v_re, v_im, lbar, coefT, mf_re, mf_im, xdump, hy_re, hy_im);
+hipError_t fields_coeff(hipStream_t st, int W, int G, int ldc, uint64_t seed, uint64_t t,
+                        int system_id, double dt, const double* v_re, const double* v_im,
+                        const double* lbar, T* coef, double* mf_re, double* mf_im, double* xdump,
+                        double* hy_re, double* hy_im) {
+  if (coef && ldc < G) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_fields_coeff<T>), dim3(W), dim3(256), 0, st, W, G, ldc, seed, t, system_id,
+                     dt, v_re, v_im, lbar, coef, mf_re, mf_im, xdump, hy_re, hy_im);
   return hipGetLastError();
 }
-template hipError_t fields_coeff<double>(hipStream_t, int, int, uint64_t, uint64_t, int, double,
+template hipError_t fields_coeff<double>(hipStream_t, int, int, int, uint64_t, uint64_t, int, double,
                                          const double*, const double*, const double*, double*,
                                          double*, double*, double*, double*, double*);
-template hipError_t fields_coeff<float>(hipStream_t, int, int, uint64_t, uint64_t, int, double,
+template hipError_t fields_coeff<float>(hipStream_t, int, int, int, uint64_t, uint64_t, int, double,
                                         const double*, const double*, const double*, float*,
                                         double*, double*, double*, double*, double*);
 

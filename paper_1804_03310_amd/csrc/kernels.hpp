@@ -34,12 +34,12 @@ hipError_t cgemm_walkers(hipStream_t st, int W, int Mr, int Nc, int K, const T* 
                          T* Outr, T* Outi, double* D1r, double* D1i, double* D2r, double* D2i,
                          int ldo, long sO, double alpha);
 
-// Fields x, shifted propagator coefficients coefT[g][2w + {0,1}] = i sqrt(dt)(x - xbar)
-// (re, im) and the mean-field log factor mf[w].
+// Fields x, shifted propagator coefficients coef[2w + {0,1}][g] = i sqrt(dt)(x - xbar)
+// (re, im rows of length ldc >= G, zeros beyond G) and the mean-field log factor mf[w].
 template <typename T>
-hipError_t fields_coeff(hipStream_t st, int W, int G, uint64_t seed, uint64_t t, int system_id,
-                        double dt, const double* v_re, const double* v_im, const double* lbar,
-                        T* coefT, double* mf_re, double* mf_im, double* xdump,
+hipError_t fields_coeff(hipStream_t st, int W, int G, int ldc, uint64_t seed, uint64_t t,
+                        int system_id, double dt, const double* v_re, const double* v_im,
+                        const double* lbar, T* coef, double* mf_re, double* mf_im, double* xdump,
                         double* hy_re = nullptr, double* hy_im = nullptr);
 
 // Where the overlap kernels put Theta: the FP64 matrix th[w][m][Nt] (thr
@@ -199,6 +199,11 @@ hipError_t qform(hipStream_t st, int W, int Kp0, int Kp1, int nseg, const int4* 
 // exx[2 w + s] = sum over spin s's segments of part[w][seg]
 hipError_t qform_reduce(hipStream_t st, int W, int nseg0, int nseg1, const double* part,
                         double* exx_re, double* exx_im);
+// Propagator build out[r][n] = sum_g coef[r][g] L[g][n], coef [R][Gp] row-major
+// (zero padded), L [G][Ncol]; MFMA in TC, output in TO.
+template <typename TC, typename TO>
+hipError_t abuild(hipStream_t st, int R, int Ncol, int G, int Gp, const TC* coef, const TC* L,
+                  TO* out);
 // vs[w][0][g] = sum_z part[z][w][g] (both spins' traces together), vs[w][1][g] = 0
 hipError_t fbias_to_vs(hipStream_t st, int W, int G, int nz, const double* part_re,
                        const double* part_im, double* vs_re, double* vs_im);

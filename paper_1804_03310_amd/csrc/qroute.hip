@@ -67,6 +67,30 @@ __device__ inline void tile_store(T* lds, const typename V4<T>::type (&pre)[4]) 
   }
 }
 
+// As tile_fetch for a matrix with nrows x ncols valid entries: zeros outside
+// (16-byte reads where four columns are valid and aligned, else per element).
+template <typename T>
+__device__ inline void tile_fetch_guarded(const T* __restrict__ A, long ld, long r0, long c0,
+                                          long nrows, long ncols, typename V4<T>::type (&pre)[4]) {
+  typedef typename V4<T>::type t4;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int idx = e * 256 + threadIdx.x, row = idx >> 4, c4 = idx & 15;
+    const long r = r0 + row, c = c0 + 4 * c4;
+    t4 v = {0, 0, 0, 0};
+    if (r < nrows) {
+      if ((ld & 3) == 0 && c + 3 < ncols) {
+        v = *(const t4*)(A + r * ld + c);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (c + j < ncols) v[j] = A[r * ld + c + j];
+      }
+    }
+    pre[e] = v;
+  }
+}
+
 // A fragments of 16 walkers (rows) over one k tile: a[4 u + j] holds
 // ts[w][k0 + 16 u + 4 q + j] of walker w = w0 + li (zero beyond W).
 template <typename T>
@@ -294,6 +318,93 @@ template hipError_t fbias_mm<float>(hipStream_t, int, int, int, int, int, const 
                                     const float*, const float*, double*, double*);
 template hipError_t fbias_mm<double>(hipStream_t, int, int, int, int, int, const double*,
                                      const double*, const double*, double*, double*);
+
+// ---------------------------------------------------------------------------
+// Propagator build (Eq. 2-3): A_prop[r][n] = sum_g coef[r][g] L[g][n] for the
+// 2W rows r = 2 w + (re, im) of the shifted field coefficients (row-major,
+// zero padded to Gp) and n over the M^2 operator entries; MFMA in TC, output
+// rounded to TO.  Block = 4 waves x GW groups of 16 rows x 64 columns, row
+// chunk fastest.
+// ---------------------------------------------------------------------------
+template <typename TC, typename TO>
+__global__ __launch_bounds__(256) void k_abuild(int R, int Ncol, int G, int Gp, int nchunk,
+                                                const TC* __restrict__ coef,
+                                                const TC* __restrict__ L, TO* __restrict__ out) {
+  constexpr int GW = QGeom<TC>::GW;
+  typedef typename V4<TC>::type t4;
+  typedef Mfma<TC> MM;
+  __shared__ __attribute__((aligned(32))) TC lds[2][QT * QLD];
+  const int chunk = blockIdx.x % nchunk, nt = blockIdx.x / nchunk;
+  const int l = lane_id(), li = l & 15, q = l >> 4;
+  const int rb = chunk * 64 * GW + wave_id() * 16 * GW;
+  const int nkt = Gp / QT;
+  typename MM::acc_t z[GW][4];
+#pragma unroll
+  for (int g = 0; g < GW; ++g)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) z[g][jb] = MM::zero();
+  TC ar[GW][16];
+  t4 pre[4];
+  tile_fetch_guarded<TC>(L, Ncol, 0, (long)nt * QT, G, Ncol, pre);
+  tile_store<TC, false>(lds[0], pre);
+#pragma unroll
+  for (int g = 0; g < GW; ++g) afrag_fetch<TC>(coef, Gp, R, rb + 16 * g, 0, li, q, ar[g]);
+  __syncthreads();
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int buf = kt & 1;
+    const bool more = kt + 1 < nkt;
+    if (more) tile_fetch_guarded<TC>(L, Ncol, (long)(kt + 1) * QT, (long)nt * QT, G, Ncol, pre);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const t4 b = *(const t4*)(lds[buf] + (16 * u + 4 * q + j) * QLD + 4 * li);
+#pragma unroll
+        for (int g = 0; g < GW; ++g)
+#pragma unroll
+          for (int jb = 0; jb < 4; ++jb) z[g][jb] = MM::mma(ar[g][4 * u + j], b[jb], z[g][jb]);
+      }
+    if (more) {
+      tile_store<TC, false>(lds[buf ^ 1], pre);
+#pragma unroll
+      for (int g = 0; g < GW; ++g)
+        afrag_fetch<TC>(coef, Gp, R, rb + 16 * g, (long)(kt + 1) * QT, li, q, ar[g]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int g = 0; g < GW; ++g)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long r = rb + 16 * g + MM::row(q, v);
+      if (r >= R) continue;
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        const long c = (long)nt * QT + 4 * li + jb;
+        if (c < Ncol) out[r * Ncol + c] = (TO)z[g][jb][v];
+      }
+    }
+}
+
+template <typename TC, typename TO>
+hipError_t abuild(hipStream_t st, int R, int Ncol, int G, int Gp, const TC* coef, const TC* L,
+                  TO* out) {
+  constexpr int GW = QGeom<TC>::GW;
+  if (R <= 0 || Ncol <= 0 || G <= 0 || Gp % QT || Gp < G) return hipErrorInvalidValue;
+  const int nchunk = (R + 64 * GW - 1) / (64 * GW);
+  const long blocks = (long)nchunk * ((Ncol + QT - 1) / QT);
+  hipLaunchKernelGGL((k_abuild<TC, TO>), dim3((unsigned)blocks), dim3(256), 0, st, R, Ncol, G, Gp,
+                     nchunk, coef, L, out);
+  return hipGetLastError();
+}
+template hipError_t abuild<float, float>(hipStream_t, int, int, int, int, const float*, const float*,
+                                         float*);
+template hipError_t abuild<float, double>(hipStream_t, int, int, int, int, const float*,
+                                          const float*, double*);
+template hipError_t abuild<double, float>(hipStream_t, int, int, int, int, const double*,
+                                          const double*, float*);
+template hipError_t abuild<double, double>(hipStream_t, int, int, int, int, const double*,
+                                           const double*, double*);
 
 // ---------------------------------------------------------------------------
 // Quadratic form: segment (s, I, J0, J1) of spin s adds, for every walker of
