@@ -518,8 +518,45 @@ template <int NT>
 struct OvlWave {
   static constexpr int NP = 16 * NT;
   static constexpr int LD = NP + 2;                          // even: 16-byte aligned rows
-  static constexpr int DOUBLES = 2 * NP * LD + 2 * NP + NP;  // S re/im, pivot row, pi
+  // S re/im, two pivot-row buffers of NP (re, im) pairs, pi
+  static constexpr int DOUBLES = 2 * NP * LD + 4 * NP + NP;
 };
+
+// The value lane l ^ 32 holds (one cross-half lane swap, no LDS).
+__device__ inline double other_half(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const bool upper = lane_id() >= 32;
+  const unsigned nlo = upper ? rl[0] : rl[1], nhi = upper ? rh[0] : rh[1];
+  return __longlong_as_double((long long)(((unsigned long long)nhi << 32) | nlo));
+}
+
+template <int CTRL>
+__device__ inline unsigned long long dpp_u64(unsigned long long x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)x, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// Maximum over each 16-lane row: quad butterflies, then row rotations by 4 and 8.
+__device__ inline unsigned long long row_max16_u64(unsigned long long x) {
+  unsigned long long y = dpp_u64<0xB1>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x4E>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x124>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x128>(x);
+  return y > x ? y : x;
+}
+
+__device__ inline unsigned long long readlane_u64(unsigned long long v, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
 
 template <int NT>
 __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, SpinGeom s0, SpinGeom s1,
@@ -547,9 +584,8 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
   }
   double* Sr = olds + wv * L::DOUBLES;
   double* Si = Sr + NP * LD;
-  double* rowr = Si + NP * LD;
-  double* rowi = rowr + NP;
-  int* piarr = (int*)(rowi + NP);
+  double2* prow = (double2*)(Si + NP * LD);  // [2][NP] pivot-row buffers
+  int* piarr = (int*)(Si + NP * LD + 4 * NP);
   const int li = l & 15, lk = l >> 4;
   // ---- S = D_0^T phi (zero padded to NP x NP) ----
   {
@@ -630,65 +666,68 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
   unsigned int used = 0u;
   int mypi = 0, mypinv = 0;
   double pkr = 1.0, pki = 0.0;
-  // a runtime loop over the pivot columns: an unrolled one does not fit the
-  // instruction cache
-#pragma unroll 1
-  for (int k = 0; k < N; ++k) {
-    const int hk = k >> 4, ck = k & 15;
-    double fr = 0.0, fi = 0.0;
+  // Pivot steps unrolled in groups of 16 so that the column index within a
+  // lane's row half is a constant.  Per step: the column k value of every
+  // row (the other half's through a lane swap), the pivot as the largest
+  // |S_ik|^2 among unused rows (16-lane DPP maxima, then lanes 0 and 16),
+  // the raw pivot row published through LDS, and one update for every row,
+  // row_i -= f_i row_p with f_i = S_ik / pv, where the pivot row's own
+  // f = 1 - 1 / pv leaves it scaled by 1 / pv; column k becomes 1 / pv in
+  // the pivot row and -f_i elsewhere (in-place Gauss-Jordan inverse).
+  for (int hk = 0; hk < NT; ++hk) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      fr = (c == ck) ? xr[c] : fr;
-      fi = (c == ck) ? xi[c] : fi;
-    }
-    if (NT == 2) {
-      const double orr = __shfl_xor(fr, 32, AFQ_WAVE), oii = __shfl_xor(fi, 32, AFQ_WAVE);
-      if (h != hk) { fr = orr; fi = oii; }
-    }
-    // candidate key: |S_ik|^2 (non-negative, so its bits order as unsigned)
-    // with the low five mantissa bits replaced by 31 - i (lowest row wins a
-    // tie); rows already used and padding rows get 0
-    const double mag = fr * fr + fi * fi;
-    unsigned long long key =
-        (i < N && !((used >> i) & 1u))
-            ? (((unsigned long long)__double_as_longlong(mag) & ~31ull) | (unsigned long long)(31 - i))
-            : 0ull;
+    for (int ck = 0; ck < 16; ++ck) {
+      const int k = 16 * hk + ck;
+      if (k >= N) break;
+      double fr = xr[ck], fi = xi[ck];
+      if (NT == 2) {
+        const double orr = other_half(fr), oii = other_half(fi);
+        if (h != hk) { fr = orr; fi = oii; }
+      }
+      // candidate key: |S_ik|^2 (non-negative, so its bits order as unsigned)
+      // with the low five mantissa bits replaced by 31 - i (lowest row wins a
+      // tie); rows already used and padding rows get 0
+      const double mag = fr * fr + fi * fi;
+      unsigned long long key =
+          (i < N && !((used >> i) & 1u))
+              ? (((unsigned long long)__double_as_longlong(mag) & ~31ull) | (unsigned long long)(31 - i))
+              : 0ull;
+      key = row_max16_u64(key);
+      const unsigned long long k0 = readlane_u64(key, 0), k1 = readlane_u64(key, 16);
+      const int p = 31 - (int)((k0 > k1 ? k0 : k1) & 31ull);
+      used |= 1u << p;
+      double2* rb = prow + (k & 1) * NP;
+      if (owner && i == p) {
 #pragma unroll
-    for (int o = NP / 2; o >= 1; o >>= 1) {
-      const unsigned long long ok = (unsigned long long)__shfl_xor((long long)key, o, AFQ_WAVE);
-      key = ok > key ? ok : key;
-    }
-    const int p = 31 - (int)(__builtin_amdgcn_readfirstlane((int)(key & 31ull)));
-    used |= 1u << p;
-    const zdbl pv = {readlane_d(fr, p), readlane_d(fi, p)};
-    const zdbl pinv = zdiv(zdbl{1.0, 0.0}, pv);
-    if (l == k) { pkr = pv.re; pki = pv.im; mypi = p; }
-    if (i == p) mypinv = k;
-    if (owner && i == p) {
+        for (int c = 0; c < 16; ++c) rb[16 * h + c] = make_double2(xr[c], xi[c]);
+      }
+      const double pvr = readlane_d(fr, p), pvi = readlane_d(fi, p);
+      const double rden = 1.0 / (pvr * pvr + pvi * pvi);
+      const double pir = pvr * rden, pii = -pvi * rden;
+      if (l == k) { pkr = pvr; pki = pvi; mypi = p; }
+      if (i == p) mypinv = k;
+      double gr, gi;
+      if (i == p) {
+        gr = 1.0 - pir;
+        gi = -pii;
+      } else {
+        gr = fr * pir - fi * pii;
+        gi = fr * pii + fi * pir;
+      }
+      wave_lds_sync();
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
-        const int j = 16 * h + c;
-        const zdbl v = (j == k) ? pinv : zmul(zdbl{xr[c], xi[c]}, pinv);
-        rowr[j] = v.re;
-        rowi[j] = v.im;
+        const double2 r = rb[16 * h + c];
+        double nr = xr[c] - (gr * r.x - gi * r.y);
+        double ni = xi[c] - (gr * r.y + gi * r.x);
+        if (c == ck && (NT == 1 || h == hk)) {
+          nr = (i == p) ? pir : -gr;
+          ni = (i == p) ? pii : -gi;
+        }
+        xr[c] = nr;
+        xi[c] = ni;
       }
     }
-    wave_lds_sync();
-    const zdbl nf = zmul(zdbl{-fr, -fi}, pinv);
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const int j = 16 * h + c;
-      const double rr = rowr[j], ri = rowi[j];
-      if (i == p) {
-        xr[c] = rr; xi[c] = ri;
-      } else if (j == k) {
-        xr[c] = nf.re; xi[c] = nf.im;
-      } else {
-        xr[c] = xr[c] - (fr * rr - fi * ri);
-        xi[c] = xi[c] - (fr * ri + fi * rr);
-      }
-    }
-    wave_lds_sync();
   }
   // ---- log det: pivots and the sign of pi ----
   if (l < N) piarr[l] = mypi;
