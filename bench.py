@@ -449,7 +449,7 @@ def main():
     fbias_report = None
     n_fb, ms_fb = ktimes["force_bias"]
     if route == "q" and n_fb and not multi:
-        # the force-bias class: Theta split, k_fbias_mm and the partial sum
+        # the force-bias class: the k_fbias_mm launch
         fb_flops = fbias_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
         fb_s = (ms_fb / n_fb) / 1e3
         fbias_report = {"flops_per_launch": fb_flops, "avg_launch_ms": fb_s * 1e3,

@@ -356,7 +356,7 @@ bool q_plan(int M, int G, int n_up, int n_dn, std::vector<int4>* segs, int nseg[
   const int nel[2] = {n_up, n_dn};
   int nt[2];
   for (int s = 0; s < 2; ++s) nt[s] = qpad((long)M * nel[s]) / 64;
-  const long cap = acc_cap(M, G, n_up + n_dn);
+  const long cap = (long)M * (n_up + n_dn);  // doubles per walker in ws.Ta_re
   for (int S = std::max(4, std::min(16, (std::max(nt[0], nt[1]) + 4) / 5)); ; S *= 2) {
     long tot = 0;
     for (int s = 0; s < 2; ++s) {
@@ -478,10 +478,8 @@ afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqm
     }
     return AFQMC_OK;
   }
-  if (qr) {
-    afqmc_status rq = measure_qroute(tr, wk, ws, f32, st);
-    if (rq != AFQMC_OK) return rq;
-  } else if (G > 0) {
+  if (qr) return measure_qroute(tr, wk, ws, f32, st);
+  if (G > 0) {
     TimedLaunch tl(&hm->timer, KC_EXCHANGE, st);
     if (chol == AFQMC_BF16) {
       AFQ_CK(afq::exchange_bf16(st, W, M, tr->MP32, Nt, G, s0, s1, ws.th_re, ws.th_im, ws.vs_re,
@@ -624,33 +622,37 @@ int force_bias_partials(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bool f
   return nz;
 }
 
-// E_L ingredients by the Q route (single determinant): the force bias into
-// the per-spin trace layout, then per spin theta^T Q theta over the split
-// Theta that the force bias left in ws.P_* (partials in ws.ACC_re).
+// E_L by the Q route (single determinant) from the split Theta rows in
+// ws.P_*: force-bias partials (ws.ACC_*), theta^T Q theta segment partials
+// (ws.Ta_re), then one combination kernel for v, exx, E_L and log S.
 afqmc_status measure_qroute(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bool fp32,
                             hipStream_t st) {
   afqmc_ham* hm = tr->ham;
   const int W = wk->n_walkers, G = hm->G;
+  int nz;
   {
     TimedLaunch tl(&hm->timer, KC_FBIAS, st);
     hipError_t e;
-    const int nz = force_bias_partials(tr, wk, ws, fp32, st, &e);
+    nz = force_bias_partials(tr, wk, ws, fp32, st, &e);
     AFQ_CK(e);
-    AFQ_CK(afq::fbias_to_vs(st, W, G, nz, ws.ACC_re, ws.ACC_im, ws.vs_re, ws.vs_im));
   }
   const int nseg = tr->nseg[0] + tr->nseg[1];
+  double* qpart = (double*)ws.Ta_re;
   {
     TimedLaunch tl(&hm->timer, KC_EXCHANGE, st);
     if (fp32) {
       AFQ_CK(afq::qform<float>(st, W, tr->Kp[0], tr->Kp[1], nseg, tr->qsegs, (const float*)ws.P_re,
-                               (const float*)ws.P_im, tr->Q32[0], tr->Q32[1], ws.ACC_re));
+                               (const float*)ws.P_im, tr->Q32[0], tr->Q32[1], qpart));
     } else {
       AFQ_CK(afq::qform<double>(st, W, tr->Kp[0], tr->Kp[1], nseg, tr->qsegs, ws.P_re, ws.P_im,
-                                tr->Q64[0], tr->Q64[1], ws.ACC_re));
+                                tr->Q64[0], tr->Q64[1], qpart));
     }
   }
   TimedLaunch tl(&hm->timer, KC_OTHER, st);
-  AFQ_CK(afq::qform_reduce(st, W, tr->nseg[0], tr->nseg[1], ws.ACC_re, ws.exx_re, ws.exx_im));
+  AFQ_CK(afq::combine_qroute(st, W, G, nz, tr->nseg[0], tr->nseg[1], hm->e_core, ws.ACC_re,
+                             ws.ACC_im, qpart, ws.e1_re, ws.e1_im, ws.ld_re, ws.ld_im, ws.v_re,
+                             ws.v_im, ws.exx_re, ws.exx_im, ws.lsn_re, ws.lsn_im, ws.eln_re,
+                             ws.eln_im, ws.vfin));
   return AFQMC_OK;
 }
 

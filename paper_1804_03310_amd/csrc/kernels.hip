@@ -1626,35 +1626,6 @@ hipError_t hybrid_force_bias_finish(hipStream_t st, int W, int G, int nz, const 
   return hipGetLastError();
 }
 
-// force bias of the Q route into the per-spin trace layout: vs[w][0][g] =
-// sum_z part[z][w][g], vs[w][1][g] = 0 (the combination adds the two)
-__global__ void k_fbias_to_vs(int W, int G, int nz, const double* __restrict__ part_re,
-                              const double* __restrict__ part_im, double* vs_re, double* vs_im) {
-  const long n = (long)W * G;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    const long w = e / G, g = e % G;
-    double sr = 0.0, si = 0.0;
-    for (int z = 0; z < nz; ++z) {
-      sr += part_re[(long)z * n + e];
-      si += part_im[(long)z * n + e];
-    }
-    vs_re[(w * 2) * G + g] = sr;
-    vs_im[(w * 2) * G + g] = si;
-    vs_re[(w * 2 + 1) * G + g] = 0.0;
-    vs_im[(w * 2 + 1) * G + g] = 0.0;
-  }
-}
-
-hipError_t fbias_to_vs(hipStream_t st, int W, int G, int nz, const double* part_re,
-                       const double* part_im, double* vs_re, double* vs_im) {
-  const long n = (long)W * G;
-  if (n == 0) return hipSuccess;
-  const int blocks = (int)std::min<long>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_fbias_to_vs, dim3(blocks), dim3(256), 0, st, W, G, nz, part_re, part_im,
-                     vs_re, vs_im);
-  return hipGetLastError();
-}
-
 __global__ __launch_bounds__(256) void k_reset_dead(int M, int Nt, int G, const int* dead,
                                                     const double* D0, double ref_ls_re,
                                                     double ref_ls_im, double ref_el_re,
@@ -1789,9 +1760,97 @@ __global__ __launch_bounds__(256) void k_mgs(int M, int Nt, int n_up, int n_dn,
   }
 }
 
+// Same for M <= 64: one wave per (walker, spin), lane m owning row m of every
+// column; the columns sit in LDS as [k][m] (each lane touches only its own
+// row there), so the only cross-lane step is the sum over rows, a
+// fixed-order DPP reduction (16-lane rows, then lanes 0, 16, 32, 48) taken
+// for four columns at a time.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+template <int NV>
+__device__ inline void wave_sum_dpp(double (&x)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] += dpp_f64<0xB1>(x[v]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] += dpp_f64<0x4E>(x[v]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] += dpp_f64<0x124>(x[v]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] += dpp_f64<0x128>(x[v]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    x[v] = (readlane_d(x[v], 0) + readlane_d(x[v], 16)) + (readlane_d(x[v], 32) + readlane_d(x[v], 48));
+}
+
+__global__ __launch_bounds__(128) void k_mgs_wave(int M, int Nt, int n_up, int n_dn,
+                                                  double* __restrict__ phr,
+                                                  double* __restrict__ phi) {
+  extern __shared__ __attribute__((aligned(16))) double mlds[];
+  const int w = blockIdx.x, s = wave_id(), l = lane_id();
+  const int N = s ? n_dn : n_up, off = s ? n_up : 0;
+  const int Nmax = n_up > n_dn ? n_up : n_dn;
+  double2* Lc = (double2*)mlds + (long)s * Nmax * M;  // [k][m]
+  const long wb = (long)w * M * Nt;
+  if (N == 0) return;
+  for (int e = l; e < M * N; e += AFQ_WAVE) {
+    const int m = e / N, k = e % N;
+    Lc[k * M + m] = make_double2(phr[wb + (long)m * Nt + off + k], phi[wb + (long)m * Nt + off + k]);
+  }
+  wave_lds_sync();
+  const bool act = l < M;
+  for (int j = 0; j < N; ++j) {
+    double2 q = act ? Lc[j * M + l] : make_double2(0.0, 0.0);
+    double nv[1] = {q.x * q.x + q.y * q.y};
+    wave_sum_dpp<1>(nv);
+    const double r = sqrt(nv[0]);
+    q.x /= r;
+    q.y /= r;
+    if (act) Lc[j * M + l] = q;
+    for (int k0 = j + 1; k0 < N; k0 += 4) {
+      double2 a[4];
+      double p[8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u;
+        a[u] = (act && k < N) ? Lc[k * M + l] : make_double2(0.0, 0.0);
+        p[2 * u] = q.x * a[u].x + q.y * a[u].y;  // conj(q) a
+        p[2 * u + 1] = q.x * a[u].y - q.y * a[u].x;
+      }
+      wave_sum_dpp<8>(p);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u;
+        if (act && k < N) {
+          a[u].x -= p[2 * u] * q.x - p[2 * u + 1] * q.y;
+          a[u].y -= p[2 * u] * q.y + p[2 * u + 1] * q.x;
+          Lc[k * M + l] = a[u];
+        }
+      }
+    }
+  }
+  wave_lds_sync();
+  for (int e = l; e < M * N; e += AFQ_WAVE) {
+    const int m = e / N, k = e % N;
+    const double2 v = Lc[k * M + m];
+    phr[wb + (long)m * Nt + off + k] = v.x;
+    phi[wb + (long)m * Nt + off + k] = v.y;
+  }
+}
+
 hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double* phr, double* phi,
                size_t max_lds) {
   const int N = n_up > n_dn ? n_up : n_dn;
+  const size_t lds_wave = (size_t)2 * N * M * 2 * sizeof(double);
+  if (M <= AFQ_WAVE && lds_wave <= max_lds) {
+    hipLaunchKernelGGL(k_mgs_wave, dim3(W), dim3(128), lds_wave, st, M, Nt, n_up, n_dn, phr, phi);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)2 * M * N * sizeof(double);
   if (lds <= max_lds)
     hipLaunchKernelGGL(k_mgs<true>, dim3(W, 2), dim3(256), lds, st, M, Nt, n_up, n_dn, phr, phi);

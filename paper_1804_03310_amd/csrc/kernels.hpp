@@ -196,17 +196,19 @@ hipError_t fbias_mm(hipStream_t st, int W, int Ktot, int G, int Gp, int nz, cons
 template <typename T>
 hipError_t qform(hipStream_t st, int W, int Kp0, int Kp1, int nseg, const int4* segs, const T* tsr,
                  const T* tsi, const T* Q0, const T* Q1, double* part);
-// exx[2 w + s] = sum over spin s's segments of part[w][seg]
-hipError_t qform_reduce(hipStream_t st, int W, int nseg0, int nseg1, const double* part,
-                        double* exx_re, double* exx_im);
 // Propagator build out[r][n] = sum_g coef[r][g] L[g][n], coef [R][Gp] row-major
 // (zero padded), L [G][Ncol]; MFMA in TC, output in TO.
 template <typename TC, typename TO>
 hipError_t abuild(hipStream_t st, int R, int Ncol, int G, int Gp, const TC* coef, const TC* L,
                   TO* out);
-// vs[w][0][g] = sum_z part[z][w][g] (both spins' traces together), vs[w][1][g] = 0
-hipError_t fbias_to_vs(hipStream_t st, int W, int G, int nz, const double* part_re,
-                       const double* part_im, double* vs_re, double* vs_im);
+// Q-route E_L: force bias from nz partials, exchange from the segment partials,
+// combined with E1 and log det (one wave per walker).
+hipError_t combine_qroute(hipStream_t st, int W, int G, int nz, int nseg0, int nseg1, double e_core,
+                          const double* fp_re, const double* fp_im, const double* qpart,
+                          const double* e1_re, const double* e1_im, const double* ld_re,
+                          const double* ld_im, double* v_re, double* v_im, double* exx_re,
+                          double* exx_im, double* lsn_re, double* lsn_im, double* eln_re,
+                          double* eln_im, int* vfin);
 hipError_t fields_coeff_bf16(hipStream_t st, int W, int G, int ldg, uint64_t seed, uint64_t t,
                              int system_id, double dt, const double* v_re, const double* v_im,
                              const double* lbar, void* coef, double* mf_re, double* mf_im,

@@ -520,16 +520,41 @@ template hipError_t qform<float>(hipStream_t, int, int, int, int, const int4*, c
 template hipError_t qform<double>(hipStream_t, int, int, int, int, const int4*, const double*,
                                   const double*, const double*, const double*, double*);
 
-// exx[2 w + s] = sum over spin s's segments of part[w][seg]: one wave per
-// walker, lanes striding over the segments, then a fixed-order butterfly.
-__global__ __launch_bounds__(256) void k_qform_reduce(int W, int nseg0, int nseg1,
-                                                      const double* __restrict__ part,
-                                                      double* __restrict__ exx_re,
-                                                      double* __restrict__ exx_im) {
+// Q-route combination, one wave per walker: v_g = sum_z fpart[z][w][g] (the
+// force-bias partials, fixed order), the exchange terms exx_s = sum over spin
+// s's segments of qpart[w][seg], then E_L = e_core + E1 + 1/2 sum_g v_g^2 -
+// 1/2 (exx_0 + exx_1) and log S = log det_0 + log det_1 (Sec. II local
+// energy); vfin = 0 when a force-bias entry is not finite.
+__global__ __launch_bounds__(256) void k_combine_qroute(
+    int W, int G, int nz, int nseg0, int nseg1, double e_core, const double* __restrict__ fp_re,
+    const double* __restrict__ fp_im, const double* __restrict__ qpart,
+    const double* __restrict__ e1_re, const double* __restrict__ e1_im,
+    const double* __restrict__ ld_re, const double* __restrict__ ld_im, double* __restrict__ v_re,
+    double* __restrict__ v_im, double* exx_re, double* exx_im, double* lsn_re, double* lsn_im,
+    double* eln_re, double* eln_im, int* vfin) {
   const int w = blockIdx.x * 4 + wave_id(), l = lane_id();
   if (w >= W) return;
+  const long n = (long)W * G;
+  double jr = 0.0, ji = 0.0;
+  int fin = 1;
+  for (int g = l; g < G; g += AFQ_WAVE) {
+    double a = 0.0, b = 0.0;
+    for (int z = 0; z < nz; ++z) {
+      a += fp_re[z * n + (long)w * G + g];
+      b += fp_im[z * n + (long)w * G + g];
+    }
+    v_re[(long)w * G + g] = a;
+    v_im[(long)w * G + g] = b;
+    jr += a * a - b * b;
+    ji += 2.0 * a * b;
+    if (!isfinite(a) || !isfinite(b)) fin = 0;
+  }
+  jr = wave_sum(jr);
+  ji = wave_sum(ji);
+  const double f = wave_sum((double)fin);
   const int nseg = nseg0 + nseg1;
-  const double* p = part + (long)w * nseg * 2;
+  const double* p = qpart + (long)w * nseg * 2;
+  double x[2][2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int lo = s ? nseg0 : 0, hi = s ? nseg : nseg0;
@@ -538,19 +563,31 @@ __global__ __launch_bounds__(256) void k_qform_reduce(int W, int nseg0, int nseg
       a += p[2 * sg];
       b += p[2 * sg + 1];
     }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (l == 0) {
-      exx_re[2 * w + s] = a;
-      exx_im[2 * w + s] = b;
-    }
+    x[s][0] = wave_sum(a);
+    x[s][1] = wave_sum(b);
+  }
+  if (l == 0) {
+    exx_re[2 * w] = x[0][0];
+    exx_re[2 * w + 1] = x[1][0];
+    exx_im[2 * w] = x[0][1];
+    exx_im[2 * w + 1] = x[1][1];
+    eln_re[w] = e_core + (e1_re[2 * w] + e1_re[2 * w + 1]) + 0.5 * jr - 0.5 * (x[0][0] + x[1][0]);
+    eln_im[w] = (e1_im[2 * w] + e1_im[2 * w + 1]) + 0.5 * ji - 0.5 * (x[0][1] + x[1][1]);
+    lsn_re[w] = ld_re[2 * w] + ld_re[2 * w + 1];
+    lsn_im[w] = ld_im[2 * w] + ld_im[2 * w + 1];
+    vfin[w] = (f == (double)AFQ_WAVE) ? 1 : 0;
   }
 }
 
-hipError_t qform_reduce(hipStream_t st, int W, int nseg0, int nseg1, const double* part,
-                        double* exx_re, double* exx_im) {
-  hipLaunchKernelGGL(k_qform_reduce, dim3((W + 3) / 4), dim3(256), 0, st, W, nseg0, nseg1, part,
-                     exx_re, exx_im);
+hipError_t combine_qroute(hipStream_t st, int W, int G, int nz, int nseg0, int nseg1, double e_core,
+                          const double* fp_re, const double* fp_im, const double* qpart,
+                          const double* e1_re, const double* e1_im, const double* ld_re,
+                          const double* ld_im, double* v_re, double* v_im, double* exx_re,
+                          double* exx_im, double* lsn_re, double* lsn_im, double* eln_re,
+                          double* eln_im, int* vfin) {
+  hipLaunchKernelGGL(k_combine_qroute, dim3((W + 3) / 4), dim3(256), 0, st, W, G, nz, nseg0, nseg1,
+                     e_core, fp_re, fp_im, qpart, e1_re, e1_im, ld_re, ld_im, v_re, v_im, exx_re,
+                     exx_im, lsn_re, lsn_im, eln_re, eln_im, vfin);
   return hipGetLastError();
 }
 
