@@ -230,7 +230,10 @@ def precision_report(args):
     trajectory with the same fields (includes the trajectories' divergence),
     both against the FP64 path, which the parity tests pin to the FP64 oracle
     at this size.  Only the contraction precision varies; Taylor, B1,
-    overlaps, inverses, determinants and MGS stay FP64."""
+    overlaps, inverses, determinants and MGS stay FP64.  The modes run the
+    per-vector (Ltil) exchange route, whose contractions take the mode's
+    precision; "<prec>+q" runs the Q route (FP32 contractions only while
+    M max(N) <= AFQMC_QROUTE_FP32_MAX_K, else FP64)."""
     import torch
 
     import afqmc_synth as syn
@@ -259,10 +262,16 @@ def precision_report(args):
            "unit": "Ha", "n_gpus": 1, "data": "synthetic",
            "config": {"workload": wl.name, "M": wl.M, "n_up": wl.n_up, "n_dn": wl.n_dn,
                       "n_chol": wl.n_chol, "n_walkers": W, "steps": steps, "l_scale": wl.l_scale,
-                      "varied": "propagator build and L~ Theta contractions",
+                      "varied": "propagator build and L~ Theta contractions (Ltil route); "
+                                "+q: the Q route's contractions per the FP32 size limit",
                       "fixed_fp64": "Taylor, B1, overlaps, inverses, determinants, MGS, sums"},
            "e_mix_fp64_last": float(em64[-1]), "modes": {}}
-    for prec in args.sweep_precs.split(","):
+    q_ok = trial.exchange_route == "q"
+    for mode in args.sweep_precs.split(","):
+        prec, _, rt = mode.partition("+")
+        if rt == "q" and not q_ok:
+            continue
+        trial.exchange_route = "q" if rt == "q" else "ltilde"
         # (i) kernel error: E_L on the FP64 trajectory's walkers
         w.phi_re.copy_(phi_re)
         w.phi_im.copy_(phi_im)
@@ -274,7 +283,7 @@ def precision_report(args):
         afq.walkers_from_trial(ham, trial, w)
         em = afq.propagate(ham, trial, w, steps, wl.dt, 7, 0,
                            afq.Options(chol_prec=prec, **base)).cpu().numpy()
-        out["modes"][prec] = {"el_max_abs_err": float(d.max()), "el_mean_abs_err": float(d.mean()),
+        out["modes"][mode] = {"el_max_abs_err": float(d.max()), "el_mean_abs_err": float(d.mean()),
                               "el_max_rel_err": float((d / np.abs(el64[alive])).max()),
                               "emix_max_abs_drift": float(np.abs(em - em64).max()),
                               "emix_drift_last": float(abs(em[-1] - em64[-1]))}
@@ -325,7 +334,7 @@ def main():
     ap.add_argument("--tte-steps", type=int, default=50)
     ap.add_argument("--precision-report", action="store_true",
                     help="E_L error and E_mix drift of the contraction precisions vs FP64")
-    ap.add_argument("--sweep-precs", default="fp32,bf16,fp64")
+    ap.add_argument("--sweep-precs", default="fp32,bf16,fp64,fp32+q")
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed request stream through the serving loop instead")
     ap.add_argument("--requests", type=int, default=64)
@@ -427,7 +436,11 @@ def main():
         ex_flops = exchange_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
         ex_name = ("k_exchange_full (fused Ltil*Theta, Tr X, Tr XX)"
                    if max(wl.n_up, wl.n_dn) <= 32 else "k_exchange (fused Ltil*Theta, Tr X, Tr XX)")
-    ex_peak = {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}[chol_prec]
+    # the Q route's contractions are FP32 only under FP32 and while
+    # M max(N) <= AFQMC_QROUTE_FP32_MAX_K, FP64 otherwise
+    q32 = chol_prec == "fp32" and wl.M * max(wl.n_up, wl.n_dn) <= afq._abi.QROUTE_FP32_MAX_K
+    ex_prec = ("fp32" if q32 else "fp64") if (route == "q" and not multi) else chol_prec
+    ex_peak = {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}[ex_prec]
     cands = [("exchange", ex_name, ex_flops, ex_peak)]
     if taylor_fused(wl.M, wl.n_up + wl.n_dn, taylor_prec):
         cands.append(("taylor_b1",
@@ -441,7 +454,7 @@ def main():
         ach = fl / a_s / 1e12 if n_l else float("nan")
         lines.append({"class": cls, "bound": "mfma", "kernel": nm, "achieved": ach, "peak": pk,
                       "unit": "TFLOP/s", "frac": ach / pk,
-                      "traffic": measured_traffic(wl.name, cls, chol_prec, taylor_prec),
+                      "traffic": measured_traffic(wl.name, cls, ex_prec, taylor_prec),
                       "flops_per_launch": fl, "avg_launch_ms": a_s * 1e3, "launches": n_l,
                       "ms_per_step": ms_l / max(args.steps, 1)})
     lines.sort(key=lambda d: -(d["ms_per_step"] if d["launches"] else 0.0))
@@ -475,7 +488,9 @@ def main():
                    "weight_mode": args.weight_mode, "exchange_route": route,
                    "meas_every": args.meas_every if args.weight_mode == "hybrid" else 1,
                    "precision": f"contractions {chol_prec}, Taylor/B1 {taylor_prec}, "
-                                "overlap/inverse/det/MGS/sums fp64",
+                                "overlap/inverse/det/MGS/sums fp64"
+                                + (", Q-route exchange and force bias fp64"
+                                   if route == "q" and ex_prec == "fp64" else ""),
                    "e_trial": et, "e_mix_last": e_last, "alive_walkers": alive},
         "roofline": roof,
         "roofline_other": roof_other,

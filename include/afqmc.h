@@ -59,6 +59,11 @@ typedef enum {
 typedef enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16 = 2 } afqmc_prec;
 
 #define AFQMC_MAX_EXC 4      /* excitations per spin in one determinant      */
+/* The Q exchange route (afqmc_trial_exchange_route) runs its contractions in
+ * FP32 under chol_prec FP32 only while M * max(N_up, N_dn) is at most this;
+ * above it, and under FP64, they are FP64 (the quadratic form sums M^2 N^2
+ * terms of both signs per spin, and its FP32 error grows with their number). */
+#define AFQMC_QROUTE_FP32_MAX_K 4096
 #define AFQMC_MAX_NEL 64     /* electrons per spin                           */
 #define AFQMC_MAX_M 256      /* orbitals                                     */
 
@@ -152,7 +157,9 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
  * precomputed two-index tensor Q[(n a)][(m b)] = sum_g Ltil_g[a][m]
  * Ltil_g[b][n] per spin, as the quadratic form theta^T Q theta (chosen at
  * set-up for single-determinant trials with n_chol >= 2 M and M N_sigma <=
- * 16384; the BF16 contraction mode always takes route 0). */
+ * 16384; the BF16 contraction mode always takes route 0).  Route 1
+ * contracts in FP32 under chol_prec FP32 only up to AFQMC_QROUTE_FP32_MAX_K,
+ * else in FP64. */
 afqmc_status afqmc_trial_exchange_route(const afqmc_trial *trial, int *route);
 
 /* Select the exchange route of later measurements: 0 (Ltil) is always

@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "AFQMC_OK", -1: "AFQMC_ERR_ARG", -2: "AFQMC_ERR_OOM", -3: "AF
                 -7: "AFQMC_ERR_UNSUPPORTED"}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 MAX_EXC = 4
+QROUTE_FP32_MAX_K = 4096  # AFQMC_QROUTE_FP32_MAX_K
 
 # Every symbol include/afqmc.h declares.
 EXPORTED = ["afqmc_init_hamiltonian", "afqmc_init_trial", "afqmc_walker_workspace_bytes",

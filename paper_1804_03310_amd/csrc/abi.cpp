@@ -222,7 +222,8 @@ struct afqmc_trial {
   // exchange through Q[(n a)][(m b)] = sum_g Ltil_g[a][m] Ltil_g[b][n] per spin
   // (single determinant, when the Cholesky count makes it the cheaper route)
   bool qroute = false;  // measurements take the Q route
-  bool qbuilt = false;  // Q64 / Q32 / qsegs are set up
+  bool qbuilt = false;  // Q64 / qsegs are set up
+  bool q32 = false;     // Q32 / Lq32 too: the FP32 contractions are allowed (q_fp32_ok)
   double* Q64[2] = {nullptr, nullptr};  // [Kp][Kp], zero padded
   float* Q32[2] = {nullptr, nullptr};
   int4* qsegs = nullptr;  // (spin, I, J0, J1) tile-pair segments, spin 0 first
@@ -377,6 +378,15 @@ bool q_plan(int M, int G, int n_up, int n_dn, std::vector<int4>* segs, int nseg[
   }
 }
 
+// The Q route's contractions may run in FP32 (under chol_prec FP32) only while
+// the quadratic form is short: it sums M^2 N^2 terms of both signs per spin,
+// and the FP32 rounding error grows with their number (measured per-step E_L
+// error: within 0.1 mHa at M N = 1250, 2.2e-4 Ha at M N = 10000).  Above
+// the limit the Q route runs FP64 in every mode.
+bool q_fp32_ok(int M, int n_up, int n_dn) {
+  return (long)M * std::max(n_up, n_dn) <= AFQMC_QROUTE_FP32_MAX_K;
+}
+
 bool use_qroute(int M, int G, int n_up, int n_dn, int n_det) {
   if (n_det != 1 || G < 2 * M) return false;
   if ((long)M * std::max(n_up, n_dn) > 16384) return false;
@@ -453,10 +463,11 @@ afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqm
   const bool f32 = chol == AFQMC_FP32;
   const afq::SpinGeom s0 = spin_geom(tr, 0, chol), s1 = spin_geom(tr, 1, chol);
   const bool qr = tr->n_det == 1 && G > 0 && tr->qroute && chol != AFQMC_BF16;
+  const bool q32 = f32 && tr->q32;  // Q-route contraction type
   {
     TimedLaunch tl(&hm->timer, KC_OVERLAP, st);
     AFQ_CK(afq::overlap_theta(st, W, M, Nt, s0, s1, wk->phi_re, wk->phi_im,
-                              qr ? split_out(tr, ws, f32) : fp64_out(ws), ws.ld_re, ws.ld_im,
+                              qr ? split_out(tr, ws, q32) : fp64_out(ws), ws.ld_re, ws.ld_im,
                               ws.e1_re, ws.e1_im, hm->max_lds));
   }
   if (tr->n_det > 1) {
@@ -478,7 +489,7 @@ afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqm
     }
     return AFQMC_OK;
   }
-  if (qr) return measure_qroute(tr, wk, ws, f32, st);
+  if (qr) return measure_qroute(tr, wk, ws, q32, st);
   if (G > 0) {
     TimedLaunch tl(&hm->timer, KC_EXCHANGE, st);
     if (chol == AFQMC_BF16) {
@@ -753,7 +764,7 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
     }
     afqmc_status rs;
     if (hybrid && !measuring && tr->n_det == 1 && G > 0)
-      rs = hybrid_force_bias(tr, wk, ws, opt->chol_prec != AFQMC_FP64, st);
+      rs = hybrid_force_bias(tr, wk, ws, opt->chol_prec != AFQMC_FP64 && tr->q32, st);
     else
       rs = measure_core(tr, wk, ws, opt->chol_prec, st);
     if (rs != AFQMC_OK) return rs;
@@ -885,13 +896,14 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
   tot += 3 * rnd(std::max<size_t>(g, 1) * 8) + rnd(m * Nt * 8) + rnd(mm * 8) + 2 * rnd(mm * 12);
   if (n_det > 1) tot += rnd((size_t)n_det * 40) + rnd((size_t)n_det * 8);
   const size_t kq[2] = {(size_t)qpad((long)M * n_up), (size_t)qpad((long)M * n_dn)};
-  if (n_det == 1 && g > 0) tot += rnd((kq[0] + kq[1]) * qpad(g) * 12);  // Lq
+  const size_t qb = q_fp32_ok(M, n_up, n_dn) ? 12 : 8;  // FP64 (+ FP32) copies
+  if (n_det == 1 && g > 0) tot += rnd((kq[0] + kq[1]) * qpad(g) * qb);  // Lq
   if (use_qroute(M, n_chol, n_up, n_dn, n_det)) {
     int ns[2];
     q_plan(M, n_chol, n_up, n_dn, nullptr, ns);
     tot += rnd((size_t)(ns[0] + ns[1]) * 16);
     for (int s = 0; s < 2; ++s)
-      if (nel[s]) tot += rnd(kq[s] * kq[s] * 8) + rnd(kq[s] * kq[s] * 4);
+      if (nel[s]) tot += rnd(kq[s] * kq[s] * 8) + (qb == 12 ? rnd(kq[s] * kq[s] * 4) : 0);
   }
   tot += 2 * rnd((size_t)n_walkers * m * Nt * 8) + 5 * rnd((size_t)n_walkers * 8);  // walkers
   tot += layout_dims(M, n_chol, (long)Nt, n_det, n_walkers, nullptr).total;
@@ -1095,17 +1107,22 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
   }
   for (int s = 0; s < 2; ++s) tr->Kp[s] = qpad((long)M * nel[s]);
   tr->Gp = qpad(G);
+  tr->q32 = q_fp32_ok(M, n_up, n_dn);
   if (n_det == 1 && G > 0) {
     const size_t nk = (size_t)(tr->Kp[0] + tr->Kp[1]) * tr->Gp;
-    void *q64, *q32;
-    if (tr->arena.alloc(&q64, nk * 8) || tr->arena.alloc(&q32, nk * 4))
-      return bad(AFQMC_ERR_OOM, "trial allocation failed");
+    void* q64;
+    if (tr->arena.alloc(&q64, nk * 8)) return bad(AFQMC_ERR_OOM, "trial allocation failed");
     tr->Lq64 = (double*)q64;
-    tr->Lq32 = (float*)q32;
     if (afq::build_lsplit(st, G, tr->Gp, M, tr->MP4, n_up, n_dn, tr->NP[0], tr->NP[1], tr->Kp[0],
-                          tr->Kp[1], tr->Lt64[0], tr->Lt64[1], tr->Lq64) != hipSuccess ||
-        afq::convert_f64_f32(st, tr->Lq64, tr->Lq32, (long)nk) != hipSuccess)
+                          tr->Kp[1], tr->Lt64[0], tr->Lt64[1], tr->Lq64) != hipSuccess)
       return bad(AFQMC_ERR_DEVICE, "force-bias operand");
+    if (tr->q32) {
+      void* q32;
+      if (tr->arena.alloc(&q32, nk * 4)) return bad(AFQMC_ERR_OOM, "trial allocation failed");
+      tr->Lq32 = (float*)q32;
+      if (afq::convert_f64_f32(st, tr->Lq64, tr->Lq32, (long)nk) != hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "force-bias operand");
+    }
   }
   if (use_qroute(M, G, n_up, n_dn, n_det)) {
     std::vector<int4> segs;
@@ -1120,8 +1137,9 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
     for (int s = 0; s < 2; ++s) {
       if (nel[s] == 0) continue;
       const long Kq = tr->Kp[s], Kp = (long)tr->MP4 * tr->NP[s];
-      void *q64, *q32;
-      if (tr->arena.alloc(&q64, (size_t)Kq * Kq * 8) || tr->arena.alloc(&q32, (size_t)Kq * Kq * 4))
+      void *q64, *q32 = nullptr;
+      if (tr->arena.alloc(&q64, (size_t)Kq * Kq * 8) ||
+          (tr->q32 && tr->arena.alloc(&q32, (size_t)Kq * Kq * 4)))
         return bad(AFQMC_ERR_OOM, "trial allocation failed");
       tr->Q64[s] = (double*)q64;
       tr->Q32[s] = (float*)q32;
@@ -1135,8 +1153,8 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
               hipSuccess &&
           afq::perm_qpad<double>(st, M, nel[s], tr->NP[s], tr->MP4, (int)Kq, P, tr->Q64[s]) ==
               hipSuccess &&
-          afq::perm_qpad<float>(st, M, nel[s], tr->NP[s], tr->MP4, (int)Kq, P, tr->Q32[s]) ==
-              hipSuccess &&
+          (!tr->q32 || afq::perm_qpad<float>(st, M, nel[s], tr->NP[s], tr->MP4, (int)Kq, P,
+                                             tr->Q32[s]) == hipSuccess) &&
           hipStreamSynchronize(st) == hipSuccess;
       (void)hipFree(P);
       if (!ok) return bad(AFQMC_ERR_DEVICE, "Q set-up");
