@@ -217,17 +217,20 @@ afqmc_status afqmc_reconfigure(afqmc_trial *trial, afqmc_walkers *walkers, uint6
 afqmc_status afqmc_fields(uint64_t seed, uint64_t t, int n_walkers, int n_chol,
                           int system_id, double *x_dev, void *stream);
 
-/* Kernel timing.  When enabled, every launch of the kernels of one class
+/* Kernel timing.  For each class whose bit is set in class_mask (bit c for
+ * class c, 0 turns timing off), every launch of the kernels of that class
  * made by this Hamiltonian's calls is bracketed by a pair of HIP events
- * recorded on the launch stream.  Classes: 0 fused exchange / force bias
- * (L~ Theta contraction), 1 propagator build sum_g c_g L_g, 2 Taylor and
- * B1 products, 3 overlap / inverse / Theta, 4 MGS, 5 comb, 6 other
- * per-walker kernels, 7 force bias alone (the hybrid form's steps without
- * an E_L measurement).  afqmc_timing_read synchronises on the recorded
- * events, returns the number of timed launches and their summed duration in
- * milliseconds for one class, and clears that class. */
+ * recorded on the launch stream (events are created when timing is turned
+ * on, not per launch).  Classes: 0 exchange (the per-vector L~ Theta
+ * contraction with the force-bias traces, or the Q route's quadratic form),
+ * 1 propagator build sum_g c_g L_g, 2 Taylor and B1 products, 3 overlap /
+ * inverse / Theta, 4 MGS, 5 comb, 6 other per-walker kernels, 7 force-bias
+ * GEMM (Q route and the hybrid form's steps without an E_L measurement).
+ * afqmc_timing_read synchronises on the recorded events, returns the number
+ * of timed launches and their summed duration in milliseconds for one class,
+ * and clears that class. */
 #define AFQMC_NUM_KERNEL_CLASSES 8
-afqmc_status afqmc_timing_enable(afqmc_ham *ham, int enable);
+afqmc_status afqmc_timing_enable(afqmc_ham *ham, int class_mask);
 afqmc_status afqmc_timing_read(afqmc_ham *ham, int kernel_class, int64_t *launches,
                                double *total_ms);
 

@@ -191,8 +191,17 @@ def reconfigure(trial: Trial, w: Walkers, seed: int, pc_index: int, stream=None)
     return out.value
 
 
-def timing_enable(ham: Hamiltonian, enable: bool = True) -> None:
-    check(_lib.afqmc_timing_enable(ham._h, 1 if enable else 0))
+def timing_enable(ham: Hamiltonian, classes=True) -> None:
+    """Time the kernel classes named in `classes` (True: all, False: none)."""
+    if classes is True:
+        mask = (1 << len(_abi.KERNEL_CLASSES)) - 1
+    elif classes is False or classes is None:
+        mask = 0
+    else:
+        mask = 0
+        for c in classes:
+            mask |= 1 << _abi.KERNEL_CLASSES.index(c)
+    check(_lib.afqmc_timing_enable(ham._h, mask))
 
 
 def timing_read(ham: Hamiltonian, kernel_class: str):

@@ -108,12 +108,21 @@ void jacobi_eigh(int n, std::vector<double> A, std::vector<double>& V, std::vect
 }  // namespace
 
 struct KernelTimer {
-  bool enabled = false;
+  unsigned mask = 0;  // bit c: time class c
   std::vector<hipEvent_t> pool;
   struct Pending { int cls; hipEvent_t a, b; };
   std::vector<Pending> pending;
   double total_ms[AFQMC_NUM_KERNEL_CLASSES] = {0};
   int64_t count[AFQMC_NUM_KERNEL_CLASSES] = {0};
+  // create events ahead of a timed region (none are created inside it while
+  // the pool lasts)
+  void reserve(size_t n) {
+    while (pool.size() < n) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      pool.push_back(e);
+    }
+  }
   hipEvent_t take() {
     if (pool.empty()) {
       hipEvent_t e = nullptr;
@@ -155,7 +164,7 @@ struct TimedLaunch {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   TimedLaunch(KernelTimer* t_, int cls_, hipStream_t st_) : t(t_), cls(cls_), st(st_) {
-    if (t && t->enabled) {
+    if (t && ((t->mask >> cls) & 1u)) {
       a = t->take();
       b = t->take();
       if (a && b) (void)hipEventRecord(a, st);
@@ -1362,9 +1371,10 @@ afqmc_status afqmc_propagate(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk, 
   return propagate_typed<double, double>(tr, wk, ws, b1, n_steps, dt, seed, step0, opt, emix_dev, st);
 }
 
-afqmc_status afqmc_timing_enable(afqmc_ham* hm, int enable) {
+afqmc_status afqmc_timing_enable(afqmc_ham* hm, int class_mask) {
   if (!hm) return fail(AFQMC_ERR_ARG, "NULL ham");
-  hm->timer.enabled = enable != 0;
+  hm->timer.mask = (unsigned)class_mask & ((1u << AFQMC_NUM_KERNEL_CLASSES) - 1u);
+  if (hm->timer.mask) hm->timer.reserve(4096);
   return AFQMC_OK;
 }
 
