@@ -290,6 +290,88 @@ def precision_report(args):
     print(json.dumps(out), flush=True)
 
 
+def cs_report(args):
+    """Correlated sampling (Sec. I, Sec. V) on the hydrogen-chain workload:
+    the neutral system (N_up = N_dn) and its cation (one down electron fewer)
+    propagated from their trial states with the same seed and system id, so
+    that every step draws the same fields for both, in `cs_repeats`
+    independent repeats (population control off, as in correlated sampling);
+    the cumulative average of E_cation - E_neutral over the repeats with its
+    error bar (afqmc_cs_difference), beside the same difference from
+    independent fields.  Then a long population-controlled run of the neutral
+    system whose E_mix series gets a reblocking error bar (afqmc_reblock).
+    All propagation on the GPU; the statistics on the host through the
+    C ABI."""
+    import torch
+
+    import afqmc_synth as syn
+    import paper_1804_03310_amd as afq
+
+    wl = syn.WORKLOADS[args.workload]
+    inp = syn.workload_system(wl)
+    torch.cuda.set_device(0)
+    ham = afq.Hamiltonian(inp.h, inp.L, inp.e_core)
+    nu, nd = wl.n_up, wl.n_dn
+    systems = {"neutral": afq.Trial(ham, nu, nd, inp.C_up, inp.C_dn),
+               "cation": afq.Trial(ham, nu, nd - 1, inp.C_up, inp.C_dn)}
+    W, T, R = args.cs_walkers, args.cs_steps, args.cs_repeats
+    walkers, etrial = {}, {}
+    for k, tr in systems.items():
+        walkers[k] = afq.Walkers(tr, W)
+        afq.walkers_from_trial(ham, tr, walkers[k])
+        etrial[k] = afq.local_energy(ham, tr, walkers[k])
+    emix = torch.empty(T, dtype=torch.float64, device="cuda")
+
+    def run(k, seed):
+        o = afq.Options(taylor_order=wl.taylor_order, ortho_every=wl.ortho_every, pc_every=0,
+                        e_trial=etrial[k])
+        afq.walkers_from_trial(ham, systems[k], walkers[k])
+        afq.propagate(ham, systems[k], walkers[k], T, wl.dt, seed, 0, o, emix=emix)
+        return emix.cpu().numpy().copy()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    neu = np.array([run("neutral", 1000 + r) for r in range(R)])
+    cat = np.array([run("cation", 1000 + r) for r in range(R)])
+    cat_ind = np.array([run("cation", 5000 + r) for r in range(R)])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    first = min(T // 10, 10)
+    m_cs, s_cs = afq.cs_difference(neu, cat, first)
+    m_in, s_in = afq.cs_difference(neu, cat_ind, first)
+    # long run with population control: reblocking of the E_mix series
+    L = args.cs_long_steps
+    wl_long = afq.Walkers(systems["neutral"], wl.n_walkers)
+    afq.walkers_from_trial(ham, systems["neutral"], wl_long)
+    e_long = torch.empty(L, dtype=torch.float64, device="cuda")
+    o = afq.Options(taylor_order=wl.taylor_order, ortho_every=wl.ortho_every,
+                    pc_every=wl.pc_every, e_trial=etrial["neutral"])
+    afq.propagate(ham, systems["neutral"], wl_long, L, wl.dt, 77, 0, o, emix=e_long)
+    series = e_long.cpu().numpy()[L // 5:]
+    mean, sems, plateau = afq.reblock(series)
+    out = {"metric": "correlated-sampling energy difference and reblocking error bars",
+           "unit": "Ha", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": wl.name, "neutral": [nu, nd], "cation": [nu, nd - 1],
+                      "repeats": R, "walkers": W, "steps": T, "dt": wl.dt,
+                      "averaged_from_step": first, "pc": "off (correlated sampling)",
+                      "long_run": {"walkers": wl.n_walkers, "steps": L, "pc_every": wl.pc_every,
+                                   "discarded": L // 5}},
+           "e_trial": etrial,
+           "delta_e_cs": float(m_cs[-1]), "sem_cs": float(s_cs[-1]),
+           "delta_e_independent": float(m_in[-1]), "sem_independent": float(s_in[-1]),
+           "sem_ratio_independent_over_cs": float(s_in[-1] / s_cs[-1]),
+           # correlation over the repeats of the two systems' E_mix at a few steps
+           "corr_neutral_cation": {str(t): float(np.corrcoef(neu[:, t], cat[:, t])[0, 1])
+                                   for t in sorted({0, 4, 9, 19, 49, 99, T - 1}) if t < T},
+           "corr_neutral_cation_independent": {
+               str(t): float(np.corrcoef(neu[:, t], cat_ind[:, t])[0, 1])
+               for t in sorted({0, 4, 9, 19, 49, 99, T - 1}) if t < T},
+           "walker_steps_per_s": 3 * R * W * T / elapsed,
+           "reblock": {"mean": mean, "sem_by_level": sems, "plateau": plateau,
+                       "sem": sems[plateau] if plateau >= 0 else None, "naive_sem": sems[0]}}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(wl, inp, sample_walkers, sample_steps):
     from oracle import Oracle, Options as OOptions
     try:
@@ -344,6 +426,13 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-chunk", type=int, default=10)
+    ap.add_argument("--cs", action="store_true",
+                    help="correlated-sampling energy difference (neutral vs cation sharing the "
+                         "fields) over repeats, and a reblocking analysis of a long run")
+    ap.add_argument("--cs-repeats", type=int, default=16)
+    ap.add_argument("--cs-walkers", type=int, default=256)
+    ap.add_argument("--cs-steps", type=int, default=100)
+    ap.add_argument("--cs-long-steps", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise copy of 256 MiB (reads 256 MiB, writes "
                          "256 MiB) so that HBM byte counters can be scaled")
@@ -359,6 +448,9 @@ def main():
         return
     if args.precision_report:
         precision_report(args)
+        return
+    if args.cs:
+        cs_report(args)
         return
 
     import torch

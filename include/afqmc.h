@@ -234,6 +234,30 @@ afqmc_status afqmc_timing_enable(afqmc_ham *ham, int class_mask);
 afqmc_status afqmc_timing_read(afqmc_ham *ham, int kernel_class, int64_t *launches,
                                double *total_ms);
 
+/* Statistics of energy series, on the host (host pointers, no device work,
+ * no stream).  afqmc_reblock: blocking analysis of a correlated series x[n]
+ * (finite values, n >= 2), used for the error bars of long population-
+ * controlled runs (Sec. II remark; Flyvbjerg-Petersen blocking).  Level 0 is
+ * the series, level k+1 averages neighbouring pairs of level k (an odd last
+ * value is dropped), levels continue while they hold >= 2 values, at most
+ * max_levels.  *mean = mean of the whole series; sem[k] (caller-allocated,
+ * max_levels) = sqrt(s_k^2 / n_k) with the unbiased variance s_k^2 of level
+ * k; *plateau = the first level k with sem[k+1] - sem[k] <= sem[k] /
+ * sqrt(2 (n_k - 1)), or -1.  AFQMC_ERR_NONFINITE for a non-finite value.
+ *
+ * afqmc_cs_difference: correlated sampling (Sec. I, Sec. V: two systems
+ * propagated with the same fields, i.e. the same seed and system id, in
+ * independent repeats).  a, b: [repeats][steps] energy series (NaN where a
+ * step has no measurement); per repeat the cumulative average of b - a from
+ * step `first` on over the steps where both are finite; mean[t] and sem[t]
+ * (caller-allocated [steps]) are its mean over the repeats and the standard
+ * error of that mean (NaN before the first finite step, sem NaN for one
+ * repeat). */
+afqmc_status afqmc_reblock(const double *x, int n, int max_levels, double *mean, double *sem,
+                           int *n_levels, int *plateau);
+afqmc_status afqmc_cs_difference(const double *a, const double *b, int repeats, int steps,
+                                 int first, double *mean, double *sem);
+
 void afqmc_free_hamiltonian(afqmc_ham *ham);
 void afqmc_free_trial(afqmc_trial *trial);
 

@@ -25,3 +25,4 @@ from .afqmc import (  # noqa: F401
     taylor_apply,
     modified_cholesky,
 )
+from .stats import reblock, cs_difference  # noqa: F401

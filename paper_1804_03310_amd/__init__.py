@@ -19,7 +19,7 @@ from ._abi import AfqmcError, OptionsStruct, WalkersStruct, check
 
 __all__ = ["Hamiltonian", "Trial", "Walkers", "Options", "AfqmcError", "propagate",
            "local_energy", "orthonormalize", "reconfigure", "fields", "walkers_from_trial",
-           "timing_enable", "timing_read"]
+           "timing_enable", "timing_read", "reblock", "cs_difference"]
 
 _lib = _abi.load()
 
@@ -189,6 +189,34 @@ def reconfigure(trial: Trial, w: Walkers, seed: int, pc_index: int, stream=None)
     check(_lib.afqmc_reconfigure(trial._t, ctypes.byref(w.struct), int(seed), int(pc_index),
                                  ctypes.byref(out), _stream_ptr(stream)))
     return out.value
+
+
+def reblock(x, max_levels: int = 64):
+    """Blocking analysis of a correlated energy series on the host (C ABI
+    afqmc_reblock).  Returns (mean, [standard error per level], plateau
+    level or -1)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+    sem = np.zeros(max_levels)
+    mean = ctypes.c_double()
+    nl, pl = ctypes.c_int(), ctypes.c_int()
+    check(_lib.afqmc_reblock(x.ctypes.data, x.size, max_levels, ctypes.byref(mean), sem.ctypes.data,
+                             ctypes.byref(nl), ctypes.byref(pl)))
+    return mean.value, [float(v) for v in sem[:nl.value]], pl.value
+
+
+def cs_difference(a, b, first: int = 0):
+    """Correlated-sampling difference of two [repeats][steps] energy series on
+    the host (C ABI afqmc_cs_difference).  Returns (mean[steps], sem[steps]) of
+    the cumulative average of b - a over the repeats."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64))
+    if a.shape != b.shape or a.ndim != 2:
+        raise ValueError("a and b must be [repeats][steps] of the same shape")
+    mean = np.zeros(a.shape[1])
+    sem = np.zeros(a.shape[1])
+    check(_lib.afqmc_cs_difference(a.ctypes.data, b.ctypes.data, a.shape[0], a.shape[1], int(first),
+                                   mean.ctypes.data, sem.ctypes.data))
+    return mean, sem
 
 
 def timing_enable(ham: Hamiltonian, classes=True) -> None:

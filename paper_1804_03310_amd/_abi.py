@@ -28,6 +28,7 @@ EXPORTED = ["afqmc_init_hamiltonian", "afqmc_init_trial", "afqmc_walker_workspac
             "afqmc_orthonormalize", "afqmc_reconfigure", "afqmc_fields",
             "afqmc_timing_enable", "afqmc_timing_read", "afqmc_footprint_bytes",
             "afqmc_trial_exchange_route", "afqmc_trial_set_exchange_route",
+            "afqmc_reblock", "afqmc_cs_difference",
             "afqmc_free_hamiltonian", "afqmc_free_trial", "afqmc_last_error"]
 KERNEL_CLASSES = ["exchange", "propagator_build", "taylor_b1", "overlap_theta", "mgs", "comb",
                   "other", "force_bias"]
@@ -85,6 +86,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                           ctypes.POINTER(c_size_t)]),
         "afqmc_trial_exchange_route": (c_int, [P, ctypes.POINTER(c_int)]),
         "afqmc_trial_set_exchange_route": (c_int, [P, c_int]),
+        "afqmc_reblock": (c_int, [P, c_int, c_int, P, P, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+        "afqmc_cs_difference": (c_int, [P, P, c_int, c_int, c_int, P, P]),
         "afqmc_timing_read": (c_int, [P, c_int, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(c_double)]),
         "afqmc_free_hamiltonian": (None, [P]),

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libafqmc.so")
-SOURCES = ["kernels.hip", "qroute.hip", "multidet.hip", "bf16.hip", "abi.cpp"]
+SOURCES = ["kernels.hip", "qroute.hip", "multidet.hip", "bf16.hip", "abi.cpp", "stats.cpp"]
 ARCH = os.environ.get("AFQMC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -805,6 +805,11 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
 
 }  // namespace
 
+namespace afq {
+// The thread's last-error message, for the ABI functions of other files.
+afqmc_status set_error(afqmc_status s, const char* msg) { return fail(s, msg); }
+}  // namespace afq
+
 extern "C" {
 
 const char* afqmc_last_error(void) { return g_err.c_str(); }
