@@ -2031,23 +2031,24 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
   T* TT = Bm + M * LDK;  // ping-pong term buffers, transposed [Nt][LDK] (re, im)
   auto tt = [&](int buf, int part) { return TT + (2 * buf + part) * Nt * LDK; };
   const T* Ag = A + (long)w * 2 * mm;
-  for (int e = threadIdx.x; e < M * LDK; e += blockDim.x) {
-    const int i = e / LDK, k = e % LDK;
-    const bool ok = k < M;
-    Ar[e] = ok ? Ag[(long)i * M + k] : (T)0;
-    Ai[e] = ok ? Ag[mm + (long)i * M + k] : (T)0;
-    Bm[e] = ok ? B1m[(long)i * M + k] : (T)0;
-  }
+  // rows by wavefronts, the contiguous index by lanes (no index division)
+  for (int i = wv; i < M; i += NWAVE)
+    for (int k = l; k < LDK; k += AFQ_WAVE) {
+      const bool ok = k < M;
+      Ar[i * LDK + k] = ok ? Ag[(long)i * M + k] : (T)0;
+      Ai[i * LDK + k] = ok ? Ag[mm + (long)i * M + k] : (T)0;
+      Bm[i * LDK + k] = ok ? B1m[(long)i * M + k] : (T)0;
+    }
   const long wb = (long)w * mn;
   // phi read row-major (coalesced), stored transposed; padding k >= M zero
-  for (int e = threadIdx.x; e < MP4 * Nt; e += blockDim.x) {
-    const int k = e / Nt, c = e % Nt;
-    const bool ok = k < M;
-    tt(0, 0)[c * LDK + k] = ok ? (T)phr[wb + (long)k * Nt + c] : (T)0;
-    tt(0, 1)[c * LDK + k] = ok ? (T)phi[wb + (long)k * Nt + c] : (T)0;
-    tt(1, 0)[c * LDK + k] = (T)0;
-    tt(1, 1)[c * LDK + k] = (T)0;
-  }
+  for (int k = wv; k < MP4; k += NWAVE)
+    for (int c = l; c < Nt; c += AFQ_WAVE) {
+      const bool ok = k < M;
+      tt(0, 0)[c * LDK + k] = ok ? (T)phr[wb + (long)k * Nt + c] : (T)0;
+      tt(0, 1)[c * LDK + k] = ok ? (T)phi[wb + (long)k * Nt + c] : (T)0;
+      tt(1, 0)[c * LDK + k] = (T)0;
+      tt(1, 1)[c * LDK + k] = (T)0;
+    }
   const int RT = (M + 15) / 16, CT = (Nt + 15) / 16, ntile = RT * CT;
   double sr[MT][4], si[MT][4];
 #pragma unroll
