@@ -415,14 +415,22 @@ template hipError_t abuild<double, double>(hipStream_t, int, int, int, int, cons
 // with theta_J in the epilogue, per lane in FP64, and the 16 column lanes
 // are summed once at the end in a fixed order.
 // ---------------------------------------------------------------------------
+// One group of 16 walkers per wavefront and all four column tiles in one
+// pass; for FP32 the epilogue's theta_J values are requested before the
+// tile's MFMAs, so that their latency hides behind them.
+template <typename T> struct QFGeom {
+  static constexpr int GW = 1, NJ = 4;
+  static constexpr bool PREF = sizeof(T) == 4;
+};
+
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_qform(int W, int Ktot, int Kp0, int Kp1, int nchunk,
-                                                  int nseg,
-                                               const int4* __restrict__ segs,
+                                               int nseg, const int4* __restrict__ segs,
                                                const T* __restrict__ tsr, const T* __restrict__ tsi,
                                                const T* __restrict__ Q0, const T* __restrict__ Q1,
                                                double* __restrict__ part) {
-  constexpr int GW = QGeom<T>::GW, NJ = QGeom<T>::NJ;
+  constexpr int GW = QFGeom<T>::GW, NJ = QFGeom<T>::NJ;
+  constexpr bool PREF = QFGeom<T>::PREF;
   typedef typename V4<T>::type t4;
   typedef Mfma<T> MM;
   __shared__ __attribute__((aligned(32))) T lds[2][QT * QLD];
@@ -456,6 +464,19 @@ __global__ __launch_bounds__(256, 2) void k_qform(int W, int Ktot, int Kp0, int 
     const bool more = J + 1 < seg.w;
     if (more) tile_fetch<T>(Q, Kp, I0, (long)(J + 1) * QT, pre);
     const double f = J == seg.y ? 1.0 : 2.0;
+    t4 xpr[GW][4], xpi[GW][4];  // theta_J of the lane's rows (PREF)
+    if (PREF) {
+#pragma unroll
+      for (int g = 0; g < GW; ++g)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int w = wb + 16 * g + MM::row(q, v);
+          const long o = (long)w * Ktot + soff + (long)J * QT + 4 * li;
+          const t4 z = {0, 0, 0, 0};
+          xpr[g][v] = w < W ? *(const t4*)(tsr + o) : z;
+          xpi[g][v] = w < W ? *(const t4*)(tsi + o) : z;
+        }
+    }
 #pragma unroll
     for (int jb0 = 0; jb0 < 4; jb0 += NJ) {
       typename MM::acc_t zr[GW][NJ], zi[GW][NJ];
@@ -474,7 +495,8 @@ __global__ __launch_bounds__(256, 2) void k_qform(int W, int Ktot, int Kp0, int 
           double a = 0.0, b = 0.0;
 #pragma unroll
           for (int jj = 0; jj < NJ; ++jj) {
-            const double xr = (double)tsr[o + jj], xi = (double)tsi[o + jj];
+            const double xr = PREF ? (double)xpr[g][v][jb0 + jj] : (double)tsr[o + jj];
+            const double xi = PREF ? (double)xpi[g][v][jb0 + jj] : (double)tsi[o + jj];
             const double yr = (double)zr[g][jj][v], yi = (double)zi[g][jj][v];
             a += xr * yr - xi * yi;
             b += xr * yi + xi * yr;
@@ -506,7 +528,7 @@ __global__ __launch_bounds__(256, 2) void k_qform(int W, int Ktot, int Kp0, int 
 template <typename T>
 hipError_t qform(hipStream_t st, int W, int Kp0, int Kp1, int nseg, const int4* segs, const T* tsr,
                  const T* tsi, const T* Q0, const T* Q1, double* part) {
-  constexpr int GW = QGeom<T>::GW;
+  constexpr int GW = QFGeom<T>::GW;
   if (nseg == 0) return hipSuccess;
   if (W <= 0 || Kp0 % QT || Kp1 % QT) return hipErrorInvalidValue;
   const int nchunk = (W + 64 * GW - 1) / (64 * GW);
