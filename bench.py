@@ -412,8 +412,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=80)
-    ap.add_argument("--tte-repeats", type=int, default=5)
-    ap.add_argument("--tte-steps", type=int, default=50)
+    ap.add_argument("--tte-repeats", type=int, default=20,
+                    help="time-to-energy repeats (field seeds 0 .. repeats - 1)")
+    ap.add_argument("--tte-steps", type=int, default=0,
+                    help="steps of each time-to-energy run (0: the workload's full run)")
     ap.add_argument("--precision-report", action="store_true",
                     help="E_L error and E_mix drift of the contraction precisions vs FP64")
     ap.add_argument("--sweep-precs", default="fp32,bf16,fp64,fp32+q")
@@ -481,6 +483,8 @@ def main():
                   chol_prec=chol_prec, taylor_prec=taylor_prec, weight_mode=args.weight_mode,
                   meas_every=args.meas_every)
     opt = afq.Options(pc_every=wl.pc_every, e_trial=et, **opt_kw)
+    if args.tte_steps <= 0:
+        args.tte_steps = wl.n_steps
     if args.weight_mode == "hybrid":  # the time-to-energy runs end on a measured step
         args.tte_steps = -(-args.tte_steps // args.meas_every) * args.meas_every
     emix = torch.empty(max(args.steps, args.warmup, args.tte_steps, 1), dtype=torch.float64,
@@ -522,7 +526,7 @@ def main():
         afq.walkers_from_trial(ham, trial, w)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        e = afq.propagate(ham, trial, w, args.tte_steps, wl.dt, 100 + r, 0, opt, emix=emix)
+        e = afq.propagate(ham, trial, w, args.tte_steps, wl.dt, r, 0, opt, emix=emix)
         _ = float(e[args.tte_steps - 1].item())
         tte.append(time.perf_counter() - t1)
 
