@@ -518,7 +518,7 @@ template <int NT>
 struct OvlWave {
   static constexpr int NP = 16 * NT;
   static constexpr int LD = NP + 2;                          // even: 16-byte aligned rows
-  // S re/im, two pivot-row buffers of NP (re, im) pairs, pi
+  // S re/im, two pivot-row buffers (NP re, then NP im), pi
   static constexpr int DOUBLES = 2 * NP * LD + 4 * NP + NP;
 };
 
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
   }
   double* Sr = olds + wv * L::DOUBLES;
   double* Si = Sr + NP * LD;
-  double2* prow = (double2*)(Si + NP * LD);  // [2][NP] pivot-row buffers
+  double* prow = Si + NP * LD;  // [2][re, im][NP] pivot-row buffers
   int* piarr = (int*)(Si + NP * LD + 4 * NP);
   const int li = l & 15, lk = l >> 4;
   // ---- S = D_0^T phi (zero padded to NP x NP) ----
@@ -696,10 +696,14 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
       const unsigned long long k0 = readlane_u64(key, 0), k1 = readlane_u64(key, 16);
       const int p = 31 - (int)((k0 > k1 ? k0 : k1) & 31ull);
       used |= 1u << p;
-      double2* rb = prow + (k & 1) * NP;
+      double* rbr = prow + (k & 1) * 2 * NP;  // re of the row, then im
+      double* rbi = rbr + NP;
       if (owner && i == p) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) rb[16 * h + c] = make_double2(xr[c], xi[c]);
+        for (int c = 0; c < 16; c += 2) {
+          *(double2*)(rbr + 16 * h + c) = make_double2(xr[c], xr[c + 1]);
+          *(double2*)(rbi + 16 * h + c) = make_double2(xi[c], xi[c + 1]);
+        }
       }
       const double pvr = readlane_d(fr, p), pvi = readlane_d(fi, p);
       const double rden = 1.0 / (pvr * pvr + pvi * pvi);
@@ -716,16 +720,22 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
       }
       wave_lds_sync();
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const double2 r = rb[16 * h + c];
-        double nr = xr[c] - (gr * r.x - gi * r.y);
-        double ni = xi[c] - (gr * r.y + gi * r.x);
-        if (c == ck && (NT == 1 || h == hk)) {
-          nr = (i == p) ? pir : -gr;
-          ni = (i == p) ? pii : -gi;
+      for (int c = 0; c < 16; c += 2) {
+        const double2 r2 = *(const double2*)(rbr + 16 * h + c);
+        const double2 i2 = *(const double2*)(rbi + 16 * h + c);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const double rr = u ? r2.y : r2.x, ri = u ? i2.y : i2.x;
+          // x - g r as two fused multiply-adds per part
+          double nr = fma(gi, ri, fma(-gr, rr, xr[c + u]));
+          double ni = fma(-gi, rr, fma(-gr, ri, xi[c + u]));
+          if (c + u == ck && (NT == 1 || h == hk)) {
+            nr = (i == p) ? pir : -gr;
+            ni = (i == p) ? pii : -gi;
+          }
+          xr[c + u] = nr;
+          xi[c + u] = ni;
         }
-        xr[c] = nr;
-        xi[c] = ni;
       }
     }
   }
