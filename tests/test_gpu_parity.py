@@ -85,7 +85,8 @@ def test_local_energy_at_trial_equals_oracle(afq):
 @pytest.mark.parametrize("M,n_up,n_dn,G,W", [(10, 5, 5, 40, 16), (23, 7, 4, 37, 9),
                                                (50, 25, 25, 250, 6), (40, 17, 0, 30, 5),
                                                (29, 20, 9, 33, 7), (70, 31, 32, 41, 3),
-                                               (70, 40, 33, 23, 3)])
+                                               (70, 40, 33, 23, 3), (12, 5, 0, 30, 130),
+                                               (16, 7, 6, 40, 65)])
 def test_local_energy_random_walkers_fp64(afq, M, n_up, n_dn, G, W):
     _say(f"local energy random walkers M={M} N={n_up}/{n_dn} G={G} W={W}")
     inp = syn.make_system(M, n_up, n_dn, G, 8.0, seed=M + G, e_core=0.75)
@@ -109,7 +110,8 @@ def test_local_energy_random_walkers_fp64(afq, M, n_up, n_dn, G, W):
 @pytest.mark.parametrize("M,n_up,n_dn,G,W", [(23, 7, 4, 37, 9), (29, 20, 9, 33, 7),
                                                (50, 25, 25, 250, 6), (40, 17, 0, 30, 5),
                                                (70, 40, 33, 23, 3), (90, 50, 64, 19, 2),
-                                               (80, 40, 20, 21, 3), (75, 49, 0, 17, 2)])
+                                               (80, 40, 20, 21, 3), (75, 49, 0, 17, 2),
+                                               (12, 5, 0, 30, 130), (16, 7, 6, 40, 65)])
 def test_local_energy_random_walkers_fp32(afq, M, n_up, n_dn, G, W):
     """FP32 contractions (reached through a zero-step propagate, which
     refreshes E_L with the step's precision): relative 1e-5.  The walkers
@@ -195,18 +197,21 @@ def test_split_calls_equal_one_call(afq):
     assert np.allclose(np.concatenate([e1, e2]), e_all, rtol=0, atol=1e-11)
 
 
-def test_orthonormalize_parity(afq):
-    _say("orthonormalize")
-    inp = syn.make_system(30, 9, 6, 20, 8.0, seed=4)
-    ham, trial, w = _make(afq, inp, 7)
-    re, im = syn.random_walkers(30, 9, 6, 7, seed=5, scale=0.4)
-    phi = np.concatenate([inp.C_up[:, :9], inp.C_dn[:, :6]], axis=1)[None] + re + 1j * im
+@pytest.mark.parametrize("M,nu,nd,W", [(30, 9, 6, 7), (64, 20, 0, 5), (80, 12, 11, 3)])
+def test_orthonormalize_parity(afq, M, nu, nd, W):
+    """MGS per walker and spin: one wavefront per matrix up to M = 64 (M = 64
+    fills every lane), the block form above."""
+    _say(f"orthonormalize M={M} N={nu}/{nd} W={W}")
+    inp = syn.make_system(M, nu, nd, 20, 8.0, seed=4)
+    ham, trial, w = _make(afq, inp, W)
+    re, im = syn.random_walkers(M, nu, nd, W, seed=5, scale=0.4)
+    phi = np.concatenate([inp.C_up[:, :nu], inp.C_dn[:, :nd]], axis=1)[None] + re + 1j * im
     _set_phi(w, phi)
     afq.local_energy(ham, trial, w)
     e0 = _np(w.eloc[0]).copy()
     afq.orthonormalize(ham, trial, w)
     o = Oracle.from_inputs(inp)
-    st = o.init_walkers(7, phi=phi)
+    st = o.init_walkers(W, phi=phi)
     o.orthonormalize(st)
     got = _np(w.phi_re) + 1j * _np(w.phi_im)
     assert np.allclose(got, st.phi, atol=1e-12)
