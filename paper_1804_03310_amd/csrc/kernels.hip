@@ -8,8 +8,9 @@ namespace afq {
 
 // ===========================================================================
 // Real GEMM, 64x64 block tile, 4 waves of 32x32, K staged through LDS in
-// chunks of 16.  Used for the propagator build sum_g c_{w,g} L_g (Eq. 2-3:
-// one GEMM over all walkers, [2W x G] x [G x M^2]) and for set-up products.
+// chunks of 16.  Used for set-up products (the half rotation, the Q tensor's
+// P = R^T R, the multi-determinant operands); the per-step propagator build
+// and force bias have their own kernels (qroute.hip).
 // ===========================================================================
 template <typename TIn, typename TOut, bool A_KMAJ>
 __global__ __launch_bounds__(256) void k_gemm_real(int Mr, int Nc, int K, const TIn* __restrict__ A,
@@ -87,19 +88,6 @@ template hipError_t gemm_real<double, double, true>(hipStream_t, int, int, int, 
 template hipError_t gemm_real<double, double, false>(hipStream_t, int, int, int, const double*, int,
                                                      long, const double*, int, long, double*, int,
                                                      long, int, double);
-template hipError_t gemm_real<float, float, true>(hipStream_t, int, int, int, const float*, int,
-                                                  long, const float*, int, long, float*, int, long,
-                                                  int, double);
-template hipError_t gemm_real<double, float, true>(hipStream_t, int, int, int, const double*, int,
-                                                   long, const double*, int, long, float*, int,
-                                                   long, int, double);
-template hipError_t gemm_real<float, double, true>(hipStream_t, int, int, int, const float*, int,
-                                                   long, const float*, int, long, double*, int,
-                                                   long, int, double);
-template hipError_t gemm_real<float, double, false>(hipStream_t, int, int, int, const float*, int,
-                                                    long, const float*, int, long, double*, int,
-                                                    long, int, double);
-
 // ===========================================================================
 // Walker-batched complex GEMM for the one-body factors B1 and the Taylor
 // terms of exp(A) (Thouless: the propagator acts on a determinant by a

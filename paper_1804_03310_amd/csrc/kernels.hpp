@@ -170,7 +170,7 @@ hipError_t transpose_f64_bf16(hipStream_t st, int rows, int cols, int ld_dst, lo
 template <typename TOut>
 hipError_t gemm_bf16(hipStream_t st, int Mr, int Nc, int K, const void* A, int lda, const void* B,
                      int ldb, TOut* C, int ldc, double alpha);
-// Hybrid weights: v = Theta_flat Lcat by split-K GEMM partials summed here;
+// Hybrid weights: v from the force-bias GEMM's split-K partials summed here;
 // lsn = ld_up + ld_dn and vfin = all v finite per walker.
 hipError_t hybrid_force_bias_finish(hipStream_t st, int W, int G, int nz, const double* part_re,
                                     const double* part_im, double* v_re, double* v_im,
