@@ -626,7 +626,9 @@ struct Bf16Tag {};
 
 // Force bias v_g = sum_k ts[k] Lq[k][g] for all walkers (single determinant)
 // from the split Theta rows in ws.P_* (contraction type), as a GEMM split over
-// k into nz partials in ws.ACC_* (free outside the propagation); returns nz.
+// k into nz partials in ws.ACC_* (free outside the propagation; float
+// partials when the contraction is FP32, as the MFMA accumulated them);
+// returns nz.
 int force_bias_partials(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bool fp32,
                         hipStream_t st, hipError_t* err) {
   afqmc_ham* hm = tr->ham;
@@ -635,7 +637,8 @@ int force_bias_partials(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bool f
   const int nz = afq::fbias_nz(W, Ktot, G, fp32 ? 4 : 8, acc_cap(M, G, Nt));
   if (fp32)
     *err = afq::fbias_mm<float>(st, W, Ktot, G, tr->Gp, nz, (const float*)ws.P_re,
-                                (const float*)ws.P_im, tr->Lq32, ws.ACC_re, ws.ACC_im);
+                                (const float*)ws.P_im, tr->Lq32, (float*)ws.ACC_re,
+                                (float*)ws.ACC_im);
   else
     *err = afq::fbias_mm<double>(st, W, Ktot, G, tr->Gp, nz, ws.P_re, ws.P_im, tr->Lq64, ws.ACC_re,
                                  ws.ACC_im);
@@ -669,10 +672,17 @@ afqmc_status measure_qroute(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bo
     }
   }
   TimedLaunch tl(&hm->timer, KC_OTHER, st);
-  AFQ_CK(afq::combine_qroute(st, W, G, nz, tr->nseg[0], tr->nseg[1], hm->e_core, ws.ACC_re,
-                             ws.ACC_im, qpart, ws.e1_re, ws.e1_im, ws.ld_re, ws.ld_im, ws.v_re,
-                             ws.v_im, ws.exx_re, ws.exx_im, ws.lsn_re, ws.lsn_im, ws.eln_re,
-                             ws.eln_im, ws.vfin));
+  if (fp32)
+    AFQ_CK(afq::combine_qroute<float>(st, W, G, nz, tr->nseg[0], tr->nseg[1], hm->e_core,
+                                      (const float*)ws.ACC_re, (const float*)ws.ACC_im, qpart,
+                                      ws.e1_re, ws.e1_im, ws.ld_re, ws.ld_im, ws.v_re, ws.v_im,
+                                      ws.exx_re, ws.exx_im, ws.lsn_re, ws.lsn_im, ws.eln_re,
+                                      ws.eln_im, ws.vfin));
+  else
+    AFQ_CK(afq::combine_qroute<double>(st, W, G, nz, tr->nseg[0], tr->nseg[1], hm->e_core,
+                                       ws.ACC_re, ws.ACC_im, qpart, ws.e1_re, ws.e1_im, ws.ld_re,
+                                       ws.ld_im, ws.v_re, ws.v_im, ws.exx_re, ws.exx_im,
+                                       ws.lsn_re, ws.lsn_im, ws.eln_re, ws.eln_im, ws.vfin));
   return AFQMC_OK;
 }
 
@@ -694,8 +704,15 @@ afqmc_status hybrid_force_bias(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws,
     nz = force_bias_partials(tr, wk, ws, fp32, st, &e);
     AFQ_CK(e);
   }
-  AFQ_CK(afq::hybrid_force_bias_finish(st, W, G, nz, ws.ACC_re, ws.ACC_im, ws.v_re, ws.v_im, ws.ld_re,
-                                       ws.ld_im, ws.lsn_re, ws.lsn_im, ws.vfin));
+  if (fp32)
+    AFQ_CK(afq::hybrid_force_bias_finish<float>(st, W, G, nz, (const float*)ws.ACC_re,
+                                                (const float*)ws.ACC_im, ws.v_re, ws.v_im,
+                                                ws.ld_re, ws.ld_im, ws.lsn_re, ws.lsn_im,
+                                                ws.vfin));
+  else
+    AFQ_CK(afq::hybrid_force_bias_finish<double>(st, W, G, nz, ws.ACC_re, ws.ACC_im, ws.v_re,
+                                                 ws.v_im, ws.ld_re, ws.ld_im, ws.lsn_re,
+                                                 ws.lsn_im, ws.vfin));
   return AFQMC_OK;
 }
 

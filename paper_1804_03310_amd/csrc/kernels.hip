@@ -1586,8 +1586,9 @@ hipError_t weight_update(hipStream_t st, int W, int mode, double dt, double e_tr
   return hipGetLastError();
 }
 
-__global__ void k_hybrid_finish(int W, int G, int nz, const double* __restrict__ part_re,
-                                const double* __restrict__ part_im, double* v_re, double* v_im,
+template <typename TP>
+__global__ void k_hybrid_finish(int W, int G, int nz, const TP* __restrict__ part_re,
+                                const TP* __restrict__ part_im, double* v_re, double* v_im,
                                 const double* __restrict__ ld_re, const double* __restrict__ ld_im,
                                 double* lsn_re, double* lsn_im, int* vfin) {
   // one block per walker: v_g = sum_z part[z][w][g] (fixed order), flags
@@ -1599,8 +1600,8 @@ __global__ void k_hybrid_finish(int W, int G, int nz, const double* __restrict__
   for (int g = threadIdx.x; g < G; g += blockDim.x) {
     double sr = 0.0, si = 0.0;
     for (int z = 0; z < nz; ++z) {
-      sr += part_re[((long)z * W + w) * G + g];
-      si += part_im[((long)z * W + w) * G + g];
+      sr += (double)part_re[((long)z * W + w) * G + g];
+      si += (double)part_im[((long)z * W + w) * G + g];
     }
     v_re[(long)w * G + g] = sr;
     v_im[(long)w * G + g] = si;
@@ -1615,14 +1616,22 @@ __global__ void k_hybrid_finish(int W, int G, int nz, const double* __restrict__
   }
 }
 
-hipError_t hybrid_force_bias_finish(hipStream_t st, int W, int G, int nz, const double* part_re,
-                                    const double* part_im, double* v_re, double* v_im,
+template <typename TP>
+hipError_t hybrid_force_bias_finish(hipStream_t st, int W, int G, int nz, const TP* part_re,
+                                    const TP* part_im, double* v_re, double* v_im,
                                     const double* ld_re, const double* ld_im, double* lsn_re,
                                     double* lsn_im, int* vfin) {
-  hipLaunchKernelGGL(k_hybrid_finish, dim3(W), dim3(256), 0, st, W, G, nz, part_re, part_im, v_re,
-                     v_im, ld_re, ld_im, lsn_re, lsn_im, vfin);
+  hipLaunchKernelGGL((k_hybrid_finish<TP>), dim3(W), dim3(256), 0, st, W, G, nz, part_re, part_im,
+                     v_re, v_im, ld_re, ld_im, lsn_re, lsn_im, vfin);
   return hipGetLastError();
 }
+template hipError_t hybrid_force_bias_finish<float>(hipStream_t, int, int, int, const float*,
+                                                    const float*, double*, double*, const double*,
+                                                    const double*, double*, double*, int*);
+template hipError_t hybrid_force_bias_finish<double>(hipStream_t, int, int, int, const double*,
+                                                     const double*, double*, double*,
+                                                     const double*, const double*, double*,
+                                                     double*, int*);
 
 __global__ __launch_bounds__(256) void k_reset_dead(int M, int Nt, int G, const int* dead,
                                                     const double* D0, double ref_ls_re,

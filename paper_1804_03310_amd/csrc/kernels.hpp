@@ -172,8 +172,9 @@ hipError_t gemm_bf16(hipStream_t st, int Mr, int Nc, int K, const void* A, int l
                      int ldb, TOut* C, int ldc, double alpha);
 // Hybrid weights: v from the force-bias GEMM's split-K partials summed here;
 // lsn = ld_up + ld_dn and vfin = all v finite per walker.
-hipError_t hybrid_force_bias_finish(hipStream_t st, int W, int G, int nz, const double* part_re,
-                                    const double* part_im, double* v_re, double* v_im,
+template <typename TP>
+hipError_t hybrid_force_bias_finish(hipStream_t st, int W, int G, int nz, const TP* part_re,
+                                    const TP* part_im, double* v_re, double* v_im,
                                     const double* ld_re, const double* ld_im, double* lsn_re,
                                     double* lsn_im, int* vfin);
 // Q route (qroute.hip), over the split Theta rows ts[w][Ktot] that the
@@ -188,10 +189,11 @@ hipError_t perm_qpad(hipStream_t st, int M, int N, int NP, int MP4, int Kp, cons
 // Number of k ranges of the force-bias GEMM (partials of nz W G doubles must
 // fit cap_per_walker W doubles).
 int fbias_nz(int W, int Ktot, int G, int elem_size, long cap_per_walker);
-// part[z][w][g] = sum over range z of ts[w][k] Lq[k][g], re and im.
+// part[z][w][g] = sum over range z of ts[w][k] Lq[k][g], re and im (in T: the
+// partial sums as the MFMA accumulated them).
 template <typename T>
 hipError_t fbias_mm(hipStream_t st, int W, int Ktot, int G, int Gp, int nz, const T* tsr,
-                    const T* tsi, const T* Lq, double* part_re, double* part_im);
+                    const T* tsi, const T* Lq, T* part_re, T* part_im);
 // part[w][seg] (re, im) of theta^T Q theta over the segment's tile pairs.
 template <typename T>
 hipError_t qform(hipStream_t st, int W, int Kp0, int Kp1, int nseg, const int4* segs, const T* tsr,
@@ -203,8 +205,9 @@ hipError_t abuild(hipStream_t st, int R, int Ncol, int G, int Gp, const TC* coef
                   TO* out);
 // Q-route E_L: force bias from nz partials, exchange from the segment partials,
 // combined with E1 and log det (one wave per walker).
+template <typename TP>
 hipError_t combine_qroute(hipStream_t st, int W, int G, int nz, int nseg0, int nseg1, double e_core,
-                          const double* fp_re, const double* fp_im, const double* qpart,
+                          const TP* fp_re, const TP* fp_im, const double* qpart,
                           const double* e1_re, const double* e1_im, const double* ld_re,
                           const double* ld_im, double* v_re, double* v_im, double* exx_re,
                           double* exx_im, double* lsn_re, double* lsn_im, double* eln_re,

@@ -228,8 +228,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_fbias_mm(int W, int Ktot, int G, int Gp, int nchunk,
                                                   int tiles_per_z, const T* __restrict__ tsr,
                                                   const T* __restrict__ tsi, const T* __restrict__ Lq,
-                                                  double* __restrict__ part_re,
-                                                  double* __restrict__ part_im) {
+                                                  T* __restrict__ part_re,
+                                                  T* __restrict__ part_im) {
   constexpr int GW = QGeom<T>::GW;
   typedef typename V4<T>::type t4;
   typedef Mfma<T> MM;
@@ -284,8 +284,8 @@ __global__ __launch_bounds__(256) void k_fbias_mm(int W, int Ktot, int G, int Gp
       for (int jb = 0; jb < 4; ++jb) {
         const int c = gt * QT + 4 * li + jb;
         if (c < G) {
-          part_re[zo + (long)w * G + c] = (double)zr[g][jb][v];
-          part_im[zo + (long)w * G + c] = (double)zi[g][jb][v];
+          part_re[zo + (long)w * G + c] = (T)zr[g][jb][v];
+          part_im[zo + (long)w * G + c] = (T)zi[g][jb][v];
         }
       }
     }
@@ -303,7 +303,7 @@ int fbias_nz(int W, int Ktot, int G, int elem_size, long cap_per_walker) {
 
 template <typename T>
 hipError_t fbias_mm(hipStream_t st, int W, int Ktot, int G, int Gp, int nz, const T* tsr,
-                    const T* tsi, const T* Lq, double* part_re, double* part_im) {
+                    const T* tsi, const T* Lq, T* part_re, T* part_im) {
   constexpr int GW = QGeom<T>::GW;
   const int nkt = Ktot / QT;
   if (W <= 0 || G <= 0 || nkt == 0 || nz < 1 || Gp % QT || Ktot % QT) return hipErrorInvalidValue;
@@ -315,7 +315,7 @@ hipError_t fbias_mm(hipStream_t st, int W, int Ktot, int G, int Gp, int nz, cons
   return hipGetLastError();
 }
 template hipError_t fbias_mm<float>(hipStream_t, int, int, int, int, int, const float*,
-                                    const float*, const float*, double*, double*);
+                                    const float*, const float*, float*, float*);
 template hipError_t fbias_mm<double>(hipStream_t, int, int, int, int, int, const double*,
                                      const double*, const double*, double*, double*);
 
@@ -547,9 +547,10 @@ template hipError_t qform<double>(hipStream_t, int, int, int, int, const int4*, 
 // s's segments of qpart[w][seg], then E_L = e_core + E1 + 1/2 sum_g v_g^2 -
 // 1/2 (exx_0 + exx_1) and log S = log det_0 + log det_1 (Sec. II local
 // energy); vfin = 0 when a force-bias entry is not finite.
+template <typename TP>
 __global__ __launch_bounds__(256) void k_combine_qroute(
-    int W, int G, int nz, int nseg0, int nseg1, double e_core, const double* __restrict__ fp_re,
-    const double* __restrict__ fp_im, const double* __restrict__ qpart,
+    int W, int G, int nz, int nseg0, int nseg1, double e_core, const TP* __restrict__ fp_re,
+    const TP* __restrict__ fp_im, const double* __restrict__ qpart,
     const double* __restrict__ e1_re, const double* __restrict__ e1_im,
     const double* __restrict__ ld_re, const double* __restrict__ ld_im, double* __restrict__ v_re,
     double* __restrict__ v_im, double* exx_re, double* exx_im, double* lsn_re, double* lsn_im,
@@ -562,8 +563,8 @@ __global__ __launch_bounds__(256) void k_combine_qroute(
   for (int g = l; g < G; g += AFQ_WAVE) {
     double a = 0.0, b = 0.0;
     for (int z = 0; z < nz; ++z) {
-      a += fp_re[z * n + (long)w * G + g];
-      b += fp_im[z * n + (long)w * G + g];
+      a += (double)fp_re[z * n + (long)w * G + g];
+      b += (double)fp_im[z * n + (long)w * G + g];
     }
     v_re[(long)w * G + g] = a;
     v_im[(long)w * G + g] = b;
@@ -601,16 +602,27 @@ __global__ __launch_bounds__(256) void k_combine_qroute(
   }
 }
 
+template <typename TP>
 hipError_t combine_qroute(hipStream_t st, int W, int G, int nz, int nseg0, int nseg1, double e_core,
-                          const double* fp_re, const double* fp_im, const double* qpart,
+                          const TP* fp_re, const TP* fp_im, const double* qpart,
                           const double* e1_re, const double* e1_im, const double* ld_re,
                           const double* ld_im, double* v_re, double* v_im, double* exx_re,
                           double* exx_im, double* lsn_re, double* lsn_im, double* eln_re,
                           double* eln_im, int* vfin) {
-  hipLaunchKernelGGL(k_combine_qroute, dim3((W + 3) / 4), dim3(256), 0, st, W, G, nz, nseg0, nseg1,
+  hipLaunchKernelGGL((k_combine_qroute<TP>), dim3((W + 3) / 4), dim3(256), 0, st, W, G, nz, nseg0, nseg1,
                      e_core, fp_re, fp_im, qpart, e1_re, e1_im, ld_re, ld_im, v_re, v_im, exx_re,
                      exx_im, lsn_re, lsn_im, eln_re, eln_im, vfin);
   return hipGetLastError();
 }
+template hipError_t combine_qroute<float>(hipStream_t, int, int, int, int, int, double,
+                                          const float*, const float*, const double*, const double*,
+                                          const double*, const double*, const double*, double*,
+                                          double*, double*, double*, double*, double*, double*,
+                                          double*, int*);
+template hipError_t combine_qroute<double>(hipStream_t, int, int, int, int, int, double,
+                                           const double*, const double*, const double*,
+                                           const double*, const double*, const double*,
+                                           const double*, double*, double*, double*, double*,
+                                           double*, double*, double*, double*, int*);
 
 }  // namespace afq
