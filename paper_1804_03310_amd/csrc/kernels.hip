@@ -2072,7 +2072,19 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
   }
   __syncthreads();
   int cur = 0;
-  const t4 z4 = {0, 0, 0, 0};
+  // LDS offsets of the lane's A row and term column per tile, clamped to the
+  // last row / column: the clamped lanes read real (finite) entries, so the
+  // reads need no mask, and what they give lands only in output rows >= M or
+  // columns >= Nt, which are never stored (store_term writes zero rows
+  // there).  A wave's tiles beyond the last (tile >= ntile) are computed the
+  // same way and never stored, so the products have no branches.
+  int arow[MT], bcol[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const int tile = wv + NWAVE * t;
+    arow[t] = min(16 * (tile / CT) + li, M - 1) * LDK;
+    bcol[t] = min(16 * (tile % CT) + li, Nt - 1) * LDK;
+  }
   // one product of an M x M operator with the current term: real (B1 - I) or
   // complex A, both from LDS
   auto product = [&](bool cplx, acc_t (&cr)[MT], acc_t (&ci)[MT]) {
@@ -2086,22 +2098,15 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
       t4 b_r[MT], b_i[MT];
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
-        const int tile = wv + NWAVE * t;
-        const int c = 16 * (tile % CT) + li;
         if (SB && t > 0) { b_r[t] = b_r[0]; b_i[t] = b_i[0]; continue; }
-        const bool ok = tile < ntile && c < Nt;
-        b_r[t] = ok ? *(const t4*)(br_ + c * LDK + kk) : z4;
-        b_i[t] = ok ? *(const t4*)(bi_ + c * LDK + kk) : z4;
+        b_r[t] = *(const t4*)(br_ + bcol[t] + kk);
+        b_i[t] = *(const t4*)(bi_ + bcol[t] + kk);
       }
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
-        const int tile = wv + NWAVE * t;
-        if (tile >= ntile) continue;
-        const int i = 16 * (tile / CT) + li;
-        const bool ok = i < M;
         if (cplx) {
-          const t4 a_r = ok ? *(const t4*)(Ar + i * LDK + kk) : z4;
-          const t4 a_i = ok ? *(const t4*)(Ai + i * LDK + kk) : z4;
+          const t4 a_r = *(const t4*)(Ar + arow[t] + kk);
+          const t4 a_i = *(const t4*)(Ai + arow[t] + kk);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             cr[t] = MM::mma(a_r[j], b_r[t][j], cr[t]);
@@ -2110,7 +2115,7 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
             ci[t] = MM::mma(a_i[j], b_r[t][j], ci[t]);
           }
         } else {
-          const t4 a = ok ? *(const t4*)(Bm + i * LDK + kk) : z4;
+          const t4 a = *(const t4*)(Bm + arow[t] + kk);
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             cr[t] = MM::mma(a[j], b_r[t][j], cr[t]);
@@ -2123,28 +2128,25 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
       const int k = k0 + lk;
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
-        const int tile = wv + NWAVE * t;
-        if (tile >= ntile) continue;
-        const int i = 16 * (tile / CT) + li, c = 16 * (tile % CT) + li;
-        const T b_r = c < Nt ? br_[c * LDK + k] : (T)0;
-        const T b_i = c < Nt ? bi_[c * LDK + k] : (T)0;
+        const T b_r = br_[bcol[t] + k];
+        const T b_i = bi_[bcol[t] + k];
         if (cplx) {
-          const T a_r = i < M ? Ar[i * LDK + k] : (T)0;
-          const T a_i = i < M ? Ai[i * LDK + k] : (T)0;
+          const T a_r = Ar[arow[t] + k];
+          const T a_i = Ai[arow[t] + k];
           cr[t] = MM::mma(a_r, b_r, cr[t]);
           cr[t] = MM::mma(-a_i, b_i, cr[t]);
           ci[t] = MM::mma(a_r, b_i, ci[t]);
           ci[t] = MM::mma(a_i, b_r, ci[t]);
         } else {
-          const T a = i < M ? Bm[i * LDK + k] : (T)0;
+          const T a = Bm[arow[t] + k];
           cr[t] = MM::mma(a, b_r, cr[t]);
           ci[t] = MM::mma(a, b_i, ci[t]);
         }
       }
     }
   };
-  // term^T[c][r] for the lane's rows; rows M .. MP4 - 1 receive the zeros
-  // the products give there, rows from MP4 on are not stored
+  // term^T[c][r] for the lane's rows; rows M .. MP4 - 1 receive zeros (the k
+  // padding of the next product), rows from MP4 on are not stored
   auto store_term = [&](int buf, const double (&xr)[MT][4], const double (&xi)[MT][4]) {
     T* outr = tt(buf, 0);
     T* outi = tt(buf, 1);
@@ -2156,8 +2158,12 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
       if (sizeof(T) == 4) {
         const int r0 = 16 * rt + 4 * lk;  // rows r0 .. r0 + 3 (MP4 is a multiple of 4)
         if (r0 < MP4) {
-          const t4 vr = {(T)xr[t][0], (T)xr[t][1], (T)xr[t][2], (T)xr[t][3]};
-          const t4 vi = {(T)xi[t][0], (T)xi[t][1], (T)xi[t][2], (T)xi[t][3]};
+          t4 vr, vi;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            vr[v] = r0 + v < M ? (T)xr[t][v] : (T)0;
+            vi[v] = r0 + v < M ? (T)xi[t][v] : (T)0;
+          }
           *(t4*)(outr + c * LDK + r0) = vr;
           *(t4*)(outi + c * LDK + r0) = vi;
         }
@@ -2166,8 +2172,8 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
         for (int v = 0; v < 4; ++v) {
           const int r = 16 * rt + MM::row(lk, v);
           if (r < MP4) {
-            outr[c * LDK + r] = (T)xr[t][v];
-            outi[c * LDK + r] = (T)xi[t][v];
+            outr[c * LDK + r] = r < M ? (T)xr[t][v] : (T)0;
+            outi[c * LDK + r] = r < M ? (T)xi[t][v] : (T)0;
           }
         }
       }
