@@ -73,6 +73,10 @@ template <typename T>
 __device__ inline void tile_fetch_guarded(const T* __restrict__ A, long ld, long r0, long c0,
                                           long nrows, long ncols, typename V4<T>::type (&pre)[4]) {
   typedef typename V4<T>::type t4;
+  if (r0 + QT <= nrows && c0 + QT <= ncols && (ld & 3) == 0) {  // whole tile inside
+    tile_fetch<T>(A, ld, r0, c0, pre);
+    return;
+  }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int idx = e * 256 + threadIdx.x, row = idx >> 4, c4 = idx & 15;
@@ -92,16 +96,16 @@ __device__ inline void tile_fetch_guarded(const T* __restrict__ A, long ld, long
 }
 
 // A fragments of 16 walkers (rows) over one k tile: a[4 u + j] holds
-// ts[w][k0 + 16 u + 4 q + j] of walker w = w0 + li (zero beyond W).
+// ts[w][k0 + 16 u + 4 q + j] of walker w = w0 + li.  Rows beyond W read the
+// last walker's row (no masked loads); the kernels never store those rows.
 template <typename T>
 __device__ inline void afrag_fetch(const T* __restrict__ ts, long Ktot, int W, int w0, long k0,
                                    int li, int q, T (&a)[16]) {
   typedef typename V4<T>::type t4;
-  const int w = w0 + li;
+  const int w = min(w0 + li, W - 1);
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    t4 v = {0, 0, 0, 0};
-    if (w < W) v = *(const t4*)(ts + (long)w * Ktot + k0 + 16 * u + 4 * q);
+    const t4 v = *(const t4*)(ts + (long)w * Ktot + k0 + 16 * u + 4 * q);
 #pragma unroll
     for (int j = 0; j < 4; ++j) a[4 * u + j] = v[j];
   }
@@ -421,10 +425,11 @@ template hipError_t abuild<double, double>(hipStream_t, int, int, int, int, cons
 template <typename T> struct QFGeom {
   static constexpr int GW = 1, NJ = 4;
   static constexpr bool PREF = sizeof(T) == 4;
+  static constexpr int WAVES = sizeof(T) == 4 ? 3 : 2;  // waves per SIMD (launch bound)
 };
 
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_qform(int W, int Ktot, int Kp0, int Kp1, int nchunk,
+__global__ __launch_bounds__(256, QFGeom<T>::WAVES) void k_qform(int W, int Ktot, int Kp0, int Kp1, int nchunk,
                                                int nseg, const int4* __restrict__ segs,
                                                const T* __restrict__ tsr, const T* __restrict__ tsi,
                                                const T* __restrict__ Q0, const T* __restrict__ Q1,
@@ -470,11 +475,10 @@ __global__ __launch_bounds__(256, 2) void k_qform(int W, int Ktot, int Kp0, int 
       for (int g = 0; g < GW; ++g)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int w = wb + 16 * g + MM::row(q, v);
+          const int w = min(wb + 16 * g + MM::row(q, v), W - 1);
           const long o = (long)w * Ktot + soff + (long)J * QT + 4 * li;
-          const t4 z = {0, 0, 0, 0};
-          xpr[g][v] = w < W ? *(const t4*)(tsr + o) : z;
-          xpi[g][v] = w < W ? *(const t4*)(tsi + o) : z;
+          xpr[g][v] = *(const t4*)(tsr + o);
+          xpi[g][v] = *(const t4*)(tsi + o);
         }
     }
 #pragma unroll
@@ -489,8 +493,11 @@ __global__ __launch_bounds__(256, 2) void k_qform(int W, int Ktot, int Kp0, int 
       for (int g = 0; g < GW; ++g)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int w = wb + 16 * g + MM::row(q, v);
-          if (w >= W) continue;
+          // rows beyond W repeat the last walker (afrag_fetch) and are not
+          // stored; without the prefetch they are skipped (fewer live loads)
+          const int wr = wb + 16 * g + MM::row(q, v);
+          if (!PREF && wr >= W) continue;
+          const int w = min(wr, W - 1);
           const long o = (long)w * Ktot + soff + (long)J * QT + 4 * li + jb0;
           double a = 0.0, b = 0.0;
 #pragma unroll
