@@ -549,11 +549,13 @@ template hipError_t qform<float>(hipStream_t, int, int, int, int, const int4*, c
 template hipError_t qform<double>(hipStream_t, int, int, int, int, const int4*, const double*,
                                   const double*, const double*, const double*, double*);
 
-// Q-route combination, one wave per walker: v_g = sum_z fpart[z][w][g] (the
-// force-bias partials, fixed order), the exchange terms exx_s = sum over spin
-// s's segments of qpart[w][seg], then E_L = e_core + E1 + 1/2 sum_g v_g^2 -
-// 1/2 (exx_0 + exx_1) and log S = log det_0 + log det_1 (Sec. II local
-// energy); vfin = 0 when a force-bias entry is not finite.
+// Q-route combination, one block of four waves per walker (many loads in
+// flight per walker: the kernel only moves data): v_g = sum_z fpart[z][w][g]
+// (the force-bias partials, fixed order), the exchange terms exx_s = sum over
+// spin s's segments of qpart[w][seg], then E_L = e_core + E1 + 1/2 sum_g v_g^2
+// - 1/2 (exx_0 + exx_1) and log S = log det_0 + log det_1 (Sec. II local
+// energy); vfin = 0 when a force-bias entry is not finite.  The sums over
+// threads are wave sums, then the four waves' values in wave order.
 template <typename TP>
 __global__ __launch_bounds__(256) void k_combine_qroute(
     int W, int G, int nz, int nseg0, int nseg1, double e_core, const TP* __restrict__ fp_re,
@@ -562,12 +564,11 @@ __global__ __launch_bounds__(256) void k_combine_qroute(
     const double* __restrict__ ld_re, const double* __restrict__ ld_im, double* __restrict__ v_re,
     double* __restrict__ v_im, double* exx_re, double* exx_im, double* lsn_re, double* lsn_im,
     double* eln_re, double* eln_im, int* vfin) {
-  const int w = blockIdx.x * 4 + wave_id(), l = lane_id();
-  if (w >= W) return;
+  __shared__ double red[4][7];
+  const int w = blockIdx.x, t = threadIdx.x, wv = wave_id(), l = lane_id();
   const long n = (long)W * G;
-  double jr = 0.0, ji = 0.0;
-  int fin = 1;
-  for (int g = l; g < G; g += AFQ_WAVE) {
+  double jr = 0.0, ji = 0.0, nonfin = 0.0;
+  for (int g = t; g < G; g += blockDim.x) {
     double a = 0.0, b = 0.0;
     for (int z = 0; z < nz; ++z) {
       a += (double)fp_re[z * n + (long)w * G + g];
@@ -577,11 +578,8 @@ __global__ __launch_bounds__(256) void k_combine_qroute(
     v_im[(long)w * G + g] = b;
     jr += a * a - b * b;
     ji += 2.0 * a * b;
-    if (!isfinite(a) || !isfinite(b)) fin = 0;
+    if (!isfinite(a) || !isfinite(b)) nonfin = 1.0;
   }
-  jr = wave_sum(jr);
-  ji = wave_sum(ji);
-  const double f = wave_sum((double)fin);
   const int nseg = nseg0 + nseg1;
   const double* p = qpart + (long)w * nseg * 2;
   double x[2][2];
@@ -589,23 +587,34 @@ __global__ __launch_bounds__(256) void k_combine_qroute(
   for (int s = 0; s < 2; ++s) {
     const int lo = s ? nseg0 : 0, hi = s ? nseg : nseg0;
     double a = 0.0, b = 0.0;
-    for (int sg = lo + l; sg < hi; sg += AFQ_WAVE) {
+    for (int sg = lo + t; sg < hi; sg += blockDim.x) {
       a += p[2 * sg];
       b += p[2 * sg + 1];
     }
-    x[s][0] = wave_sum(a);
-    x[s][1] = wave_sum(b);
+    x[s][0] = a;
+    x[s][1] = b;
   }
+  double v7[7] = {jr, ji, nonfin, x[0][0], x[0][1], x[1][0], x[1][1]};
+#pragma unroll
+  for (int k = 0; k < 7; ++k) v7[k] = wave_sum(v7[k]);
   if (l == 0) {
-    exx_re[2 * w] = x[0][0];
-    exx_re[2 * w + 1] = x[1][0];
-    exx_im[2 * w] = x[0][1];
-    exx_im[2 * w + 1] = x[1][1];
-    eln_re[w] = e_core + (e1_re[2 * w] + e1_re[2 * w + 1]) + 0.5 * jr - 0.5 * (x[0][0] + x[1][0]);
-    eln_im[w] = (e1_im[2 * w] + e1_im[2 * w + 1]) + 0.5 * ji - 0.5 * (x[0][1] + x[1][1]);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) red[wv][k] = v7[k];
+  }
+  __syncthreads();
+  if (t == 0) {
+    double r[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) r[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    exx_re[2 * w] = r[3];
+    exx_re[2 * w + 1] = r[5];
+    exx_im[2 * w] = r[4];
+    exx_im[2 * w + 1] = r[6];
+    eln_re[w] = e_core + (e1_re[2 * w] + e1_re[2 * w + 1]) + 0.5 * r[0] - 0.5 * (r[3] + r[5]);
+    eln_im[w] = (e1_im[2 * w] + e1_im[2 * w + 1]) + 0.5 * r[1] - 0.5 * (r[4] + r[6]);
     lsn_re[w] = ld_re[2 * w] + ld_re[2 * w + 1];
     lsn_im[w] = ld_im[2 * w] + ld_im[2 * w + 1];
-    vfin[w] = (f == (double)AFQ_WAVE) ? 1 : 0;
+    vfin[w] = r[2] == 0.0 ? 1 : 0;
   }
 }
 
@@ -616,7 +625,7 @@ hipError_t combine_qroute(hipStream_t st, int W, int G, int nz, int nseg0, int n
                           const double* ld_im, double* v_re, double* v_im, double* exx_re,
                           double* exx_im, double* lsn_re, double* lsn_im, double* eln_re,
                           double* eln_im, int* vfin) {
-  hipLaunchKernelGGL((k_combine_qroute<TP>), dim3((W + 3) / 4), dim3(256), 0, st, W, G, nz, nseg0, nseg1,
+  hipLaunchKernelGGL((k_combine_qroute<TP>), dim3(W), dim3(256), 0, st, W, G, nz, nseg0, nseg1,
                      e_core, fp_re, fp_im, qpart, e1_re, e1_im, ld_re, ld_im, v_re, v_im, exx_re,
                      exx_im, lsn_re, lsn_im, eln_re, eln_im, vfin);
   return hipGetLastError();
