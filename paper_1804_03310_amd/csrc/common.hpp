@@ -37,7 +37,9 @@ template <> struct Mfma<float> {
 };
 
 __device__ inline int lane_id() { return threadIdx.x & (AFQ_WAVE - 1); }
-__device__ inline int wave_id() { return threadIdx.x / AFQ_WAVE; }
+// The wavefront's index in its block, marked wave-uniform (a scalar value), so
+// that what depends on it only (branches, addresses) stays scalar.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / AFQ_WAVE); }
 
 // Intra-wave LDS hand-off: make this wave's LDS writes visible to its lanes.
 __device__ inline void wave_lds_sync() {

@@ -558,7 +558,7 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
   using MM = Mfma<double>;
   typedef MM::acc_t acc_t;
   extern __shared__ __attribute__((aligned(16))) double olds[];
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int wv = wave_id(), l = threadIdx.x & 63;
   const int w = blockIdx.x, s = wv;
   const SpinGeom g = s ? s1 : s0;
   const int N = g.N, off = g.off;
