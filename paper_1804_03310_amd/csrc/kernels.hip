@@ -769,6 +769,16 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
   const int RT = (M + 15) >> 4;
   double er = 0.0, ei = 0.0;
   for (int R = 0; R < RT; ++R) {
+    // this tile's phi and h~ entries requested together (h~ clamped to valid
+    // entries, used only where stored), so that their latencies overlap
+    double hvt[NT][4];
+#pragma unroll
+    for (int J = 0; J < NT; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = min(16 * R + MM::row(lk, v), M - 1), b = min(16 * J + li, N - 1);
+        hvt[J][v] = g.htil[(long)b * M + m];
+      }
     if (R > 0) load_phi_tile(par, pai, R);
     acc_t tr[NT], ti[NT];
 #pragma unroll
@@ -792,9 +802,8 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
         const int m = 16 * R + MM::row(lk, v), b = 16 * J + li;
         if (m < M && b < N) {
           theta_store(to, w, M, Nt, off, s, N, m, b, tr[J][v], ti[J][v]);
-          const double hv = g.htil[(long)b * M + m];
-          er += hv * tr[J][v];
-          ei += hv * ti[J][v];
+          er += hvt[J][v] * tr[J][v];
+          ei += hvt[J][v] * ti[J][v];
         }
       }
   }
