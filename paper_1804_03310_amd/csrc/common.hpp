@@ -131,14 +131,17 @@ __device__ inline double u64_to_unit(uint64_t r) {
 __device__ inline void gaussian4(uint64_t seed, uint64_t t, uint64_t walker, uint64_t q,
                                  uint64_t system, double z[4]) {
   PhiloxOut r = philox4x64_10(t, walker, q, system, seed, AFQ_STREAM_FIELDS);
-  const double twopi = 6.283185307179586476925286766559;
   const double u0 = u64_to_unit(r.w[0]), u1 = u64_to_unit(r.w[1]);
   const double u2 = u64_to_unit(r.w[2]), u3 = u64_to_unit(r.w[3]);
   const double r01 = sqrt(-2.0 * log(u0)), r23 = sqrt(-2.0 * log(u2));
-  z[0] = r01 * cos(twopi * u1);
-  z[1] = r01 * sin(twopi * u1);
-  z[2] = r23 * cos(twopi * u3);
-  z[3] = r23 * sin(twopi * u3);
+  // cos and sin of 2 pi u with one reduction each (2 u is exact)
+  double s1, c1, s3, c3;
+  sincospi(2.0 * u1, &s1, &c1);
+  sincospi(2.0 * u3, &s3, &c3);
+  z[0] = r01 * c1;
+  z[1] = r01 * s1;
+  z[2] = r23 * c3;
+  z[3] = r23 * s3;
 }
 
 // ---------------------------------------------------------------------------
