@@ -1824,9 +1824,9 @@ __global__ __launch_bounds__(128) void k_mgs_wave(int M, int Nt, int n_up, int n
     double2 q = act ? Lc[j * M + l] : make_double2(0.0, 0.0);
     double nv[1] = {q.x * q.x + q.y * q.y};
     wave_sum_dpp<1>(nv);
-    const double r = sqrt(nv[0]);
-    q.x /= r;
-    q.y /= r;
+    const double rinv = 1.0 / sqrt(nv[0]);
+    q.x *= rinv;
+    q.y *= rinv;
     if (act) Lc[j * M + l] = q;
     for (int k0 = j + 1; k0 < N; k0 += 4) {
       double2 a[4];
