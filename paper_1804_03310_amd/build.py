@@ -32,7 +32,8 @@ def compile_commands(out: str):
         obj = os.path.join(CSRC, "_build", src + ".o")
         cmds.append([hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    cmds.append([hipcc(), f"--offload-arch={ARCH}", "-shared", *objs, "-o", out])
+    # no undefined symbols: a declaration without a definition fails here, not at load
+    cmds.append([hipcc(), f"--offload-arch={ARCH}", "-shared", "-Wl,--no-undefined", *objs, "-o", out])
     return cmds
 
 

@@ -634,7 +634,7 @@ int force_bias_partials(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, bool f
   afqmc_ham* hm = tr->ham;
   const int W = wk->n_walkers, M = hm->M, G = hm->G, Nt = tr->Nt;
   const int Ktot = tr->Kp[0] + tr->Kp[1];
-  const int nz = afq::fbias_nz(W, Ktot, G, fp32 ? 4 : 8, acc_cap(M, G, Nt));
+  const int nz = afq::fbias_nz(W, Ktot, G, acc_cap(M, G, Nt));
   if (fp32)
     *err = afq::fbias_mm<float>(st, W, Ktot, G, tr->Gp, nz, (const float*)ws.P_re,
                                 (const float*)ws.P_im, tr->Lq32, (float*)ws.ACC_re,

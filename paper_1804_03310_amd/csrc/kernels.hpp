@@ -186,9 +186,9 @@ hipError_t build_lsplit(hipStream_t st, int G, int Gp, int M, int MP4, int n_up,
 // Q[(n a)][(m b)] = P[(m NP + a)][(n NP + b)] into [Kp][Kp], zero padded.
 template <typename T>
 hipError_t perm_qpad(hipStream_t st, int M, int N, int NP, int MP4, int Kp, const double* P, T* Q);
-// Number of k ranges of the force-bias GEMM (partials of nz W G doubles must
-// fit cap_per_walker W doubles).
-int fbias_nz(int W, int Ktot, int G, int elem_size, long cap_per_walker);
+// Number of k ranges of the force-bias GEMM (about 512 blocks; partials of
+// nz W G elements must fit cap_per_walker W doubles).
+int fbias_nz(int W, int Ktot, int G, long cap_per_walker);
 // part[z][w][g] = sum over range z of ts[w][k] Lq[k][g], re and im (in T: the
 // partial sums as the MFMA accumulated them).
 template <typename T>

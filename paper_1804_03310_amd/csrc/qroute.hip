@@ -23,12 +23,10 @@ template <typename T> struct V4;
 template <> struct V4<float> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct V4<double> { typedef double type __attribute__((ext_vector_type(4))); };
 
-// Walker groups of 16 per wave: two for FP32 (each B fragment feeds the MFMAs
-// of both), one for FP64 (register budget).  NJ: column tiles per pass of the
-// quadratic form (FP32 takes two passes of two to stay within 256 VGPRs).
+// Row groups of 16 per wave in the A-build: two for FP32 (each B fragment
+// feeds the MFMAs of both), one for FP64 (register budget).
 template <typename T> struct QGeom {
   static constexpr int GW = sizeof(T) == 4 ? 2 : 1;
-  static constexpr int NJ = sizeof(T) == 4 ? 2 : 4;
 };
 
 constexpr int QT = 64;       // tile edge along k and along the output columns
@@ -224,9 +222,10 @@ template hipError_t perm_qpad<float>(hipStream_t, int, int, int, int, int, const
 // ---------------------------------------------------------------------------
 // Force bias v[w][g] = sum_k ts[w][k] Lq[k][g] (re and im rows of Theta as
 // two A operands against one B), split over k into nz ranges of whole tiles:
-// part[z][w][g].  Block = 4 waves x GW groups of 16 walkers x 64 columns;
-// block index chunk-fastest, so with 8 walker chunks each XCD keeps its
-// chunk's Theta rows in its own L2.
+// part[z][w][g].  Block = 4 waves x 16 walkers x 64 columns (one walker group
+// per wave: two blocks per CU keep two waves per SIMD in flight); block index
+// chunk-fastest, so with a multiple of 8 walker chunks each XCD keeps its
+// chunks' Theta rows in its own L2.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_fbias_mm(int W, int Ktot, int G, int Gp, int nchunk,
@@ -234,7 +233,7 @@ __global__ __launch_bounds__(256) void k_fbias_mm(int W, int Ktot, int G, int Gp
                                                   const T* __restrict__ tsi, const T* __restrict__ Lq,
                                                   T* __restrict__ part_re,
                                                   T* __restrict__ part_im) {
-  constexpr int GW = QGeom<T>::GW;
+  constexpr int GW = 1;  // walker groups of 16 per wave
   typedef typename V4<T>::type t4;
   typedef Mfma<T> MM;
   __shared__ __attribute__((aligned(32))) T lds[2][QT * QLD];
@@ -295,20 +294,19 @@ __global__ __launch_bounds__(256) void k_fbias_mm(int W, int Ktot, int G, int Gp
     }
 }
 
-int fbias_nz(int W, int Ktot, int G, int elem_size, long cap_per_walker) {
-  const int GW = elem_size == 4 ? 2 : 1;
-  const int nchunk = (W + 64 * GW - 1) / (64 * GW);
+int fbias_nz(int W, int Ktot, int G, long cap_per_walker) {
+  const int nchunk = (W + 63) / 64;
   const int ngt = (G + QT - 1) / QT;
   const int nkt = Ktot / QT;
-  // about 256 blocks (one per CU), within the partials' capacity
-  int nz = std::max(1, std::min(nkt, (256 + nchunk * ngt - 1) / (nchunk * ngt)));
+  // about 512 blocks (two per CU), within the partials' capacity
+  int nz = std::max(1, std::min(nkt, (512 + nchunk * ngt - 1) / (nchunk * ngt)));
   return (int)std::max<long>(1, std::min<long>(nz, cap_per_walker / std::max(G, 1)));
 }
 
 template <typename T>
 hipError_t fbias_mm(hipStream_t st, int W, int Ktot, int G, int Gp, int nz, const T* tsr,
                     const T* tsi, const T* Lq, T* part_re, T* part_im) {
-  constexpr int GW = QGeom<T>::GW;
+  constexpr int GW = 1;
   const int nkt = Ktot / QT;
   if (W <= 0 || G <= 0 || nkt == 0 || nz < 1 || Gp % QT || Ktot % QT) return hipErrorInvalidValue;
   const int nchunk = (W + 64 * GW - 1) / (64 * GW);
