@@ -4,7 +4,8 @@ Python binding of the C ABI in include/afqmc.h.  This module only marshals
 arguments: host inputs go in as numpy float64 arrays, walker state lives in
 torch CUDA tensors (device memory) and work is enqueued on torch's current
 stream.  Every step of the walker update runs in the HIP kernels of
-libafqmc.so; importing this package fails if that library has not been built.
+libafqmc.so; importing this package builds that library when it is missing or
+stale (hipcc, gfx950) and fails if it cannot be built or loaded.
 """
 from __future__ import annotations
 

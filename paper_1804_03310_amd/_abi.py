@@ -61,13 +61,20 @@ _lib = None
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load libafqmc.so; raises if it has not been built (no fallback)."""
+    """Load libafqmc.so, building it first (hipcc, gfx950) when it is missing
+    or was built from other sources.  There is no fallback: if the library
+    cannot be built or loaded this raises ImportError."""
     global _lib
     if _lib is not None:
         return _lib
+    if path == LIB_PATH:
+        from . import build as _build
+        try:
+            _build.ensure_built()
+        except Exception as e:  # no hipcc, compile error
+            raise ImportError(f"HIP library {path} could not be built: {e}") from e
     if not os.path.exists(path):
-        raise ImportError(f"HIP library {path} is missing: run paper_1804_03310_amd/build.py "
-                          "(or __graft_entry__.build()) first")
+        raise ImportError(f"HIP library {path} is missing")
     lib = ctypes.CDLL(path)
     P = c_void_p
     sig = {

@@ -4,12 +4,18 @@ import numpy as np
 import pytest
 
 import afqmc_synth as syn
-from paper_1804_03310_amd.serving import Request, Server, footprint_bytes
+
+
+def _serving():
+    # imported inside the tests: the package loads (and if needed builds) the
+    # HIP library, and a failure there must not stop collection of the others
+    from paper_1804_03310_amd import serving
+    return serving
 
 
 def _req(M, W, steps, arrival, seed=0, system_id=0, n_dn=None, prec="fp64"):
     inp = syn.make_system(M, M // 4, M // 4 if n_dn is None else n_dn, 2 * M, 8.0, seed=M)
-    return Request(h=inp.h, L=inp.L, e_core=0.0, C_up=inp.C_up, C_dn=inp.C_dn, n_up=inp.n_up,
+    return _serving().Request(h=inp.h, L=inp.L, e_core=0.0, C_up=inp.C_up, C_dn=inp.C_dn, n_up=inp.n_up,
                    n_dn=inp.n_dn, n_walkers=W, n_steps=steps, dt=0.005, seed=seed,
                    system_id=system_id, arrival=arrival, chol_prec=prec, taylor_prec=prec,
                    ortho_every=2, pc_every=5)
@@ -29,7 +35,10 @@ class SimExecutor:
         self.t += dt
 
     def footprint(self, req):
-        return footprint_bytes(req)
+        # host-side stand-in for the library's footprint query: L, one A and a
+        # few orbital-sized arrays per walker, in bytes
+        M, nt = req.M, req.n_up + req.n_dn
+        return 8 * (req.n_chol * M * M + req.n_walkers * (2 * M * M + 8 * M * nt))
 
     def start(self, req):
         self.started.append(req.tag)
@@ -47,6 +56,7 @@ class SimExecutor:
 
 
 def test_footprint_grows_with_size():
+    footprint_bytes = _serving().footprint_bytes
     a = footprint_bytes(_req(16, 32, 10, 0))
     b = footprint_bytes(_req(32, 32, 10, 0))
     c = footprint_bytes(_req(32, 128, 10, 0))
@@ -54,10 +64,11 @@ def test_footprint_grows_with_size():
 
 
 def test_admission_respects_budget_and_first_fit():
+    Server = _serving().Server
     ex = SimExecutor()
     big = _req(40, 256, 50, 0.0)
     small = [_req(12, 32, 20, 0.001 * i) for i in range(6)]
-    budget = footprint_bytes(big) + footprint_bytes(small[0])
+    budget = ex.footprint(big) + ex.footprint(small[0])
     srv = Server(budget, executor=ex, max_active=4, chunk_steps=10, clock=ex.clock)
     big.tag = "big"
     ids = [srv.submit(big)]
@@ -82,6 +93,7 @@ def test_admission_respects_budget_and_first_fit():
 
 
 def test_slots_limit_concurrency():
+    Server = _serving().Server
     ex = SimExecutor()
     reqs = [_req(8, 16, 10, 0.0) for _ in range(5)]
     srv = Server(10 ** 12, executor=ex, max_active=2, chunk_steps=5, clock=ex.clock)
@@ -101,6 +113,7 @@ def test_results_identical_alone_and_in_mix():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     print("[gpu-case] serving alone vs mix", flush=True)
+    Server = _serving().Server
     mk = lambda: [_req(8, 16, 12, 0.0, seed=3, system_id=1),
                   _req(8, 16, 12, 0.0, seed=3, system_id=1, n_dn=1),   # cation of the pair
                   _req(12, 32, 12, 0.0, seed=5),
