@@ -8,13 +8,18 @@ MGS every 10 steps, comb every 20 steps.  A step is one pass of the whole
 walker update over all walkers.  Inputs are synthetic (seeded generators).
 
 Prints one JSON line.  `value` is walker-steps/s over the timed steps with all
-inputs resident in HBM.  `roofline` reports the fused exchange / force-bias
-kernel (the dominant one): algorithmic flops per launch divided by its average
-duration, measured with HIP events on the launch stream over the timed region.
+inputs resident in HBM.  `roofline` reports whichever of the two matrix-core
+classes takes more time per step, the exchange (quadratic form, per-vector
+exchange or multi-determinant energy kernel) or the Taylor propagation (the
+fused kernel, or the chain of walker-batched GEMMs where the operands do not
+fit one CU): algorithmic flops per launch divided by the average launch
+duration, measured with HIP events on the launch stream over the timed region;
+the other class is under `roofline_other`.
 `accuracy` (hydrogen-chain workload) runs all walkers for 100 steps with
 population control off and compares E_mix per step with the stored FP64
 oracle run under tests/golden.  `cpu_baseline` times the FP64 numpy oracle on
-a bounded sample of the same workload on the host cores.
+a bounded sample of the same workload on the host cores (BLAS threads as
+the host gives them), and beside it on one thread.
 """
 from __future__ import annotations
 
@@ -372,13 +377,8 @@ def cs_report(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, inp, sample_walkers, sample_steps):
+def _oracle_rate(wl, inp, sample_walkers, sample_steps):
     from oracle import Oracle, Options as OOptions
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
     o = Oracle.from_inputs(inp)
     st = o.init_walkers(sample_walkers)
     et = o.mixed_energy(st)
@@ -387,10 +387,31 @@ def cpu_baseline(wl, inp, sample_walkers, sample_steps):
     t0 = time.perf_counter()
     o.propagate(st, sample_steps, wl.dt, 0, 1, opt)
     dt = time.perf_counter() - t0
-    return {"value": sample_walkers * sample_steps / dt, "unit": "walker-steps/s", "cores": threads,
+    return sample_walkers * sample_steps / dt, dt
+
+
+def cpu_baseline(wl, inp, sample_walkers, sample_steps):
+    """The FP64 numpy oracle (not tuned) on a bounded sample of the workload:
+    once with the BLAS threads the host gives it (`cores`), once on one
+    thread over a quarter of the steps."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads, threadpool_limits = os.cpu_count() or 1, None
+    rate, dt = _oracle_rate(wl, inp, sample_walkers, sample_steps)
+    one = None
+    if threadpool_limits is not None:
+        n1 = max(sample_steps // 4, 1)
+        with threadpool_limits(limits=1):
+            r1, d1 = _oracle_rate(wl, inp, sample_walkers, n1)
+        one = {"value": r1, "cores": 1,
+               "sample": f"{sample_walkers} walkers x {n1} steps, one BLAS thread, {d1:.1f} s"}
+    return {"value": rate, "unit": "walker-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{sample_walkers} walkers x {sample_steps} steps of {wl.name} "
-                      f"(FP64 numpy oracle, comb off), {dt:.1f} s"}
+                      f"(FP64 numpy oracle, comb off), {dt:.1f} s",
+            "single_thread": one}
 
 
 def main():
@@ -548,22 +569,34 @@ def main():
     q32 = chol_prec == "fp32" and wl.M * max(wl.n_up, wl.n_dn) <= afq._abi.QROUTE_FP32_MAX_K
     ex_prec = ("fp32" if q32 else "fp64") if (route == "q" and not multi) else chol_prec
     ex_peak = {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}[ex_prec]
+    # per step: the exchange class is one launch; the Taylor class is one
+    # fused launch, or a chain of GEMM launches (B1, each term, B1) whose
+    # algorithmic flops are shared out over the chain's launches
     cands = [("exchange", ex_name, ex_flops, ex_peak)]
+    tay_flops = taylor_flops_per_walker(wl.M, wl.n_up + wl.n_dn, wl.taylor_order) * W
+    tay_peak = {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS}[taylor_prec]
     if taylor_fused(wl.M, wl.n_up + wl.n_dn, taylor_prec):
         cands.append(("taylor_b1",
                       "k_propagate_fused (B1 exp(A) B1 phi, Taylor order %d)" % wl.taylor_order,
-                      taylor_flops_per_walker(wl.M, wl.n_up + wl.n_dn, wl.taylor_order) * W,
-                      {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS}[taylor_prec]))
+                      tay_flops, tay_peak))
+    else:
+        cands.append(("taylor_b1",
+                      "k_cgemm_walkers chain (B1, %d Taylor terms, B1; walker-batched complex "
+                      "GEMMs; the chain timed as one bracket per step)" % wl.taylor_order, tay_flops,
+                      tay_peak))
     lines = []
-    for cls, nm, fl, pk in cands:
+    for cls, nm, fl_step, pk in cands:
         n_l, ms_l = ktimes[cls]
+        per_step = n_l / max(args.steps, 1)
+        fl = fl_step / per_step if n_l else float("nan")  # flops per launch
         a_s = (ms_l / n_l) / 1e3 if n_l else float("nan")
         ach = fl / a_s / 1e12 if n_l else float("nan")
         lines.append({"class": cls, "bound": "mfma", "kernel": nm, "achieved": ach, "peak": pk,
                       "unit": "TFLOP/s", "frac": ach / pk,
                       "traffic": measured_traffic(wl.name, cls, ex_prec, taylor_prec),
-                      "flops_per_launch": fl, "avg_launch_ms": a_s * 1e3, "launches": n_l,
-                      "ms_per_step": ms_l / max(args.steps, 1)})
+                      "flops_per_launch": fl, "flops_per_step": fl_step,
+                      "avg_launch_ms": a_s * 1e3, "launches": n_l,
+                      "launches_per_step": per_step, "ms_per_step": ms_l / max(args.steps, 1)})
     lines.sort(key=lambda d: -(d["ms_per_step"] if d["launches"] else 0.0))
     roof, roof_other = lines[0], lines[1:]
     fbias_report = None

@@ -208,7 +208,11 @@ afqmc_status afqmc_orthonormalize(afqmc_ham *ham, afqmc_trial *trial, afqmc_walk
  * (seed, 1), counter (pc_index, 0, 0, system_id), word 0); tooth j at
  * ((j + xi) W_tot) / K picks the first walker whose prefix sum exceeds it.
  * Walker state is copied from the parents and weights reset to 1.
- * norm_factor_host (nullable) receives W_tot / K (synchronises the stream). */
+ * norm_factor_host (nullable) receives W_tot / K (synchronises the stream).
+ * If W_tot is not positive and finite (every walker dead) the population is
+ * left unchanged and the norm factor is 0; with norm_factor_host the call
+ * then returns AFQMC_ERR_NONFINITE.  Inside afqmc_propagate such a population
+ * stays dead and its E_mix entries are not finite. */
 afqmc_status afqmc_reconfigure(afqmc_trial *trial, afqmc_walkers *walkers, uint64_t seed,
                                uint64_t pc_index, double *norm_factor_host, void *stream);
 

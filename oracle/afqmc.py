@@ -584,6 +584,8 @@ class Oracle:
         """Comb (population control); copies walker state, resets weights to 1."""
         xi = comb_uniform(seed, pc_index, system_id)
         parents, norm = comb_parents(st.weight, xi)
+        if not (norm > 0.0 and np.isfinite(norm)):
+            return 0.0  # every walker dead: population left as it is
         st.phi = st.phi[parents].copy()
         st.logS = st.logS[parents].copy()
         st.eloc = st.eloc[parents].copy()

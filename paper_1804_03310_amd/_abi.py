@@ -75,6 +75,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
             raise ImportError(f"HIP library {path} could not be built: {e}") from e
     if not os.path.exists(path):
         raise ImportError(f"HIP library {path} is missing")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+    # Loaded first, it is the one the dynamic linker hands this library, so
+    # the library's kernels and torch's allocations and streams live in one
+    # runtime.  Loaded the other way round, the process holds two runtimes and
+    # the library's sees no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P = c_void_p
     sig = {

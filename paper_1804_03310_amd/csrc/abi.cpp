@@ -581,7 +581,7 @@ afqmc_status reconfigure_impl(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, 
     AFQ_CK(afq::gather_rows(st, W, it.row, ws.parent, snap, it.p));
     snap += (size_t)W * it.row;
   }
-  AFQ_CK(afq::fill(st, wk->weight, W, 1.0));
+  AFQ_CK(afq::comb_weights(st, W, ws.scal + 2, wk->weight));
   return AFQMC_OK;
 }
 
@@ -1344,6 +1344,8 @@ afqmc_status afqmc_reconfigure(afqmc_trial* tr, afqmc_walkers* wk, uint64_t seed
   if (norm_factor_host) {
     AFQ_CK(hipMemcpyAsync(norm_factor_host, ws.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
     AFQ_CK(hipStreamSynchronize(st));
+    if (!(*norm_factor_host > 0.0))
+      return fail(AFQMC_ERR_NONFINITE, "comb: the sum of weights is not positive and finite");
   }
   return AFQMC_OK;
 }

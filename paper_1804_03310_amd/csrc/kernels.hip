@@ -1911,6 +1911,13 @@ __global__ __launch_bounds__(1024) void k_comb_parents(int W, const double* __re
   __syncthreads();
   const double wtot = sh[0], xi = sh[1];
   const int last = last_sh;
+  if (!(wtot > 0.0) || !isfinite(wtot)) {
+    // every walker dead (or a non-finite weight): the population is left as
+    // it is and the norm factor 0 tells the caller
+    for (int j = threadIdx.x; j < W; j += blockDim.x) parent[j] = j;
+    if (threadIdx.x == 0 && norm_out) norm_out[0] = 0.0;
+    return;
+  }
   for (int j = threadIdx.x; j < W; j += blockDim.x) {
     const double zj = (((double)j + xi) * wtot) / (double)W;
     int lo = 0, hi = W;  // first index with C[k] > zj in [lo, hi]
@@ -1944,6 +1951,18 @@ __global__ __launch_bounds__(256) void k_gather_rows(long row, const int* __rest
 hipError_t gather_rows(hipStream_t st, int W, long row, const int* parent, const double* src,
                        double* dst) {
   hipLaunchKernelGGL(k_gather_rows, dim3(W), dim3(256), 0, st, row, parent, src, dst);
+  return hipGetLastError();
+}
+
+// Weights after the comb: 1, unless the comb found no positive finite total
+// (norm factor 0), in which case they stay as they are.
+__global__ void k_comb_weights(int W, const double* __restrict__ norm, double* __restrict__ weight) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < W && norm[0] > 0.0) weight[j] = 1.0;
+}
+
+hipError_t comb_weights(hipStream_t st, int W, const double* norm, double* weight) {
+  hipLaunchKernelGGL(k_comb_weights, dim3((W + 255) / 256), dim3(256), 0, st, W, norm, weight);
   return hipGetLastError();
 }
 

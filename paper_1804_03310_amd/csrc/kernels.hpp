@@ -108,10 +108,13 @@ hipError_t mixed_energy(hipStream_t st, int W, const double* weight, const doubl
 hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double* phr, double* phi,
                size_t max_lds);
 
-// Comb: parents and norm factor (single thread, left-to-right sums).
+// Comb: parents and norm factor (single thread, left-to-right sums).  With no
+// positive finite total weight: identity parents and norm factor 0.
 hipError_t comb_parents(hipStream_t st, int W, const double* weight, uint64_t seed,
                         uint64_t pc_index, int system_id, double* cbuf, int* parent,
                         double* norm_out);
+// Weights after the comb: 1 where the norm factor is positive, else unchanged.
+hipError_t comb_weights(hipStream_t st, int W, const double* norm, double* weight);
 // Gather rows of length `row` doubles from src[parent[j]] to dst[j], for `nbuf` buffers.
 hipError_t gather_rows(hipStream_t st, int W, long row, const int* parent, const double* src,
                        double* dst);

@@ -87,3 +87,19 @@ def test_package_fails_loudly_without_library(tmp_path):
             _abi.load(str(tmp_path / "missing.so"))
         finally:
             _abi._lib = saved
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the package before torch must not map a second HIP runtime
+    (torch ships its own copy of libamdhip64 under the same soname; two copies
+    in one process leave the library without a device)."""
+    import subprocess
+    import sys
+    code = ("import paper_1804_03310_amd, torch, os\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = {os.path.realpath(l.split()[-1]) for l in maps if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1", r.stdout

@@ -132,21 +132,14 @@ def _small_system(M, n_up, n_dn, n_chol, seed, tau_d=4.0):
     return inp
 
 
-@pytest.mark.parametrize("M,n_up,n_dn", [(6, 3, 3), (7, 3, 2), (5, 2, 0)])
-def test_local_energy_at_trial_is_hartree_fock(M, n_up, n_dn):
-    """E_L(phi = D_0) equals the HF energy written from the 4-index V (Eq. 1)."""
-    inp = _small_system(M, n_up, n_dn, 9, seed=M + n_up)
-    # an unrestricted trial: different orbitals per spin
-    rng = np.random.default_rng(5)
-    Cdn = np.linalg.qr(rng.standard_normal((M, M)))[0]
-    o = Oracle(inp.h, inp.L, inp.e_core, inp.C_up, Cdn, n_up, n_dn)
-    st = o.init_walkers(2)
-    V = fock.eri_from_chol(inp.L)
-    occ = [inp.C_up[:, :n_up], Cdn[:, :n_dn]]
-    # MO-basis integrals per spin pair
-    E = inp.e_core
+def _hf_energy(h, L, e_core, occ):
+    """Hartree-Fock energy of the determinant with occupied orbitals occ[spin]
+    from the 4-index V of Eq. 1 (Coulomb between all pairs, exchange within a
+    spin)."""
+    V = fock.eri_from_chol(L)
+    E = e_core
     for s in range(2):
-        E += np.trace(occ[s].T @ inp.h @ occ[s])
+        E += np.trace(occ[s].T @ h @ occ[s])
     for s in range(2):
         for t in range(2):
             Vmo = np.einsum("ia,jb,kc,ld,ijkl->abcd", occ[s], occ[t], occ[s], occ[t], V)
@@ -156,6 +149,19 @@ def test_local_energy_at_trial_is_hartree_fock(M, n_up, n_dn):
                     E += 0.5 * Vmo[a, b, a, b]
                     if s == t:
                         E -= 0.5 * Vmo[a, b, b, a]
+    return E
+
+
+@pytest.mark.parametrize("M,n_up,n_dn", [(6, 3, 3), (7, 3, 2), (5, 2, 0)])
+def test_local_energy_at_trial_is_hartree_fock(M, n_up, n_dn):
+    """E_L(phi = D_0) equals the HF energy written from the 4-index V (Eq. 1)."""
+    inp = _small_system(M, n_up, n_dn, 9, seed=M + n_up)
+    # an unrestricted trial: different orbitals per spin
+    rng = np.random.default_rng(5)
+    Cdn = np.linalg.qr(rng.standard_normal((M, M)))[0]
+    o = Oracle(inp.h, inp.L, inp.e_core, inp.C_up, Cdn, n_up, n_dn)
+    st = o.init_walkers(2)
+    E = _hf_energy(inp.h, inp.L, inp.e_core, [inp.C_up[:, :n_up], Cdn[:, :n_dn]])
     assert np.allclose(st.eloc, E, rtol=0, atol=1e-11)
     assert np.allclose(st.logS, 0.0, atol=1e-12)
     # force-bias input at the trial is lbar
@@ -414,6 +420,61 @@ def test_comb_matches_brute_force_and_bounds():
             if k:
                 assert parents[j] == k[0]
         assert np.all(np.diff(parents) >= 0)
+
+
+def test_dead_walker_reset_to_reference_state():
+    """Sec. II phaseless constraint: a walker whose weight becomes zero or
+    non-finite dies.  It is reset to the reference determinant with weight 0,
+    so its overlap is 1 (log S = 0), its E_L the Hartree-Fock energy of D_0
+    from the 4-index V and its force-bias input v_g = sum_sigma Tr(D_0^T L_g
+    D_0); it drops out of E_mix, the comb never picks it, and the other
+    walkers are untouched."""
+    M, n_up, n_dn = 6, 3, 2
+    inp = _small_system(M, n_up, n_dn, 9, seed=21)
+    o = Oracle.from_inputs(inp)
+    opt = Options(taylor_order=6, e_trial=0.0)
+    st = o.init_walkers(5)
+    o.step(st, 0, 3, 0.01, opt)
+    ref = st.copy()
+    st.weight[1] = 0.0
+    st.weight[3] = np.nan
+    o.step(st, 1, 3, 0.01, opt)
+    o.step(ref, 1, 3, 0.01, opt)
+    dead, live = [1, 3], [0, 2, 4]
+    occ = [inp.C_up[:, :n_up], inp.C_dn[:, :n_dn]]
+    d0 = np.concatenate(occ, axis=1)
+    vbar = np.array([sum(np.trace(c.T @ Lg @ c) for c in occ) for Lg in inp.L])
+    e_hf = _hf_energy(inp.h, inp.L, inp.e_core, occ)
+    for k in dead:
+        assert st.weight[k] == 0.0
+        assert np.array_equal(st.phi[k], d0.astype(complex))
+        assert abs(st.logS[k]) < 1e-12
+        assert abs(st.eloc[k] - e_hf) < 1e-11
+        assert np.allclose(st.v[k], vbar, rtol=0, atol=1e-12)
+    for k in live:
+        assert st.weight[k] == ref.weight[k] and st.weight[k] > 0
+        assert np.array_equal(st.phi[k], ref.phi[k])
+        assert st.eloc[k] == ref.eloc[k]
+    wl = st.weight[live]
+    emix = math.fsum(wl * st.eloc[live].real) / math.fsum(wl)
+    assert abs(Oracle.mixed_energy(st) - emix) < 1e-12 * abs(emix)
+    for pc in range(20):
+        parents, _ = comb_parents(st.weight, comb_uniform(3, pc))
+        assert not set(parents.tolist()) & set(dead)
+
+
+def test_comb_with_no_live_walker_leaves_population():
+    """A comb over an all-dead population has no teeth to place (W_tot = 0):
+    the population is left as it is and the norm factor is 0."""
+    inp = _small_system(5, 2, 2, 6, seed=2)
+    o = Oracle.from_inputs(inp)
+    st = o.init_walkers(4)
+    o.step(st, 0, 1, 0.01, Options(e_trial=0.0))
+    st.weight[:] = 0.0
+    before = st.copy()
+    assert o.reconfigure(st, 1, 0) == 0.0
+    assert np.array_equal(st.weight, before.weight)
+    assert np.array_equal(st.phi, before.phi)
 
 
 def test_comb_uniform_in_unit_interval():
