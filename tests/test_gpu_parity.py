@@ -252,6 +252,64 @@ def test_reconfigure_parity(afq, W):
     assert np.all(np.isin(_np(w.eloc[0]), el_before))
 
 
+def test_dead_walkers_reset_like_the_oracle(afq):
+    """Walkers whose weight is zero or not finite die (Sec. II phaseless
+    constraint): reset to D_0 with its reference log S, E_L and v, weight 0,
+    still propagated, left out of E_mix.  Two of 16 walkers are killed before
+    a 3-step FP64 run; every walker's state and E_mix match the oracle."""
+    _say("dead-walker reset plain-M10 fp64")
+    wl = syn.WORKLOADS["plain-M10"]
+    inp = syn.workload_system(wl)
+    W = 16
+    ham, trial, w = _make(afq, inp, W)
+    afq.walkers_from_trial(ham, trial, w)
+    et = afq.local_energy(ham, trial, w)
+    kw = dict(taylor_order=6, ortho_every=2, pc_every=0, e_trial=et)
+    afq.propagate(ham, trial, w, 2, wl.dt, 9, 0, afq.Options(**kw))
+    o = Oracle.from_inputs(inp)
+    st = o.init_walkers(W)
+    o.propagate(st, 2, wl.dt, 9, 0, OOptions(**kw))
+    wt = _np(w.weight).copy()
+    wt[3], wt[11] = 0.0, np.nan
+    w.weight.copy_(torch.from_numpy(wt))
+    st.weight[3], st.weight[11] = 0.0, np.nan
+    em = _np(afq.propagate(ham, trial, w, 3, wl.dt, 9, 2, afq.Options(**kw)))
+    oe = o.propagate(st, 3, wl.dt, 9, 2, OOptions(**kw))
+    assert np.max(np.abs(em - oe)) <= 1e-9
+    got_w = _np(w.weight)
+    assert got_w[3] == 0.0 and got_w[11] == 0.0
+    assert np.allclose(got_w, st.weight, rtol=1e-9, atol=0)
+    phi = _np(w.phi_re) + 1j * _np(w.phi_im)
+    assert np.allclose(phi, st.phi, rtol=0, atol=1e-10)
+    D0 = np.concatenate([inp.C_up[:, :inp.n_up], inp.C_dn[:, :inp.n_dn]], axis=1)
+    for k in (3, 11):
+        assert np.allclose(phi[k], D0, atol=1e-14)
+    ls = _np(w.logovlp[0]) + 1j * _np(w.logovlp[1])
+    el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
+    assert np.allclose(ls.real, st.logS.real, atol=1e-9)
+    assert np.allclose(_wrap(ls.imag - st.logS.imag), 0, atol=1e-9)
+    assert np.allclose(el, st.eloc, rtol=1e-10)
+
+
+def test_reconfigure_all_dead_reports_nonfinite(afq):
+    """A comb over an all-dead population: AFQMC_ERR_NONFINITE, walkers left
+    as they are (weights stay 0)."""
+    _say("reconfigure all dead")
+    inp = syn.make_system(6, 2, 2, 4, 8.0, seed=6)
+    ham, trial, w = _make(afq, inp, 9)
+    afq.walkers_from_trial(ham, trial, w)
+    re, im = syn.random_walkers(6, 2, 2, 9, seed=3, scale=0.3)
+    D0 = np.concatenate([inp.C_up[:, :2], inp.C_dn[:, :2]], axis=1)
+    _set_phi(w, D0[None] + re + 1j * im)
+    w.weight.zero_()
+    before = _np(w.phi_re).copy()
+    with pytest.raises(afq.AfqmcError) as e:
+        afq.reconfigure(trial, w, 13, 4)
+    assert e.value.status == -6
+    assert np.array_equal(_np(w.weight), np.zeros(9))
+    assert np.array_equal(_np(w.phi_re), before)
+
+
 def _one_step_sampled(afq, inp, W, sample, dt, prec, taylor_order=6, route=None):
     """One step of all W walkers from the reference on the GPU; the oracle
     repeats the step for the sampled walkers alone (counter-based fields)."""
