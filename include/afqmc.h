@@ -216,6 +216,22 @@ afqmc_status afqmc_orthonormalize(afqmc_ham *ham, afqmc_trial *trial, afqmc_walk
 afqmc_status afqmc_reconfigure(afqmc_trial *trial, afqmc_walkers *walkers, uint64_t seed,
                                uint64_t pc_index, double *norm_factor_host, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the comb of
+ * afqmc_reconfigure, same arguments and results (bitwise), with its scratch
+ * (prefix sums, parents, norm factor, gather snapshot) in a static device
+ * array of AFQMC_NOALLOC_SCRATCH_BYTES per device instead of the walker
+ * workspace; the workspace must still be passed (it holds the walkers'
+ * force-bias traces).  Allocates nothing (no hipMalloc, hipFree or library
+ * allocation).  AFQMC_ERR_ARG when the walker count does not fit the array
+ * (n_walkers * 20 bytes + 768 bytes > AFQMC_NOALLOC_SCRATCH_BYTES); any
+ * walker shape fits (the snapshot is taken column range by column range).
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device race.  The array lives until the process ends. */
+#define AFQMC_NOALLOC_SCRATCH_BYTES (32u << 20)
+afqmc_status afqmc_reconfigure_noalloc(afqmc_trial *trial, afqmc_walkers *walkers, uint64_t seed,
+                                       uint64_t pc_index, double *norm_factor_host, void *stream);
+
 /* The auxiliary fields afqmc_propagate draws at global step t:
  * x_dev [n_walkers][n_chol] device float64. */
 afqmc_status afqmc_fields(uint64_t seed, uint64_t t, int n_walkers, int n_chol,

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "AFQMC_OK", -1: "AFQMC_ERR_ARG", -2: "AFQMC_ERR_OOM", -3: "AF
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 MAX_EXC = 4
 QROUTE_FP32_MAX_K = 4096  # AFQMC_QROUTE_FP32_MAX_K
+NOALLOC_SCRATCH_BYTES = 32 << 20  # AFQMC_NOALLOC_SCRATCH_BYTES
 
 # Every symbol include/afqmc.h declares.
 EXPORTED = ["afqmc_init_hamiltonian", "afqmc_init_trial", "afqmc_walker_workspace_bytes",
@@ -28,7 +29,7 @@ EXPORTED = ["afqmc_init_hamiltonian", "afqmc_init_trial", "afqmc_walker_workspac
             "afqmc_orthonormalize", "afqmc_reconfigure", "afqmc_fields",
             "afqmc_timing_enable", "afqmc_timing_read", "afqmc_footprint_bytes",
             "afqmc_trial_exchange_route", "afqmc_trial_set_exchange_route",
-            "afqmc_reblock", "afqmc_cs_difference",
+            "afqmc_reblock", "afqmc_cs_difference", "afqmc_reconfigure_noalloc",
             "afqmc_free_hamiltonian", "afqmc_free_trial", "afqmc_last_error"]
 KERNEL_CLASSES = ["exchange", "propagator_build", "taylor_b1", "overlap_theta", "mgs", "comb",
                   "other", "force_bias"]
@@ -93,6 +94,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "afqmc_local_energy": (c_int, [P, P, ctypes.POINTER(WalkersStruct), P, P]),
         "afqmc_orthonormalize": (c_int, [P, P, ctypes.POINTER(WalkersStruct), P]),
         "afqmc_reconfigure": (c_int, [P, ctypes.POINTER(WalkersStruct), c_uint64, c_uint64, P, P]),
+        "afqmc_reconfigure_noalloc": (c_int, [P, ctypes.POINTER(WalkersStruct), c_uint64, c_uint64,
+                                              P, P]),
         "afqmc_fields": (c_int, [c_uint64, c_uint64, c_int, c_int, c_int, P, P]),
         "afqmc_timing_enable": (c_int, [P, c_int]),
         "afqmc_footprint_bytes": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int,

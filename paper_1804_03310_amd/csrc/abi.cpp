@@ -825,6 +825,54 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
 namespace afq {
 // The thread's last-error message, for the ABI functions of other files.
 afqmc_status set_error(afqmc_status s, const char* msg) { return fail(s, msg); }
+
+// The comb of afqmc_reconfigure with its scratch (prefix sums, parents, norm
+// factor, gather snapshot) carved from the device buffer `scratch` of
+// `scratch_bytes` instead of the walker workspace; the workspace still holds
+// the walkers' force-bias traces, which are gathered with the rest.  The
+// snapshot is used column range by column range, so any walker shape fits
+// once the parents, prefix sums and one column of all walkers do.  Enqueues
+// nothing that allocates.
+afqmc_status reconfigure_scratch(afqmc_trial* tr, afqmc_walkers* wk, uint64_t seed,
+                                 uint64_t pc_index, char* scratch, size_t scratch_bytes,
+                                 double* norm_factor_host, hipStream_t st) {
+  if (!tr) return fail(AFQMC_ERR_ARG, "NULL trial");
+  afqmc_status s = check_walkers(tr, wk);
+  if (s != AFQMC_OK) return s;
+  const int W = wk->n_walkers;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t head = 256 + up((size_t)W * sizeof(int)) + up((size_t)W * sizeof(double));
+  if (!scratch || scratch_bytes < head + (size_t)W * sizeof(double))
+    return fail(AFQMC_ERR_ARG, "n_walkers too large for the scratch buffer");
+  double* norm = (double*)scratch;
+  int* parent = (int*)(scratch + 256);
+  double* cbuf = (double*)(scratch + 256 + up((size_t)W * sizeof(int)));
+  double* snap = (double*)(scratch + head);
+  const size_t snap_doubles = (scratch_bytes - head) / sizeof(double);
+  afqmc_ham* hm = tr->ham;
+  AFQ_CK(hipSetDevice(hm->device));
+  const WS ws = layout(tr, W, wk->workspace);
+  const long row = (long)hm->M * tr->Nt, G = hm->G;
+  // (no kernel timing here: its events may be created on demand)
+  AFQ_CK(afq::comb_parents(st, W, wk->weight, seed, pc_index, wk->system_id, cbuf, parent, norm));
+  struct Item { double* p; long row; };
+  const Item items[] = {{wk->phi_re, row},     {wk->phi_im, row},     {wk->logovlp_re, 1},
+                        {wk->logovlp_im, 1},   {wk->eloc_re, 1},      {wk->eloc_im, 1},
+                        {ws.v_re, G},          {ws.v_im, G}};
+  for (const Item& it : items)
+    AFQ_CK(afq::gather_rows_chunked(st, W, it.row, parent, it.p, snap, snap_doubles));
+  AFQ_CK(afq::comb_weights(st, W, norm, wk->weight));
+  if (norm_factor_host) {
+    AFQ_CK(hipMemcpyAsync(norm_factor_host, norm, sizeof(double), hipMemcpyDeviceToHost, st));
+    AFQ_CK(hipStreamSynchronize(st));
+    if (!(*norm_factor_host > 0.0))
+      return fail(AFQMC_ERR_NONFINITE, "comb: the sum of weights is not positive and finite");
+  }
+  return AFQMC_OK;
+}
+
+// Device of a trial (for callers outside this file).
+int trial_device(const afqmc_trial* tr) { return tr->ham->device; }
 }  // namespace afq
 
 extern "C" {

@@ -1954,6 +1954,39 @@ hipError_t gather_rows(hipStream_t st, int W, long row, const int* parent, const
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_snap_cols(long row, long c0, int cw,
+                                                   const double* __restrict__ src,
+                                                   double* __restrict__ snap) {
+  const long j = blockIdx.x;
+  for (int e = threadIdx.x; e < cw; e += blockDim.x) snap[j * cw + e] = src[j * row + c0 + e];
+}
+
+__global__ __launch_bounds__(256) void k_gather_cols(long row, long c0, int cw,
+                                                     const int* __restrict__ parent,
+                                                     const double* __restrict__ snap,
+                                                     double* __restrict__ dst) {
+  const long j = blockIdx.x;
+  const long p = parent[j];
+  for (int e = threadIdx.x; e < cw; e += blockDim.x) dst[j * row + c0 + e] = snap[p * cw + e];
+}
+
+hipError_t gather_rows_chunked(hipStream_t st, int W, long row, const int* parent,
+                               double* src_dst, double* snap, size_t snap_doubles) {
+  if (W < 1 || row < 1) return hipSuccess;
+  if (snap_doubles < (size_t)W) return hipErrorInvalidValue;
+  const long cw_max = (long)(snap_doubles / (size_t)W);
+  for (long c0 = 0; c0 < row; c0 += cw_max) {
+    const int cw = (int)std::min(cw_max, row - c0);
+    hipLaunchKernelGGL(k_snap_cols, dim3(W), dim3(256), 0, st, row, c0, cw, src_dst, snap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_cols, dim3(W), dim3(256), 0, st, row, c0, cw, parent, snap, src_dst);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Weights after the comb: 1, unless the comb found no positive finite total
 // (norm factor 0), in which case they stay as they are.
 __global__ void k_comb_weights(int W, const double* __restrict__ norm, double* __restrict__ weight) {

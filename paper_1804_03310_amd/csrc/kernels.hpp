@@ -118,6 +118,11 @@ hipError_t comb_weights(hipStream_t st, int W, const double* norm, double* weigh
 // Gather rows of length `row` doubles from src[parent[j]] to dst[j], for `nbuf` buffers.
 hipError_t gather_rows(hipStream_t st, int W, long row, const int* parent, const double* src,
                        double* dst);
+// The same gather through a snapshot of at most snap_doubles doubles
+// (>= W): column ranges of the rows are snapshotted and gathered in turn,
+// so src_dst is updated in place through a bounded buffer.
+hipError_t gather_rows_chunked(hipStream_t st, int W, long row, const int* parent,
+                               double* src_dst, double* snap, size_t snap_doubles);
 hipError_t fill(hipStream_t st, double* p, long n, double value);
 hipError_t broadcast_rows(hipStream_t st, int W, long row, const double* src, double* dst);
 
