@@ -216,6 +216,67 @@ afqmc_status afqmc_orthonormalize(afqmc_ham *ham, afqmc_trial *trial, afqmc_walk
 afqmc_status afqmc_reconfigure(afqmc_trial *trial, afqmc_walkers *walkers, uint64_t seed,
                                uint64_t pc_index, double *norm_factor_host, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Groups: the walkers of several systems (uneven M, N, n_chol, walker counts)
+ * propagated together, Sec. II's step for every walker of every member in
+ * one launch of the walker-resident kernel: one workgroup per walker keeps
+ * its orbitals, propagator, Taylor terms, overlap inverses and force bias in
+ * LDS for a segment of steps; the operators are shared through L2.  Each
+ * member's results are those of afqmc_propagate with the same arguments
+ * (same readings of the method, same fields) computed in FP64 whatever the
+ * options' precisions, and they are bitwise the same alone or in any group
+ * and for every launch shape (every sum is taken in an order fixed by the
+ * problem, not by the thread count).  A segment (steps, mixed energies,
+ * combs, step counter) is captured once as a HIP graph and replayed; combs
+ * fall at segment ends (segment length = gcd of the members' pc_every, else
+ * a free length), ortho inside the kernel.
+ * Limits: single-determinant trials, local-energy weights, M <= 64,
+ * N_sigma <= M, a walker's arrays within one CU's LDS
+ * (8 (8 M N + 2 M^2 + 12 n_chol) bytes, about; afqmc_resident_supported).
+ * The walker buffers of each member must keep their addresses while the
+ * group exists.  At most 64 members, all on one device. */
+typedef struct afqmc_group afqmc_group;
+typedef struct {
+  afqmc_ham *ham;
+  afqmc_trial *trial;
+  afqmc_walkers *walkers;
+  double dt;
+  uint64_t seed;
+  afqmc_options opt;
+} afqmc_group_member;
+
+/* *ok = 1 if the trial's system fits the walker-resident kernel. */
+afqmc_status afqmc_resident_supported(const afqmc_trial *trial, int *ok);
+
+/* Builds a group (B1 per member, device tables, comb buffers).  Launch shape:
+ * the tuning cache's entry for the group's shape signature (device, sorted
+ * member shapes, segment rule), else 256 threads per walker block. */
+afqmc_status afqmc_group_create(afqmc_group **out, int n_members,
+                                const afqmc_group_member *members, void *stream);
+
+/* n_steps steps of every member, global step indices step0 .. step0 +
+ * n_steps - 1 (one field stream per member: its seed and system_id).  The
+ * call first refreshes logovlp, eloc and the force-bias traces from phi.
+ * emix_dev (nullable) holds n_members device pointers (each nullable) that
+ * receive the member's E_mix after each step, as afqmc_propagate's emix_dev. */
+afqmc_status afqmc_group_propagate(afqmc_group *group, int n_steps, uint64_t step0,
+                                   double *const *emix_dev, void *stream);
+
+/* Autotuner: times `steps` steps (at least two segments) of the group for each
+ * launch shape (threads per walker block 64/128/256/512; segment length
+ * 10/20/50 when no member combs), from the same saved walker state each time,
+ * restores the state, keeps the fastest shape and writes it to the tuning
+ * cache (if a cache path is set).  us_per_step (nullable) gets its time. */
+afqmc_status afqmc_group_tune(afqmc_group *group, int steps, double *us_per_step, void *stream);
+afqmc_status afqmc_group_config(const afqmc_group *group, int *threads, int *segment_steps,
+                                int *tuned /* 0 default, 1 measured, 2 cached */);
+afqmc_status afqmc_group_set_config(afqmc_group *group, int threads, int segment_steps);
+void afqmc_free_group(afqmc_group *group);
+
+/* JSON file the autotuner reads and writes (NULL or "": none; default: the
+ * environment variable AFQMC_TUNE_CACHE). */
+afqmc_status afqmc_tune_cache_path(const char *path);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): the comb of
  * afqmc_reconfigure, same arguments and results (bitwise), with its scratch

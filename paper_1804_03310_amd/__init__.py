@@ -16,11 +16,12 @@ from typing import Optional
 import numpy as np
 
 from . import _abi
-from ._abi import AfqmcError, OptionsStruct, WalkersStruct, check
+from ._abi import AfqmcError, GroupMemberStruct, OptionsStruct, WalkersStruct, check
 
 __all__ = ["Hamiltonian", "Trial", "Walkers", "Options", "AfqmcError", "propagate",
            "local_energy", "orthonormalize", "reconfigure", "fields", "walkers_from_trial",
-           "timing_enable", "timing_read", "reblock", "cs_difference"]
+           "timing_enable", "timing_read", "reblock", "cs_difference", "Group", "GroupMember",
+           "resident_supported", "tune_cache_path"]
 
 _lib = _abi.load()
 
@@ -172,6 +173,81 @@ def propagate(ham: Hamiltonian, trial: Trial, w: Walkers, n_steps: int, dt: floa
                                int(seed), int(step0), ctypes.byref(o), emix.data_ptr(),
                                _stream_ptr(stream)))
     return emix
+
+
+@dataclass
+class GroupMember:
+    """One system of a group: its Hamiltonian, trial, walkers, time step,
+    field seed and options (afqmc_group_member)."""
+    ham: Hamiltonian
+    trial: Trial
+    walkers: Walkers
+    dt: float
+    seed: int
+    opt: Options
+
+
+def resident_supported(trial: Trial) -> bool:
+    ok = ctypes.c_int()
+    check(_lib.afqmc_resident_supported(trial._t, ctypes.byref(ok)))
+    return bool(ok.value)
+
+
+def tune_cache_path(path: Optional[str]) -> None:
+    check(_lib.afqmc_tune_cache_path(None if path is None else path.encode()))
+
+
+class Group:
+    """Several systems propagated together by the walker-resident kernel
+    (afqmc_group_*): one launch per segment of steps over every walker of
+    every member, each segment a replayed HIP graph."""
+
+    def __init__(self, members, stream=None):
+        self.members = list(members)
+        n = len(self.members)
+        self._structs = (GroupMemberStruct * n)()
+        for k, m in enumerate(self.members):
+            self._structs[k] = GroupMemberStruct(m.ham._h, m.trial._t, ctypes.pointer(m.walkers.struct),
+                                                 float(m.dt), int(m.seed), m.opt.struct())
+        out = ctypes.c_void_p()
+        check(_lib.afqmc_group_create(ctypes.byref(out), n, self._structs, _stream_ptr(stream)))
+        self._g = out
+
+    def propagate(self, n_steps: int, step0: int = 0, emix=None, stream=None):
+        """Enqueue n_steps steps of every member; returns the list of E_mix
+        device tensors (one per member, [n_steps])."""
+        torch = _torch()
+        if emix is None:
+            emix = [torch.empty(max(n_steps, 1), dtype=torch.float64, device=m.walkers.weight.device)
+                    for m in self.members]
+        ptrs = (ctypes.c_void_p * len(self.members))(
+            *[e.data_ptr() if e is not None else None for e in emix])
+        check(_lib.afqmc_group_propagate(self._g, int(n_steps), int(step0), ptrs, _stream_ptr(stream)))
+        return emix
+
+    def tune(self, steps: int = 40, stream=None) -> float:
+        us = ctypes.c_double()
+        check(_lib.afqmc_group_tune(self._g, int(steps), ctypes.byref(us), _stream_ptr(stream)))
+        return us.value
+
+    @property
+    def config(self):
+        """(threads per walker block, segment steps, tuned: 0 default / 1 measured / 2 cached)."""
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(_lib.afqmc_group_config(self._g, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def set_config(self, threads: int, segment_steps: int) -> None:
+        check(_lib.afqmc_group_set_config(self._g, int(threads), int(segment_steps)))
+
+    def __del__(self):
+        g = getattr(self, "_g", None)
+        if g and _lib is not None:
+            try:
+                _lib.afqmc_free_group(g)
+            except Exception:  # interpreter shutdown
+                pass
+            self._g = None
 
 
 def local_energy(ham: Hamiltonian, trial: Trial, w: Walkers, stream=None) -> float:

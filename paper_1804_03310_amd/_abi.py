@@ -30,6 +30,9 @@ EXPORTED = ["afqmc_init_hamiltonian", "afqmc_init_trial", "afqmc_walker_workspac
             "afqmc_timing_enable", "afqmc_timing_read", "afqmc_footprint_bytes",
             "afqmc_trial_exchange_route", "afqmc_trial_set_exchange_route",
             "afqmc_reblock", "afqmc_cs_difference", "afqmc_reconfigure_noalloc",
+            "afqmc_resident_supported", "afqmc_group_create", "afqmc_group_propagate",
+            "afqmc_group_tune", "afqmc_group_config", "afqmc_group_set_config",
+            "afqmc_free_group", "afqmc_tune_cache_path",
             "afqmc_free_hamiltonian", "afqmc_free_trial", "afqmc_last_error"]
 KERNEL_CLASSES = ["exchange", "propagator_build", "taylor_b1", "overlap_theta", "mgs", "comb",
                   "other", "force_bias"]
@@ -50,6 +53,11 @@ class OptionsStruct(ctypes.Structure):
 
 
 WEIGHT_MODES = {"local": 0, "hybrid": 1}
+
+
+class GroupMemberStruct(ctypes.Structure):
+    _fields_ = [("ham", c_void_p), ("trial", c_void_p), ("walkers", ctypes.POINTER(WalkersStruct)),
+                ("dt", c_double), ("seed", c_uint64), ("opt", OptionsStruct)]
 
 
 class AfqmcError(RuntimeError):
@@ -106,6 +114,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "afqmc_cs_difference": (c_int, [P, P, c_int, c_int, c_int, P, P]),
         "afqmc_timing_read": (c_int, [P, c_int, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(c_double)]),
+        "afqmc_resident_supported": (c_int, [P, ctypes.POINTER(c_int)]),
+        "afqmc_group_create": (c_int, [ctypes.POINTER(P), c_int, ctypes.POINTER(GroupMemberStruct), P]),
+        "afqmc_group_propagate": (c_int, [P, c_int, c_uint64, ctypes.POINTER(P), P]),
+        "afqmc_group_tune": (c_int, [P, c_int, ctypes.POINTER(c_double), P]),
+        "afqmc_group_config": (c_int, [P, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                       ctypes.POINTER(c_int)]),
+        "afqmc_group_set_config": (c_int, [P, c_int, c_int]),
+        "afqmc_free_group": (None, [P]),
+        "afqmc_tune_cache_path": (c_int, [ctypes.c_char_p]),
         "afqmc_free_hamiltonian": (None, [P]),
         "afqmc_free_trial": (None, [P]),
         "afqmc_last_error": (ctypes.c_char_p, []),

@@ -23,8 +23,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libafqmc.so")
 STAMP = LIB + ".sha256"
-SOURCES = ["kernels.hip", "qroute.hip", "multidet.hip", "bf16.hip", "noalloc.hip", "abi.cpp",
-           "stats.cpp"]
+SOURCES = ["kernels.hip", "qroute.hip", "multidet.hip", "bf16.hip", "resident.hip", "noalloc.hip",
+           "abi.cpp", "stats.cpp"]
 ARCH = os.environ.get("AFQMC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1490,3 +1490,496 @@ afqmc_status afqmc_fields(uint64_t seed, uint64_t t, int n_walkers, int n_chol, 
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Groups: walkers of several systems propagated together by the
+// walker-resident kernel (one workgroup per walker, a segment of steps per
+// launch), each segment [steps, mixed energies, combs, step counter]
+// captured once as a HIP graph and replayed; launch shape (threads per
+// walker block, segment length) from a small autotuner with a JSON cache.
+// ===========================================================================
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+
+#include "resident.hpp"
+
+struct afqmc_group {
+  int device = 0;
+  int n = 0;
+  std::vector<afqmc_group_member> members;
+  std::vector<afq::ResMember> h_mem;
+  afq::ResMember* d_mem = nullptr;
+  uint64_t* tdev = nullptr;
+  double* wsum = nullptr;
+  int wsum_K = 0;
+  int w_total = 0, w_max = 0;
+  size_t lds_bytes = 0;
+  int threads = 256;
+  int K = 20;
+  bool k_fixed = false;  // K = gcd of the members' comb intervals
+  int tuned = 0;         // 0: default shape, 1: measured, 2: from the cache
+  std::string signature;
+  hipStream_t cap = nullptr;  // private stream the segment graph is captured on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  Arena arena;
+};
+
+namespace {
+
+std::mutex g_tune_mu;
+std::string g_tune_path;
+bool g_tune_path_set = false;
+
+std::string tune_path() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!g_tune_path_set) {
+    const char* e = std::getenv("AFQMC_TUNE_CACHE");
+    if (e) g_tune_path = e;
+    g_tune_path_set = true;
+  }
+  return g_tune_path;
+}
+
+// The cache file: {"afqmc_tune": 1, "entries": {  one line per entry
+//   "<signature>": {"threads": T, "segment": K, "us_per_step": X},  ... }}
+struct TuneEntry { int threads = 0, segment = 0; double us = 0.0; };
+
+std::map<std::string, TuneEntry> tune_read(const std::string& path) {
+  std::map<std::string, TuneEntry> out;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t q0 = line.find('"');
+    const size_t q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+    const size_t br = q1 == std::string::npos ? q1 : line.find('{', q1);
+    if (br == std::string::npos) continue;
+    TuneEntry e;
+    if (std::sscanf(line.c_str() + br, "{\"threads\": %d, \"segment\": %d, \"us_per_step\": %lf",
+                    &e.threads, &e.segment, &e.us) == 3)
+      out[line.substr(q0 + 1, q1 - q0 - 1)] = e;
+  }
+  return out;
+}
+
+void tune_write(const std::string& path, const std::string& sig, const TuneEntry& e) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::map<std::string, TuneEntry> all = tune_read(path);
+  all[sig] = e;
+  const std::string tmp = path + ".tmp";
+  {
+    std::ofstream f(tmp);
+    f << "{\"afqmc_tune\": 1, \"entries\": {\n";
+    size_t i = 0;
+    for (const auto& kv : all) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "{\"threads\": %d, \"segment\": %d, \"us_per_step\": %.3f}",
+                    kv.second.threads, kv.second.segment, kv.second.us);
+      f << "\"" << kv.first << "\": " << buf << (++i < all.size() ? ",\n" : "\n");
+    }
+    f << "}}\n";
+  }
+  std::rename(tmp.c_str(), path.c_str());
+}
+
+// Whether a trial with these options can run in the resident kernel.
+afqmc_status resident_check(const afqmc_trial* tr, const afqmc_options* o, size_t* lds) {
+  const afqmc_ham* hm = tr->ham;
+  const int M = hm->M, Nt = tr->Nt;
+  if (tr->n_det != 1) return fail(AFQMC_ERR_UNSUPPORTED, "resident path: single-determinant trials only");
+  if (o && o->weight_mode != AFQMC_WEIGHT_LOCAL_ENERGY)
+    return fail(AFQMC_ERR_UNSUPPORTED, "resident path: local-energy weights only");
+  if (M > afq::kResMaxM || std::max(tr->nel[0], tr->nel[1]) > M)
+    return fail(AFQMC_ERR_UNSUPPORTED, "resident path: M <= 64 and N_sigma <= M");
+  const afq::ResLds Lo = afq::res_lds(M, Nt, hm->G);
+  const size_t bytes = (size_t)Lo.total * sizeof(double);
+  if (bytes > hm->max_lds)
+    return fail(AFQMC_ERR_UNSUPPORTED, "resident path: the walker does not fit one CU's LDS");
+  if (lds) *lds = bytes;
+  return AFQMC_OK;
+}
+
+void group_drop_graph(afqmc_group* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->exec = nullptr;
+  g->graph = nullptr;
+}
+
+afqmc_status group_segment(afqmc_group* g, int len, hipStream_t st) {
+  AFQ_CK(afq::res_steps(st, g->d_mem, g->n, g->w_total, g->threads, g->lds_bytes, g->tdev, len, 0,
+                        g->wsum));
+  AFQ_CK(afq::res_emix(st, g->d_mem, g->n, g->w_total, g->tdev, len, g->wsum));
+  AFQ_CK(afq::res_comb(st, g->d_mem, g->n, g->w_total, g->tdev, len, g->w_max));
+  AFQ_CK(afq::res_advance(st, g->tdev, len));
+  return AFQMC_OK;
+}
+
+afqmc_status group_run(afqmc_group* g, int n_steps, uint64_t step0, double* const* emix,
+                       hipStream_t st, bool use_graph) {
+  std::vector<double*> em(g->n, nullptr);
+  for (int m = 0; m < g->n; ++m) em[m] = emix ? emix[m] : nullptr;
+  AFQ_CK(afq::res_begin(st, g->d_mem, g->n, g->tdev, step0, em.data()));
+  // the call first refreshes log S, E_L and v from phi
+  AFQ_CK(afq::res_steps(st, g->d_mem, g->n, g->w_total, g->threads, g->lds_bytes, g->tdev, 0, 1,
+                        g->wsum));
+  int left = n_steps;
+  uint64_t t = step0;
+  if (g->k_fixed) {  // segments end where combs fall
+    const int head = (int)((g->K - (int)(t % (uint64_t)g->K)) % g->K);
+    const int h = std::min(head, left);
+    if (h > 0) {
+      afqmc_status s = group_segment(g, h, st);
+      if (s != AFQMC_OK) return s;
+      left -= h;
+      t += (uint64_t)h;
+    }
+  }
+  while (left >= g->K) {
+    if (use_graph) {
+      if (!g->exec) {
+        AFQ_CK(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+        afqmc_status s = group_segment(g, g->K, g->cap);
+        hipGraph_t gr = nullptr;
+        const hipError_t ec = hipStreamEndCapture(g->cap, &gr);
+        if (s != AFQMC_OK) {
+          if (gr) (void)hipGraphDestroy(gr);
+          return s;
+        }
+        AFQ_CK(ec);
+        g->graph = gr;
+        AFQ_CK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+      }
+      AFQ_CK(hipGraphLaunch(g->exec, st));
+    } else {
+      afqmc_status s = group_segment(g, g->K, st);
+      if (s != AFQMC_OK) return s;
+    }
+    left -= g->K;
+    t += (uint64_t)g->K;
+  }
+  if (left > 0) {
+    afqmc_status s = group_segment(g, left, st);
+    if (s != AFQMC_OK) return s;
+  }
+  return AFQMC_OK;
+}
+
+afqmc_status group_shape(afqmc_group* g, int threads, int K) {
+  if (threads < 64 || threads > 512 || threads % 64) return fail(AFQMC_ERR_ARG, "threads: 64..512, multiple of 64");
+  if (K < 1 || K > 1024) return fail(AFQMC_ERR_ARG, "segment steps: 1..1024");
+  if (g->k_fixed && K != g->K) return fail(AFQMC_ERR_ARG, "segment steps are fixed by the combs");
+  if (K > g->wsum_K) {
+    void* p = nullptr;
+    AFQ_CK(g->arena.alloc(&p, (size_t)K * g->w_total * 2 * sizeof(double)));
+    g->wsum = (double*)p;
+    g->wsum_K = K;
+  }
+  if (threads != g->threads || K != g->K) group_drop_graph(g);
+  g->threads = threads;
+  g->K = K;
+  return AFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+afqmc_status afqmc_tune_cache_path(const char* path) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_path = path ? path : "";
+  g_tune_path_set = true;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_resident_supported(const afqmc_trial* trial, int* ok) {
+  if (!trial || !ok) return fail(AFQMC_ERR_ARG, "NULL trial / ok");
+  *ok = resident_check(trial, nullptr, nullptr) == AFQMC_OK ? 1 : 0;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_group_create(afqmc_group** out, int n, const afqmc_group_member* mem,
+                                void* stream) {
+  if (!out || !mem || n < 1 || n > afq::kResMaxMembers)
+    return fail(AFQMC_ERR_ARG, "group: out, members and 1 <= n <= 64 required");
+  *out = nullptr;
+  int device = -1;
+  size_t lds = 0;
+  for (int m = 0; m < n; ++m) {
+    const afqmc_group_member& x = mem[m];
+    if (!x.ham || !x.trial || !x.walkers) return fail(AFQMC_ERR_ARG, "group member with a NULL object");
+    if (x.trial->ham != x.ham) return fail(AFQMC_ERR_STATE, "trial was built on another Hamiltonian");
+    if (device >= 0 && x.ham->device != device) return fail(AFQMC_ERR_ARG, "group members on several devices");
+    device = x.ham->device;
+    afqmc_status s = check_walkers(x.trial, x.walkers);
+    if (s != AFQMC_OK) return s;
+    const afqmc_options& o = x.opt;
+    if (!(x.dt > 0.0) || !std::isfinite(x.dt)) return fail(AFQMC_ERR_ARG, "dt must be positive");
+    if (o.taylor_order < 1 || o.taylor_order > 64) return fail(AFQMC_ERR_ARG, "taylor_order");
+    if (o.ortho_every < 0 || o.pc_every < 0) return fail(AFQMC_ERR_ARG, "negative interval");
+    if (!std::isfinite(o.e_trial)) return fail(AFQMC_ERR_ARG, "e_trial is not finite");
+    size_t l = 0;
+    s = resident_check(x.trial, &o, &l);
+    if (s != AFQMC_OK) return s;
+    lds = std::max(lds, l);
+    for (int k = 0; k < m; ++k)
+      if (mem[k].walkers->phi_re == x.walkers->phi_re || mem[k].walkers->workspace == x.walkers->workspace)
+        return fail(AFQMC_ERR_ARG, "two group members share walker buffers");
+  }
+  AFQ_CK(hipSetDevice(device));
+  hipStream_t st = (hipStream_t)stream;
+  afqmc_group* g = new afqmc_group();
+  g->device = device;
+  g->n = n;
+  g->members.assign(mem, mem + n);
+  g->lds_bytes = lds;
+  auto bad = [&](afqmc_status code, const std::string& what) {
+    group_drop_graph(g);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    g->arena.release();
+    delete g;
+    return fail(code, what);
+  };
+  int kg = 0;
+  std::ostringstream sig;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) sig << prop.gcnArchName;
+  }
+  sig << ";resident";
+  std::vector<std::string> shapes;
+  for (int m = 0; m < n; ++m) {
+    const afqmc_group_member& x = mem[m];
+    afqmc_trial* tr = x.trial;
+    afqmc_ham* hm = x.ham;
+    afqmc_status err = AFQMC_OK;
+    B1Entry* b1 = get_b1(tr, x.dt, st, &err);
+    if (!b1) return bad(err, g_err);
+    const int W = x.walkers->n_walkers;
+    const WS ws = layout(tr, W, x.walkers->workspace);
+    afq::ResMember r;
+    std::memset(&r, 0, sizeof r);
+    r.M = hm->M;
+    r.Nt = tr->Nt;
+    r.n0 = tr->nel[0];
+    r.n1 = tr->nel[1];
+    r.G = hm->G;
+    r.W = W;
+    r.wbase = g->w_total;
+    r.system_id = x.walkers->system_id;
+    r.ortho_every = x.opt.ortho_every;
+    r.pc_every = x.opt.pc_every;
+    r.MP4 = tr->MP4;
+    r.NP0 = tr->NP[0];
+    r.NP1 = tr->NP[1];
+    r.order = x.opt.taylor_order;
+    r.seed = x.seed;
+    r.dt = x.dt;
+    r.sqdt = std::sqrt(x.dt);
+    r.e_trial = x.opt.e_trial;
+    r.e_core = hm->e_core;
+    r.ref_ls_re = tr->ref_ls[0];
+    r.ref_ls_im = tr->ref_ls[1];
+    r.ref_el_re = tr->ref_el[0];
+    r.ref_el_im = tr->ref_el[1];
+    r.L = hm->L;
+    r.B1m = b1->d64;
+    r.D0 = tr->D0;
+    r.Lt0 = tr->Lt64[0];
+    r.Lt1 = tr->Lt64[1];
+    r.ht0 = tr->htil[0];
+    r.ht1 = tr->htil[1];
+    r.lbar = tr->lbar;
+    r.vref_re = tr->vref_re;
+    r.vref_im = tr->vref_im;
+    r.phi_re = x.walkers->phi_re;
+    r.phi_im = x.walkers->phi_im;
+    r.weight = x.walkers->weight;
+    r.ls_re = x.walkers->logovlp_re;
+    r.ls_im = x.walkers->logovlp_im;
+    r.el_re = x.walkers->eloc_re;
+    r.el_im = x.walkers->eloc_im;
+    r.v_re = ws.v_re;
+    r.v_im = ws.v_im;
+    void *ps = nullptr, *pp = nullptr, *pc = nullptr, *pn = nullptr;
+    const size_t row = 2 * (size_t)r.M * r.Nt + 4 + 2 * (size_t)r.G;
+    if (g->arena.alloc(&pn, 2 * sizeof(double)) ||
+        (r.pc_every > 0 && (g->arena.alloc(&ps, (size_t)W * row * sizeof(double)) ||
+                            g->arena.alloc(&pp, (size_t)W * sizeof(int)) ||
+                            g->arena.alloc(&pc, (size_t)W * sizeof(double)))))
+      return bad(AFQMC_ERR_OOM, "group allocation failed");
+    r.snap = (double*)ps;
+    r.parent = (int*)pp;
+    r.cbuf = (double*)pc;
+    r.comb_scal = (double*)pn;
+    if (hipMemsetAsync(pn, 0, 2 * sizeof(double), st) != hipSuccess)
+      return bad(AFQMC_ERR_DEVICE, "memset");
+    g->h_mem.push_back(r);
+    g->w_total += W;
+    g->w_max = std::max(g->w_max, W);
+    if (r.pc_every > 0) kg = std::gcd(kg, r.pc_every);
+    std::ostringstream s1;
+    s1 << r.M << "," << r.Nt << "," << r.G << "," << W << "," << r.order;
+    shapes.push_back(s1.str());
+  }
+  std::sort(shapes.begin(), shapes.end());
+  for (const auto& s1 : shapes) sig << "|" << s1;
+  g->k_fixed = kg > 0;
+  g->K = kg > 0 ? kg : 20;
+  sig << ";segment=" << (kg > 0 ? std::to_string(kg) : std::string("free"));
+  g->signature = sig.str();
+  void *pm = nullptr, *pt = nullptr;
+  if (g->arena.alloc(&pm, (size_t)n * sizeof(afq::ResMember)) || g->arena.alloc(&pt, 256))
+    return bad(AFQMC_ERR_OOM, "group allocation failed");
+  g->d_mem = (afq::ResMember*)pm;
+  g->tdev = (uint64_t*)pt;
+  if (hipMemcpyAsync(g->d_mem, g->h_mem.data(), (size_t)n * sizeof(afq::ResMember),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return bad(AFQMC_ERR_DEVICE, "group table upload");
+  if (hipStreamCreate(&g->cap) != hipSuccess) return bad(AFQMC_ERR_DEVICE, "capture stream");
+  // launch shape: the tuning cache's entry for this signature, else 256 threads
+  int thr = 256, K = g->K;
+  const std::string path = tune_path();
+  if (!path.empty()) {
+    const auto all = tune_read(path);
+    const auto it = all.find(g->signature);
+    if (it != all.end() && (!g->k_fixed || it->second.segment == g->K)) {
+      thr = it->second.threads;
+      K = it->second.segment;
+      g->tuned = 2;
+    }
+  }
+  g->threads = 0;
+  if (group_shape(g, thr, K) != AFQMC_OK) {
+    g->tuned = 0;
+    if (group_shape(g, 256, g->K) != AFQMC_OK) return bad(AFQMC_ERR_OOM, g_err);
+  }
+  *out = g;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_group_propagate(afqmc_group* g, int n_steps, uint64_t step0,
+                                  double* const* emix_dev, void* stream) {
+  if (!g) return fail(AFQMC_ERR_ARG, "NULL group");
+  if (n_steps < 0) return fail(AFQMC_ERR_ARG, "n_steps must be >= 0");
+  AFQ_CK(hipSetDevice(g->device));
+  return group_run(g, n_steps, step0, emix_dev, (hipStream_t)stream, true);
+}
+
+afqmc_status afqmc_group_config(const afqmc_group* g, int* threads, int* segment_steps, int* tuned) {
+  if (!g) return fail(AFQMC_ERR_ARG, "NULL group");
+  if (threads) *threads = g->threads;
+  if (segment_steps) *segment_steps = g->K;
+  if (tuned) *tuned = g->tuned;
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_group_set_config(afqmc_group* g, int threads, int segment_steps) {
+  if (!g) return fail(AFQMC_ERR_ARG, "NULL group");
+  AFQ_CK(hipSetDevice(g->device));
+  afqmc_status s = group_shape(g, threads, segment_steps);
+  if (s == AFQMC_OK) g->tuned = 0;
+  return s;
+}
+
+afqmc_status afqmc_group_tune(afqmc_group* g, int steps, double* us_per_step, void* stream) {
+  if (!g) return fail(AFQMC_ERR_ARG, "NULL group");
+  if (steps < 1) return fail(AFQMC_ERR_ARG, "steps must be >= 1");
+  AFQ_CK(hipSetDevice(g->device));
+  hipStream_t st = (hipStream_t)stream;
+  // save every member's walker state; candidates all run the same steps from it
+  struct Saved { double* p; const double* src; size_t n; };
+  std::vector<Saved> saved;
+  Arena tmp;
+  for (const afq::ResMember& r : g->h_mem) {
+    const size_t mn = (size_t)r.W * r.M * r.Nt, wg = (size_t)r.W * r.G;
+    const std::pair<const double*, size_t> bufs[] = {
+        {r.phi_re, mn}, {r.phi_im, mn}, {r.weight, (size_t)r.W}, {r.ls_re, (size_t)r.W},
+        {r.ls_im, (size_t)r.W}, {r.el_re, (size_t)r.W}, {r.el_im, (size_t)r.W}, {r.v_re, wg},
+        {r.v_im, wg}};
+    for (const auto& b : bufs) {
+      if (b.second == 0) continue;
+      void* p = nullptr;
+      if (tmp.alloc(&p, b.second * sizeof(double)) != hipSuccess) {
+        tmp.release();
+        return fail(AFQMC_ERR_OOM, "tuning snapshot");
+      }
+      saved.push_back({(double*)p, b.first, b.second});
+      if (hipMemcpyAsync(p, b.first, b.second * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        tmp.release();
+        return fail(AFQMC_ERR_DEVICE, "tuning snapshot copy");
+      }
+    }
+  }
+  auto restore = [&]() -> hipError_t {
+    for (const Saved& s : saved) {
+      const hipError_t e = hipMemcpyAsync((void*)s.src, s.p, s.n * 8, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  const int thr_c[] = {64, 128, 256, 512};
+  std::vector<int> k_c;
+  if (g->k_fixed) k_c.push_back(g->K);
+  else k_c = {10, 20, 50};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    tmp.release();
+    return fail(AFQMC_ERR_DEVICE, "tuning events");
+  }
+  double best = std::numeric_limits<double>::infinity();
+  int bt = g->threads, bk = g->K;
+  afqmc_status s = AFQMC_OK;
+  for (int K : k_c)
+    for (int thr : thr_c) {
+      s = group_shape(g, thr, K);
+      if (s != AFQMC_OK) break;
+      const int n = std::max(steps, 2 * K);
+      // one untimed pass (graph capture, caches), then the timed one
+      for (int pass = 0; pass < 2 && s == AFQMC_OK; ++pass) {
+        if (restore() != hipSuccess) { s = fail(AFQMC_ERR_DEVICE, "tuning restore"); break; }
+        if (pass == 1 && hipEventRecord(e0, st) != hipSuccess) { s = fail(AFQMC_ERR_DEVICE, "event"); break; }
+        s = group_run(g, n, 0, nullptr, st, true);
+        if (pass == 1 && s == AFQMC_OK) {
+          float ms = 0.f;
+          if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            s = fail(AFQMC_ERR_DEVICE, "tuning timing");
+            break;
+          }
+          const double us = 1e3 * ms / n;
+          if (us < best) { best = us; bt = thr; bk = K; }
+        }
+      }
+      if (s != AFQMC_OK) break;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const hipError_t re = restore();
+  const hipError_t se = hipStreamSynchronize(st);
+  tmp.release();
+  if (s != AFQMC_OK) return s;
+  if (re != hipSuccess || se != hipSuccess) return fail(AFQMC_ERR_DEVICE, "tuning restore");
+  s = group_shape(g, bt, bk);
+  if (s != AFQMC_OK) return s;
+  g->tuned = 1;
+  if (us_per_step) *us_per_step = best;
+  const std::string path = tune_path();
+  if (!path.empty()) tune_write(path, g->signature, TuneEntry{bt, bk, best});
+  return AFQMC_OK;
+}
+
+void afqmc_free_group(afqmc_group* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  group_drop_graph(g);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  g->arena.release();
+  delete g;
+}
+
+}  // extern "C"

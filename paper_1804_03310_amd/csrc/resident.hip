@@ -1,0 +1,759 @@
+// Walker-resident propagation (Sec. II step; walkers of several systems in
+// one launch).  One workgroup owns one walker for a segment of K timesteps:
+// its orbitals, propagator, Taylor terms, overlap inverses and force bias
+// live in LDS, and the operators (L_g, B1 - I, D_0, the half-rotated Ltil_g,
+// htil, lbar) are read from global memory, where every walker of the system
+// shares them through L2.  Each step is the one of the per-kernel chain:
+//   fields x (Philox4x64-10 + Box-Muller, counter (t, walker, g/4, system)),
+//   A = i sqrt(dt) sum_g (x_g - xbar_g) L_g with xbar = -i sqrt(dt)(v - lbar),
+//   phi <- B1 exp(A) B1 phi (Taylor series), S = D_0^T phi per spin with its
+//   inverse and log det (Gauss-Jordan, partial pivoting), Theta = phi S^-1,
+//   E_L = e_core + sum Tr(htil Theta) + 1/2 sum_g (sum_s Tr X)^2
+//         - 1/2 sum_s sum_g Tr(X X), X = Ltil_g Theta,
+//   the phaseless weight, the dead-walker reset, and MGS every ortho_every
+//   steps with log S recomputed.
+// All arithmetic is FP64.  Every sum is taken in an order fixed by the
+// problem (serial loops over a fixed index range, or per-item partials
+// summed serially), never by the thread count, so a walker's results are
+// bitwise the same for any block size and any group it runs in.
+#include <math.h>
+
+#include "common.hpp"
+#include "resident.hpp"
+
+namespace afq {
+
+namespace {
+
+// Member of walker block b (wave-uniform, so its fields are scalar loads).
+__device__ inline int res_find_member(const ResMember* mem, int n_mem, int b) {
+  int m = 0;
+  for (int k = 1; k < n_mem; ++k)
+    if (mem[k].wbase <= b) m = k;
+  return __builtin_amdgcn_readfirstlane(m);
+}
+
+// Out = In + B (In), B real [M][M] in global memory, In complex [M][Nt] in LDS.
+__device__ void res_apply_b1(int M, int Nt, const double* __restrict__ B, const double* Inr,
+                             const double* Ini, double* Outr, double* Outi) {
+  const int n = M * Nt;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int i = e / Nt, c = e - i * Nt;
+    const double* b = B + (long)i * M;
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < M; ++k) {
+      const double bk = b[k];
+      sr = fma(bk, Inr[k * Nt + c], sr);
+      si = fma(bk, Ini[k * Nt + c], si);
+    }
+    Outr[e] = Inr[e] + sr;
+    Outi[e] = Ini[e] + si;
+  }
+}
+
+// Out = alpha A In (A complex [M][M], In complex [M][Nt], all in LDS); Z += Out.
+__device__ void res_taylor_term(int M, int Nt, const double* Ar, const double* Ai,
+                                const double* Inr, const double* Ini, double* Outr, double* Outi,
+                                double* Zr, double* Zi, double alpha) {
+  const int n = M * Nt;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int i = e / Nt, c = e - i * Nt;
+    const double* ar = Ar + i * M;
+    const double* ai = Ai + i * M;
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < M; ++k) {
+      const double xr = Inr[k * Nt + c], xi = Ini[k * Nt + c];
+      sr = fma(ar[k], xr, sr);
+      sr = fma(-ai[k], xi, sr);
+      si = fma(ar[k], xi, si);
+      si = fma(ai[k], xr, si);
+    }
+    sr *= alpha;
+    si *= alpha;
+    Outr[e] = sr;
+    Outi[e] = si;
+    Zr[e] += sr;
+    Zi[e] += si;
+  }
+}
+
+// In-place inverse of an N x N complex matrix (row-major in LDS) by one
+// wavefront: Gauss-Jordan with partial pivoting (largest |S_ik|, lowest row
+// on ties), rows swapped explicitly, columns unscrambled at the end.  Returns
+// log det = sum log|pivot| + i arg(prod pivot / |pivot| * (-1)^swaps) in
+// every lane; non-finite when S is singular.
+__device__ zdbl res_gj_inverse(int N, double* Sr, double* Si) {
+  const int l = lane_id();
+  double lmag = 0.0, phr = 1.0, phi = 0.0;
+  int myp = l;  // lane k keeps the row swapped with row k at step k
+  for (int k = 0; k < N; ++k) {
+    double key = -1.0;
+    int idx = N;
+    if (l >= k && l < N) {
+      const double a = Sr[l * N + k], b = Si[l * N + k];
+      key = a * a + b * b;
+      idx = l;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double ok = __shfl_xor(key, o, AFQ_WAVE);
+      const int oi = __shfl_xor(idx, o, AFQ_WAVE);
+      if (ok > key || (ok == key && oi < idx)) { key = ok; idx = oi; }
+    }
+    const int p = __builtin_amdgcn_readfirstlane(idx < N ? idx : k);
+    if (l == k) myp = p;
+    if (p != k) {
+      for (int j = l; j < N; j += AFQ_WAVE) {
+        const double tr = Sr[k * N + j], ti = Si[k * N + j];
+        Sr[k * N + j] = Sr[p * N + j];
+        Si[k * N + j] = Si[p * N + j];
+        Sr[p * N + j] = tr;
+        Si[p * N + j] = ti;
+      }
+      phr = -phr;
+      phi = -phi;
+    }
+    wave_lds_sync();
+    const zdbl pv = {Sr[k * N + k], Si[k * N + k]};
+    const double mag = hypot(pv.re, pv.im);
+    lmag += log(mag);
+    {
+      const double ur = pv.re / mag, ui = pv.im / mag;
+      const double nr = phr * ur - phi * ui, ni = phr * ui + phi * ur;
+      phr = nr;
+      phi = ni;
+    }
+    const zdbl inv = zdiv(zdbl{1.0, 0.0}, pv);
+    wave_lds_sync();
+    for (int j = l; j < N; j += AFQ_WAVE) {
+      const zdbl x = (j == k) ? zdbl{1.0, 0.0} : zdbl{Sr[k * N + j], Si[k * N + j]};
+      const zdbl y = zmul(x, inv);
+      Sr[k * N + j] = y.re;
+      Si[k * N + j] = y.im;
+    }
+    wave_lds_sync();
+    if (l < N && l != k) {
+      const zdbl f = {Sr[l * N + k], Si[l * N + k]};
+      for (int j = 0; j < N; ++j) {
+        const zdbl x = (j == k) ? zdbl{0.0, 0.0} : zdbl{Sr[l * N + j], Si[l * N + j]};
+        const zdbl r = {Sr[k * N + j], Si[k * N + j]};
+        Sr[l * N + j] = x.re - (f.re * r.re - f.im * r.im);
+        Si[l * N + j] = x.im - (f.re * r.im + f.im * r.re);
+      }
+    }
+    wave_lds_sync();
+  }
+  for (int k = N - 1; k >= 0; --k) {
+    const int p = __builtin_amdgcn_readlane(myp, k);
+    if (p != k && l < N) {
+      const double tr = Sr[l * N + k], ti = Si[l * N + k];
+      Sr[l * N + k] = Sr[l * N + p];
+      Si[l * N + k] = Si[l * N + p];
+      Sr[l * N + p] = tr;
+      Si[l * N + p] = ti;
+    }
+    wave_lds_sync();
+  }
+  return zdbl{lmag, atan2(phi, phr)};
+}
+
+// log det of both spins' overlaps S = D_0^T phi, inverses left in Y (spin 0
+// at Y[0 .. n0^2), spin 1 after it).  Results in sc[0..3].
+__device__ void res_overlaps(const ResMember& P, const ResLds& Lo, double* sm) {
+  const int M = P.M, Nt = P.Nt;
+  const double* phr = sm + Lo.ph_r;
+  const double* phi = sm + Lo.ph_i;
+  double* Yr = sm + Lo.Y_r;
+  double* Yi = sm + Lo.Y_i;
+  const int n0 = P.n0, n1 = P.n1;
+  const int tot = n0 * n0 + n1 * n1;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int s = e < n0 * n0 ? 0 : 1;
+    const int N = s ? n1 : n0, off = s ? n0 : 0;
+    const int r = s ? e - n0 * n0 : e;
+    const int a = r / N, b = r - a * N;
+    double sr = 0.0, si = 0.0;
+    for (int m = 0; m < M; ++m) {
+      const double d = P.D0[m * Nt + off + a];
+      sr = fma(d, phr[m * Nt + off + b], sr);
+      si = fma(d, phi[m * Nt + off + b], si);
+    }
+    Yr[e] = sr;
+    Yi[e] = si;
+  }
+  __syncthreads();
+  const int wv = wave_id(), nwv = blockDim.x / AFQ_WAVE;
+  for (int s = 0; s < 2; ++s) {
+    const int N = s ? n1 : n0;
+    if (wv != (nwv > 1 ? s : 0)) continue;
+    zdbl ld = {0.0, 0.0};
+    if (N > 0) ld = res_gj_inverse(N, Yr + (s ? n0 * n0 : 0), Yi + (s ? n0 * n0 : 0));
+    if (lane_id() == 0) {
+      sm[Lo.sc + 2 * s] = ld.re;
+      sm[Lo.sc + 2 * s + 1] = ld.im;
+    }
+  }
+  __syncthreads();
+}
+
+// Theta = phi S^-1 into X; E1 = sum_s Tr(htil Theta); the force-bias traces
+// v'_g = sum_s Tr(Ltil_g Theta) into cf; E_K = -1/2 sum_s sum_g Tr(X X).
+// Leaves E_L in sc[4..5], log S (sum of spins) in sc[6..7] and the finite
+// flag of v' in sc[8].
+__device__ void res_measure(const ResMember& P, const ResLds& Lo, double* sm) {
+  const int M = P.M, Nt = P.Nt, G = P.G, n0 = P.n0, n1 = P.n1;
+  res_overlaps(P, Lo, sm);
+  const double* phr = sm + Lo.ph_r;
+  const double* phi = sm + Lo.ph_i;
+  double* Xr = sm + Lo.X_r;
+  double* Xi = sm + Lo.X_i;
+  const double* Yr = sm + Lo.Y_r;
+  const double* Yi = sm + Lo.Y_i;
+  // Theta[m][off + b] = sum_k phi[m][off + k] Sinv[k][b]
+  for (int e = threadIdx.x; e < M * Nt; e += blockDim.x) {
+    const int m = e / Nt, c = e - m * Nt;
+    const int s = c < n0 ? 0 : 1;
+    const int N = s ? n1 : n0, off = s ? n0 : 0, b = c - off;
+    const double* Sr = Yr + (s ? n0 * n0 : 0);
+    const double* Si = Yi + (s ? n0 * n0 : 0);
+    double tr = 0.0, ti = 0.0;
+    for (int k = 0; k < N; ++k) {
+      const double ar = phr[m * Nt + off + k], ai = phi[m * Nt + off + k];
+      const double br = Sr[k * N + b], bi = Si[k * N + b];
+      tr = fma(ar, br, tr);
+      tr = fma(-ai, bi, tr);
+      ti = fma(ar, bi, ti);
+      ti = fma(ai, br, ti);
+    }
+    Xr[e] = tr;
+    Xi[e] = ti;
+  }
+  __syncthreads();
+  // E1 partials per column (s, a): sum_m htil[a][m] Theta[m][off + a]
+  double* red = sm + Lo.red;
+  for (int c = threadIdx.x; c < Nt; c += blockDim.x) {
+    const int s = c < n0 ? 0 : 1;
+    const int a = c - (s ? n0 : 0);
+    const double* h = (s ? P.ht1 : P.ht0) + (long)a * M;
+    double er = 0.0, ei = 0.0;
+    for (int m = 0; m < M; ++m) {
+      er = fma(h[m], Xr[m * Nt + c], er);
+      ei = fma(h[m], Xi[m * Nt + c], ei);
+    }
+    red[2 * c] = er;
+    red[2 * c + 1] = ei;
+  }
+  // exchange per spin, X_g = Ltil_g Theta for a batch of g at a time in Z
+  double* Zr = sm + Lo.Z_r;
+  double* Zi = sm + Lo.Z_i;
+  double* trr = sm + Lo.tr_r;
+  double* tri = sm + Lo.tr_i;
+  double* xxr = sm + Lo.xx_r;
+  double* xxi = sm + Lo.xx_i;
+  const int G1 = G > 0 ? G : 1;
+  for (int s = 0; s < 2; ++s) {
+    const int N = s ? n1 : n0, off = s ? n0 : 0, NP = s ? P.NP1 : P.NP0;
+    const double* Lt = s ? P.Lt1 : P.Lt0;
+    if (N == 0) {
+      for (int g = threadIdx.x; g < G; g += blockDim.x) {
+        trr[s * G1 + g] = tri[s * G1 + g] = 0.0;
+        xxr[s * G1 + g] = xxi[s * G1 + g] = 0.0;
+      }
+      continue;
+    }
+    const int B = (M * Nt) / (N * N);
+    for (int g0 = 0; g0 < G; g0 += B) {
+      const int nb = min(B, G - g0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < nb * N * N; e += blockDim.x) {
+        const int gl = e / (N * N), r = e - gl * N * N;
+        const int a = r / N, b = r - a * N;
+        const double* lt = Lt + (long)(g0 + gl) * P.MP4 * NP + a;
+        double xr = 0.0, xi = 0.0;
+        for (int m = 0; m < M; ++m) {
+          const double l = lt[(long)m * NP];
+          xr = fma(l, Xr[m * Nt + off + b], xr);
+          xi = fma(l, Xi[m * Nt + off + b], xi);
+        }
+        Zr[e] = xr;
+        Zi[e] = xi;
+      }
+      __syncthreads();
+      for (int gl = threadIdx.x; gl < nb; gl += blockDim.x) {
+        const double* zr = Zr + gl * N * N;
+        const double* zi = Zi + gl * N * N;
+        double tr = 0.0, ti = 0.0, qr = 0.0, qi = 0.0;
+        for (int a = 0; a < N; ++a) {
+          tr += zr[a * N + a];
+          ti += zi[a * N + a];
+          for (int b = 0; b < N; ++b) {
+            const double ar = zr[a * N + b], ai = zi[a * N + b];
+            const double br = zr[b * N + a], bi = zi[b * N + a];
+            qr += ar * br - ai * bi;
+            qi += ar * bi + ai * br;
+          }
+        }
+        trr[s * G1 + g0 + gl] = tr;
+        tri[s * G1 + g0 + gl] = ti;
+        xxr[s * G1 + g0 + gl] = qr;
+        xxi[s * G1 + g0 + gl] = qi;
+      }
+    }
+  }
+  __syncthreads();
+  double* cfr = sm + Lo.cf_r;
+  double* cfi = sm + Lo.cf_i;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    cfr[g] = trr[g] + trr[G1 + g];
+    cfi[g] = tri[g] + tri[G1 + g];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e1r = 0.0, e1i = 0.0;
+    for (int c = 0; c < Nt; ++c) {
+      e1r += red[2 * c];
+      e1i += red[2 * c + 1];
+    }
+    double ejr = 0.0, eji = 0.0, ekr = 0.0, eki = 0.0;
+    int fin = 1;
+    for (int g = 0; g < G; ++g) {
+      const double vr = cfr[g], vi = cfi[g];
+      if (!isfinite(vr) || !isfinite(vi)) fin = 0;
+      ejr += vr * vr - vi * vi;
+      eji += 2.0 * vr * vi;
+    }
+    for (int s = 0; s < 2; ++s)
+      for (int g = 0; g < G; ++g) {
+        ekr += xxr[s * G1 + g];
+        eki += xxi[s * G1 + g];
+      }
+    double* sc = sm + Lo.sc;
+    sc[4] = P.e_core + e1r + 0.5 * ejr - 0.5 * ekr;
+    sc[5] = e1i + 0.5 * eji - 0.5 * eki;
+    sc[6] = sc[0] + sc[2];
+    sc[7] = sc[1] + sc[3];
+    sc[8] = fin ? 1.0 : 0.0;
+  }
+  __syncthreads();
+}
+
+// MGS of both spin blocks (one wavefront per spin, lane m owning row m),
+// positive real diagonal of R.
+__device__ void res_mgs(const ResMember& P, const ResLds& Lo, double* sm) {
+  const int M = P.M, Nt = P.Nt;
+  double* phr = sm + Lo.ph_r;
+  double* phi = sm + Lo.ph_i;
+  const int wv = wave_id(), nwv = blockDim.x / AFQ_WAVE, l = lane_id();
+  for (int s = 0; s < 2; ++s) {
+    if (wv != (nwv > 1 ? s : 0)) continue;
+    const int N = s ? P.n1 : P.n0, off = s ? P.n0 : 0;
+    for (int j = 0; j < N; ++j) {
+      double qr = l < M ? phr[l * Nt + off + j] : 0.0;
+      double qi = l < M ? phi[l * Nt + off + j] : 0.0;
+      const double nrm = sqrt(wave_sum(qr * qr + qi * qi));
+      const double inv = 1.0 / nrm;
+      qr *= inv;
+      qi *= inv;
+      if (l < M) {
+        phr[l * Nt + off + j] = qr;
+        phi[l * Nt + off + j] = qi;
+      }
+      for (int k = j + 1; k < N; ++k) {
+        double ar = l < M ? phr[l * Nt + off + k] : 0.0;
+        double ai = l < M ? phi[l * Nt + off + k] : 0.0;
+        const double rr = wave_sum(qr * ar + qi * ai);
+        const double ri = wave_sum(qr * ai - qi * ar);
+        ar -= rr * qr - ri * qi;
+        ai -= rr * qi + ri * qr;
+        if (l < M) {
+          phr[l * Nt + off + k] = ar;
+          phi[l * Nt + off + k] = ai;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(512) void k_res_steps(const ResMember* __restrict__ mem, int n_mem,
+                                                   int w_total, const uint64_t* __restrict__ tdev,
+                                                   int K, int refresh, double* __restrict__ wsum) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x;
+  const ResMember& P = mem[res_find_member(mem, n_mem, b)];
+  const int w = b - P.wbase;
+  const int M = P.M, Nt = P.Nt, G = P.G, mn = M * Nt;
+  const ResLds Lo = res_lds(M, Nt, G);
+  double* phr = sm + Lo.ph_r;
+  double* phi = sm + Lo.ph_i;
+  double* vr = sm + Lo.v_r;
+  double* vi = sm + Lo.v_i;
+  double* sc = sm + Lo.sc;
+  for (int e = threadIdx.x; e < mn; e += blockDim.x) {
+    phr[e] = P.phi_re[(long)w * mn + e];
+    phi[e] = P.phi_im[(long)w * mn + e];
+  }
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    vr[g] = P.v_re[(long)w * G + g];
+    vi[g] = P.v_im[(long)w * G + g];
+  }
+  // walker scalars: sc[16..21] = weight, log S (re, im), E_L (re, im)
+  if (threadIdx.x == 0) {
+    sc[16] = P.weight[w];
+    sc[17] = P.ls_re[w];
+    sc[18] = P.ls_im[w];
+    sc[19] = P.el_re[w];
+    sc[20] = P.el_im[w];
+  }
+  __syncthreads();
+  if (refresh) {
+    res_measure(P, Lo, sm);
+    for (int g = threadIdx.x; g < G; g += blockDim.x) {
+      vr[g] = sm[Lo.cf_r + g];
+      vi[g] = sm[Lo.cf_i + g];
+    }
+    if (threadIdx.x == 0) {
+      sc[17] = sc[6];
+      sc[18] = sc[7];
+      sc[19] = sc[4];
+      sc[20] = sc[5];
+    }
+    __syncthreads();
+  }
+  const uint64_t t0 = K > 0 ? *tdev : 0;
+  const double sq = P.sqdt;
+  double* cfr = sm + Lo.cf_r;
+  double* cfi = sm + Lo.cf_i;
+  double* red = sm + Lo.red;
+  double* Ar = sm + Lo.A_r;
+  double* Ai = sm + Lo.A_i;
+  double* Xr = sm + Lo.X_r;
+  double* Xi = sm + Lo.X_i;
+  double* Yr = sm + Lo.Y_r;
+  double* Yi = sm + Lo.Y_i;
+  double* Zr = sm + Lo.Z_r;
+  double* Zi = sm + Lo.Z_i;
+  for (int s = 0; s < K; ++s) {
+    const uint64_t t = t0 + (uint64_t)s;
+    // fields, shifted coefficients xs = x - xbar and the mean-field log factor
+    const int nq = (G + 3) / 4;
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+      double z[4];
+      gaussian4(P.seed, t, (uint64_t)w, (uint64_t)q, (uint64_t)P.system_id, z);
+      double pr = 0.0, pi = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int g = 4 * q + j;
+        if (g < G) {
+          const double lb = P.lbar[g];
+          const double xsr = z[j] - sq * vi[g];
+          const double xsi = sq * (vr[g] - lb);
+          cfr[g] = xsr;
+          cfi[g] = xsi;
+          pr += sq * xsi * lb;
+          pi += -sq * xsr * lb;
+        }
+      }
+      red[2 * q] = pr;
+      red[2 * q + 1] = pi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double mr = 0.0, mi = 0.0;
+      for (int q = 0; q < nq; ++q) {
+        mr += red[2 * q];
+        mi += red[2 * q + 1];
+      }
+      sc[10] = mr;
+      sc[11] = mi;
+    }
+    // A = i sq sum_g xs_g L_g (symmetric): upper triangle, mirrored
+    for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
+      const int i = e / M, j = e - i * M;
+      if (i > j) continue;
+      double ar = 0.0, ai = 0.0;
+      const double* l = P.L + e;
+      for (int g = 0; g < G; ++g) {
+        const double lv = l[(long)g * M * M];
+        ar = fma(cfi[g], lv, ar);
+        ai = fma(cfr[g], lv, ai);
+      }
+      ar *= -sq;
+      ai *= sq;
+      Ar[e] = ar;
+      Ai[e] = ai;
+      Ar[j * M + i] = ar;
+      Ai[j * M + i] = ai;
+    }
+    // X = B1 phi
+    res_apply_b1(M, Nt, P.B1m, phr, phi, Xr, Xi);
+    __syncthreads();
+    for (int e = threadIdx.x; e < mn; e += blockDim.x) {
+      Zr[e] = Xr[e];
+      Zi[e] = Xi[e];
+    }
+    __syncthreads();
+    double* cr = Xr;
+    double* ci = Xi;
+    double* nr = Yr;
+    double* ni = Yi;
+    for (int n = 1; n <= P.order; ++n) {
+      res_taylor_term(M, Nt, Ar, Ai, cr, ci, nr, ni, Zr, Zi, 1.0 / n);
+      __syncthreads();
+      double* tr = cr;
+      double* ti = ci;
+      cr = nr;
+      ci = ni;
+      nr = tr;
+      ni = ti;
+    }
+    // phi = B1 ACC
+    res_apply_b1(M, Nt, P.B1m, Zr, Zi, phr, phi);
+    __syncthreads();
+    res_measure(P, Lo, sm);
+    // phaseless weight (local-energy form), dead-walker reset
+    if (threadIdx.x == 0) {
+      const double er = sc[4], ei = sc[5];
+      const double lr = sc[6] - sc[17] + sc[10];
+      const double li = sc[7] - sc[18] + sc[11];
+      const double c = cos(li);
+      const double wn = sc[16] * exp(-P.dt * (er - P.e_trial)) * (c > 0.0 ? c : 0.0);
+      const bool ok = isfinite(wn) && isfinite(er) && isfinite(ei) && isfinite(lr) &&
+                      isfinite(li) && isfinite(sc[6]) && isfinite(sc[7]) && sc[8] != 0.0 &&
+                      wn > 0.0;
+      if (ok) {
+        sc[16] = wn;
+        sc[17] = sc[6];
+        sc[18] = sc[7];
+        sc[19] = er;
+        sc[20] = ei;
+      } else {
+        sc[16] = 0.0;
+        sc[17] = P.ref_ls_re;
+        sc[18] = P.ref_ls_im;
+        sc[19] = P.ref_el_re;
+        sc[20] = P.ref_el_im;
+      }
+      sc[12] = ok ? 1.0 : 0.0;
+      const long o = ((long)s * w_total + b) * 2;
+      wsum[o] = sc[16] * sc[19];
+      wsum[o + 1] = sc[16];
+    }
+    __syncthreads();
+    const bool alive = sc[12] != 0.0;
+    for (int g = threadIdx.x; g < G; g += blockDim.x) {
+      vr[g] = alive ? cfr[g] : P.vref_re[g];
+      vi[g] = alive ? cfi[g] : P.vref_im[g];
+    }
+    if (!alive)
+      for (int e = threadIdx.x; e < mn; e += blockDim.x) {
+        phr[e] = P.D0[e];
+        phi[e] = 0.0;
+      }
+    __syncthreads();
+    if (P.ortho_every > 0 && (t + 1) % (uint64_t)P.ortho_every == 0) {
+      res_mgs(P, Lo, sm);
+      res_overlaps(P, Lo, sm);
+      if (threadIdx.x == 0) {
+        sc[17] = sc[0] + sc[2];
+        sc[18] = sc[1] + sc[3];
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = threadIdx.x; e < mn; e += blockDim.x) {
+    P.phi_re[(long)w * mn + e] = phr[e];
+    P.phi_im[(long)w * mn + e] = phi[e];
+  }
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    P.v_re[(long)w * G + g] = vr[g];
+    P.v_im[(long)w * G + g] = vi[g];
+  }
+  if (threadIdx.x == 0) {
+    P.weight[w] = sc[16];
+    P.ls_re[w] = sc[17];
+    P.ls_im[w] = sc[18];
+    P.el_re[w] = sc[19];
+    P.el_im[w] = sc[20];
+  }
+}
+
+hipError_t res_steps(hipStream_t st, const ResMember* mem, int n_mem, int w_total, int threads,
+                     size_t lds_bytes, const uint64_t* tdev, int K, int refresh, double* wsum) {
+  if (w_total < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_res_steps, dim3(w_total), dim3(threads), lds_bytes, st, mem, n_mem, w_total,
+                     tdev, K, refresh, wsum);
+  return hipGetLastError();
+}
+
+// E_mix of every member and step of a segment: block (member, step), the
+// member's walkers summed in a fixed order (256 threads, block_sum).
+__global__ __launch_bounds__(256) void k_res_emix(const ResMember* __restrict__ mem, int w_total,
+                                                  const uint64_t* __restrict__ tdev,
+                                                  const double* __restrict__ wsum) {
+  __shared__ double red[4];
+  const ResMember& P = mem[blockIdx.x];
+  const int s = blockIdx.y;
+  if (!P.emix) return;
+  double num = 0.0, den = 0.0;
+  for (int w = threadIdx.x; w < P.W; w += blockDim.x) {
+    const long o = ((long)s * w_total + P.wbase + w) * 2;
+    num += wsum[o];
+    den += wsum[o + 1];
+  }
+  num = block_sum(num, red);
+  den = block_sum(den, red);
+  if (threadIdx.x == 0) P.emix[(long)(*tdev + (uint64_t)s - P.call_step0)] = num / den;
+}
+
+hipError_t res_emix(hipStream_t st, const ResMember* mem, int n_mem, int w_total,
+                    const uint64_t* tdev, int K, const double* wsum) {
+  if (K < 1 || n_mem < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_res_emix, dim3(n_mem, K), dim3(256), 0, st, mem, w_total, tdev, wsum);
+  return hipGetLastError();
+}
+
+// The systematic comb of a member whose comb falls at the end of the segment
+// (after step t with (t + 1) % pc_every == 0): one block per member, the same
+// algorithm as the single-system comb (left-to-right prefix sums in one
+// thread, tooth j at ((j + xi) W_tot) / K, first walker whose prefix exceeds
+// it); no teeth when W_tot is not positive and finite.
+__global__ __launch_bounds__(1024) void k_res_comb_parents(const ResMember* __restrict__ mem,
+                                                           const uint64_t* __restrict__ tdev,
+                                                           int K) {
+  __shared__ double sh[3];
+  __shared__ int last_sh;
+  const ResMember& P = mem[blockIdx.x];
+  const uint64_t tl = *tdev + (uint64_t)K - 1;
+  const bool due = P.pc_every > 0 && (tl + 1) % (uint64_t)P.pc_every == 0;
+  const int W = P.W;
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    int last = W - 1;
+    if (due)
+      for (int k = 0; k < W; ++k) {
+        const double wk = P.weight[k];
+        if (wk > 0.0) last = k;
+        acc = acc + wk;
+        P.cbuf[k] = acc;
+      }
+    const PhiloxOut r = philox4x64_10(tl, 0ull, 0ull, (uint64_t)P.system_id, P.seed, AFQ_STREAM_COMB);
+    sh[0] = acc;
+    sh[1] = u64_to_unit(r.w[0]);
+    sh[2] = (due && acc > 0.0 && isfinite(acc)) ? 1.0 : 0.0;
+    last_sh = last;
+    P.comb_scal[0] = due ? acc / (double)W : 0.0;
+    P.comb_scal[1] = sh[2];
+  }
+  __syncthreads();
+  if (sh[2] == 0.0) return;
+  const double wtot = sh[0], xi = sh[1];
+  const int last = last_sh;
+  for (int j = threadIdx.x; j < W; j += blockDim.x) {
+    const double zj = (((double)j + xi) * wtot) / (double)W;
+    int lo = 0, hi = W;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (P.cbuf[mid] > zj) hi = mid; else lo = mid + 1;
+    }
+    P.parent[j] = (lo < W) ? lo : last;
+  }
+}
+
+// Snapshot (phase 0) or gather from the parents (phase 1) of one walker of a
+// combing member: orbitals, log S, E_L and the force-bias traces.
+__global__ __launch_bounds__(256) void k_res_comb_move(const ResMember* __restrict__ mem, int n_mem,
+                                                       int phase) {
+  const int b = blockIdx.x;
+  const ResMember& P = mem[res_find_member(mem, n_mem, b)];
+  if (P.comb_scal[1] == 0.0) return;
+  const int w = b - P.wbase;
+  const long mn = (long)P.M * P.Nt, G = P.G, row = 2 * mn + 4 + 2 * G;
+  if (phase == 0) {
+    double* d = P.snap + w * row;
+    for (long e = threadIdx.x; e < mn; e += blockDim.x) {
+      d[e] = P.phi_re[w * mn + e];
+      d[mn + e] = P.phi_im[w * mn + e];
+    }
+    for (long g = threadIdx.x; g < G; g += blockDim.x) {
+      d[2 * mn + 4 + g] = P.v_re[w * G + g];
+      d[2 * mn + 4 + G + g] = P.v_im[w * G + g];
+    }
+    if (threadIdx.x == 0) {
+      d[2 * mn] = P.ls_re[w];
+      d[2 * mn + 1] = P.ls_im[w];
+      d[2 * mn + 2] = P.el_re[w];
+      d[2 * mn + 3] = P.el_im[w];
+    }
+  } else {
+    const double* s = P.snap + (long)P.parent[w] * row;
+    for (long e = threadIdx.x; e < mn; e += blockDim.x) {
+      P.phi_re[w * mn + e] = s[e];
+      P.phi_im[w * mn + e] = s[mn + e];
+    }
+    for (long g = threadIdx.x; g < G; g += blockDim.x) {
+      P.v_re[w * G + g] = s[2 * mn + 4 + g];
+      P.v_im[w * G + g] = s[2 * mn + 4 + G + g];
+    }
+    if (threadIdx.x == 0) {
+      P.ls_re[w] = s[2 * mn];
+      P.ls_im[w] = s[2 * mn + 1];
+      P.el_re[w] = s[2 * mn + 2];
+      P.el_im[w] = s[2 * mn + 3];
+      P.weight[w] = 1.0;
+    }
+  }
+}
+
+hipError_t res_comb(hipStream_t st, const ResMember* mem, int n_mem, int w_total,
+                    const uint64_t* tdev, int K, int w_max) {
+  if (K < 1 || n_mem < 1 || w_total < 1) return hipSuccess;
+  (void)w_max;
+  hipLaunchKernelGGL(k_res_comb_parents, dim3(n_mem), dim3(1024), 0, st, mem, tdev, K);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_res_comb_move, dim3(w_total), dim3(256), 0, st, mem, n_mem, 0);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_res_comb_move, dim3(w_total), dim3(256), 0, st, mem, n_mem, 1);
+  return hipGetLastError();
+}
+
+__global__ void k_res_advance(uint64_t* tdev, int K) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *tdev += (uint64_t)K;
+}
+
+hipError_t res_advance(hipStream_t st, uint64_t* tdev, int K) {
+  hipLaunchKernelGGL(k_res_advance, dim3(1), dim3(64), 0, st, tdev, K);
+  return hipGetLastError();
+}
+
+struct ResCallArgs {
+  uint64_t step0;
+  int n_mem;
+  double* emix[kResMaxMembers];
+};
+
+__global__ void k_res_begin(ResMember* mem, uint64_t* tdev, ResCallArgs a) {
+  const int m = threadIdx.x;
+  if (m < a.n_mem) {
+    mem[m].call_step0 = a.step0;
+    mem[m].emix = a.emix[m];
+  }
+  if (m == 0) *tdev = a.step0;
+}
+
+hipError_t res_begin(hipStream_t st, ResMember* mem, int n_mem, uint64_t* tdev, uint64_t step0,
+                     double* const* emix) {
+  if (n_mem < 1 || n_mem > kResMaxMembers) return hipErrorInvalidValue;
+  ResCallArgs a;
+  a.step0 = step0;
+  a.n_mem = n_mem;
+  for (int m = 0; m < kResMaxMembers; ++m) a.emix[m] = m < n_mem ? emix[m] : nullptr;
+  hipLaunchKernelGGL(k_res_begin, dim3(1), dim3(kResMaxMembers), 0, st, mem, tdev, a);
+  return hipGetLastError();
+}
+
+}  // namespace afq
