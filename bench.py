@@ -83,6 +83,33 @@ def multidet_flops_per_walker(M, n_up, n_dn, G):
     return sum((G + 1) * (4 * M * M * n + 8 * n ** 3) for n in (n_up, n_dn) if n)
 
 
+def resident_flops_per_walker(M, n_up, n_dn, G, order):
+    """Algorithmic flops of one walker-step of the walker-resident kernel
+    (real flops, complex walkers): A = sum_g c_g L_g, complex coefficients
+    times real M x M (4 M^2 G); B1 twice and `order` Taylor terms
+    ((8 order + 8) M^2 Nt); per spin the overlap D_0^T phi (4 M N^2), its
+    inverse (8 N^3) and Theta = phi S^-1 (8 M N^2); per spin and g the
+    exchange X = Ltil_g Theta (4 N^2 M) and Tr(X X) (8 N^2)."""
+    Nt = n_up + n_dn
+    f = 4 * M * M * G + (8 * order + 8) * M * M * Nt
+    for n in (n_up, n_dn):
+        f += 4 * M * n * n + 8 * n ** 3 + 8 * M * n * n + G * (4 * n * n * M + 8 * n * n)
+    return f
+
+
+# Systems of a batched group: (label, M, n_up, n_dn, n_chol, walkers, tau_d,
+# health-scaled, ortho_every, pc_every, hamiltonian seed, field seed, system id).
+# The two M = 12 members are a neutral / cation correlated-sampling pair on
+# one Hamiltonian sharing one field stream (same seed and system id).
+BATCHED_MIX = [
+    ("plain-M10", 10, 5, 5, 40, 64, 8.0, False, 2, 0, 0, 0, 0),
+    ("M12-neutral", 12, 6, 6, 36, 512, 8.0, False, 2, 0, 12, 11, 1),
+    ("M12-cation", 12, 6, 5, 36, 512, 8.0, False, 2, 0, 12, 11, 1),
+    ("M8", 8, 4, 4, 24, 256, 8.0, False, 2, 20, 8, 12, 2),
+    ("M14", 14, 4, 3, 30, 33, 8.0, False, 3, 20, 14, 13, 3),
+]
+
+
 GOLDEN = {"hchain-M50": ("hchain-M50_W1024_T100.txt", 1024, 100, 1)}
 
 TRAFFIC = {("hchain-M50", "exchange"): "hchain-M50_qform_traffic.json",
@@ -295,6 +322,128 @@ def precision_report(args):
     print(json.dumps(out), flush=True)
 
 
+def group_bench(args):
+    """Walker-resident group path (afqmc_group_*): several systems in one
+    launch per segment, segments replayed as HIP graphs.  --workload W with
+    --path resident runs that workload's system as a group of one; --batched
+    runs the uneven BATCHED_MIX group.  Reports walker-steps/s over all
+    members, the resident kernel's roofline (algorithmic flops per launch over
+    its HIP-event-timed average duration against the FP64 peak: the kernel
+    computes in FP64 on the vector ALUs, whose peak equals the FP64 matrix
+    peak), the same members run one after the other through the per-kernel
+    chain, and (batched) each member's E_mix alone vs in the group."""
+    import torch
+
+    import afqmc_synth as syn
+    import paper_1804_03310_amd as afq
+
+    torch.cuda.set_device(0)
+    if args.tune_cache:
+        afq.tune_cache_path(args.tune_cache)
+    if args.batched:
+        spec = BATCHED_MIX
+        name = "batched-mix"
+    else:
+        wl = syn.WORKLOADS[args.workload]
+        spec = [(wl.name, wl.M, wl.n_up, wl.n_dn, wl.n_chol, args.walkers or wl.n_walkers, wl.tau_d,
+                 wl.l_scale != 1.0, wl.ortho_every, wl.pc_every, wl.ham_seed, wl.field_seed, 0)]
+        name = wl.name
+    systems = {}
+
+    def system(M, nu, nd, G, tau, scaled, hseed):
+        key = (M, G, tau, scaled, hseed)
+        if key not in systems:
+            systems[key] = syn.make_system(M, nu, nu, G, tau, seed=hseed,
+                                           l_scale=syn.health_scale(M) if scaled else 1.0)
+        return systems[key]
+
+    def members():
+        out = []
+        for (lab, M, nu, nd, G, W, tau, scaled, oe, pc, hseed, fseed, sid) in spec:
+            inp = system(M, nu, nd, G, tau, scaled, hseed)
+            ham = afq.Hamiltonian(inp.h, inp.L, inp.e_core)
+            trial = afq.Trial(ham, nu, nd, inp.C_up, inp.C_dn)
+            w = afq.Walkers(trial, W, system_id=sid)
+            afq.walkers_from_trial(ham, trial, w)
+            et = afq.local_energy(ham, trial, w)
+            opt = afq.Options(taylor_order=6, ortho_every=oe, pc_every=pc, e_trial=et,
+                              chol_prec="fp64", taylor_prec="fp64")
+            out.append(afq.GroupMember(ham, trial, w, 0.005, fseed, opt))
+        return out
+
+    mem = members()
+    g = afq.Group(mem)
+    tuned_us = g.tune(steps=max(2 * g.config[1], 40)) if args.tune else None
+    threads, K, tuned = g.config
+    n_ws = sum(m.walkers.n_walkers for m in mem)
+    if args.warmup:
+        g.propagate(args.warmup, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    em = g.propagate(args.steps, args.warmup)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    e_last = [float(e[args.steps - 1].item()) for e in em]
+    # kernel timing pass (direct launches with events) for the roofline
+    g.timing(True)
+    g.propagate(args.steps, args.warmup + args.steps)
+    torch.cuda.synchronize()
+    n_l, n_s, ms = g.timing_read()
+    g.timing(False)
+    flops_step = sum(resident_flops_per_walker(m.ham.M, m.trial.n_up, m.trial.n_dn,
+                                               m.ham.n_chol, m.opt.taylor_order)
+                     * m.walkers.n_walkers for m in mem)
+    per_launch = flops_step * n_s / max(n_l, 1)
+    avg_s = ms / max(n_l, 1) / 1e3
+    ach = per_launch / avg_s / 1e12 if n_l else float("nan")
+    # the same members, one after the other, through the per-kernel chain
+    cm = members()
+    for m in cm:
+        afq.propagate(m.ham, m.trial, m.walkers, args.warmup, m.dt, m.seed, 0, m.opt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for m in cm:
+        afq.propagate(m.ham, m.trial, m.walkers, args.steps, m.dt, m.seed, args.warmup, m.opt)
+    torch.cuda.synchronize()
+    chain_s = time.perf_counter() - t1
+    same = None
+    if args.batched:
+        same = True
+        fresh = members()
+        gm = afq.Group(fresh)
+        ref = [e.cpu().numpy() for e in gm.propagate(args.steps, 0)]
+        for k in range(len(fresh)):
+            one = members()[k]
+            e1 = afq.Group([one]).propagate(args.steps, 0)[0].cpu().numpy()
+            same = same and bool(np.array_equal(e1, ref[k]))
+    value = n_ws * args.steps / elapsed
+    out = {"metric": "walker-steps/sec on 1 MI355X, walker-resident group path (FP64)",
+           "value": value, "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / max(args.steps, 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": name, "members": [
+               {"label": x[0], "M": x[1], "n_up": x[2], "n_dn": x[3], "n_chol": x[4],
+                "walkers": x[5], "ortho_every": x[8], "pc_every": x[9], "system_id": x[12]}
+               for x in spec],
+               "launch": {"threads_per_walker": threads, "segment_steps": K,
+                          "tuned": ["default", "measured", "cache"][tuned], "tune_us_per_step": tuned_us},
+               "e_mix_last": e_last},
+           "roofline": {"bound": "fp64", "kernel": "k_res_steps (walker-resident, one workgroup "
+                        "per walker, a segment of steps per launch)",
+                        "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                        "flops_per_launch": per_launch, "avg_launch_ms": avg_s * 1e3,
+                        "launches": n_l, "steps_per_launch": n_s / max(n_l, 1)},
+           "per_kernel_chain": {"value": n_ws * args.steps / chain_s,
+                                "ms_per_step": 1e3 * chain_s / max(args.steps, 1),
+                                "note": "the same members run one after the other through "
+                                        "afqmc_propagate's per-kernel chain, FP64"},
+           "speedup_vs_chain": chain_s / elapsed,
+           "alone_vs_group_bitwise": same}
+    print(json.dumps(out), flush=True)
+
+
 def cs_report(args):
     """Correlated sampling (Sec. I, Sec. V) on the hydrogen-chain workload:
     the neutral system (N_up = N_dn) and its cation (one down electron fewer)
@@ -456,6 +605,13 @@ def main():
     ap.add_argument("--cs-walkers", type=int, default=256)
     ap.add_argument("--cs-steps", type=int, default=100)
     ap.add_argument("--cs-long-steps", type=int, default=1000)
+    ap.add_argument("--path", choices=["chain", "resident"], default="chain",
+                    help="per-kernel chain (afqmc_propagate) or the walker-resident group "
+                         "kernel (afqmc_group_*, FP64, systems up to M = 64)")
+    ap.add_argument("--batched", action="store_true",
+                    help="a group of uneven systems in one resident launch per segment")
+    ap.add_argument("--tune", action="store_true", help="autotune the group's launch shape first")
+    ap.add_argument("--tune-cache", default="", help="JSON file of the autotuner's choices")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise copy of 256 MiB (reads 256 MiB, writes "
                          "256 MiB) so that HBM byte counters can be scaled")
@@ -474,6 +630,9 @@ def main():
         return
     if args.cs:
         cs_report(args)
+        return
+    if args.batched or args.path == "resident":
+        group_bench(args)
         return
 
     import torch

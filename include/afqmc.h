@@ -231,8 +231,11 @@ afqmc_status afqmc_reconfigure(afqmc_trial *trial, afqmc_walkers *walkers, uint6
  * fall at segment ends (segment length = gcd of the members' pc_every, else
  * a free length), ortho inside the kernel.
  * Limits: single-determinant trials, local-energy weights, M <= 64,
- * N_sigma <= M, a walker's arrays within one CU's LDS
- * (8 (8 M N + 2 M^2 + 12 n_chol) bytes, about; afqmc_resident_supported).
+ * N_sigma <= M, and a walker's arrays plus the system's operators (L, Ltil,
+ * B1, D_0, htil, lbar, staged in LDS once per segment) within one CU's LDS:
+ * about 8 (n_chol (M^2 + M N) + 3 M^2 + 10 M N + 14 n_chol) bytes with
+ * N = N_up + N_dn, so tiny systems (M = 10, N = 10, 40 vectors: 77 KB;
+ * afqmc_resident_supported tells). 
  * The walker buffers of each member must keep their addresses while the
  * group exists.  At most 64 members, all on one device. */
 typedef struct afqmc_group afqmc_group;
@@ -271,6 +274,13 @@ afqmc_status afqmc_group_tune(afqmc_group *group, int steps, double *us_per_step
 afqmc_status afqmc_group_config(const afqmc_group *group, int *threads, int *segment_steps,
                                 int *tuned /* 0 default, 1 measured, 2 cached */);
 afqmc_status afqmc_group_set_config(afqmc_group *group, int threads, int segment_steps);
+/* Kernel timing of the resident kernel: while enabled, segments are launched
+ * directly (not as graphs) with HIP events around each resident launch on
+ * the call's stream; timing_read (synchronises) returns and clears the
+ * launches, the steps they covered and their total time. */
+afqmc_status afqmc_group_timing(afqmc_group *group, int enable);
+afqmc_status afqmc_group_timing_read(afqmc_group *group, int64_t *launches, int64_t *steps,
+                                     double *total_ms);
 void afqmc_free_group(afqmc_group *group);
 
 /* JSON file the autotuner reads and writes (NULL or "": none; default: the

@@ -240,6 +240,17 @@ class Group:
     def set_config(self, threads: int, segment_steps: int) -> None:
         check(_lib.afqmc_group_set_config(self._g, int(threads), int(segment_steps)))
 
+    def timing(self, enable: bool) -> None:
+        """Time the resident launches with HIP events (segments then launch
+        directly, not as graphs)."""
+        check(_lib.afqmc_group_timing(self._g, 1 if enable else 0))
+
+    def timing_read(self):
+        """(launches, steps covered, total ms) of the timed resident launches; clears them."""
+        n, s, ms = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        check(_lib.afqmc_group_timing_read(self._g, ctypes.byref(n), ctypes.byref(s), ctypes.byref(ms)))
+        return n.value, s.value, ms.value
+
     def __del__(self):
         g = getattr(self, "_g", None)
         if g and _lib is not None:

@@ -32,7 +32,8 @@ EXPORTED = ["afqmc_init_hamiltonian", "afqmc_init_trial", "afqmc_walker_workspac
             "afqmc_reblock", "afqmc_cs_difference", "afqmc_reconfigure_noalloc",
             "afqmc_resident_supported", "afqmc_group_create", "afqmc_group_propagate",
             "afqmc_group_tune", "afqmc_group_config", "afqmc_group_set_config",
-            "afqmc_free_group", "afqmc_tune_cache_path",
+            "afqmc_free_group", "afqmc_tune_cache_path", "afqmc_group_timing",
+            "afqmc_group_timing_read",
             "afqmc_free_hamiltonian", "afqmc_free_trial", "afqmc_last_error"]
 KERNEL_CLASSES = ["exchange", "propagator_build", "taylor_b1", "overlap_theta", "mgs", "comb",
                   "other", "force_bias"]
@@ -122,6 +123,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(c_int)]),
         "afqmc_group_set_config": (c_int, [P, c_int, c_int]),
         "afqmc_free_group": (None, [P]),
+        "afqmc_group_timing": (c_int, [P, c_int]),
+        "afqmc_group_timing_read": (c_int, [P, ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(c_double)]),
         "afqmc_tune_cache_path": (c_int, [ctypes.c_char_p]),
         "afqmc_free_hamiltonian": (None, [P]),
         "afqmc_free_trial": (None, [P]),

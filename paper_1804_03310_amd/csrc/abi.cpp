@@ -1525,6 +1525,10 @@ struct afqmc_group {
   hipStream_t cap = nullptr;  // private stream the segment graph is captured on
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // kernel timing of the resident launches (direct launches, no graph, while on)
+  KernelTimer timer;
+  bool timing = false;
+  int64_t timed_steps = 0;
   Arena arena;
 };
 
@@ -1594,7 +1598,7 @@ afqmc_status resident_check(const afqmc_trial* tr, const afqmc_options* o, size_
     return fail(AFQMC_ERR_UNSUPPORTED, "resident path: local-energy weights only");
   if (M > afq::kResMaxM || std::max(tr->nel[0], tr->nel[1]) > M)
     return fail(AFQMC_ERR_UNSUPPORTED, "resident path: M <= 64 and N_sigma <= M");
-  const afq::ResLds Lo = afq::res_lds(M, Nt, hm->G);
+  const afq::ResLds Lo = afq::res_lds(M, Nt, hm->G, std::max(tr->nel[0], tr->nel[1]));
   const size_t bytes = (size_t)Lo.total * sizeof(double);
   if (bytes > hm->max_lds)
     return fail(AFQMC_ERR_UNSUPPORTED, "resident path: the walker does not fit one CU's LDS");
@@ -1610,8 +1614,12 @@ void group_drop_graph(afqmc_group* g) {
 }
 
 afqmc_status group_segment(afqmc_group* g, int len, hipStream_t st) {
-  AFQ_CK(afq::res_steps(st, g->d_mem, g->n, g->w_total, g->threads, g->lds_bytes, g->tdev, len, 0,
-                        g->wsum));
+  {
+    TimedLaunch tl(g->timing ? &g->timer : nullptr, 0, st);
+    AFQ_CK(afq::res_steps(st, g->d_mem, g->n, g->w_total, g->threads, g->lds_bytes, g->tdev, len,
+                          0, g->wsum));
+  }
+  if (g->timing) g->timed_steps += len;
   AFQ_CK(afq::res_emix(st, g->d_mem, g->n, g->w_total, g->tdev, len, g->wsum));
   AFQ_CK(afq::res_comb(st, g->d_mem, g->n, g->w_total, g->tdev, len, g->w_max));
   AFQ_CK(afq::res_advance(st, g->tdev, len));
@@ -1867,7 +1875,29 @@ afqmc_status afqmc_group_propagate(afqmc_group* g, int n_steps, uint64_t step0,
   if (!g) return fail(AFQMC_ERR_ARG, "NULL group");
   if (n_steps < 0) return fail(AFQMC_ERR_ARG, "n_steps must be >= 0");
   AFQ_CK(hipSetDevice(g->device));
-  return group_run(g, n_steps, step0, emix_dev, (hipStream_t)stream, true);
+  return group_run(g, n_steps, step0, emix_dev, (hipStream_t)stream, !g->timing);
+}
+
+afqmc_status afqmc_group_timing(afqmc_group* g, int enable) {
+  if (!g) return fail(AFQMC_ERR_ARG, "NULL group");
+  g->timing = enable != 0;
+  g->timer.mask = g->timing ? 1u : 0u;
+  if (g->timing) g->timer.reserve(512);
+  return AFQMC_OK;
+}
+
+afqmc_status afqmc_group_timing_read(afqmc_group* g, int64_t* launches, int64_t* steps,
+                                     double* total_ms) {
+  if (!g || !launches || !steps || !total_ms) return fail(AFQMC_ERR_ARG, "NULL argument");
+  AFQ_CK(hipSetDevice(g->device));
+  AFQ_CK(g->timer.drain());
+  *launches = g->timer.count[0];
+  *total_ms = g->timer.total_ms[0];
+  *steps = g->timed_steps;
+  g->timer.count[0] = 0;
+  g->timer.total_ms[0] = 0.0;
+  g->timed_steps = 0;
+  return AFQMC_OK;
 }
 
 afqmc_status afqmc_group_config(const afqmc_group* g, int* threads, int* segment_steps, int* tuned) {

@@ -1,9 +1,11 @@
 // Walker-resident propagation (Sec. II step; walkers of several systems in
 // one launch).  One workgroup owns one walker for a segment of K timesteps:
 // its orbitals, propagator, Taylor terms, overlap inverses and force bias
-// live in LDS, and the operators (L_g, B1 - I, D_0, the half-rotated Ltil_g,
-// htil, lbar) are read from global memory, where every walker of the system
-// shares them through L2.  Each step is the one of the per-kernel chain:
+// live in LDS, and so do the system's operators (L_g, B1 - I, D_0, the
+// half-rotated Ltil_g, htil, lbar), staged once per segment from global
+// memory (the kernel is for tiny systems, whose walker steps are too small to
+// fill the chip one kernel launch per sub-step: the latency-bound regime).
+// Each step is the one of the per-kernel chain:
 //   fields x (Philox4x64-10 + Box-Muller, counter (t, walker, g/4, system)),
 //   A = i sqrt(dt) sum_g (x_g - xbar_g) L_g with xbar = -i sqrt(dt)(v - lbar),
 //   phi <- B1 exp(A) B1 phi (Taylor series), S = D_0^T phi per spin with its
@@ -33,14 +35,15 @@ __device__ inline int res_find_member(const ResMember* mem, int n_mem, int b) {
   return __builtin_amdgcn_readfirstlane(m);
 }
 
-// Out = In + B (In), B real [M][M] in global memory, In complex [M][Nt] in LDS.
-__device__ void res_apply_b1(int M, int Nt, const double* __restrict__ B, const double* Inr,
+// Out = In + B (In), B real [M][M], In complex [M][Nt], all in LDS.
+__device__ void res_apply_b1(int M, int Nt, const double* B, const double* Inr,
                              const double* Ini, double* Outr, double* Outi) {
   const int n = M * Nt;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int i = e / Nt, c = e - i * Nt;
     const double* b = B + (long)i * M;
     double sr = 0.0, si = 0.0;
+#pragma unroll 4
     for (int k = 0; k < M; ++k) {
       const double bk = b[k];
       sr = fma(bk, Inr[k * Nt + c], sr);
@@ -61,6 +64,7 @@ __device__ void res_taylor_term(int M, int Nt, const double* Ar, const double* A
     const double* ar = Ar + i * M;
     const double* ai = Ai + i * M;
     double sr = 0.0, si = 0.0;
+#pragma unroll 4
     for (int k = 0; k < M; ++k) {
       const double xr = Inr[k * Nt + c], xi = Ini[k * Nt + c];
       sr = fma(ar[k], xr, sr);
@@ -81,11 +85,15 @@ __device__ void res_taylor_term(int M, int Nt, const double* Ar, const double* A
 // wavefront: Gauss-Jordan with partial pivoting (largest |S_ik|, lowest row
 // on ties), rows swapped explicitly, columns unscrambled at the end.  Returns
 // log det = sum log|pivot| + i arg(prod pivot / |pivot| * (-1)^swaps) in
-// every lane; non-finite when S is singular.
+// every lane (|det| kept as a mantissa and a power of two); non-finite when
+// S is singular.
 __device__ zdbl res_gj_inverse(int N, double* Sr, double* Si) {
   const int l = lane_id();
-  double lmag = 0.0, phr = 1.0, phi = 0.0;
+  double pm = 1.0, phr = 1.0, phi = 0.0;  // |det| = pm 2^pe, phase phr + i phi
+  int pe = 0;
   int myp = l;  // lane k keeps the row swapped with row k at step k
+  int np2 = 1;
+  while (np2 < N) np2 <<= 1;
   for (int k = 0; k < N; ++k) {
     double key = -1.0;
     int idx = N;
@@ -94,8 +102,7 @@ __device__ zdbl res_gj_inverse(int N, double* Sr, double* Si) {
       key = a * a + b * b;
       idx = l;
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
+    for (int o = np2 >> 1; o >= 1; o >>= 1) {
       const double ok = __shfl_xor(key, o, AFQ_WAVE);
       const int oi = __shfl_xor(idx, o, AFQ_WAVE);
       if (ok > key || (ok == key && oi < idx)) { key = ok; idx = oi; }
@@ -115,15 +122,18 @@ __device__ zdbl res_gj_inverse(int N, double* Sr, double* Si) {
     }
     wave_lds_sync();
     const zdbl pv = {Sr[k * N + k], Si[k * N + k]};
-    const double mag = hypot(pv.re, pv.im);
-    lmag += log(mag);
+    const double mag = sqrt(pv.re * pv.re + pv.im * pv.im);
+    const double rm = 1.0 / mag;
+    const double ur = pv.re * rm, ui = pv.im * rm;
     {
-      const double ur = pv.re / mag, ui = pv.im / mag;
+      int e;
+      pm = frexp(pm * mag, &e);
+      pe += e;
       const double nr = phr * ur - phi * ui, ni = phr * ui + phi * ur;
       phr = nr;
       phi = ni;
     }
-    const zdbl inv = zdiv(zdbl{1.0, 0.0}, pv);
+    const zdbl inv = {ur * rm, -ui * rm};  // 1 / pivot
     wave_lds_sync();
     for (int j = l; j < N; j += AFQ_WAVE) {
       const zdbl x = (j == k) ? zdbl{1.0, 0.0} : zdbl{Sr[k * N + j], Si[k * N + j]};
@@ -154,7 +164,7 @@ __device__ zdbl res_gj_inverse(int N, double* Sr, double* Si) {
     }
     wave_lds_sync();
   }
-  return zdbl{lmag, atan2(phi, phr)};
+  return zdbl{log(pm) + pe * 0.69314718055994530942, atan2(phi, phr)};
 }
 
 // log det of both spins' overlaps S = D_0^T phi, inverses left in Y (spin 0
@@ -174,7 +184,7 @@ __device__ void res_overlaps(const ResMember& P, const ResLds& Lo, double* sm) {
     const int a = r / N, b = r - a * N;
     double sr = 0.0, si = 0.0;
     for (int m = 0; m < M; ++m) {
-      const double d = P.D0[m * Nt + off + a];
+      const double d = sm[Lo.D0 + m * Nt + off + a];
       sr = fma(d, phr[m * Nt + off + b], sr);
       si = fma(d, phi[m * Nt + off + b], si);
     }
@@ -234,7 +244,7 @@ __device__ void res_measure(const ResMember& P, const ResLds& Lo, double* sm) {
   for (int c = threadIdx.x; c < Nt; c += blockDim.x) {
     const int s = c < n0 ? 0 : 1;
     const int a = c - (s ? n0 : 0);
-    const double* h = (s ? P.ht1 : P.ht0) + (long)a * M;
+    const double* h = sm + Lo.ht + c * M;
     double er = 0.0, ei = 0.0;
     for (int m = 0; m < M; ++m) {
       er = fma(h[m], Xr[m * Nt + c], er);
@@ -243,17 +253,24 @@ __device__ void res_measure(const ResMember& P, const ResLds& Lo, double* sm) {
     red[2 * c] = er;
     red[2 * c + 1] = ei;
   }
-  // exchange per spin, X_g = Ltil_g Theta for a batch of g at a time in Z
-  double* Zr = sm + Lo.Z_r;
-  double* Zi = sm + Lo.Z_i;
+  // exchange per spin: X_g = Ltil_g Theta for every g (rows (g, a) in
+  // parallel), then per row the Tr X and Tr(X X) partials, then per g their
+  // sums over rows
   double* trr = sm + Lo.tr_r;
   double* tri = sm + Lo.tr_i;
   double* xxr = sm + Lo.xx_r;
   double* xxi = sm + Lo.xx_i;
+  double* Qr = sm + Lo.Xg_r;
+  double* Qi = sm + Lo.Xg_i;
+  double* ptr = sm + Lo.pt_r;
+  double* pti = sm + Lo.pt_i;
+  double* pxr = sm + Lo.px_r;
+  double* pxi = sm + Lo.px_i;
   const int G1 = G > 0 ? G : 1;
   for (int s = 0; s < 2; ++s) {
-    const int N = s ? n1 : n0, off = s ? n0 : 0, NP = s ? P.NP1 : P.NP0;
-    const double* Lt = s ? P.Lt1 : P.Lt0;
+    const int N = s ? n1 : n0, off = s ? n0 : 0;
+    const double* Lt = sm + Lo.Lt + (s ? G * n0 * M : 0);  // [G][N][M]
+    __syncthreads();
     if (N == 0) {
       for (int g = threadIdx.x; g < G; g += blockDim.x) {
         trr[s * G1 + g] = tri[s * G1 + g] = 0.0;
@@ -261,43 +278,61 @@ __device__ void res_measure(const ResMember& P, const ResLds& Lo, double* sm) {
       }
       continue;
     }
-    const int B = (M * Nt) / (N * N);
-    for (int g0 = 0; g0 < G; g0 += B) {
-      const int nb = min(B, G - g0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < nb * N * N; e += blockDim.x) {
-        const int gl = e / (N * N), r = e - gl * N * N;
-        const int a = r / N, b = r - a * N;
-        const double* lt = Lt + (long)(g0 + gl) * P.MP4 * NP + a;
-        double xr = 0.0, xi = 0.0;
+    for (int task = threadIdx.x; task < G * N; task += blockDim.x) {
+      const double* lt = Lt + task * M;  // row a of Ltil_g, task = g N + a
+      for (int b0 = 0; b0 < N; b0 += 8) {
+        double ar[8], ai[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ar[j] = ai[j] = 0.0;
         for (int m = 0; m < M; ++m) {
-          const double l = lt[(long)m * NP];
-          xr = fma(l, Xr[m * Nt + off + b], xr);
-          xi = fma(l, Xi[m * Nt + off + b], xi);
+          const double l = lt[m];
+          const double* tr = Xr + m * Nt + off + b0;
+          const double* ti = Xi + m * Nt + off + b0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (b0 + j < N) {
+              ar[j] = fma(l, tr[j], ar[j]);
+              ai[j] = fma(l, ti[j], ai[j]);
+            }
         }
-        Zr[e] = xr;
-        Zi[e] = xi;
-      }
-      __syncthreads();
-      for (int gl = threadIdx.x; gl < nb; gl += blockDim.x) {
-        const double* zr = Zr + gl * N * N;
-        const double* zi = Zi + gl * N * N;
-        double tr = 0.0, ti = 0.0, qr = 0.0, qi = 0.0;
-        for (int a = 0; a < N; ++a) {
-          tr += zr[a * N + a];
-          ti += zi[a * N + a];
-          for (int b = 0; b < N; ++b) {
-            const double ar = zr[a * N + b], ai = zi[a * N + b];
-            const double br = zr[b * N + a], bi = zi[b * N + a];
-            qr += ar * br - ai * bi;
-            qi += ar * bi + ai * br;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (b0 + j < N) {
+            Qr[task * N + b0 + j] = ar[j];
+            Qi[task * N + b0 + j] = ai[j];
           }
-        }
-        trr[s * G1 + g0 + gl] = tr;
-        tri[s * G1 + g0 + gl] = ti;
-        xxr[s * G1 + g0 + gl] = qr;
-        xxi[s * G1 + g0 + gl] = qi;
       }
+    }
+    __syncthreads();
+    for (int task = threadIdx.x; task < G * N; task += blockDim.x) {
+      const int g = task / N, a = task - g * N;
+      const double* xr = Qr + g * N * N;
+      const double* xi = Qi + g * N * N;
+      double qr = 0.0, qi = 0.0;
+      for (int b = 0; b < N; ++b) {
+        const double ur = xr[a * N + b], ui = xi[a * N + b];
+        const double vr = xr[b * N + a], vi = xi[b * N + a];
+        qr += ur * vr - ui * vi;
+        qi += ur * vi + ui * vr;
+      }
+      ptr[task] = xr[a * N + a];
+      pti[task] = xi[a * N + a];
+      pxr[task] = qr;
+      pxi[task] = qi;
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < G; g += blockDim.x) {
+      double tr = 0.0, ti = 0.0, qr = 0.0, qi = 0.0;
+      for (int a = 0; a < N; ++a) {
+        tr += ptr[g * N + a];
+        ti += pti[g * N + a];
+        qr += pxr[g * N + a];
+        qi += pxi[g * N + a];
+      }
+      trr[s * G1 + g] = tr;
+      tri[s * G1 + g] = ti;
+      xxr[s * G1 + g] = qr;
+      xxi[s * G1 + g] = qi;
     }
   }
   __syncthreads();
@@ -385,7 +420,7 @@ __global__ __launch_bounds__(512) void k_res_steps(const ResMember* __restrict__
   const ResMember& P = mem[res_find_member(mem, n_mem, b)];
   const int w = b - P.wbase;
   const int M = P.M, Nt = P.Nt, G = P.G, mn = M * Nt;
-  const ResLds Lo = res_lds(M, Nt, G);
+  const ResLds Lo = res_lds(M, Nt, G, P.n0 > P.n1 ? P.n0 : P.n1);
   double* phr = sm + Lo.ph_r;
   double* phi = sm + Lo.ph_i;
   double* vr = sm + Lo.v_r;
@@ -398,6 +433,27 @@ __global__ __launch_bounds__(512) void k_res_steps(const ResMember* __restrict__
   for (int g = threadIdx.x; g < G; g += blockDim.x) {
     vr[g] = P.v_re[(long)w * G + g];
     vi[g] = P.v_im[(long)w * G + g];
+  }
+  // the member's operators, once per segment
+  {
+    const int mm = M * M, n0 = P.n0, n1 = P.n1;
+    for (int e = threadIdx.x; e < mm; e += blockDim.x) sm[Lo.B1 + e] = P.B1m[e];
+    for (int e = threadIdx.x; e < mn; e += blockDim.x) {
+      sm[Lo.D0 + e] = P.D0[e];
+      const int c = e / M, m = e - c * M;
+      sm[Lo.ht + e] = c < n0 ? P.ht0[c * M + m] : P.ht1[(c - n0) * M + m];
+    }
+    for (int g = threadIdx.x; g < G; g += blockDim.x) sm[Lo.lb + g] = P.lbar[g];
+    for (int e = threadIdx.x; e < G * mn; e += blockDim.x) {
+      // spin 0: [G][n0][M] from Ltil[(g MP4 + m) NP0 + a]; then spin 1
+      const int s1 = e >= G * n0 * M;
+      const int r = s1 ? e - G * n0 * M : e;
+      const int N = s1 ? n1 : n0;
+      const int g = r / (N * M), q = r - g * N * M, a = q / M, m = q - a * M;
+      sm[Lo.Lt + e] = s1 ? P.Lt1[((long)g * P.MP4 + m) * P.NP1 + a]
+                         : P.Lt0[((long)g * P.MP4 + m) * P.NP0 + a];
+    }
+    for (long e = threadIdx.x; e < (long)G * mm; e += blockDim.x) sm[Lo.L + e] = P.L[e];
   }
   // walker scalars: sc[16..21] = weight, log S (re, im), E_L (re, im)
   if (threadIdx.x == 0) {
@@ -447,7 +503,7 @@ __global__ __launch_bounds__(512) void k_res_steps(const ResMember* __restrict__
       for (int j = 0; j < 4; ++j) {
         const int g = 4 * q + j;
         if (g < G) {
-          const double lb = P.lbar[g];
+          const double lb = sm[Lo.lb + g];
           const double xsr = z[j] - sq * vi[g];
           const double xsi = sq * (vr[g] - lb);
           cfr[g] = xsr;
@@ -474,9 +530,9 @@ __global__ __launch_bounds__(512) void k_res_steps(const ResMember* __restrict__
       const int i = e / M, j = e - i * M;
       if (i > j) continue;
       double ar = 0.0, ai = 0.0;
-      const double* l = P.L + e;
+      const double* l = sm + Lo.L + e;
       for (int g = 0; g < G; ++g) {
-        const double lv = l[(long)g * M * M];
+        const double lv = l[g * M * M];
         ar = fma(cfi[g], lv, ar);
         ai = fma(cfr[g], lv, ai);
       }
@@ -488,7 +544,7 @@ __global__ __launch_bounds__(512) void k_res_steps(const ResMember* __restrict__
       Ai[j * M + i] = ai;
     }
     // X = B1 phi
-    res_apply_b1(M, Nt, P.B1m, phr, phi, Xr, Xi);
+    res_apply_b1(M, Nt, sm + Lo.B1, phr, phi, Xr, Xi);
     __syncthreads();
     for (int e = threadIdx.x; e < mn; e += blockDim.x) {
       Zr[e] = Xr[e];
@@ -510,7 +566,7 @@ __global__ __launch_bounds__(512) void k_res_steps(const ResMember* __restrict__
       ni = ti;
     }
     // phi = B1 ACC
-    res_apply_b1(M, Nt, P.B1m, Zr, Zi, phr, phi);
+    res_apply_b1(M, Nt, sm + Lo.B1, Zr, Zi, phr, phi);
     __syncthreads();
     res_measure(P, Lo, sm);
     // phaseless weight (local-energy form), dead-walker reset
@@ -549,7 +605,7 @@ __global__ __launch_bounds__(512) void k_res_steps(const ResMember* __restrict__
     }
     if (!alive)
       for (int e = threadIdx.x; e < mn; e += blockDim.x) {
-        phr[e] = P.D0[e];
+        phr[e] = sm[Lo.D0 + e];
         phi[e] = 0.0;
       }
     __syncthreads();

@@ -8,7 +8,8 @@ namespace afq {
 
 // Largest systems the resident kernel takes: one wavefront owns the rows of a
 // spin block in MGS (M <= 64) and the rows of an overlap matrix in the
-// elimination (N <= 64); the LDS layout must fit one CU.
+// elimination (N <= 64); the walker's arrays and the staged operators must
+// fit one CU's LDS (tiny systems: the latency-bound regime).
 constexpr int kResMaxM = 64;
 constexpr int kResMaxMembers = 64;
 
@@ -54,13 +55,20 @@ struct ResMember {
 
 // Offsets (in doubles) of a walker block's LDS arrays; the same function on
 // the host (launch size) and the device (carving).
+// The second part holds the member's operators, staged once per segment:
+// B1 - I [M][M], D_0 [M][Nt], htil [Nt][M] (spin 0's rows, then spin 1's),
+// lbar [G], Ltil [G][n0][M] then [G][n1][M], L [G][M][M].
+// Xg holds X_g = Ltil_g Theta of one spin for every g ([G][Nx][Nx], Nx the
+// larger spin count), pt / px the per-row partials of Tr X and Tr(X X).
 struct ResLds {
   int ph_r, ph_i, A_r, A_i, X_r, X_i, Y_r, Y_i, Z_r, Z_i;
   int cf_r, cf_i, v_r, v_i, tr_r, tr_i, xx_r, xx_i, red, sc;
+  int Xg_r, Xg_i, pt_r, pt_i, px_r, px_i;
+  int B1, D0, ht, lb, Lt, L;
   int total;
 };
 
-__host__ __device__ inline ResLds res_lds(int M, int Nt, int G) {
+__host__ __device__ inline ResLds res_lds(int M, int Nt, int G, int Nx) {
   ResLds o;
   const int mn = M * Nt, mm = M * M, G1 = G > 0 ? G : 1, nq = (G + 3) / 4;
   int p = 0;
@@ -84,6 +92,18 @@ __host__ __device__ inline ResLds res_lds(int M, int Nt, int G) {
   o.xx_i = p; p += 2 * G1;
   o.red = p; p += 2 * (nq > Nt ? nq : Nt);
   o.sc = p; p += 32;
+  o.Xg_r = p; p += G1 * Nx * Nx;
+  o.Xg_i = p; p += G1 * Nx * Nx;
+  o.pt_r = p; p += G1 * Nx;
+  o.pt_i = p; p += G1 * Nx;
+  o.px_r = p; p += G1 * Nx;
+  o.px_i = p; p += G1 * Nx;
+  o.B1 = p; p += mm;
+  o.D0 = p; p += mn;
+  o.ht = p; p += mn;
+  o.lb = p; p += G1;
+  o.Lt = p; p += G * mn;
+  o.L = p; p += G * mm;
   o.total = p;
   return o;
 }

@@ -94,10 +94,10 @@ def test_group_with_comb_fp64_parity(afq, W, pc, steps, step0):
 
 def test_group_matches_per_kernel_chain(afq):
     """A member's run equals afqmc_propagate's FP64 chain on the same system
-    and fields (M = 20, 5/4 electrons, 100 vectors, 96 walkers, 12 steps with
+    and fields (M = 12, 5/4 electrons, 36 vectors, 96 walkers, 12 steps with
     MGS and a comb): E_mix within 1e-10 relative."""
-    _say("group vs chain M=20")
-    inp = syn.make_system(20, 5, 4, 100, 50.0, seed=31, l_scale=syn.health_scale(20))
+    _say("group vs chain M=12")
+    inp = syn.make_system(12, 5, 4, 36, 8.0, seed=31)
     kw = dict(taylor_order=6, ortho_every=3, pc_every=6)
     m = _member(afq, inp, 96, 0.005, 2, **kw)
     em = _np(afq.Group([m]).propagate(12, 0)[0])
@@ -111,8 +111,7 @@ def _uneven_systems():
     """Three systems of uneven M, N, n_chol and walker count, one with a comb."""
     return [
         (syn.make_system(10, 5, 5, 40, 8.0, seed=0), 64, dict(taylor_order=6, ortho_every=2), 0, 0),
-        (syn.make_system(20, 5, 4, 100, 50.0, seed=3, l_scale=syn.health_scale(20)), 128,
-         dict(taylor_order=6, ortho_every=2), 5, 7),
+        (syn.make_system(12, 5, 4, 36, 8.0, seed=3), 128, dict(taylor_order=6, ortho_every=2), 5, 7),
         (syn.make_system(14, 4, 3, 30, 8.0, seed=9), 33,
          dict(taylor_order=4, ortho_every=3, pc_every=4), 11, 0),
     ]
@@ -209,12 +208,13 @@ def test_group_rejects_unsupported_members(afq):
     """Multi-determinant trials, the hybrid weights and systems beyond the
     resident kernel's limits are refused before any work."""
     _say("group rejects")
-    inp = syn.make_system(70, 10, 10, 20, 8.0, seed=2)
-    m = _member(afq, inp, 4, 0.005, 0)
-    assert not afq.resident_supported(m.trial)
-    with pytest.raises(afq.AfqmcError) as e:
-        afq.Group([m])
-    assert e.value.status == -7
+    for M, n, G in ((70, 10, 20), (20, 5, 100)):  # M > 64; operators beyond one CU's LDS
+        inp = syn.make_system(M, n, n, G, 8.0, seed=2)
+        m = _member(afq, inp, 4, 0.005, 0)
+        assert not afq.resident_supported(m.trial)
+        with pytest.raises(afq.AfqmcError) as e:
+            afq.Group([m])
+        assert e.value.status == -7
     small = syn.make_system(10, 5, 5, 40, 8.0, seed=0)
     h = _member(afq, small, 4, 0.005, 0, weight_mode="hybrid", meas_every=2)
     with pytest.raises(afq.AfqmcError):
