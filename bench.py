@@ -571,7 +571,7 @@ def main():
     ap.add_argument("--workload", default="hchain-M50")
     ap.add_argument("--walkers", type=int, default=0)
     ap.add_argument("--prec", default="",
-                    help="override precisions: 'chol' or 'chol,taylor' from fp64/fp32/bf16")
+                    help="override precisions: 'chol' or 'chol,taylor' from fp64/fp32/bf16/bf16x3")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--weight-mode", choices=["local", "hybrid"], default="local",
                     help="local-energy weights every step (default) or the hybrid form")
@@ -588,7 +588,7 @@ def main():
                     help="steps of each time-to-energy run (0: the workload's full run)")
     ap.add_argument("--precision-report", action="store_true",
                     help="E_L error and E_mix drift of the contraction precisions vs FP64")
-    ap.add_argument("--sweep-precs", default="fp32,bf16,fp64,fp32+q")
+    ap.add_argument("--sweep-precs", default="fp32,bf16,bf16x3,fp64,fp32+q")
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed request stream through the serving loop instead")
     ap.add_argument("--requests", type=int, default=64)
@@ -655,7 +655,7 @@ def main():
                       inp.coeff if multi else None, inp.exc if multi else None)
     if args.exchange_route != "auto":
         trial.exchange_route = args.exchange_route
-    route = trial.exchange_route if chol_prec != "bf16" else "ltilde"
+    route = trial.exchange_route if chol_prec not in ("bf16", "bf16x3") else "ltilde"
     w = afq.Walkers(trial, W)
     afq.walkers_from_trial(ham, trial, w)
     et = afq.local_energy(ham, trial, w)
@@ -727,7 +727,10 @@ def main():
     # M max(N) <= AFQMC_QROUTE_FP32_MAX_K, FP64 otherwise
     q32 = chol_prec == "fp32" and wl.M * max(wl.n_up, wl.n_dn) <= afq._abi.QROUTE_FP32_MAX_K
     ex_prec = ("fp32" if q32 else "fp64") if (route == "q" and not multi) else chol_prec
-    ex_peak = {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}[ex_prec]
+    # BF16X3 takes three bf16 MFMA products per algorithmic product: its
+    # fraction is against the bf16 peak (so at most 1/3)
+    ex_peak = {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS,
+               "bf16x3": BF16_PEAK_TFLOPS}[ex_prec]
     # per step: the exchange class is one launch; the Taylor class is one
     # fused launch, or a chain of GEMM launches (B1, each term, B1) whose
     # algorithmic flops are shared out over the chain's launches
@@ -778,7 +781,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[chol_prec],
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "bf16x3": "bf16x3"}[chol_prec],
         "data": "synthetic",
         "config": {"workload": wl.name, "M": wl.M, "n_up": wl.n_up, "n_dn": wl.n_dn,
                    "n_chol": wl.n_chol, "n_walkers": W, "dt": wl.dt,

@@ -55,8 +55,14 @@ typedef enum {
 
 /* Arithmetic of a contraction (Sec. III: single- vs double-precision).
  * AFQMC_BF16: bf16 operands with FP32 accumulation on the matrix cores
- * (contractions only; single-determinant trials). */
-typedef enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16 = 2 } afqmc_prec;
+ * (contractions only; single-determinant trials).
+ * AFQMC_BF16X3: every operand split in two bf16 terms, x = hi + lo with
+ * hi = bf16(x) and lo = bf16(x - hi) (about 16 significant bits), and each
+ * product taken as hi hi + hi lo + lo hi (the lo lo term, of relative size
+ * 2^-18, dropped) on the bf16 matrix cores with FP32 accumulation: three
+ * bf16 MFMAs per product, for the propagator build and the Ltil Theta
+ * contraction (same limits as AFQMC_BF16). */
+typedef enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16 = 2, AFQMC_BF16X3 = 3 } afqmc_prec;
 
 #define AFQMC_MAX_EXC 4      /* excitations per spin in one determinant      */
 /* The Q exchange route (afqmc_trial_exchange_route) runs its contractions in
@@ -90,7 +96,8 @@ typedef struct {
 } afqmc_walkers;
 
 /* Run options.  taylor_order: terms of the series for exp(A) (>= 1);
- * chol_prec may be AFQMC_BF16, taylor_prec only AFQMC_FP64 or AFQMC_FP32.
+ * chol_prec may be AFQMC_BF16 or AFQMC_BF16X3, taylor_prec only AFQMC_FP64
+ * or AFQMC_FP32.
  * ortho_every / pc_every: orthonormalise / comb after global step t when
  * (t+1) is a multiple (0 = never).  e_trial: E_T of the weight factor.
  * chol_prec: arithmetic of sum_g x_g L_g and of Ltil_g Theta;

@@ -18,7 +18,7 @@ AFQMC_OK = 0
 STATUS_NAMES = {0: "AFQMC_OK", -1: "AFQMC_ERR_ARG", -2: "AFQMC_ERR_OOM", -3: "AFQMC_ERR_DEVICE",
                 -4: "AFQMC_ERR_STATE", -5: "AFQMC_ERR_SINGULAR", -6: "AFQMC_ERR_NONFINITE",
                 -7: "AFQMC_ERR_UNSUPPORTED"}
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 MAX_EXC = 4
 QROUTE_FP32_MAX_K = 4096  # AFQMC_QROUTE_FP32_MAX_K
 NOALLOC_SCRATCH_BYTES = 32 << 20  # AFQMC_NOALLOC_SCRATCH_BYTES

@@ -191,6 +191,7 @@ struct afqmc_ham {
   double* L = nullptr;   // [G][M][M]
   float* Lf = nullptr;   // [G][M][M]
   void* Lbf = nullptr;   // [G][M][M] bf16
+  void* Lbf_lo = nullptr;  // [G][M][M] bf16, second term of the split (BF16X3)
   double* L2 = nullptr;  // sum_g L_g L_g
   std::vector<double> h_host;
   Arena arena;
@@ -217,6 +218,7 @@ struct afqmc_trial {
   double* Apk64[2] = {nullptr, nullptr};  // NP <= 32: exchange A operand, repacked
   float* Apk32[2] = {nullptr, nullptr};
   void* Ltbf[2] = {nullptr, nullptr};  // [G][NP][MP32] bf16 (m contiguous)
+  void* Ltbf_lo[2] = {nullptr, nullptr};  // the split's second terms (BF16X3)
   int MP32 = 32;
   double* lbar = nullptr;
   double* D0 = nullptr;
@@ -417,7 +419,8 @@ afq::SpinGeom spin_geom(const afqmc_trial* tr, int s, afqmc_prec prec) {
   g.NP = tr->NP[s];
   g.C = tr->C[s];
   g.htil = tr->htil[s];
-  g.Lt = prec == AFQMC_BF16 ? tr->Ltbf[s] : fp32 ? (const void*)tr->Lt32[s] : (const void*)tr->Lt64[s];
+  g.Lt = (prec == AFQMC_BF16 || prec == AFQMC_BF16X3) ? tr->Ltbf[s]
+         : fp32 ? (const void*)tr->Lt32[s] : (const void*)tr->Lt64[s];
   g.Apk = fp32 ? (const void*)tr->Apk32[s] : (const void*)tr->Apk64[s];
   return g;
 }
@@ -471,7 +474,8 @@ afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqm
   const int W = wk->n_walkers, M = hm->M, G = hm->G, Nt = tr->Nt;
   const bool f32 = chol == AFQMC_FP32;
   const afq::SpinGeom s0 = spin_geom(tr, 0, chol), s1 = spin_geom(tr, 1, chol);
-  const bool qr = tr->n_det == 1 && G > 0 && tr->qroute && chol != AFQMC_BF16;
+  const bool bf = chol == AFQMC_BF16 || chol == AFQMC_BF16X3;
+  const bool qr = tr->n_det == 1 && G > 0 && tr->qroute && !bf;
   const bool q32 = f32 && tr->q32;  // Q-route contraction type
   {
     TimedLaunch tl(&hm->timer, KC_OVERLAP, st);
@@ -501,8 +505,10 @@ afqmc_status measure_core(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, afqm
   if (qr) return measure_qroute(tr, wk, ws, q32, st);
   if (G > 0) {
     TimedLaunch tl(&hm->timer, KC_EXCHANGE, st);
-    if (chol == AFQMC_BF16) {
-      AFQ_CK(afq::exchange_bf16(st, W, M, tr->MP32, Nt, G, s0, s1, ws.th_re, ws.th_im, ws.vs_re,
+    if (bf) {
+      const bool x3 = chol == AFQMC_BF16X3;
+      AFQ_CK(afq::exchange_bf16(st, W, M, tr->MP32, Nt, G, s0, s1, x3 ? tr->Ltbf_lo[0] : nullptr,
+                                x3 ? tr->Ltbf_lo[1] : nullptr, ws.th_re, ws.th_im, ws.vs_re,
                                 ws.vs_im, ws.exx_re, ws.exx_im, hm->max_lds));
     } else if (f32) {
       AFQ_CK(afq::exchange<float>(st, W, M, tr->MP4, Nt, G, s0, s1, ws.th_re, ws.th_im, ws.vs_re,
@@ -736,9 +742,12 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
   for (int s = 0; s < n_steps; ++s) {
     const uint64_t t = step0 + (uint64_t)s;
     const bool measuring = !hybrid || (t + 1) % (uint64_t)opt->meas_every == 0;
+    // BF16X3: the coefficients' second terms follow the first ones in coefT
+    const bool x3 = opt->chol_prec == AFQMC_BF16X3;
+    void* coef_lo = x3 ? (void*)((char*)ws.coefT + (size_t)2 * W * G * 2) : nullptr;
     if constexpr (BF) {
       AFQ_CK(afq::fields_coeff_bf16(st, W, G, G, seed, t, wk->system_id, dt, ws.v_re, ws.v_im,
-                                    tr->lbar, ws.coefT, ws.mf_re, ws.mf_im, hyr, hyi));
+                                    tr->lbar, ws.coefT, coef_lo, ws.mf_re, ws.mf_im, hyr, hyi));
     } else {
       AFQ_CK(afq::fields_coeff<TC>(st, W, G, Gp, seed, t, wk->system_id, dt, ws.v_re, ws.v_im,
                                    tr->lbar, coefT, ws.mf_re, ws.mf_im, nullptr, hyr, hyi));
@@ -746,7 +755,8 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
     if (G > 0) {
       TimedLaunch tl(&hm->timer, KC_ABUILD, st);
       if constexpr (BF) {
-        AFQ_CK(afq::gemm_bf16<TT>(st, 2 * W, (int)mm, G, ws.coefT, G, hm->Lbf, (int)mm, A, (int)mm, 1.0));
+        AFQ_CK(afq::gemm_bf16<TT>(st, 2 * W, (int)mm, G, ws.coefT, coef_lo, G, hm->Lbf,
+                                  x3 ? hm->Lbf_lo : nullptr, (int)mm, A, (int)mm, 1.0));
       } else {
         AFQ_CK((afq::abuild<TC, TT>(st, 2 * W, (int)mm, G, Gp, coefT, Lc, A)));
       }
@@ -912,7 +922,7 @@ afqmc_status afqmc_init_hamiltonian(afqmc_ham** out, int device, void* stream, i
   void *ph, *pL, *pLf, *pL2, *pLb;
   if (hm->arena.alloc(&ph, mm * 8) || hm->arena.alloc(&pL, gmm * 8) ||
       hm->arena.alloc(&pLf, gmm * 4) || hm->arena.alloc(&pL2, mm * 8) ||
-      hm->arena.alloc(&pLb, gmm * 2)) {
+      hm->arena.alloc(&pLb, gmm * 2) || hm->arena.alloc(&hm->Lbf_lo, gmm * 2)) {
     hm->arena.release();
     delete hm;
     return fail(AFQMC_ERR_OOM, "hamiltonian allocation failed");
@@ -931,7 +941,9 @@ afqmc_status afqmc_init_hamiltonian(afqmc_ham** out, int device, void* stream, i
   if (n_chol > 0) {
     if (hipMemcpyAsync(hm->L, L, gmm * 8, hipMemcpyHostToDevice, st) != hipSuccess) return bad("L upload");
     if (afq::convert_f64_f32(st, hm->L, hm->Lf, (long)gmm) != hipSuccess) return bad("L convert");
-    if (afq::convert_f64_bf16(st, hm->L, hm->Lbf, (long)gmm) != hipSuccess) return bad("L convert");
+    if (afq::convert_f64_bf16(st, hm->L, hm->Lbf, (long)gmm) != hipSuccess ||
+        afq::convert_f64_bf16_lo(st, hm->L, hm->Lbf_lo, (long)gmm) != hipSuccess)
+      return bad("L convert");
   }
   // sum_g L_g L_g as one GEMM over the stacked index (g, k)
   if (afq::gemm_real<double, double, true>(st, M, M, n_chol * M, hm->L, M, 0, hm->L, M, 0, hm->L2,
@@ -958,12 +970,12 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
   auto rnd = [&](size_t b) { return (std::max(b, a) + a - 1) / a * a; };
   const int nel[2] = {n_up, n_dn};
   const size_t MP4 = round_up(M, 4), MP32 = round_up(M, 32), Nt = (size_t)n_up + n_dn;
-  size_t tot = rnd(mm * 8) * 2 + rnd(g * mm * 8) + rnd(g * mm * 4) + rnd(g * mm * 2);  // ham
+  size_t tot = rnd(mm * 8) * 2 + rnd(g * mm * 8) + rnd(g * mm * 4) + 2 * rnd(g * mm * 2);  // ham
   for (int s = 0; s < 2; ++s) {                                                        // trial
     const size_t NP = round_up(std::max(nel[s], 1), 16);
     const size_t nlt = (g * MP4 + 16) * NP;
     tot += rnd(mm * 8) + rnd(std::max(nel[s], 1) * m * 8) + rnd(nlt * 8) + rnd(nlt * 4) +
-           rnd(g * NP * MP32 * 2);
+           2 * rnd(g * NP * MP32 * 2);
     if (NP <= 32 && g > 0) {
       const size_t npk = pack_exchange_elems(g, MP4, NP);
       tot += rnd(npk * 8) + rnd(npk * 4);
@@ -1117,13 +1129,18 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
         return bad(AFQMC_ERR_DEVICE, "exchange operand repack");
     }
     {
-      void* pb = nullptr;
+      void *pb = nullptr, *pbl = nullptr;
       const size_t nb = (size_t)G * tr->NP[s] * tr->MP32;
-      if (tr->arena.alloc(&pb, nb * 2)) return bad(AFQMC_ERR_OOM, "trial allocation failed");
+      if (tr->arena.alloc(&pb, nb * 2) || tr->arena.alloc(&pbl, nb * 2))
+        return bad(AFQMC_ERR_OOM, "trial allocation failed");
       tr->Ltbf[s] = pb;
-      if (hipMemsetAsync(pb, 0, nb * 2, st) != hipSuccess) return bad(AFQMC_ERR_DEVICE, "memset");
+      tr->Ltbf_lo[s] = pbl;
+      if (hipMemsetAsync(pb, 0, nb * 2, st) != hipSuccess ||
+          hipMemsetAsync(pbl, 0, nb * 2, st) != hipSuccess)
+        return bad(AFQMC_ERR_DEVICE, "memset");
       if (G > 0 && afq::transpose_f64_bf16(st, tr->MP4, tr->NP[s], tr->MP32, (long)tr->MP4 * tr->NP[s],
-                                           (long)tr->NP[s] * tr->MP32, G, tr->Lt64[s], pb) != hipSuccess)
+                                           (long)tr->NP[s] * tr->MP32, G, tr->Lt64[s], pb,
+                                           pbl) != hipSuccess)
         return bad(AFQMC_ERR_DEVICE, "bf16 half-rotation");
     }
     if (nel[s] > 0) {
@@ -1414,11 +1431,11 @@ afqmc_status afqmc_propagate(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk, 
     return fail(AFQMC_ERR_ARG, "weight_mode must be AFQMC_WEIGHT_LOCAL_ENERGY or AFQMC_WEIGHT_HYBRID");
   if (opt->weight_mode == AFQMC_WEIGHT_HYBRID && opt->meas_every < 1)
     return fail(AFQMC_ERR_ARG, "meas_every must be >= 1 in the hybrid form");
-  if ((opt->chol_prec != AFQMC_FP64 && opt->chol_prec != AFQMC_FP32 &&
-       opt->chol_prec != AFQMC_BF16) ||
+  const bool bfp = opt->chol_prec == AFQMC_BF16 || opt->chol_prec == AFQMC_BF16X3;
+  if ((opt->chol_prec != AFQMC_FP64 && opt->chol_prec != AFQMC_FP32 && !bfp) ||
       (opt->taylor_prec != AFQMC_FP64 && opt->taylor_prec != AFQMC_FP32))
     return fail(AFQMC_ERR_UNSUPPORTED, "precision");
-  if (opt->chol_prec == AFQMC_BF16 && tr->n_det > 1)
+  if (bfp && tr->n_det > 1)
     return fail(AFQMC_ERR_UNSUPPORTED, "bf16 contractions with a multi-determinant trial");
   AFQ_CK(hipSetDevice(hm->device));
   hipStream_t st = (hipStream_t)stream;
@@ -1429,7 +1446,7 @@ afqmc_status afqmc_propagate(afqmc_ham* hm, afqmc_trial* tr, afqmc_walkers* wk, 
   s = measure_set(tr, wk, ws, opt->chol_prec, st);
   if (s != AFQMC_OK) return s;
   const bool c32 = opt->chol_prec == AFQMC_FP32, t32 = opt->taylor_prec == AFQMC_FP32;
-  if (opt->chol_prec == AFQMC_BF16) {
+  if (bfp) {
     if (t32)
       return propagate_typed<Bf16Tag, float>(tr, wk, ws, b1, n_steps, dt, seed, step0, opt, emix_dev, st);
     return propagate_typed<Bf16Tag, double>(tr, wk, ws, b1, n_steps, dt, seed, step0, opt, emix_dev, st);

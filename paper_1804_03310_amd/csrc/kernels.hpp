@@ -172,12 +172,15 @@ hipError_t md_energy(hipStream_t st, int W, const MDParams& p, const double* thr
 
 namespace afq {
 // BF16 contraction path (bf16.hip).
+// Split bf16 operands (BF16X3): x = hi + lo, hi = bf16(x), lo = bf16(x - hi).
 hipError_t convert_f64_bf16(hipStream_t st, const double* src, void* dst, long n);
+hipError_t convert_f64_bf16_lo(hipStream_t st, const double* src, void* dst, long n);
 hipError_t transpose_f64_bf16(hipStream_t st, int rows, int cols, int ld_dst, long s_src,
-                              long s_dst, int batch, const double* src, void* dst);
+                              long s_dst, int batch, const double* src, void* dst, void* dst_lo);
+// Al / Bl non-null: the three-product split form.
 template <typename TOut>
-hipError_t gemm_bf16(hipStream_t st, int Mr, int Nc, int K, const void* A, int lda, const void* B,
-                     int ldb, TOut* C, int ldc, double alpha);
+hipError_t gemm_bf16(hipStream_t st, int Mr, int Nc, int K, const void* A, const void* Al, int lda,
+                     const void* B, const void* Bl, int ldb, TOut* C, int ldc, double alpha);
 // Hybrid weights: v from the force-bias GEMM's split-K partials summed here;
 // lsn = ld_up + ld_dn and vfin = all v finite per walker.
 template <typename TP>
@@ -220,13 +223,16 @@ hipError_t combine_qroute(hipStream_t st, int W, int G, int nz, int nseg0, int n
                           const double* ld_im, double* v_re, double* v_im, double* exx_re,
                           double* exx_im, double* lsn_re, double* lsn_im, double* eln_re,
                           double* eln_im, int* vfin);
+// coef_lo (nullable): the split's second terms of the coefficients.
 hipError_t fields_coeff_bf16(hipStream_t st, int W, int G, int ldg, uint64_t seed, uint64_t t,
                              int system_id, double dt, const double* v_re, const double* v_im,
-                             const double* lbar, void* coef, double* mf_re, double* mf_im,
-                             double* hy_re = nullptr, double* hy_im = nullptr);
+                             const double* lbar, void* coef, void* coef_lo, double* mf_re,
+                             double* mf_im, double* hy_re = nullptr, double* hy_im = nullptr);
+// Lt_lo0 / Lt_lo1 non-null: the three-product split form.
 hipError_t exchange_bf16(hipStream_t st, int W, int M, int MP32, int Nt, int G, SpinGeom s0,
-                         SpinGeom s1, const double* thr, const double* thi, double* vs_re,
-                         double* vs_im, double* exx_re, double* exx_im, size_t max_lds);
+                         SpinGeom s1, const void* Lt_lo0, const void* Lt_lo1, const double* thr,
+                         const double* thi, double* vs_re, double* vs_im, double* exx_re,
+                         double* exx_im, size_t max_lds);
 }  // namespace afq
 
 namespace afq {
