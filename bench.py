@@ -223,15 +223,29 @@ def serving_bench(args):
                  chunk_steps=args.serve_chunk)
     ids = [srv.submit(r) for r in reqs]
     t0 = time.perf_counter()
-    srv.run()
+    reported = 0
+    while srv.step():  # the server's run loop, with a progress line every 16 results
+        if len(srv.results) >= reported + 16:
+            reported = len(srv.results)
+            print(f"[serving] {reported}/{n} done at {time.perf_counter() - t0:.1f} s, "
+                  f"{len(srv.active)} active", file=sys.stderr, flush=True)
+        if not srv.active and srv.pending:
+            wait = srv.requests[srv.pending[0]].arrival - srv.now()
+            if wait > 0:
+                time.sleep(min(wait, 0.05))
+        else:
+            time.sleep(0.0005)
     wall = time.perf_counter() - t0
     st = srv.stats()
     res = [srv.poll(k) for k in ids]
-    # alone vs mix: the first pair's two members and the largest single request
-    check = [k for k, r in enumerate(reqs) if r.tag[0] == "pair"][:2]
+    # alone vs mix: args.serve_check requests rerun one at a time (correlated
+    # pairs' members and single requests, the smaller ones first to bound the
+    # time), each E_mix series compared bitwise with its run in the mix
+    pairs = [k for k, r in enumerate(reqs) if r.tag[0] == "pair"]
     singles = [k for k, r in enumerate(reqs) if r.tag[0] == "single"]
-    if singles:
-        check.append(max(singles, key=lambda k: reqs[k].M * reqs[k].n_walkers))
+    cost = lambda k: reqs[k].M ** 4 * reqs[k].n_walkers
+    half = args.serve_check // 2
+    check = sorted(pairs, key=cost)[:half] + sorted(singles, key=cost)[:args.serve_check - half]
     same = True
     for k in check:
         r = reqs[k]
@@ -241,6 +255,8 @@ def serving_bench(args):
         rid = s1.submit(r1)
         s1.run()
         same = same and res[k] is not None and np.array_equal(s1.poll(rid).emix, res[k].emix)
+        print(f"[serving] alone vs mix: request {k} (M={r.M}, W={r.n_walkers}) "
+              f"{'same' if same else 'DIFFERENT'}", file=sys.stderr, flush=True)
     ws = sum(r.n_walkers * r.n_steps for r, x in zip(reqs, res) if x is not None and x.error is None)
     out = {"metric": "serving: walker-steps/s over a mixed request stream; p50/p99 arrival-to-result latency",
            "value": ws / wall, "unit": "walker-steps/s", "n_gpus": 1, "higher_is_better": True,
@@ -252,7 +268,13 @@ def serving_bench(args):
                       "chunk_steps": args.serve_chunk},
            "wall_s": wall, "completed": st.get("completed"), "rejected": st.get("rejected"),
            "p50_s": st.get("p50_s"), "p99_s": st.get("p99_s"), "peak_bytes": st.get("peak_bytes"),
-           "alone_vs_mix_bitwise": bool(same), "alone_vs_mix_checked": len(check)}
+           "makespan_s": st.get("makespan_s"),
+           "latency_by_M": {str(M): {"p50_s": float(np.percentile(
+               [x.latency for x, r in zip(res, reqs) if x is not None and r.M == M], 50))}
+               for M in sorted({r.M for r in reqs})},
+           "alone_vs_mix_bitwise": bool(same), "alone_vs_mix_checked": len(check),
+           "alone_vs_mix_requests": [{"M": reqs[k].M, "W": reqs[k].n_walkers, "kind": reqs[k].tag[0]}
+                                     for k in check]}
     print(json.dumps(out), flush=True)
 
 
@@ -591,13 +613,15 @@ def main():
     ap.add_argument("--sweep-precs", default="fp32,bf16,bf16x3,fp64,fp32+q")
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed request stream through the serving loop instead")
-    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--rate", type=float, default=20.0)
-    ap.add_argument("--serve-steps", type=int, default=50)
+    ap.add_argument("--serve-steps", type=int, default=200)
     ap.add_argument("--serve-seed", type=int, default=0)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-chunk", type=int, default=10)
+    ap.add_argument("--serve-check", type=int, default=16,
+                    help="requests rerun alone and compared bitwise with their run in the mix")
     ap.add_argument("--cs", action="store_true",
                     help="correlated-sampling energy difference (neutral vs cation sharing the "
                          "fields) over repeats, and a reblocking analysis of a long run")

@@ -152,9 +152,9 @@ afqmc_status afqmc_walker_workspace_bytes(const afqmc_trial *trial, int n_walker
                                           size_t *bytes);
 
 /* Device bytes one system of these sizes occupies: Hamiltonian, trial
- * (including one cached B1), the caller's walker buffers for n_walkers
- * walkers and their workspace.  For admission decisions before anything is
- * allocated. */
+ * (including one cached B1 and the largest transient its set-up allocates),
+ * the caller's walker buffers for n_walkers walkers and their workspace.
+ * For admission decisions before anything is allocated. */
 afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_det,
                                    int n_walkers, size_t *bytes);
 

@@ -993,8 +993,13 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
     int ns[2];
     q_plan(M, n_chol, n_up, n_dn, nullptr, ns);
     tot += rnd((size_t)(ns[0] + ns[1]) * 16);
-    for (int s = 0; s < 2; ++s)
+    size_t tr_max = 0;  // the set-up transient P = R^T R, one spin at a time
+    for (int s = 0; s < 2; ++s) {
       if (nel[s]) tot += rnd(kq[s] * kq[s] * 8) + (qb == 12 ? rnd(kq[s] * kq[s] * 4) : 0);
+      const size_t kp = MP4 * (size_t)round_up(std::max(nel[s], 1), 16);
+      if (nel[s]) tr_max = std::max(tr_max, rnd(kp * kp * 8));
+    }
+    tot += tr_max;
   }
   tot += 2 * rnd((size_t)n_walkers * m * Nt * 8) + 5 * rnd((size_t)n_walkers * 8);  // walkers
   tot += layout_dims(M, n_chol, (long)Nt, n_det, n_walkers, nullptr).total;
@@ -1239,9 +1244,11 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
         return bad(AFQMC_ERR_OOM, "trial allocation failed");
       tr->Q64[s] = (double*)q64;
       tr->Q32[s] = (float*)q32;
-      // P = R^T R over the padded index (m NP + a), then the index permutation
+      // P = R^T R over the padded index (m NP + a), then the index permutation;
+      // P is a stream-ordered transient (no device-wide synchronisation when it
+      // is freed; afqmc_footprint_bytes counts it)
       double* P = nullptr;
-      if (hipMalloc(&P, (size_t)Kp * Kp * 8) != hipSuccess)
+      if (hipMallocAsync((void**)&P, (size_t)Kp * Kp * 8, st) != hipSuccess)
         return bad(AFQMC_ERR_OOM, "Q set-up allocation failed");
       const bool ok =
           afq::gemm_real<double, double, true>(st, (int)Kp, (int)Kp, G, tr->Lt64[s], (int)Kp, 0,
@@ -1252,8 +1259,8 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
           (!tr->q32 || afq::perm_qpad<float>(st, M, nel[s], tr->NP[s], tr->MP4, (int)Kq, P,
                                              tr->Q32[s]) == hipSuccess) &&
           hipStreamSynchronize(st) == hipSuccess;
-      (void)hipFree(P);
-      if (!ok) return bad(AFQMC_ERR_DEVICE, "Q set-up");
+      const bool freed = hipFreeAsync(P, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+      if (!ok || !freed) return bad(AFQMC_ERR_DEVICE, "Q set-up");
     }
     tr->qbuilt = true;
     tr->qroute = true;
