@@ -325,39 +325,58 @@ __global__ __launch_bounds__(256) void k_md_energy(MDParams p, int Nmax, int NPm
       }
       // P = (L_g C)^T Theta_0: rows p < M, columns b < N
       const T* __restrict__ A = (const T*)p.sp[s].LC + (long)g * M * M;
-      const int RT = (M + 15) / 16, CT = (N + 15) / 16;
-      for (int t = wv; t < RT * CT; t += 4) {
-        const int rt = t / CT, ct = t % CT;
-        acc_t ar = MM::zero(), ai = MM::zero();
-        const int prow = 16 * rt + li;
-        // A (L_g C, L2 or memory resident) in batches of eight k steps, all
-        // eight loads in flight before the first MFMA of the batch
-        const int KSt = MP4 / 4;
-        for (int kb = 0; kb < KSt; kb += 8) {
-          T a[8];
+      const int RT = (M + 15) / 16, CT = (N + 15) / 16, NTL = RT * CT;
+      const T* tbs = s ? tb[1] : tb[0];
+      // two output tiles of the wave at a time; the A fragments (L_g C, read
+      // from L2 / the infinity cache) of both tiles for a batch of KB k steps
+      // are requested together before the first MFMA, so one memory latency
+      // covers the batch (FP32: KB = 32 covers M <= 128 in one batch)
+      constexpr int KB = sizeof(T) == 4 ? 32 : 16;
+      const int KSt = MP4 / 4;
+      for (int t0 = wv; t0 < NTL; t0 += 8) {
+        const int t1 = t0 + 4;
+        const bool has1 = t1 < NTL;
+        const int rt0 = t0 / CT, ct0 = t0 % CT, rt1 = (has1 ? t1 : t0) / CT, ct1 = (has1 ? t1 : t0) % CT;
+        // rows past M clamped to the last one (their results are never stored)
+        const int prow0 = min(16 * rt0 + li, M - 1), prow1 = min(16 * rt1 + li, M - 1);
+        acc_t ar0 = MM::zero(), ai0 = MM::zero(), ar1 = MM::zero(), ai1 = MM::zero();
+        for (int kb = 0; kb < KSt; kb += KB) {
+          T a0[KB], a1[KB];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int m = 4 * (kb + j) + lk;
-            a[j] = (kb + j < KSt && m < M && prow < M) ? A[(long)m * M + prow] : (T)0;
+          for (int j = 0; j < KB; ++j) {
+            const int m = min(4 * (kb + j) + lk, M - 1);
+            const bool ok = kb + j < KSt && 4 * (kb + j) + lk < M;
+            const T x0 = A[(long)m * M + prow0];
+            const T x1 = A[(long)m * M + prow1];
+            a0[j] = ok ? x0 : (T)0;
+            a1[j] = ok ? x1 : (T)0;
           }
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
+          for (int j = 0; j < KB; ++j) {
             if (kb + j < KSt) {
               const int m = 4 * (kb + j) + lk;
-              const T* tbs = s ? tb[1] : tb[0];
-              const T br = tbs[m * NPmax + 16 * ct + li];
-              const T bi = tbs[MP4 * NPmax + m * NPmax + 16 * ct + li];
-              ar = MM::mma(a[j], br, ar);
-              ai = MM::mma(a[j], bi, ai);
+              const T br0 = tbs[m * NPmax + 16 * ct0 + li];
+              const T bi0 = tbs[MP4 * NPmax + m * NPmax + 16 * ct0 + li];
+              const T br1 = tbs[m * NPmax + 16 * ct1 + li];
+              const T bi1 = tbs[MP4 * NPmax + m * NPmax + 16 * ct1 + li];
+              ar0 = MM::mma(a0[j], br0, ar0);
+              ai0 = MM::mma(a0[j], bi0, ai0);
+              ar1 = MM::mma(a1[j], br1, ar1);
+              ai1 = MM::mma(a1[j], bi1, ai1);
             }
           }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = 16 * rt + MM::row(lk, v), c = 16 * ct + li;
-          if (r < M && c < N) {
-            pb[r * Nmax + c] = (T)ar[v];
-            pb[M * Nmax + r * Nmax + c] = (T)ai[v];
+          const int r0 = 16 * rt0 + MM::row(lk, v), c0 = 16 * ct0 + li;
+          if (r0 < M && c0 < N) {
+            pb[r0 * Nmax + c0] = (T)ar0[v];
+            pb[M * Nmax + r0 * Nmax + c0] = (T)ai0[v];
+          }
+          const int r1 = 16 * rt1 + MM::row(lk, v), c1 = 16 * ct1 + li;
+          if (has1 && r1 < M && c1 < N) {
+            pb[r1 * Nmax + c1] = (T)ar1[v];
+            pb[M * Nmax + r1 * Nmax + c1] = (T)ai1[v];
           }
         }
       }
