@@ -2147,10 +2147,14 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
     bcol[t] = min(16 * (tile % CT) + li, Nt - 1) * LDK;
   }
   // one product of an M x M operator with the current term: real (B1 - I) or
-  // complex A, both from LDS
+  // complex A, both from LDS.  The complex product takes three real products
+  // (Gauss): P1 = Ar Tr, P2 = Ai Ti, P3 = (Ar + Ai)(Tr + Ti), re = P1 - P2,
+  // im = P3 - P1 - P2; the sums Ar + Ai and Tr + Ti are formed from the LDS
+  // operands as they are read (on the vector ALU, beside the matrix core).
   auto product = [&](bool cplx, acc_t (&cr)[MT], acc_t (&ci)[MT]) {
+    acc_t cs[MT];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) { cr[t] = MM::zero(); ci[t] = MM::zero(); }
+    for (int t = 0; t < MT; ++t) { cr[t] = MM::zero(); ci[t] = MM::zero(); cs[t] = MM::zero(); }
     const T* br_ = tt(cur, 0);
     const T* bi_ = tt(cur, 1);
     int k0 = 0;
@@ -2171,9 +2175,8 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             cr[t] = MM::mma(a_r[j], b_r[t][j], cr[t]);
-            cr[t] = MM::mma(-a_i[j], b_i[t][j], cr[t]);
-            ci[t] = MM::mma(a_r[j], b_i[t][j], ci[t]);
-            ci[t] = MM::mma(a_i[j], b_r[t][j], ci[t]);
+            ci[t] = MM::mma(a_i[j], b_i[t][j], ci[t]);
+            cs[t] = MM::mma(a_r[j] + a_i[j], b_r[t][j] + b_i[t][j], cs[t]);
           }
         } else {
           const t4 a = *(const t4*)(Bm + arow[t] + kk);
@@ -2195,14 +2198,21 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
           const T a_r = Ar[arow[t] + k];
           const T a_i = Ai[arow[t] + k];
           cr[t] = MM::mma(a_r, b_r, cr[t]);
-          cr[t] = MM::mma(-a_i, b_i, cr[t]);
-          ci[t] = MM::mma(a_r, b_i, ci[t]);
-          ci[t] = MM::mma(a_i, b_r, ci[t]);
+          ci[t] = MM::mma(a_i, b_i, ci[t]);
+          cs[t] = MM::mma(a_r + a_i, b_r + b_i, cs[t]);
         } else {
           const T a = Bm[arow[t] + k];
           cr[t] = MM::mma(a, b_r, cr[t]);
           ci[t] = MM::mma(a, b_i, ci[t]);
         }
+      }
+    }
+    if (cplx) {  // cr = P1, ci = P2, cs = P3
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const acc_t p1 = cr[t], p2 = ci[t];
+        cr[t] = p1 - p2;
+        ci[t] = cs[t] - p1 - p2;
       }
     }
   };
