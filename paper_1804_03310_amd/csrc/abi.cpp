@@ -190,6 +190,11 @@ struct afqmc_ham {
   double* h = nullptr;   // [M][M]
   double* L = nullptr;   // [G][M][M]
   float* Lf = nullptr;   // [G][M][M]
+  // upper triangles of the symmetric L_g, [G][M (M + 1) / 2] (row i: columns
+  // i .. M - 1): the propagator build of the fused propagation writes A in
+  // the same packed form (half the GEMM and half its output)
+  double* Lp = nullptr;
+  float* Lpf = nullptr;
   void* Lbf = nullptr;   // [G][M][M] bf16
   void* Lbf_lo = nullptr;  // [G][M][M] bf16, second term of the split (BF16X3)
   double* L2 = nullptr;  // sum_g L_g L_g
@@ -730,6 +735,8 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
   const int W = wk->n_walkers, M = hm->M, G = hm->G, Nt = tr->Nt;
   const long mn = (long)M * Nt, mm = (long)M * M;
   const TC* Lc = std::is_same<TC, float>::value ? (const TC*)hm->Lf : (const TC*)hm->L;
+  const TC* Lpc = std::is_same<TC, float>::value ? (const TC*)hm->Lpf : (const TC*)hm->Lp;
+  const int Mp = M * (M + 1) / 2;
   constexpr bool BF = std::is_same<TC, Bf16Tag>::value;
   const TT* B1m = std::is_same<TT, float>::value ? (const TT*)b1->d32 : (const TT*)b1->d64;
   TC* coefT = (TC*)ws.coefT;  // [2W][Gp] row-major (BF16: the kernels' own layout)
@@ -752,11 +759,15 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
       AFQ_CK(afq::fields_coeff<TC>(st, W, G, Gp, seed, t, wk->system_id, dt, ws.v_re, ws.v_im,
                                    tr->lbar, coefT, ws.mf_re, ws.mf_im, nullptr, hyr, hyi));
     }
+    const bool fused = afq::propagate_fused_fits(M, Nt, sizeof(TT), hm->max_lds);
+    const bool packed = fused && !BF;  // A as upper triangles (A is symmetric)
     if (G > 0) {
       TimedLaunch tl(&hm->timer, KC_ABUILD, st);
       if constexpr (BF) {
         AFQ_CK(afq::gemm_bf16<TT>(st, 2 * W, (int)mm, G, ws.coefT, coef_lo, G, hm->Lbf,
                                   x3 ? hm->Lbf_lo : nullptr, (int)mm, A, (int)mm, 1.0));
+      } else if (packed) {
+        AFQ_CK((afq::abuild<TC, TT>(st, 2 * W, Mp, G, Gp, coefT, Lpc, A)));
       } else {
         AFQ_CK((afq::abuild<TC, TT>(st, 2 * W, (int)mm, G, Gp, coefT, Lc, A)));
       }
@@ -766,8 +777,8 @@ afqmc_status propagate_typed(afqmc_trial* tr, afqmc_walkers* wk, const WS& ws, B
     // phi -> P = B1 phi, ACC = P
     {
     TimedLaunch tl_t(&hm->timer, KC_TAYLOR, st);
-    if (afq::propagate_fused_fits(M, Nt, sizeof(TT), hm->max_lds)) {
-      AFQ_CK(afq::propagate_fused<TT>(st, W, M, Nt, opt->taylor_order, A, B1m, wk->phi_re,
+    if (fused) {
+      AFQ_CK(afq::propagate_fused<TT>(st, W, M, Nt, opt->taylor_order, packed, A, B1m, wk->phi_re,
                                       wk->phi_im, hm->max_lds));
     } else {
     AFQ_CK((afq::cgemm_walkers<TT, double, false, 0>(st, W, M, Nt, M, B1m, nullptr, M, 0,
@@ -922,7 +933,9 @@ afqmc_status afqmc_init_hamiltonian(afqmc_ham** out, int device, void* stream, i
   void *ph, *pL, *pLf, *pL2, *pLb;
   if (hm->arena.alloc(&ph, mm * 8) || hm->arena.alloc(&pL, gmm * 8) ||
       hm->arena.alloc(&pLf, gmm * 4) || hm->arena.alloc(&pL2, mm * 8) ||
-      hm->arena.alloc(&pLb, gmm * 2) || hm->arena.alloc(&hm->Lbf_lo, gmm * 2)) {
+      hm->arena.alloc(&pLb, gmm * 2) || hm->arena.alloc(&hm->Lbf_lo, gmm * 2) ||
+      hm->arena.alloc((void**)&hm->Lp, (size_t)n_chol * (mm + M) / 2 * 8) ||
+      hm->arena.alloc((void**)&hm->Lpf, (size_t)n_chol * (mm + M) / 2 * 4)) {
     hm->arena.release();
     delete hm;
     return fail(AFQMC_ERR_OOM, "hamiltonian allocation failed");
@@ -941,6 +954,17 @@ afqmc_status afqmc_init_hamiltonian(afqmc_ham** out, int device, void* stream, i
   if (n_chol > 0) {
     if (hipMemcpyAsync(hm->L, L, gmm * 8, hipMemcpyHostToDevice, st) != hipSuccess) return bad("L upload");
     if (afq::convert_f64_f32(st, hm->L, hm->Lf, (long)gmm) != hipSuccess) return bad("L convert");
+    {  // upper triangles, row by row
+      std::vector<double> lp((size_t)n_chol * (mm + M) / 2);
+      size_t o = 0;
+      for (int g = 0; g < n_chol; ++g)
+        for (int i = 0; i < M; ++i)
+          for (int j = i; j < M; ++j) lp[o++] = L[(size_t)g * mm + (size_t)i * M + j];
+      if (hipMemcpyAsync(hm->Lp, lp.data(), lp.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess ||
+          afq::convert_f64_f32(st, hm->Lp, hm->Lpf, (long)lp.size()) != hipSuccess)
+        return bad("packed L");
+    }
     if (afq::convert_f64_bf16(st, hm->L, hm->Lbf, (long)gmm) != hipSuccess ||
         afq::convert_f64_bf16_lo(st, hm->L, hm->Lbf_lo, (long)gmm) != hipSuccess)
       return bad("L convert");
@@ -970,7 +994,8 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
   auto rnd = [&](size_t b) { return (std::max(b, a) + a - 1) / a * a; };
   const int nel[2] = {n_up, n_dn};
   const size_t MP4 = round_up(M, 4), MP32 = round_up(M, 32), Nt = (size_t)n_up + n_dn;
-  size_t tot = rnd(mm * 8) * 2 + rnd(g * mm * 8) + rnd(g * mm * 4) + 2 * rnd(g * mm * 2);  // ham
+  size_t tot = rnd(mm * 8) * 2 + rnd(g * mm * 8) + rnd(g * mm * 4) + 2 * rnd(g * mm * 2) +
+               rnd(g * (mm + m) / 2 * 12);  // ham (with the packed L copies)
   for (int s = 0; s < 2; ++s) {                                                        // trial
     const size_t NP = round_up(std::max(nel[s], 1), 16);
     const size_t nlt = (g * MP4 + 16) * NP;

@@ -2082,7 +2082,7 @@ inline int taylor_ldk(int MP4) { return ((MP4 / 4) & 1) ? MP4 : MP4 + 4; }
 
 template <typename T, int MT, bool SB>
 __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4, int LDK, int order,
-                                                         const T* __restrict__ A,
+                                                         int packed, const T* __restrict__ A,
                                                          const T* __restrict__ B1m,
                                                          double* __restrict__ phr,
                                                          double* __restrict__ phi) {
@@ -2098,15 +2098,38 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
   T* Bm = Ai + M * LDK;  // (B1 - I)[i][k]
   T* TT = Bm + M * LDK;  // ping-pong term buffers, transposed [Nt][LDK] (re, im)
   auto tt = [&](int buf, int part) { return TT + (2 * buf + part) * Nt * LDK; };
-  const T* Ag = A + (long)w * 2 * mm;
   // rows by wavefronts, the contiguous index by lanes (no index division)
-  for (int i = wv; i < M; i += NWAVE)
-    for (int k = l; k < LDK; k += AFQ_WAVE) {
-      const bool ok = k < M;
-      Ar[i * LDK + k] = ok ? Ag[(long)i * M + k] : (T)0;
-      Ai[i * LDK + k] = ok ? Ag[mm + (long)i * M + k] : (T)0;
-      Bm[i * LDK + k] = ok ? B1m[(long)i * M + k] : (T)0;
+  if (packed) {
+    // A symmetric, stored as its upper triangle [2][M (M + 1) / 2] (row i holds
+    // columns i .. M - 1): each entry goes to (i, k) and (k, i)
+    const long mp = (long)M * (M + 1) / 2;
+    const T* Ag = A + (long)w * 2 * mp;
+    for (int i = wv; i < M; i += NWAVE) {
+      const long rs = (long)i * M - (long)i * (i - 1) / 2 - i;
+      for (int k = l; k < LDK; k += AFQ_WAVE) {
+        if (k >= i && k < M) {
+          const T xr = Ag[rs + k], xi = Ag[mp + rs + k];
+          Ar[i * LDK + k] = xr;
+          Ai[i * LDK + k] = xi;
+          Ar[k * LDK + i] = xr;
+          Ai[k * LDK + i] = xi;
+        } else if (k >= M) {
+          Ar[i * LDK + k] = (T)0;
+          Ai[i * LDK + k] = (T)0;
+        }
+        Bm[i * LDK + k] = k < M ? B1m[(long)i * M + k] : (T)0;
+      }
     }
+  } else {
+    const T* Ag = A + (long)w * 2 * mm;
+    for (int i = wv; i < M; i += NWAVE)
+      for (int k = l; k < LDK; k += AFQ_WAVE) {
+        const bool ok = k < M;
+        Ar[i * LDK + k] = ok ? Ag[(long)i * M + k] : (T)0;
+        Ai[i * LDK + k] = ok ? Ag[mm + (long)i * M + k] : (T)0;
+        Bm[i * LDK + k] = ok ? B1m[(long)i * M + k] : (T)0;
+      }
+  }
   const long wb = (long)w * mn;
   // phi read row-major (coalesced), stored transposed; padding k >= M zero
   for (int k = wv; k < MP4; k += NWAVE)
@@ -2311,8 +2334,8 @@ size_t taylor_lds(int M, int Nt, size_t elem) {
 }  // namespace
 
 template <typename T>
-hipError_t propagate_fused(hipStream_t st, int W, int M, int Nt, int order, const T* A,
-                           const T* B1m, double* phr, double* phi, size_t max_lds) {
+hipError_t propagate_fused(hipStream_t st, int W, int M, int Nt, int order, bool packed,
+                           const T* A, const T* B1m, double* phr, double* phi, size_t max_lds) {
   const int MP4 = ((M + 3) / 4) * 4, LDK = taylor_ldk(MP4);
   const int CT = (Nt + 15) / 16;
   const int ntile = ((M + 15) / 16) * CT;
@@ -2322,7 +2345,7 @@ hipError_t propagate_fused(hipStream_t st, int W, int M, int Nt, int order, cons
   const bool sb = NWAVE % CT == 0;
 #define AFQ_PF(MTV, SBV)                                                                          \
   hipLaunchKernelGGL((k_propagate_fused<T, MTV, SBV>), dim3(W), dim3(64 * NWAVE), lds, st, M, Nt,   \
-                     MP4, LDK, order, A, B1m, phr, phi)
+                     MP4, LDK, order, packed ? 1 : 0, A, B1m, phr, phi)
   if (mt <= 1) AFQ_PF(1, false);
   else if (mt <= 2) { if (sb) AFQ_PF(2, true); else AFQ_PF(2, false); }
   else if (mt <= 4) { if (sb) AFQ_PF(4, true); else AFQ_PF(4, false); }
@@ -2336,9 +2359,9 @@ bool propagate_fused_fits(int M, int Nt, size_t elem, size_t max_lds) {
   return taylor_lds(M, Nt, elem) <= max_lds && ntile <= 8 * NWAVE;
 }
 
-template hipError_t propagate_fused<float>(hipStream_t, int, int, int, int, const float*,
+template hipError_t propagate_fused<float>(hipStream_t, int, int, int, int, bool, const float*,
                                            const float*, double*, double*, size_t);
-template hipError_t propagate_fused<double>(hipStream_t, int, int, int, int, const double*,
+template hipError_t propagate_fused<double>(hipStream_t, int, int, int, int, bool, const double*,
                                             const double*, double*, double*, size_t);
 
 }  // namespace afq

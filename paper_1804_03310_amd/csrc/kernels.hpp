@@ -237,8 +237,10 @@ hipError_t exchange_bf16(hipStream_t st, int W, int M, int MP32, int Nt, int G, 
 
 namespace afq {
 // Fused B1 exp(A) B1 for small M (one block per walker; see kernels.hip).
+// packed: A per walker as the upper triangles [2][M (M + 1) / 2] (re, im)
+// instead of [2][M][M].
 template <typename T>
-hipError_t propagate_fused(hipStream_t st, int W, int M, int Nt, int order, const T* A,
-                           const T* B1m, double* phr, double* phi, size_t max_lds);
+hipError_t propagate_fused(hipStream_t st, int W, int M, int Nt, int order, bool packed,
+                           const T* A, const T* B1m, double* phr, double* phi, size_t max_lds);
 bool propagate_fused_fits(int M, int Nt, size_t elem, size_t max_lds);
 }  // namespace afq
