@@ -35,7 +35,18 @@ __device__ inline int res_find_member(const ResMember* mem, int n_mem, int b) {
   return __builtin_amdgcn_readfirstlane(m);
 }
 
-// Out = In + B (In), B real [M][M], In complex [M][Nt], all in LDS.
+// Sum of n values x[i * stride] by one wavefront in an order fixed by n alone
+// (lane l adds i = l, l + 64, ... in turn, then the 64 lanes by a fixed
+// butterfly), whatever the block size; every lane gets the total.
+__device__ inline double wave_fixed_sum(const double* x, int n, int stride) {
+  double v = 0.0;
+  for (int i = lane_id(); i < n; i += AFQ_WAVE) v += x[i * stride];
+  return wave_sum(v);
+}
+
+// Out = In + B (In), B real [M][M], In complex [M][Nt], all in LDS.  (At the
+// sizes this kernel takes, thread-per-element products are faster than FP64
+// MFMA tiles, whose dependent chains leave one wavefront waiting.)
 __device__ void res_apply_b1(int M, int Nt, const double* B, const double* Inr,
                              const double* Ini, double* Outr, double* Outi) {
   const int n = M * Nt;
@@ -167,6 +178,106 @@ __device__ zdbl res_gj_inverse(int N, double* Sr, double* Si) {
   return zdbl{log(pm) + pe * 0.69314718055994530942, atan2(phi, phr)};
 }
 
+// The same inverse for N <= 8 with the rows in registers (lane i owns row
+// i) and implicit pivoting: column k is eliminated with the unused row of
+// largest |S_ik| (lowest row on ties), the pivot row broadcast by lane reads,
+// no row exchanges and no LDS traffic until the end, where
+// S^-1[k(i)][p(j)] = R[i][j] is written back (p(k): the pivot row of column k;
+// k(i): the column row i was the pivot of).  log det as res_gj_inverse, with
+// the sign of the pivot permutation from its inversion count.
+constexpr int kGjRegMax = 8;
+__device__ __noinline__ zdbl res_gj_inverse_reg(int N, double* Sr, double* Si) {
+  constexpr int NR = kGjRegMax;
+  const int l = lane_id();
+  double xr[NR], xi[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const bool ok = l < N && j < N;
+    xr[j] = ok ? Sr[l * N + j] : 0.0;
+    xi[j] = ok ? Si[l * N + j] : 0.0;
+  }
+  double pm = 1.0, phr = 1.0, phi = 0.0;
+  int pe = 0, used = 0, myk = 0, myp = 0;
+  int np2 = 1;
+  while (np2 < N) np2 <<= 1;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    if (k >= N) break;
+    double key = (l < N && !used) ? xr[k] * xr[k] + xi[k] * xi[k] : -1.0;
+    int idx = l < N && !used ? l : 64;
+    for (int o = np2 >> 1; o >= 1; o >>= 1) {
+      const double ok2 = __shfl_xor(key, o, AFQ_WAVE);
+      const int oi = __shfl_xor(idx, o, AFQ_WAVE);
+      if (ok2 > key || (ok2 == key && oi < idx)) { key = ok2; idx = oi; }
+    }
+    const int p = __builtin_amdgcn_readfirstlane(idx);
+    if (l == k) myp = p;
+    const double pvr = __shfl(xr[k], p, AFQ_WAVE), pvi = __shfl(xi[k], p, AFQ_WAVE);
+    const double mag = sqrt(pvr * pvr + pvi * pvi);
+    const double rm = 1.0 / mag;
+    const double ur = pvr * rm, ui = pvi * rm;
+    {
+      int e;
+      pm = frexp(pm * mag, &e);
+      pe += e;
+      const double nr = phr * ur - phi * ui, ni = phr * ui + phi * ur;
+      phr = nr;
+      phi = ni;
+    }
+    const double ir = ur * rm, ii = -ui * rm;  // 1 / pivot
+    const bool piv = l == p;
+    if (piv) {
+      used = 1;
+      myk = k;
+    }
+    // f = S_lk / pivot for the other rows
+    const double fr = xr[k] * ir - xi[k] * ii, fi = xr[k] * ii + xi[k] * ir;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      if (j >= N) break;
+      // every lane reads the pivot row's entry before anyone changes it
+      const double rr = __shfl(xr[j], p, AFQ_WAVE), ri = __shfl(xi[j], p, AFQ_WAVE);
+      double nr, ni;
+      if (j == k) {
+        nr = piv ? ir : -fr;
+        ni = piv ? ii : -fi;
+      } else if (piv) {
+        nr = xr[j] * ir - xi[j] * ii;
+        ni = xr[j] * ii + xi[j] * ir;
+      } else {
+        nr = xr[j] - (fr * rr - fi * ri);
+        ni = xi[j] - (fr * ri + fi * rr);
+      }
+      xr[j] = nr;
+      xi[j] = ni;
+    }
+  }
+  // sign of the pivot permutation k -> p(k): its inversion count
+  int inv = 0;
+  for (int k2 = 0; k2 < N; ++k2) {
+    const int pk2 = __builtin_amdgcn_readlane(myp, k2);
+    if (l < N && k2 > l && pk2 < myp) ++inv;
+  }
+  const double invd = wave_sum((double)inv);
+  if (((long)invd) & 1) {
+    phr = -phr;
+    phi = -phi;
+  }
+  wave_lds_sync();
+  if (l < N) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      if (j < N) {
+        const int pj = __builtin_amdgcn_readlane(myp, j);
+        Sr[myk * N + pj] = xr[j];
+        Si[myk * N + pj] = xi[j];
+      }
+    }
+  }
+  wave_lds_sync();
+  return zdbl{log(pm) + pe * 0.69314718055994530942, atan2(phi, phr)};
+}
+
 // log det of both spins' overlaps S = D_0^T phi, inverses left in Y (spin 0
 // at Y[0 .. n0^2), spin 1 after it).  Results in sc[0..3].
 __device__ void res_overlaps(const ResMember& P, const ResLds& Lo, double* sm) {
@@ -197,7 +308,8 @@ __device__ void res_overlaps(const ResMember& P, const ResLds& Lo, double* sm) {
     const int N = s ? n1 : n0;
     if (wv != (nwv > 1 ? s : 0)) continue;
     zdbl ld = {0.0, 0.0};
-    if (N > 0) ld = res_gj_inverse(N, Yr + (s ? n0 * n0 : 0), Yi + (s ? n0 * n0 : 0));
+    if (N > kGjRegMax) ld = res_gj_inverse(N, Yr + (s ? n0 * n0 : 0), Yi + (s ? n0 * n0 : 0));
+    else if (N > 0) ld = res_gj_inverse_reg(N, Yr + (s ? n0 * n0 : 0), Yi + (s ? n0 * n0 : 0));
     if (lane_id() == 0) {
       sm[Lo.sc + 2 * s] = ld.re;
       sm[Lo.sc + 2 * s + 1] = ld.im;
@@ -278,29 +390,32 @@ __device__ void res_measure(const ResMember& P, const ResLds& Lo, double* sm) {
       }
       continue;
     }
-    for (int task = threadIdx.x; task < G * N; task += blockDim.x) {
-      const double* lt = Lt + task * M;  // row a of Ltil_g, task = g N + a
-      for (int b0 = 0; b0 < N; b0 += 8) {
-        double ar[8], ai[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) ar[j] = ai[j] = 0.0;
-        for (int m = 0; m < M; ++m) {
-          const double l = lt[m];
-          const double* tr = Xr + m * Nt + off + b0;
-          const double* ti = Xi + m * Nt + off + b0;
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (b0 + j < N) {
-              ar[j] = fma(l, tr[j], ar[j]);
-              ai[j] = fma(l, ti[j], ai[j]);
-            }
+    // X for all g as one FP64 MFMA product: rows (g, a) of Ltil (k = m)
+    // times Theta's spin columns, 16 x 16 output tiles over the wavefronts;
+    // rows and columns past the ends are clamped (computed, never stored)
+    {
+      typedef Mfma<double> MM;
+      const int R = G * N, RT = (R + 15) / 16, CT = (N + 15) / 16, KS = (M + 3) / 4;
+      const int li = lane_id() & 15, lk = lane_id() >> 4;
+      const int nwv = blockDim.x / AFQ_WAVE;
+      for (int t = wave_id(); t < RT * CT; t += nwv) {
+        const int rt = t / CT, ct = t - rt * CT;
+        const int row = min(16 * rt + li, R - 1), colc = off + min(16 * ct + li, N - 1);
+        MM::acc_t cr = MM::zero(), ci = MM::zero();
+        for (int ks = 0; ks < KS; ++ks) {
+          const int k = 4 * ks + lk, kc = min(k, M - 1);
+          const double av = k < M ? Lt[row * M + kc] : 0.0;
+          cr = MM::mma(av, Xr[kc * Nt + colc], cr);
+          ci = MM::mma(av, Xi[kc * Nt + colc], ci);
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (b0 + j < N) {
-            Qr[task * N + b0 + j] = ar[j];
-            Qi[task * N + b0 + j] = ai[j];
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * rt + MM::row(lk, v), c = 16 * ct + li;
+          if (r < R && c < N) {
+            Qr[r * N + c] = cr[v];
+            Qi[r * N + c] = ci[v];
           }
+        }
       }
     }
     __syncthreads();
@@ -343,31 +458,31 @@ __device__ void res_measure(const ResMember& P, const ResLds& Lo, double* sm) {
     cfi[g] = tri[g] + tri[G1 + g];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double e1r = 0.0, e1i = 0.0;
-    for (int c = 0; c < Nt; ++c) {
-      e1r += red[2 * c];
-      e1i += red[2 * c + 1];
-    }
-    double ejr = 0.0, eji = 0.0, ekr = 0.0, eki = 0.0;
-    int fin = 1;
-    for (int g = 0; g < G; ++g) {
+  // the sums over g and over columns by wavefront 0, in fixed orders
+  if (wave_id() == 0) {
+    const double e1r = wave_fixed_sum(red, Nt, 2), e1i = wave_fixed_sum(red + 1, Nt, 2);
+    double ejr = 0.0, eji = 0.0, ekr = 0.0, eki = 0.0, bad = 0.0;
+    for (int g = lane_id(); g < G; g += AFQ_WAVE) {
       const double vr = cfr[g], vi = cfi[g];
-      if (!isfinite(vr) || !isfinite(vi)) fin = 0;
+      if (!isfinite(vr) || !isfinite(vi)) bad = 1.0;
       ejr += vr * vr - vi * vi;
       eji += 2.0 * vr * vi;
+      ekr += xxr[g] + xxr[G1 + g];
+      eki += xxi[g] + xxi[G1 + g];
     }
-    for (int s = 0; s < 2; ++s)
-      for (int g = 0; g < G; ++g) {
-        ekr += xxr[s * G1 + g];
-        eki += xxi[s * G1 + g];
-      }
-    double* sc = sm + Lo.sc;
-    sc[4] = P.e_core + e1r + 0.5 * ejr - 0.5 * ekr;
-    sc[5] = e1i + 0.5 * eji - 0.5 * eki;
-    sc[6] = sc[0] + sc[2];
-    sc[7] = sc[1] + sc[3];
-    sc[8] = fin ? 1.0 : 0.0;
+    ejr = wave_sum(ejr);
+    eji = wave_sum(eji);
+    ekr = wave_sum(ekr);
+    eki = wave_sum(eki);
+    bad = wave_sum(bad);
+    if (lane_id() == 0) {
+      double* sc = sm + Lo.sc;
+      sc[4] = P.e_core + e1r + 0.5 * ejr - 0.5 * ekr;
+      sc[5] = e1i + 0.5 * eji - 0.5 * eki;
+      sc[6] = sc[0] + sc[2];
+      sc[7] = sc[1] + sc[3];
+      sc[8] = bad == 0.0 ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
 }
@@ -516,14 +631,12 @@ __global__ __launch_bounds__(512) void k_res_steps(const ResMember* __restrict__
       red[2 * q + 1] = pi;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double mr = 0.0, mi = 0.0;
-      for (int q = 0; q < nq; ++q) {
-        mr += red[2 * q];
-        mi += red[2 * q + 1];
+    if (wave_id() == 0) {
+      const double mr = wave_fixed_sum(red, nq, 2), mi = wave_fixed_sum(red + 1, nq, 2);
+      if (lane_id() == 0) {
+        sc[10] = mr;
+        sc[11] = mi;
       }
-      sc[10] = mr;
-      sc[11] = mi;
     }
     // A = i sq sum_g xs_g L_g (symmetric): upper triangle, mirrored
     for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
