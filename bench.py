@@ -168,6 +168,43 @@ def accuracy_check(afq, torch, wl, inp, ham, trial, opt_kw):
             "reference": "FP64 oracle sums stored in tests/golden/" + fname}
 
 
+def kernel_error_check(afq, torch, wl, inp, ham, trial, opt_kw, W, n_steps=5):
+    """Per-step E_L error of the run's precision where no stored oracle run
+    exists: the walkers after n_steps FP64 steps (population control off)
+    are measured once with the run's contraction precision and once in FP64
+    (the FP64 path is held to the oracle by the parity tests at this size);
+    the largest |dE_L| over the live walkers, in Ha, against the 0.1 mHa
+    gate."""
+    w = afq.Walkers(trial, W)
+    afq.walkers_from_trial(ham, trial, w)
+    kw = dict(opt_kw)
+    prec = kw.pop("chol_prec")
+    kw.pop("taylor_prec")
+    kw.pop("weight_mode", None)
+    kw.pop("meas_every", None)
+    base = afq.Options(e_trial=0.0, pc_every=0, chol_prec="fp64", taylor_prec="fp64", **kw)
+    afq.propagate(ham, trial, w, n_steps, wl.dt, 7, 0, base)
+    torch.cuda.synchronize()
+    el64 = w.eloc[0].cpu().numpy().copy()
+    alive = (w.weight > 0).cpu().numpy()
+    phi_re, phi_im = w.phi_re.clone(), w.phi_im.clone()
+    route = trial.exchange_route
+    if prec in ("bf16", "bf16x3"):
+        trial.exchange_route = "ltilde"
+    afq.propagate(ham, trial, w, 0, wl.dt, 7, n_steps,
+                  afq.Options(e_trial=0.0, pc_every=0, chol_prec=prec, taylor_prec="fp64", **kw))
+    trial.exchange_route = route
+    el = w.eloc[0].cpu().numpy()
+    w.phi_re.copy_(phi_re)
+    w.phi_im.copy_(phi_im)
+    d = np.abs(el - el64)[alive]
+    err = float(d.max()) if d.size else float("nan")
+    return {"max_abs_dEL_Ha": err, "gate_Ha": 1e-4, "pass": bool(err <= 1e-4),
+            "walkers": int(W), "after_steps": n_steps, "contraction_prec": prec,
+            "reference": "the FP64 GPU path on the same walkers (pinned to the FP64 oracle by the "
+                         "parity tests); one measurement in the run's contraction precision"}
+
+
 def serving_bench(args):
     """Mixed request stream through the serving loop (paper_1804_03310_amd.serving):
     Poisson arrivals at 20 requests/s, M uniform over {20, 40, 80, 120, 160}
@@ -838,6 +875,9 @@ def main():
                                    "bytes_read": x.numel() * 8, "bytes_written": y.numel() * 8}
     if not args.no_accuracy and wl.name in GOLDEN and args.weight_mode == "local":
         out["accuracy"] = accuracy_check(afq, torch, wl, inp, ham, trial, opt_kw)
+    elif not args.no_accuracy:
+        out["accuracy"] = kernel_error_check(afq, torch, wl, inp, ham, trial, opt_kw,
+                                             min(W, 256))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, inp, args.cpu_walkers, args.cpu_steps)
     print(json.dumps(out), flush=True)
