@@ -75,12 +75,43 @@ def fbias_flops_per_walker(M, n_up, n_dn, G):
     return 4 * M * (n_up + n_dn) * G
 
 
-def multidet_flops_per_walker(M, n_up, n_dn, G):
+def multidet_flops_per_walker(M, n_up, n_dn, G, rows=None):
     """Multi-determinant energy: per spin and per g (the G vectors and h),
-    P_g = (C^T L_g) Theta_0 (real M x M times complex M x N: 4 M^2 N flops)
-    and X0^2 = P[:N] P[:N] (complex N x N x N: 8 N^3 flops); the per-determinant
-    corrections are O(E^2 N) and not counted."""
-    return sum((G + 1) * (4 * M * M * n + 8 * n ** 3) for n in (n_up, n_dn) if n)
+    P_g = (C^T L_g) Theta_0 over the rows formed (all M, or the R = N +
+    distinct-particle rows of the compact-row kernel: real R x M times complex
+    M x N, 4 R M N flops) and X0^2 = P[:N] P[:N] (complex N x N x N: 8 N^3);
+    the compact-row kernel also forms Ghat at its particle rows once (4 (R - N)
+    M N).  The per-determinant corrections are O(E^2 N) and not counted."""
+    f = 0
+    for s, n in enumerate((n_up, n_dn)):
+        if not n:
+            continue
+        r = M if rows is None else rows[s]
+        f += (G + 1) * (4 * r * M * n + 8 * n ** 3)
+        if rows is not None:
+            f += 4 * (r - n) * M * n
+    return f
+
+
+def multidet_compact_rows(M, n_up, n_dn, exc, chol_prec):
+    """Rows per spin that the FP32 compact-row energy kernel forms (N plus the
+    distinct particle orbitals of the determinants), or None where the
+    full-row kernel runs (FP64, or past the compact kernel's limits: M <= 128,
+    N <= 16, at most 256 determinants, 4 KS RP <= 12288 with KS = 16 for
+    M <= 64, else 32, and RP = R rounded up to 16)."""
+    n_det = exc.shape[0]
+    if chol_prec != "fp32" or M > 128 or max(n_up, n_dn) > 16 or n_det > 256:
+        return None
+    ks = 16 if M <= 64 else 32
+    max_exc = (exc.shape[2] - 1) // 2
+    rows = []
+    for s, n in enumerate((n_up, n_dn)):
+        parts = {int(exc[i, s, 1 + max_exc + e]) for i in range(n_det) for e in range(int(exc[i, s, 0]))}
+        r = n + len(parts)
+        if 4 * ks * (-(-r // 16) * 16) > 12288:
+            return None
+        rows.append(r)
+    return rows
 
 
 def resident_flops_per_walker(M, n_up, n_dn, G, order):
@@ -775,8 +806,12 @@ def main():
     # where it runs as one fused launch, the Taylor propagation; the one with
     # the larger time per step is reported, the other under "roofline_other"
     if multi:
-        ex_flops = multidet_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
-        ex_name = "k_md_energy (P = (C^T L_g) Theta_0, X0^2, per-determinant corrections)"
+        md_rows = multidet_compact_rows(wl.M, wl.n_up, wl.n_dn, inp.exc, chol_prec)
+        ex_flops = multidet_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol, md_rows) * W
+        ex_name = ("k_md_energy (P = (C^T L_g) Theta_0, X0^2, per-determinant corrections)"
+                   if md_rows is None else
+                   f"k_md_energy_rows (P = (C^T L_g) Theta_0 over {md_rows[0]} + {md_rows[1]} "
+                   "compact rows, X0^2, per-determinant corrections)")
     elif route == "q":
         ex_flops = qform_flops_per_walker(wl.M, wl.n_up, wl.n_dn) * W
         ex_name = "k_qform (theta^T Q theta, upper-triangular tile pairs)"

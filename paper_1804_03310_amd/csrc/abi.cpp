@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -255,6 +256,12 @@ struct afqmc_trial {
   double* d_coeff = nullptr;
   double* LC64[2] = {nullptr, nullptr};
   float* LC32[2] = {nullptr, nullptr};
+  // compact rows of the FP32 energy kernel (md_rows: the tables exist)
+  bool md_rows = false;
+  int mdKS = 0, mdR[2] = {0, 0}, mdRP[2] = {0, 0}, mdnp[2] = {0, 0};
+  float* LCc[2] = {nullptr, nullptr};
+  int* d_mdpair[2] = {nullptr, nullptr};
+  int* d_mddx = nullptr;
   double ref_ls[2] = {0, 0}, ref_el[2] = {0, 0};
   double* vref_re = nullptr;
   double* vref_im = nullptr;
@@ -446,6 +453,19 @@ afq::MDParams md_params(const afqmc_trial* tr, bool fp32) {
   }
   p.exc = tr->d_exc;
   p.coeff = tr->d_coeff;
+  std::memset(&p.rows, 0, sizeof(p.rows));
+  if (fp32 && tr->md_rows) {
+    p.rows.ok = 1;
+    p.rows.KS = tr->mdKS;
+    for (int s = 0; s < 2; ++s) {
+      p.rows.R[s] = tr->mdR[s];
+      p.rows.RP[s] = tr->mdRP[s];
+      p.rows.npair[s] = tr->mdnp[s];
+      p.rows.LCc[s] = tr->LCc[s];
+      p.rows.pair[s] = tr->d_mdpair[s];
+    }
+    p.rows.dx = tr->d_mddx;
+  }
   return p;
 }
 
@@ -985,6 +1005,138 @@ void afqmc_free_hamiltonian(afqmc_ham* hm) {
   delete hm;
 }
 
+namespace {
+
+// Whether the compact-row FP32 energy kernel's limits admit a multi-determinant
+// trial of these sizes (its tables are then built at set-up).
+bool md_rows_sizes_ok(int M, int n_up, int n_dn, int n_det) {
+  return n_det > 1 && M <= afq::kMdRowsMaxM && n_det <= afq::kMdRowsMaxDet &&
+         n_up <= afq::kMdRowsMaxN && n_dn <= afq::kMdRowsMaxN;
+}
+
+// Upper bound of the compact-row tables' bytes (rows: N + the distinct
+// particles, at most 2 (n_det - 1) of them), counted by the footprint.
+size_t md_rows_bound_bytes(int M, int G, int n_up, int n_dn, int n_det) {
+  if (!md_rows_sizes_ok(M, n_up, n_dn, n_det)) return 0;
+  auto rnd = [](size_t b) { return (std::max<size_t>(b, 256) + 255) / 256 * 256; };
+  const int nel[2] = {n_up, n_dn};
+  size_t t = rnd((size_t)n_det * afq::kMdDx * 4);
+  for (int s = 0; s < 2; ++s) {
+    if (!nel[s]) continue;
+    const size_t rp = round_up(std::min(M, nel[s] + 2 * (n_det - 1)), 16);
+    const size_t rows = M <= 64 ? 64 : 128;  // 4 KS
+    t += rnd((size_t)(G + 2) * rows * rp * 4) + rnd((size_t)n_det * 16) + rnd((size_t)M * 4);
+  }
+  return t;
+}
+
+// Per spin: the rows the determinants read (the N occupied orbitals, then
+// the distinct particle orbitals ascending), the distinct (particle, hole)
+// pairs, and the packed per-determinant words; then LCc = those rows of LC
+// (slots 0..G) and of C (slot G+1) in FP32.  Leaves md_rows false (the FP32
+// energy runs the full-row kernel) when a limit is not met.
+afqmc_status md_rows_setup(afqmc_trial* tr, const std::vector<int>& exc, hipStream_t st) {
+  const int M = tr->ham->M, G = tr->ham->G, n_det = tr->n_det;
+  tr->md_rows = false;
+  if (!md_rows_sizes_ok(M, tr->nel[0], tr->nel[1], n_det)) return AFQMC_OK;
+  // slot order of the determinants: by the larger excitation rank of the two
+  // spins, then by the ranks, so that the 64-lane slots mix few ranks per spin
+  std::vector<int> order(n_det);
+  for (int i = 0; i < n_det; ++i) order[i] = i;
+  auto rank = [&](int i, int s) { return exc[((size_t)i * 2 + s) * 5]; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int ka[3] = {std::max(rank(a, 0), rank(a, 1)), rank(a, 0), rank(a, 1)};
+    const int kb[3] = {std::max(rank(b, 0), rank(b, 1)), rank(b, 0), rank(b, 1)};
+    return std::lexicographical_compare(ka, ka + 3, kb, kb + 3);
+  });
+  std::vector<int> dx((size_t)n_det * afq::kMdDx, 0), rowmap[2], pairs[2];
+  for (int k = 0; k < n_det; ++k) dx[(size_t)k * afq::kMdDx + 6] = order[k];
+  int R[2], RP[2];
+  const int KS = M <= 64 ? 16 : 32;  // k steps: 4 KS >= M rows
+  for (int s = 0; s < 2; ++s) {
+    const int N = tr->nel[s];
+    std::vector<int> vl;
+    for (int i = 0; i < n_det; ++i) {
+      const int* d = &exc[((size_t)i * 2 + s) * 5];
+      for (int e = 0; e < d[0]; ++e) vl.push_back(d[3 + e]);
+    }
+    std::sort(vl.begin(), vl.end());
+    vl.erase(std::unique(vl.begin(), vl.end()), vl.end());
+    R[s] = N + (int)vl.size();
+    RP[s] = round_up(R[s], 16);
+    if (4L * KS * RP[s] > 1024L * afq::kMdRowsPF || (int)vl.size() > 255) return AFQMC_OK;
+    rowmap[s].resize(R[s]);
+    for (int a = 0; a < N; ++a) rowmap[s][a] = a;
+    for (size_t t = 0; t < vl.size(); ++t) rowmap[s][N + t] = vl[t];
+    std::map<int, int> pid;
+    for (int k = 0; k < n_det; ++k) {
+      const int i = order[k];
+      const int* d = &exc[((size_t)i * 2 + s) * 5];
+      const int E = d[0];
+      int t[2] = {0, 0}, r[2] = {0, 0}, pi[2][2] = {{0, 0}, {0, 0}};
+      for (int e = 0; e < E; ++e) {
+        r[e] = d[1 + e];
+        t[e] = (int)(std::lower_bound(vl.begin(), vl.end(), d[3 + e]) - vl.begin());
+      }
+      for (int e = 0; e < E; ++e)
+        for (int f = 0; f < E; ++f) {
+          const int key = (t[e] << 8) | r[f];
+          auto it = pid.find(key);
+          if (it == pid.end()) {
+            it = pid.emplace(key, (int)pairs[s].size()).first;
+            pairs[s].push_back(key);
+          }
+          pi[e][f] = it->second;
+        }
+      if (pairs[s].size() > 0xffff) return AFQMC_OK;
+      int* w = &dx[(size_t)k * afq::kMdDx + s * 3];
+      w[0] = (int)((unsigned)E | (unsigned)r[0] << 2 | (unsigned)r[1] << 7 | (unsigned)t[0] << 12 |
+                   (unsigned)t[1] << 20);
+      w[1] = (int)((unsigned)pi[0][0] | (unsigned)pi[0][1] << 16);
+      w[2] = (int)((unsigned)pi[1][0] | (unsigned)pi[1][1] << 16);
+    }
+  }
+  void* p;
+  if (tr->arena.alloc(&p, dx.size() * sizeof(int))) return AFQMC_ERR_OOM;
+  tr->d_mddx = (int*)p;
+  if (hipMemcpy(tr->d_mddx, dx.data(), dx.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return AFQMC_ERR_DEVICE;
+  for (int s = 0; s < 2; ++s) {
+    tr->mdR[s] = R[s];
+    tr->mdRP[s] = RP[s];
+    tr->mdnp[s] = (int)pairs[s].size();
+    if (!R[s]) {  // no electrons of this spin: a zero table the staging loads may touch
+      void* pz;
+      if (tr->arena.alloc(&pz, 64)) return AFQMC_ERR_OOM;
+      if (hipMemsetAsync(pz, 0, 64, st) != hipSuccess) return AFQMC_ERR_DEVICE;
+      tr->LCc[s] = (float*)pz;
+      continue;
+    }
+    void *pl, *pm, *pr;
+    if (tr->arena.alloc(&pl, (size_t)(G + 2) * 4 * KS * RP[s] * 4) ||
+        tr->arena.alloc(&pm, rowmap[s].size() * sizeof(int)) ||
+        tr->arena.alloc(&pr, std::max<size_t>(pairs[s].size(), 1) * sizeof(int)))
+      return AFQMC_ERR_OOM;
+    tr->LCc[s] = (float*)pl;
+    tr->d_mdpair[s] = (int*)pr;
+    if (hipMemcpy(pm, rowmap[s].data(), rowmap[s].size() * sizeof(int), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        (!pairs[s].empty() && hipMemcpy(pr, pairs[s].data(), pairs[s].size() * sizeof(int),
+                                        hipMemcpyHostToDevice) != hipSuccess))
+      return AFQMC_ERR_DEVICE;
+    if (afq::md_rows_gather(st, G + 1, M, KS, R[s], RP[s], (const int*)pm, tr->LC64[s],
+                            tr->LCc[s]) != hipSuccess ||
+        afq::md_rows_gather(st, 1, M, KS, R[s], RP[s], (const int*)pm, tr->C[s],
+                            tr->LCc[s] + (size_t)(G + 1) * 4 * KS * RP[s]) != hipSuccess)
+      return AFQMC_ERR_DEVICE;
+  }
+  tr->mdKS = KS;
+  tr->md_rows = true;
+  return AFQMC_OK;
+}
+
+}  // namespace
+
 afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_det, int n_walkers,
                                    size_t* bytes) {
   if (!bytes || M < 1 || n_chol < 0 || n_up < 0 || n_dn < 0 || n_up + n_dn < 1 || n_det < 1 ||
@@ -1011,6 +1163,7 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
   }
   tot += 3 * rnd(std::max<size_t>(g, 1) * 8) + rnd(m * Nt * 8) + rnd(mm * 8) + 2 * rnd(mm * 12);
   if (n_det > 1) tot += rnd((size_t)n_det * 40) + rnd((size_t)n_det * 8);
+  tot += md_rows_bound_bytes(M, n_chol, n_up, n_dn, n_det);
   const size_t kq[2] = {(size_t)qpad((long)M * n_up), (size_t)qpad((long)M * n_dn)};
   const size_t qb = q_fp32_ok(M, n_up, n_dn) ? 12 : 8;  // FP64 (+ FP32) copies
   if (n_det == 1 && g > 0) tot += rnd((kq[0] + kq[1]) * qpad(g) * qb);  // Lq
@@ -1317,6 +1470,8 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
       if (afq::convert_f64_f32(st, tr->LC64[s], tr->LC32[s], (long)nlc) != hipSuccess)
         return bad(AFQMC_ERR_DEVICE, "convert");
     }
+    const afqmc_status rs = md_rows_setup(tr, exc_dev, st);
+    if (rs != AFQMC_OK) return bad(rs, "compact-row tables");
     if (hipStreamSynchronize(st) != hipSuccess) return bad(AFQMC_ERR_DEVICE, "sync");
   }
   // reference state: one walker at D_0, measured in FP64

@@ -144,13 +144,41 @@ struct MDSpin {
   const double* C;
   const void* LC;
 };
+// Compact-row tables of the FP32 energy kernel.  Per spin only the rows of
+// C^T O Theta_0 that some determinant reads are formed: the N occupied rows,
+// then the distinct particle orbitals in ascending order (R rows, padded to
+// RP, a multiple of 16).  A (particle, hole) pair whose sums over the occupied
+// index a determinant needs is listed once per spin.
+struct MDRows {
+  int ok;                // the tables exist (M <= 128, N <= 16, n_det <= 256)
+  int KS;                // k steps of the operators: 16 (M <= 64) or 32
+  int R[2], RP[2], npair[2];
+  const float* LCc[2];   // [G+2][4 KS x RP, MFMA fragment order]: slot g <= G the rows of
+                         // LC[g], slot G+1 the rows of C
+  const int* pair[2];    // [npair]: (t << 8) | r, t the particle's compact index minus N
+  const int* dx;         // [n_det][kMdDx]: per slot, three packed words per spin, then
+                         // the determinant's index in the trial's list
+};
+// Packed per-(determinant, spin) words: w0 = E | r0 << 2 | r1 << 7 | t0 << 12 |
+// t1 << 20; w1 = pair(0,0) | pair(0,1) << 16; w2 = pair(1,0) | pair(1,1) << 16.
+constexpr int kMdDx = 7;
+constexpr int kMdRowsMaxM = 128;
+constexpr int kMdRowsMaxN = 16;
+constexpr int kMdRowsMaxDet = 256;
+constexpr int kMdRowsPF = 12;  // float4 staging registers per thread: 4 KS RP <= 12288
 struct MDParams {
   int M, Nt, G, n_det, MP4;
   double e_core;
   MDSpin sp[2];
   const int* exc;        // [n_det][2][5] = (E, hole0, hole1, particle0, particle1)
   const double* coeff;   // [n_det]
+  MDRows rows;
 };
+
+// LCc[slot] = (float) src[slot][m][rowmap[c]] (m < M, c < R; zero elsewhere in
+// the 4 KS x RP block) in the energy kernel's MFMA fragment order.
+hipError_t md_rows_gather(hipStream_t st, int nslot, int M, int KS, int R, int RP,
+                          const int* rowmap, const double* src, float* dst);
 
 // Per walker: Ghat = C^T Theta_0 (FP64), overlap ratio of every determinant
 // c0[w][s][i] = det(Ghat[particles, holes]), the total relative overlap

@@ -15,6 +15,8 @@
 // from the reference quantities X0 = P[0:N, :], X0^2, Ghat and P at the
 // particle rows, with O(N) work per entry and no inverse of the E x E block,
 // so zero ratios (a walker on the reference) need no special case.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -141,40 +143,17 @@ struct MdLds {
 };
 
 // t^1 and t^2 coefficients of det(Ghat[occ] + t P[occ]) for one determinant
-// and spin (relative to det A), from the reference quantities in LDS.  E (the
-// excitation rank, 1 or 2) is a template parameter so that every small E x E
-// array lives in registers; holes (h0, h1) and particles (v0, v1).
-template <int E, typename T>
-__device__ inline void md_det_coeffs_e(int N, int Nmax, int h0, int h1, int v0, int v1,
-                                       const T* gr, const T* gi, const T* pr, const T* pi,
-                                       const double* x2r, const double* x2i, Cx trx0, Cx trx2,
-                                       Cx& c1, Cx& c2) {
+// and spin (relative to det A), from its (e, f) entries (e over particles v_e,
+// f over holes r_f): S0 = Ghat[v_e][r_f], Q = P[v_e][r_f], GX = (Ghat X0)[v_e][r_f],
+// PX = (P X0)[v_e][r_f], GXX = (Ghat X0^2)[v_e][r_f], XR = X0[r_e][r_f] and
+// X2R = X0^2[r_e][r_f].  E (the excitation rank, 1 or 2) is a template
+// parameter so that every small E x E array lives in registers.
+template <int E>
+__device__ inline void md_det_algebra(const Cx (&S0)[2][2], const Cx (&Q)[2][2],
+                                      const Cx (&GX)[2][2], const Cx (&PX)[2][2],
+                                      const Cx (&GXX)[2][2], const Cx (&XR)[2][2],
+                                      const Cx (&X2R)[2][2], Cx trx0, Cx trx2, Cx& c1, Cx& c2) {
   const Cx e2 = 0.5 * (trx0 * trx0 - trx2);
-  const int hole[2] = {h0, h1}, part[2] = {v0, v1};
-  auto X0 = [&](int a, int b) { return cx((double)pr[a * Nmax + b], (double)pi[a * Nmax + b]); };
-  auto X2 = [&](int a, int b) { return cx(x2r[a * Nmax + b], x2i[a * Nmax + b]); };
-  auto Gv = [&](int v, int c) { return cx((double)gr[v * N + c], (double)gi[v * N + c]); };
-  Cx S0[2][2], Q[2][2], GX[2][2], PX[2][2], GXX[2][2], XR[2][2], X2R[2][2];
-#pragma unroll
-  for (int e = 0; e < E; ++e)
-#pragma unroll
-    for (int f = 0; f < E; ++f) {
-      const int v = part[e], r = hole[f];
-      S0[e][f] = Gv(v, r);
-      Q[e][f] = X0(v, r);
-      Cx gx = cx(0, 0), px = cx(0, 0), gxx = cx(0, 0);
-      for (int c = 0; c < N; ++c) {
-        const Cx g = Gv(v, c), pc = X0(v, c), xcr = X0(c, r);
-        gx = gx + g * xcr;
-        px = px + pc * xcr;
-        gxx = gxx + g * X2(c, r);
-      }
-      GX[e][f] = gx;
-      PX[e][f] = px;
-      GXX[e][f] = gxx;
-      XR[e][f] = X0(hole[e], r);
-      X2R[e][f] = X2(hole[e], r);
-    }
   Cx S1[2][2], S2[2][2];
 #pragma unroll
   for (int e = 0; e < E; ++e)
@@ -219,6 +198,42 @@ __device__ inline void md_det_coeffs_e(int N, int Nmax, int h0, int h1, int v0, 
   }
   c1 = d1 + t1 * d0;
   c2 = d2 + t1 * d1 + t2 * d0;
+}
+
+// The same from the full-row reference quantities in LDS (holes h0, h1 and
+// particles v0, v1 as orbital indices), the sums over the occupied index
+// taken here.
+template <int E, typename T>
+__device__ inline void md_det_coeffs_e(int N, int Nmax, int h0, int h1, int v0, int v1,
+                                       const T* gr, const T* gi, const T* pr, const T* pi,
+                                       const double* x2r, const double* x2i, Cx trx0, Cx trx2,
+                                       Cx& c1, Cx& c2) {
+  const int hole[2] = {h0, h1}, part[2] = {v0, v1};
+  auto X0 = [&](int a, int b) { return cx((double)pr[a * Nmax + b], (double)pi[a * Nmax + b]); };
+  auto X2 = [&](int a, int b) { return cx(x2r[a * Nmax + b], x2i[a * Nmax + b]); };
+  auto Gv = [&](int v, int c) { return cx((double)gr[v * N + c], (double)gi[v * N + c]); };
+  Cx S0[2][2], Q[2][2], GX[2][2], PX[2][2], GXX[2][2], XR[2][2], X2R[2][2];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int f = 0; f < E; ++f) {
+      const int v = part[e], r = hole[f];
+      S0[e][f] = Gv(v, r);
+      Q[e][f] = X0(v, r);
+      Cx gx = cx(0, 0), px = cx(0, 0), gxx = cx(0, 0);
+      for (int c = 0; c < N; ++c) {
+        const Cx g = Gv(v, c), pc = X0(v, c), xcr = X0(c, r);
+        gx = gx + g * xcr;
+        px = px + pc * xcr;
+        gxx = gxx + g * X2(c, r);
+      }
+      GX[e][f] = gx;
+      PX[e][f] = px;
+      GXX[e][f] = gxx;
+      XR[e][f] = X0(hole[e], r);
+      X2R[e][f] = X2(hole[e], r);
+    }
+  md_det_algebra<E>(S0, Q, GX, PX, GXX, XR, X2R, trx0, trx2, c1, c2);
 }
 
 template <typename T>
@@ -470,6 +485,426 @@ __global__ __launch_bounds__(256) void k_md_energy(MDParams p, int Nmax, int NPm
   }
 }
 
+// ===========================================================================
+// Energy and force bias, FP32 contractions over compact rows: four walkers per
+// block, one wavefront each.  Per (operator, spin) phase the block stages the
+// operator's rows LCc[slot] (FP32, M padded to 4 KS k rows, in MFMA fragment
+// order) in LDS once for its four walkers;
+// each wavefront forms its walker's P = LCc^T Theta_0 (R x N) by 16x16x4 MFMA
+// with Theta_0 held in registers as the B operand, then, on its own, X0^2 and
+// the traces, the sums over the occupied index of every listed (particle,
+// hole) pair, and every determinant's t^1 / t^2 coefficients.  Two leading
+// phases (one per spin) form Ghat at the particle rows the same way, from the
+// rows of C in slot G+1.  The operator of the phase after next is loaded into
+// registers while the current one is worked on, so one barrier pair per
+// phase is the only block-wide synchronisation.
+// ===========================================================================
+constexpr int kMdWaves = 4;
+
+struct MdRowsLds {
+  int ns;      // row stride (elements) of P and X0^2 in a wavefront's region
+  int wbytes;  // bytes of one wavefront's region
+  int pw, x2, gh0, gh1, tab;  // offsets inside a wavefront's region
+  int wave0;   // offset of wavefront 0's region
+  int total;
+};
+
+inline MdRowsLds md_rows_lds(const MDParams& p, int ks) {
+  MdRowsLds o;
+  auto al = [](long b) { return (int)((b + 15) & ~15L); };
+  const int N0 = p.sp[0].N, N1 = p.sp[1].N, Nmax = N0 > N1 ? N0 : N1;
+  const int R0 = p.rows.R[0], R1 = p.rows.R[1];
+  const int rp = p.rows.RP[0] > p.rows.RP[1] ? p.rows.RP[0] : p.rows.RP[1];
+  const int np = p.rows.npair[0] > p.rows.npair[1] ? p.rows.npair[0] : p.rows.npair[1];
+  o.ns = Nmax > 0 ? Nmax : 1;
+  int q = 0;
+  o.pw = q;
+  q += al((long)(R0 > R1 ? R0 : R1) * o.ns * 8);
+  o.x2 = q;
+  q += al((long)Nmax * o.ns * 8);
+  o.gh0 = q;
+  q += al((long)(R0 - N0) * N0 * 8);
+  o.gh1 = q;
+  q += al((long)(R1 - N1) * N1 * 8);
+  o.tab = q;
+  q += al((long)np * 24);
+  o.wbytes = q;
+  o.wave0 = al((long)4 * ks * rp * 4);  // the operator: 4 ks rows (k) x rp columns
+  o.total = o.wave0 + kMdWaves * o.wbytes;
+  return o;
+}
+
+// One 16-row tile of P.  The operator is stored in MFMA fragment order:
+// element (m, c) with m = 16 J + 4 jj + lk and c = 16 rt + li sits at float
+// index (((J RTP + rt) 4 + lk) 16 + li) 4 + jj, so lane (li, lk) reads the A
+// values of four k steps with one 128-bit load (`a4` points at J = 0 of the
+// tile, `jstride` = RTP 64 vectors per J).  The sum over k alternates between
+// two accumulators per part, so that consecutive MFMAs are independent.
+template <int KS>
+__device__ __forceinline__ void md_rows_tile(const afq_f4* __restrict__ a4, int jstride,
+                                             const float (&br)[KS], const float (&bi)[KS],
+                                             afq_f4& er, afq_f4& ei, afq_f4& orr, afq_f4& oi) {
+  typedef Mfma<float> MM;
+  afq_f4 an = a4[0];
+#pragma unroll
+  for (int J = 0; J < KS / 4; ++J) {
+    // the next k block's load is issued before this block's MFMAs
+    const afq_f4 a = an;
+    if (J + 1 < KS / 4) an = a4[(J + 1) * jstride];
+    er = MM::mma(a[0], br[4 * J], er);
+    ei = MM::mma(a[0], bi[4 * J], ei);
+    orr = MM::mma(a[1], br[4 * J + 1], orr);
+    oi = MM::mma(a[1], bi[4 * J + 1], oi);
+    er = MM::mma(a[2], br[4 * J + 2], er);
+    ei = MM::mma(a[2], bi[4 * J + 2], ei);
+    orr = MM::mma(a[3], br[4 * J + 3], orr);
+    oi = MM::mma(a[3], bi[4 * J + 3], oi);
+  }
+}
+
+// One determinant's coefficients for one spin from the compact-row quantities
+// of its wavefront: particles as compact indices t (row N + t of P, row t of
+// Ghat), the pair sums from the table.
+template <int E>
+__device__ inline void md_det_rows(int N, int NS, unsigned w0, unsigned w1, unsigned w2,
+                                   const float2* gh, const float2* pw, const float2* x2,
+                                   const float2* tab, Cx trx0, Cx trx2, Cx& c1, Cx& c2) {
+  const int hole[2] = {(int)((w0 >> 2) & 31u), (int)((w0 >> 7) & 31u)};
+  const int part[2] = {(int)((w0 >> 12) & 255u), (int)((w0 >> 20) & 255u)};
+  const int pidx[2][2] = {{(int)(w1 & 0xffffu), (int)(w1 >> 16)},
+                          {(int)(w2 & 0xffffu), (int)(w2 >> 16)}};
+  Cx S0[2][2], Q[2][2], GX[2][2], PX[2][2], GXX[2][2], XR[2][2], X2R[2][2];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int f = 0; f < E; ++f) {
+      const float2 g = gh[part[e] * N + hole[f]];
+      const float2 q = pw[(N + part[e]) * NS + hole[f]];
+      const float2 x = pw[hole[e] * NS + hole[f]];
+      const float2 y = x2[hole[e] * NS + hole[f]];
+      const float2* tb = tab + 3 * pidx[e][f];
+      const float2 t0 = tb[0], t1 = tb[1], t2 = tb[2];
+      S0[e][f] = cx(g.x, g.y);
+      Q[e][f] = cx(q.x, q.y);
+      XR[e][f] = cx(x.x, x.y);
+      X2R[e][f] = cx(y.x, y.y);
+      GX[e][f] = cx(t0.x, t0.y);
+      PX[e][f] = cx(t1.x, t1.y);
+      GXX[e][f] = cx(t2.x, t2.y);
+    }
+  md_det_algebra<E>(S0, Q, GX, PX, GXX, XR, X2R, trx0, trx2, c1, c2);
+}
+
+// Phase ph of the compact-row kernel works on slot md_rows_slot(ph, G) for
+// spin ph & 1: slot G+1 (the rows of C) first, then the operators 0..G.
+__device__ __forceinline__ int md_rows_slot(int ph, int G) { return ph < 2 ? G + 1 : (ph >> 1) - 1; }
+
+// Loads phase ph's operator (4 KS x RP floats in fragment order, contiguous)
+// into the staging registers, 16 bytes per thread and register; every thread
+// loads all of them (indices past the end are clamped; the set-up gives a
+// spin without electrons a 16-float table) so that the array stays in
+// registers.
+template <int KS>
+__device__ __forceinline__ void md_rows_issue(const MDParams& p, int G, int ph,
+                                              afq_f4 (&pf)[kMdRowsPF]) {
+  const int s = ph & 1, rp = s ? p.rows.RP[1] : p.rows.RP[0];
+  const float* base = s ? p.rows.LCc[1] : p.rows.LCc[0];
+  const int n4 = KS * rp;
+  const int last = n4 > 0 ? n4 - 1 : 0;
+  const afq_f4* src = (const afq_f4*)(base + (size_t)md_rows_slot(ph, G) * 4 * KS * rp);
+#pragma unroll
+  for (int u = 0; u < kMdRowsPF; ++u) {
+    const int q = threadIdx.x + 256 * u;
+    pf[u] = src[q < last ? q : last];
+  }
+}
+
+// Stores the staging registers into the LDS operator buffer (same order).
+template <int KS>
+__device__ __forceinline__ void md_rows_stage(const MDParams& p, int ph,
+                                              const afq_f4 (&pf)[kMdRowsPF], afq_f4* abuf) {
+  const int s = ph & 1, rp = s ? p.rows.RP[1] : p.rows.RP[0];
+  const int n4 = KS * rp;
+#pragma unroll
+  for (int u = 0; u < kMdRowsPF; ++u) {
+    const int q = threadIdx.x + 256 * u;
+    if (q < n4) abuf[q] = pf[u];
+  }
+}
+
+template <int KS, int DPL>
+__global__ __launch_bounds__(256) void k_md_energy_rows(
+    MDParams p, MdRowsLds L, int W, const double* __restrict__ thr, const double* __restrict__ thi,
+    const double* __restrict__ c0_re, const double* __restrict__ c0_im, const double* tot_re,
+    const double* tot_im, double* v_re, double* v_im, double* eln_re, double* eln_im, int* vfin) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  typedef Mfma<float> MM;
+  typedef MM::acc_t acc_t;
+  const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
+  const int w = blockIdx.x * kMdWaves + wv;
+  const bool live = w < W;
+  const int wr = live ? w : W - 1;  // the last block's idle wavefronts read a real walker
+  const int M = p.M, Nt = p.Nt, G = p.G, NS = L.ns, n_det = p.n_det;
+  const long wb = (long)wr * M * Nt;
+  afq_f4* abuf = (afq_f4*)lds_raw;
+  unsigned char* reg = lds_raw + L.wave0 + wv * L.wbytes;
+  float2* pw = (float2*)(reg + L.pw);
+  float2* x2 = (float2*)(reg + L.x2);
+  float2* gh0 = (float2*)(reg + L.gh0);
+  float2* gh1 = (float2*)(reg + L.gh1);
+  float2* tab = (float2*)(reg + L.tab);
+
+  // Theta_0 as B fragments: lane (li, lk) holds row 4 j + lk, column li of
+  // each spin (zero past M and past N)
+  float b0r[KS], b0i[KS], b1r[KS], b1i[KS];
+  {
+    const int N0 = p.sp[0].N, N1 = p.sp[1].N, o1 = p.sp[1].off;
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      const int m = 4 * j + lk;
+      const long o = wb + (long)(m < M ? m : 0) * Nt;
+      const bool ok0 = m < M && li < N0, ok1 = m < M && li < N1;
+      const long i0 = o + (ok0 ? li : 0), i1 = o + (ok1 ? o1 + li : 0);
+      b0r[j] = ok0 ? (float)thr[i0] : 0.f;
+      b0i[j] = ok0 ? (float)thi[i0] : 0.f;
+      b1r[j] = ok1 ? (float)thr[i1] : 0.f;
+      b1i[j] = ok1 ? (float)thi[i1] : 0.f;
+    }
+  }
+
+  // per-determinant state: determinant i = l + 64 k of this walker
+  unsigned dxw[DPL][2][3];
+  double coef[DPL];
+  Cx c0u[DPL], c0d[DPL], a2u[DPL], a2d[DPL], a11[DPL], c1p[DPL], c1h0[DPL], c1h1[DPL];
+#pragma unroll
+  for (int k = 0; k < DPL; ++k) {
+    // slot i holds determinant dx[i][6] (the set-up orders the determinants so
+    // that each 64-lane slot mixes as few excitation ranks per spin as it can)
+    const int i = l + 64 * k;
+    const bool ok = i < n_det;
+    const int* dr = p.rows.dx + (ok ? i : 0) * kMdDx;
+    const int ic = ok ? dr[6] : 0;
+    coef[k] = ok ? p.coeff[ic] : 0.0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) dxw[k][s][q] = ok ? (unsigned)dr[s * 3 + q] : 0u;
+    const long u = ((long)wr * 2) * n_det + ic, d = ((long)wr * 2 + 1) * n_det + ic;
+    c0u[k] = ok ? cx(c0_re[u], c0_im[u]) : cx(0, 0);
+    c0d[k] = ok ? cx(c0_re[d], c0_im[d]) : cx(0, 0);
+    a2u[k] = a2d[k] = a11[k] = c1p[k] = c1h0[k] = c1h1[k] = cx(0, 0);
+  }
+  const Cx tot = cx(tot_re[wr], tot_im[wr]);
+  int fin = 1;
+
+  // operator staging: phase ph = (slot, spin), slots G+1 (C) first, then 0..G
+  const int NPH = 2 * (G + 2);
+  afq_f4 pf[kMdRowsPF];
+  md_rows_issue<KS>(p, G, 0, pf);
+  md_rows_stage<KS>(p, 0, pf, abuf);
+  md_rows_issue<KS>(p, G, 1, pf);
+  __syncthreads();
+
+  for (int ph = 0; ph < NPH; ++ph) {
+    const int s = ph & 1, slot = md_rows_slot(ph, G);
+    const int N = s ? p.sp[1].N : p.sp[0].N;
+    const int R = s ? p.rows.R[1] : p.rows.R[0];
+    const int RT = (R + 15) >> 4;
+    const int RTP = (s ? p.rows.RP[1] : p.rows.RP[0]) >> 4;
+    float2* gh = s ? gh1 : gh0;
+    // P (or, in the leading phases, Ghat) one 16-row tile at a time; lane
+    // (li, lk) of tile rt holds rows 16 rt + 4 lk + v, column li
+    wave_lds_sync();
+    for (int rt = 0; rt < RT; ++rt) {
+      acc_t er = MM::zero(), ei = MM::zero(), orr = MM::zero(), oi = MM::zero();
+      const afq_f4* a4 = abuf + rt * 64 + l;
+      if (s == 0)
+        md_rows_tile<KS>(a4, RTP * 64, b0r, b0i, er, ei, orr, oi);
+      else
+        md_rows_tile<KS>(a4, RTP * 64, b1r, b1i, er, ei, orr, oi);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * rt + 4 * lk + v;
+        const float2 val = make_float2(er[v] + orr[v], ei[v] + oi[v]);
+        if (li < N && row < R) {
+          if (slot > G) {
+            if (row >= N) gh[(row - N) * N + li] = val;
+          } else {
+            pw[row * NS + li] = val;
+          }
+        }
+      }
+    }
+    __syncthreads();  // every wavefront is done with this phase's operator
+    if (ph + 1 < NPH) md_rows_stage<KS>(p, ph + 1, pf, abuf);
+    if (ph + 2 < NPH) md_rows_issue<KS>(p, G, ph + 2, pf);
+    if (slot <= G) {
+      wave_lds_sync();
+      // X0^2 and the sums of the pairs below in FP32 (the contraction type);
+      // the traces and the determinant algebra in FP64
+      for (int e = l; e < N * N; e += 64) {
+        const int a = e / N, b = e - a * N;
+        float sr = 0.f, si = 0.f;
+        for (int c = 0; c < N; ++c) {
+          const float2 x = pw[a * NS + c], y = pw[c * NS + b];
+          sr = fmaf(x.x, y.x, fmaf(-x.y, y.y, sr));
+          si = fmaf(x.x, y.y, fmaf(x.y, y.x, si));
+        }
+        x2[a * NS + b] = make_float2(sr, si);
+      }
+      wave_lds_sync();
+      double t0r = 0.0, t0i = 0.0, t2r = 0.0, t2i = 0.0;
+      if (l < N) {
+        const float2 d = pw[l * NS + l], d2 = x2[l * NS + l];
+        t0r = d.x;
+        t0i = d.y;
+        t2r = d2.x;
+        t2i = d2.y;
+      }
+      const Cx trx0 = cx(wave_sum(t0r), wave_sum(t0i)), trx2 = cx(wave_sum(t2r), wave_sum(t2i));
+      // sums over the occupied index c of the listed (particle t, hole r) pairs
+      const int np = s ? p.rows.npair[1] : p.rows.npair[0];
+      const int* pl = s ? p.rows.pair[1] : p.rows.pair[0];
+      for (int k = l; k < np; k += 64) {
+        const int pr = pl[k], t = pr >> 8, r = pr & 255;
+        const float2* gv = gh + t * N;
+        const float2* pv = pw + (N + t) * NS;
+        float gxr = 0.f, gxi = 0.f, pxr = 0.f, pxi = 0.f, ggr = 0.f, ggi = 0.f;
+        for (int c = 0; c < N; ++c) {
+          const float2 g = gv[c], q = pv[c], x = pw[c * NS + r], y = x2[c * NS + r];
+          gxr = fmaf(g.x, x.x, fmaf(-g.y, x.y, gxr));
+          gxi = fmaf(g.x, x.y, fmaf(g.y, x.x, gxi));
+          pxr = fmaf(q.x, x.x, fmaf(-q.y, x.y, pxr));
+          pxi = fmaf(q.x, x.y, fmaf(q.y, x.x, pxi));
+          ggr = fmaf(g.x, y.x, fmaf(-g.y, y.y, ggr));
+          ggi = fmaf(g.x, y.y, fmaf(g.y, y.x, ggi));
+        }
+        tab[3 * k] = make_float2(gxr, gxi);
+        tab[3 * k + 1] = make_float2(pxr, pxi);
+        tab[3 * k + 2] = make_float2(ggr, ggi);
+      }
+      wave_lds_sync();
+      Cx vn = cx(0, 0);
+#pragma unroll
+      for (int k = 0; k < DPL; ++k) {
+        const unsigned w0 = s ? dxw[k][1][0] : dxw[k][0][0];
+        const unsigned w1 = s ? dxw[k][1][1] : dxw[k][0][1];
+        const unsigned w2 = s ? dxw[k][1][2] : dxw[k][0][2];
+        const int E = (int)(w0 & 3u);
+        Cx c1, c2;
+        if (E == 0) {
+          c1 = trx0;
+          c2 = 0.5 * (trx0 * trx0 - trx2);
+        } else if (E == 1) {
+          md_det_rows<1>(N, NS, w0, w1, w2, gh, pw, x2, tab, trx0, trx2, c1, c2);
+        } else {
+          md_det_rows<2>(N, NS, w0, w1, w2, gh, pw, x2, tab, trx0, trx2, c1, c2);
+        }
+        if (slot < G) {
+          if (s == 0) {
+            a2u[k] = a2u[k] + c2;
+            c1p[k] = c1;
+          } else {
+            a2d[k] = a2d[k] + c2;
+            a11[k] = a11[k] + c1p[k] * c1;
+            vn = vn + coef[k] * (c1p[k] * c0d[k] + c0u[k] * c1);
+          }
+        } else if (s == 0) {
+          c1h0[k] = c1;
+        } else {
+          c1h1[k] = c1;
+        }
+      }
+      if (slot < G && s == 1) {
+        const double vr = wave_sum(vn.r), vi = wave_sum(vn.i);
+        if (l == 0) {
+          const Cx v = cdiv(cx(vr, vi), tot);
+          if (live) {
+            v_re[(long)w * G + slot] = v.r;
+            v_im[(long)w * G + slot] = v.i;
+          }
+          if (!isfinite(v.r) || !isfinite(v.i)) fin = 0;
+        }
+      }
+    }
+    __syncthreads();  // the next phase's operator is in LDS
+  }
+  double nr = 0.0, ni = 0.0;
+#pragma unroll
+  for (int k = 0; k < DPL; ++k) {
+    const Cx n = coef[k] * (p.e_core * (c0u[k] * c0d[k]) + c1h0[k] * c0d[k] + c0u[k] * c1h1[k] +
+                            c0d[k] * a2u[k] + c0u[k] * a2d[k] + a11[k]);
+    nr += n.r;
+    ni += n.i;
+  }
+  nr = wave_sum(nr);
+  ni = wave_sum(ni);
+  if (l == 0 && live) {
+    const Cx e = cdiv(cx(nr, ni), tot);
+    eln_re[w] = e.r;
+    eln_im[w] = e.i;
+    vfin[w] = fin;
+  }
+}
+
+// Launches the compact-row kernel when its tables exist and its LDS fits;
+// returns false (nothing launched) otherwise.
+static bool md_energy_rows(hipStream_t st, int W, const MDParams& p, const double* thr,
+                           const double* thi, const double* c0_re, const double* c0_im,
+                           const double* tot_re, const double* tot_im, double* v_re, double* v_im,
+                           double* eln_re, double* eln_im, int* vfin, size_t max_lds) {
+  if (!p.rows.ok || p.M > kMdRowsMaxM || p.n_det > kMdRowsMaxDet || W < 1) return false;
+  const int ks = p.rows.KS;
+  if (ks != 16 && ks != 32) return false;
+  const MdRowsLds L = md_rows_lds(p, ks);
+  if ((size_t)L.total > max_lds) return false;
+  const int dpl = (p.n_det + 63) / 64;
+  const dim3 grid((W + kMdWaves - 1) / kMdWaves), block(64 * kMdWaves);
+#define AFQ_MDR_LAUNCH(K, D)                                                                   \
+  hipLaunchKernelGGL((k_md_energy_rows<K, D>), grid, block, L.total, st, p, L, W, thr, thi, \
+                     c0_re, c0_im, tot_re, tot_im, v_re, v_im, eln_re, eln_im, vfin)
+  if (ks == 16) {
+    if (dpl <= 1) AFQ_MDR_LAUNCH(16, 1);
+    else if (dpl <= 2) AFQ_MDR_LAUNCH(16, 2);
+    else AFQ_MDR_LAUNCH(16, 4);
+  } else {
+    if (dpl <= 1) AFQ_MDR_LAUNCH(32, 1);
+    else if (dpl <= 2) AFQ_MDR_LAUNCH(32, 2);
+    else AFQ_MDR_LAUNCH(32, 4);
+  }
+#undef AFQ_MDR_LAUNCH
+  return true;
+}
+
+// dst (fragment order, see md_rows_tile): slot, J < KS / 4, rt < RP / 16,
+// lk < 4, li < 16, jj < 4 -> element (m, c) = (16 J + 4 jj + lk, 16 rt + li)
+// = src[slot][m][rowmap[c]] for m < M and c < R, zero otherwise.
+__global__ void k_md_rows_gather(int nslot, int M, int KS, int R, int RP,
+                                 const int* __restrict__ rowmap, const double* __restrict__ src,
+                                 float* __restrict__ dst) {
+  const int RTP = RP / 16, KJ = KS / 4;
+  const long n = (long)nslot * KJ * RTP * 256;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int jj = (int)(e & 3), li = (int)((e >> 2) & 15), lk = (int)((e >> 6) & 3);
+    const long b = e >> 8;
+    const int rt = (int)(b % RTP), J = (int)((b / RTP) % KJ);
+    const long slot = b / ((long)RTP * KJ);
+    const int m = 16 * J + 4 * jj + lk, c = 16 * rt + li;
+    dst[e] = (m < M && c < R) ? (float)src[(slot * M + m) * M + rowmap[c]] : 0.f;
+  }
+}
+
+hipError_t md_rows_gather(hipStream_t st, int nslot, int M, int KS, int R, int RP,
+                          const int* rowmap, const double* src, float* dst) {
+  if (nslot < 1 || M < 1 || M > 4 * KS || KS % 4 || RP < 16 || RP % 16 || R > RP)
+    return hipErrorInvalidValue;
+  const long n = (long)nslot * KS * RP * 4;
+  const int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_md_rows_gather, dim3(blocks), dim3(256), 0, st, nslot, M, KS, R, RP, rowmap,
+                     src, dst);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t md_energy(hipStream_t st, int W, const MDParams& p, const double* thr,
                      const double* thi, const double* c0_re, const double* c0_im,
@@ -480,6 +915,11 @@ hipError_t md_energy(hipStream_t st, int W, const MDParams& p, const double* thr
   size_t lds = (size_t)(2 * 2 * p.MP4 * NPmax + 2 * 2 * p.M * Nmax + 2 * p.M * Nmax) * sizeof(T);
   lds = (lds + 7) & ~(size_t)7;
   lds += (size_t)2 * Nmax * Nmax * sizeof(double) + 16;
+  if constexpr (sizeof(T) == 4) {
+    if (md_energy_rows(st, W, p, thr, thi, c0_re, c0_im, tot_re, tot_im, v_re, v_im, eln_re, eln_im,
+                       vfin, max_lds))
+      return hipGetLastError();
+  }
   if (lds > max_lds) return hipErrorInvalidValue;
   const int dpt = (p.n_det + 255) / 256;
 #define AFQ_MD_LAUNCH(D)                                                                         \

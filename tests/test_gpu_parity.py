@@ -638,6 +638,57 @@ def test_propagate_edge_shapes_fp64(afq, W, nu, nd):
     assert np.max(np.abs(em - oe)) <= 1e-9 * max(1.0, np.max(np.abs(oe)))
 
 
+@pytest.mark.parametrize("M,nu,nd,G,n_det,W,seed", [
+    (14, 4, 3, 9, 150, 7, 8),     # three determinants per lane
+    (12, 4, 0, 7, 30, 5, 5),      # no electrons of one spin
+    (70, 9, 8, 20, 60, 9, 21),    # M > 64: 32 k steps, several row tiles
+    (40, 17, 3, 10, 30, 5, 3),    # N > 16: the full-row kernel
+])
+def test_multidet_fp32_compact_rows_vs_oracle(afq, M, nu, nd, G, n_det, W, seed):
+    """FP32 multi-determinant E_L from the compact-row kernel (only the rows of
+    C^T L_g Theta_0 that the determinants read; past its limits, the full-row
+    kernel) against the oracle's direct per-determinant evaluation, on walkers
+    perturbed from the reference; one walker sits on the reference, where
+    every excited overlap is zero.  W is not a multiple of the kernel's four
+    walkers per block."""
+    _say(f"multidet fp32 compact rows M={M} {nu}+{nd} G={G} n_det={n_det} W={W}")
+    inp = syn.make_system(M, nu, nd, G, 4.0, n_det=n_det, seed=seed, e_core=0.3)
+    ham, trial, w = _make(afq, inp, W)
+    D0 = np.concatenate([inp.C_up[:, :nu], inp.C_dn[:, :nd]], axis=1)
+    re, im = syn.random_walkers(M, nu, nd, W, seed=seed + 1, scale=0.3)
+    phi = D0[None] + re + 1j * im
+    phi[W - 1] = D0
+    _set_phi(w, phi)
+    afq.propagate(ham, trial, w, 0, 0.01, 0, 0, afq.Options(chol_prec="fp32"))
+    el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
+    m = Oracle.from_inputs(inp).measure(phi)
+    rel = np.abs(el - m["eloc"]) / np.abs(m["eloc"])
+    print(f"max rel dE_L {rel.max():.3e}")
+    assert np.all(np.isfinite(el))
+    assert rel.max() <= 2e-5
+
+
+def test_multidet_fp32_propagate_tracks_fp64(afq):
+    """The FP32 multi-determinant path (its force bias drives the fields'
+    shift) against the FP64 path on the same walkers and fields: per-step
+    E_mix over 12 steps with MGS and the comb."""
+    _say("multidet fp32 propagate tracks fp64")
+    M, nu, nd, G = 24, 7, 5, 30
+    inp = syn.make_system(M, nu, nd, G, 8.0, n_det=25, seed=31)
+    ems = []
+    for prec in ("fp64", "fp32"):
+        ham, trial, w = _make(afq, inp, 12)
+        afq.walkers_from_trial(ham, trial, w)
+        et = afq.local_energy(ham, trial, w)
+        opt = afq.Options(e_trial=et, chol_prec=prec, taylor_prec=prec, taylor_order=6,
+                          ortho_every=2, pc_every=5)
+        ems.append(_np(afq.propagate(ham, trial, w, 12, 0.005, 0, 0, opt)))
+    err = np.abs(ems[1] - ems[0])
+    print(f"max |dE_mix| fp32 vs fp64 = {err.max():.3e} Ha")
+    assert np.all(np.isfinite(ems[1]))
+    assert err.max() <= 1e-4
+
+
 def test_multidet_with_only_the_reference_matches_single_det(afq):
     """A two-determinant trial whose second coefficient is 0 gives the
     single-determinant energies (exercises the multi-det kernels' reference
