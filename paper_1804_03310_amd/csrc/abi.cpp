@@ -261,6 +261,7 @@ struct afqmc_trial {
   int mdKS = 0, mdR[2] = {0, 0}, mdRP[2] = {0, 0}, mdnp[2] = {0, 0};
   float* LCc[2] = {nullptr, nullptr};
   int* d_mdpair[2] = {nullptr, nullptr};
+  int* d_mdpbeg[2] = {nullptr, nullptr};
   int* d_mddx = nullptr;
   double ref_ls[2] = {0, 0}, ref_el[2] = {0, 0};
   double* vref_re = nullptr;
@@ -463,6 +464,7 @@ afq::MDParams md_params(const afqmc_trial* tr, bool fp32) {
       p.rows.npair[s] = tr->mdnp[s];
       p.rows.LCc[s] = tr->LCc[s];
       p.rows.pair[s] = tr->d_mdpair[s];
+      p.rows.pbeg[s] = tr->d_mdpbeg[s];
     }
     p.rows.dx = tr->d_mddx;
   }
@@ -1025,7 +1027,7 @@ size_t md_rows_bound_bytes(int M, int G, int n_up, int n_dn, int n_det) {
     if (!nel[s]) continue;
     const size_t rp = round_up(std::min(M, nel[s] + 2 * (n_det - 1)), 16);
     const size_t rows = M <= 64 ? 64 : 128;  // 4 KS
-    t += rnd((size_t)(G + 2) * rows * rp * 4) + rnd((size_t)n_det * 16) + rnd((size_t)M * 4);
+    t += rnd((size_t)(G + 2) * rows * rp * 4) + rnd((size_t)n_det * 16) + 2 * rnd((size_t)M * 4);
   }
   return t;
 }
@@ -1049,7 +1051,7 @@ afqmc_status md_rows_setup(afqmc_trial* tr, const std::vector<int>& exc, hipStre
     const int kb[3] = {std::max(rank(b, 0), rank(b, 1)), rank(b, 0), rank(b, 1)};
     return std::lexicographical_compare(ka, ka + 3, kb, kb + 3);
   });
-  std::vector<int> dx((size_t)n_det * afq::kMdDx, 0), rowmap[2], pairs[2];
+  std::vector<int> dx((size_t)n_det * afq::kMdDx, 0), rowmap[2], pairs[2], pbeg[2];
   for (int k = 0; k < n_det; ++k) dx[(size_t)k * afq::kMdDx + 6] = order[k];
   int R[2], RP[2];
   const int KS = M <= 64 ? 16 : 32;  // k steps: 4 KS >= M rows
@@ -1064,31 +1066,41 @@ afqmc_status md_rows_setup(afqmc_trial* tr, const std::vector<int>& exc, hipStre
     vl.erase(std::unique(vl.begin(), vl.end()), vl.end());
     R[s] = N + (int)vl.size();
     RP[s] = round_up(R[s], 16);
-    if (4L * KS * RP[s] > 1024L * afq::kMdRowsPF || (int)vl.size() > 255) return AFQMC_OK;
+    // limits: the staging registers, and one consumer lane per particle
+    if (4L * KS * RP[s] > 1024L * afq::kMdRowsPF || (int)vl.size() > 64) return AFQMC_OK;
     rowmap[s].resize(R[s]);
     for (int a = 0; a < N; ++a) rowmap[s][a] = a;
     for (size_t t = 0; t < vl.size(); ++t) rowmap[s][N + t] = vl[t];
-    std::map<int, int> pid;
-    for (int k = 0; k < n_det; ++k) {
-      const int i = order[k];
-      const int* d = &exc[((size_t)i * 2 + s) * 5];
-      const int E = d[0];
-      int t[2] = {0, 0}, r[2] = {0, 0}, pi[2][2] = {{0, 0}, {0, 0}};
-      for (int e = 0; e < E; ++e) {
+    // the distinct (particle, hole) pairs, ordered by particle then hole, and
+    // each particle's first pair
+    auto dets = [&](int k, int* t, int* r) {
+      const int* d = &exc[((size_t)order[k] * 2 + s) * 5];
+      for (int e = 0; e < d[0]; ++e) {
         r[e] = d[1 + e];
         t[e] = (int)(std::lower_bound(vl.begin(), vl.end(), d[3 + e]) - vl.begin());
       }
+      return d[0];
+    };
+    std::map<int, int> pid;
+    for (int k = 0; k < n_det; ++k) {
+      int t[2] = {0, 0}, r[2] = {0, 0};
+      const int E = dets(k, t, r);
       for (int e = 0; e < E; ++e)
-        for (int f = 0; f < E; ++f) {
-          const int key = (t[e] << 8) | r[f];
-          auto it = pid.find(key);
-          if (it == pid.end()) {
-            it = pid.emplace(key, (int)pairs[s].size()).first;
-            pairs[s].push_back(key);
-          }
-          pi[e][f] = it->second;
-        }
-      if (pairs[s].size() > 0xffff) return AFQMC_OK;
+        for (int f = 0; f < E; ++f) pid.emplace((t[e] << 8) | r[f], 0);
+    }
+    if (pid.size() > 0xffff) return AFQMC_OK;
+    pbeg[s].assign(vl.size() + 1, 0);
+    for (auto& kv : pid) {
+      kv.second = (int)pairs[s].size();
+      pairs[s].push_back(kv.first);
+      ++pbeg[s][(kv.first >> 8) + 1];
+    }
+    for (size_t t = 0; t < vl.size(); ++t) pbeg[s][t + 1] += pbeg[s][t];
+    for (int k = 0; k < n_det; ++k) {
+      int t[2] = {0, 0}, r[2] = {0, 0}, pi[2][2] = {{0, 0}, {0, 0}};
+      const int E = dets(k, t, r);
+      for (int e = 0; e < E; ++e)
+        for (int f = 0; f < E; ++f) pi[e][f] = pid.at((t[e] << 8) | r[f]);
       int* w = &dx[(size_t)k * afq::kMdDx + s * 3];
       w[0] = (int)((unsigned)E | (unsigned)r[0] << 2 | (unsigned)r[1] << 7 | (unsigned)t[0] << 12 |
                    (unsigned)t[1] << 20);
@@ -1112,14 +1124,18 @@ afqmc_status md_rows_setup(afqmc_trial* tr, const std::vector<int>& exc, hipStre
       tr->LCc[s] = (float*)pz;
       continue;
     }
-    void *pl, *pm, *pr;
+    void *pl, *pm, *pr, *pq;
     if (tr->arena.alloc(&pl, (size_t)(G + 2) * 4 * KS * RP[s] * 4) ||
         tr->arena.alloc(&pm, rowmap[s].size() * sizeof(int)) ||
-        tr->arena.alloc(&pr, std::max<size_t>(pairs[s].size(), 1) * sizeof(int)))
+        tr->arena.alloc(&pr, std::max<size_t>(pairs[s].size(), 1) * sizeof(int)) ||
+        tr->arena.alloc(&pq, pbeg[s].size() * sizeof(int)))
       return AFQMC_ERR_OOM;
     tr->LCc[s] = (float*)pl;
     tr->d_mdpair[s] = (int*)pr;
+    tr->d_mdpbeg[s] = (int*)pq;
     if (hipMemcpy(pm, rowmap[s].data(), rowmap[s].size() * sizeof(int), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(pq, pbeg[s].data(), pbeg[s].size() * sizeof(int), hipMemcpyHostToDevice) !=
             hipSuccess ||
         (!pairs[s].empty() && hipMemcpy(pr, pairs[s].data(), pairs[s].size() * sizeof(int),
                                         hipMemcpyHostToDevice) != hipSuccess))

@@ -150,12 +150,15 @@ struct MDSpin {
 // RP, a multiple of 16).  A (particle, hole) pair whose sums over the occupied
 // index a determinant needs is listed once per spin.
 struct MDRows {
-  int ok;                // the tables exist (M <= 128, N <= 16, n_det <= 256)
+  int ok;                // the tables exist (M <= 128, N <= 16, at most 64 particles per
+                         // spin, n_det <= 256)
   int KS;                // k steps of the operators: 16 (M <= 64) or 32
   int R[2], RP[2], npair[2];
   const float* LCc[2];   // [G+2][4 KS x RP, MFMA fragment order]: slot g <= G the rows of
                          // LC[g], slot G+1 the rows of C
-  const int* pair[2];    // [npair]: (t << 8) | r, t the particle's compact index minus N
+  const int* pair[2];    // [npair]: (t << 8) | r, t the particle's compact index minus N,
+                         // ordered by t then r
+  const int* pbeg[2];    // [R - N + 1]: the pairs of particle t are pbeg[t] .. pbeg[t+1]-1
   const int* dx;         // [n_det][kMdDx]: per slot, three packed words per spin, then
                          // the determinant's index in the trial's list
 };

@@ -487,25 +487,30 @@ __global__ __launch_bounds__(256) void k_md_energy(MDParams p, int Nmax, int NPm
 
 // ===========================================================================
 // Energy and force bias, FP32 contractions over compact rows: four walkers per
-// block, one wavefront each.  Per (operator, spin) phase the block stages the
-// operator's rows LCc[slot] (FP32, M padded to 4 KS k rows, in MFMA fragment
-// order) in LDS once for its four walkers;
-// each wavefront forms its walker's P = LCc^T Theta_0 (R x N) by 16x16x4 MFMA
-// with Theta_0 held in registers as the B operand, then, on its own, X0^2 and
-// the traces, the sums over the occupied index of every listed (particle,
-// hole) pair, and every determinant's t^1 / t^2 coefficients.  Two leading
-// phases (one per spin) form Ghat at the particle rows the same way, from the
-// rows of C in slot G+1.  The operator of the phase after next is loaded into
-// registers while the current one is worked on, so one barrier pair per
-// phase is the only block-wide synchronisation.
+// block and two wavefronts per walker, a producer and a consumer, so that the
+// matrix-core work of one phase overlaps the vector work of the previous one.  Phases q = (slot, spin) run in the order slot G+1 (the rows of C:
+// Ghat at the particle rows), then the operators 0..G.  In step tau:
+//  - the producers form P(tau) = LCc[slot]^T Theta_0 for their walkers by
+//    16x16x4 MFMA, the operator (FP32, M padded to 4 KS k rows, in MFMA
+//    fragment order) staged in LDS once for the four walkers and Theta_0
+//    held in registers as the B operand, into LDS buffer tau mod 2;
+//  - each consumer works on P(tau - 1) of its walker: X0^2 (MFMA) and the
+//    traces, the sums over the occupied index of every listed (particle,
+//    hole) pair (the lane owning the particle, its Ghat row held in
+//    registers) with the coefficients of the single excitation it defines,
+//    and every other determinant's t^1 / t^2 coefficients, accumulated per
+//    determinant in FP64.
+// After a barrier the producers store the next operator (loaded into their
+// registers a step earlier) and request the one after it; a second barrier
+// publishes it.
 // ===========================================================================
-constexpr int kMdWaves = 4;
+constexpr int kMdWalkers = 4;
 
 struct MdRowsLds {
-  int ns;      // row stride (elements) of P and X0^2 in a wavefront's region
-  int wbytes;  // bytes of one wavefront's region
-  int pw, x2, gh0, gh1, tab;  // offsets inside a wavefront's region
-  int wave0;   // offset of wavefront 0's region
+  int ns;      // row stride (elements) of P and X0^2
+  int wbytes;  // bytes of one walker's region
+  int pw0, pw1, x2, tab, e1, s0a, s0b;  // offsets inside a walker's region
+  int wave0;   // offset of walker 0's region
   int total;
 };
 
@@ -517,20 +522,25 @@ inline MdRowsLds md_rows_lds(const MDParams& p, int ks) {
   const int rp = p.rows.RP[0] > p.rows.RP[1] ? p.rows.RP[0] : p.rows.RP[1];
   const int np = p.rows.npair[0] > p.rows.npair[1] ? p.rows.npair[0] : p.rows.npair[1];
   o.ns = Nmax > 0 ? Nmax : 1;
+  const int pwb = al((long)(R0 > R1 ? R0 : R1) * o.ns * 8);
   int q = 0;
-  o.pw = q;
-  q += al((long)(R0 > R1 ? R0 : R1) * o.ns * 8);
+  o.pw0 = q;
+  q += pwb;
+  o.pw1 = q;
+  q += pwb;
   o.x2 = q;
   q += al((long)Nmax * o.ns * 8);
-  o.gh0 = q;
-  q += al((long)(R0 - N0) * N0 * 8);
-  o.gh1 = q;
-  q += al((long)(R1 - N1) * N1 * 8);
   o.tab = q;
   q += al((long)np * 24);
+  o.e1 = q;
+  q += al((long)np * 32);
+  o.s0a = q;
+  q += al((long)p.rows.npair[0] * 8);
+  o.s0b = q;
+  q += al((long)p.rows.npair[1] * 8);
   o.wbytes = q;
   o.wave0 = al((long)4 * ks * rp * 4);  // the operator: 4 ks rows (k) x rp columns
-  o.total = o.wave0 + kMdWaves * o.wbytes;
+  o.total = o.wave0 + kMdWalkers * o.wbytes;
   return o;
 }
 
@@ -562,13 +572,28 @@ __device__ __forceinline__ void md_rows_tile(const afq_f4* __restrict__ a4, int 
   }
 }
 
+// t^1 / t^2 coefficients of a single excitation r -> v (E = 1 of the algebra
+// above) from its entries s = S0, q = Q, gx = GX, px = PX, gxx = GXX, x =
+// X0[r][r], y = X0^2[r][r], Tr X0 and e2 = (Tr^2 X0 - Tr X0^2) / 2.
+__device__ inline void md_single(Cx s, Cx q, Cx gx, Cx px, Cx gxx, Cx x, Cx y, Cx trx0, Cx e2,
+                                 Cx& c1, Cx& c2) {
+  const Cx bq = gx - s * x;
+  const Cx s1 = q - bq;
+  const Cx s2 = (gxx - s * y) - bq * x - (px - q * x);
+  const Cx t1 = trx0 - x;
+  const Cx t2 = e2 - (x * trx0 - y);
+  c1 = s1 + t1 * s;
+  c2 = s2 + t1 * s1 + t2 * s;
+}
+
 // One determinant's coefficients for one spin from the compact-row quantities
-// of its wavefront: particles as compact indices t (row N + t of P, row t of
-// Ghat), the pair sums from the table.
+// of its walker: particles as compact indices t (row N + t of P), holes r,
+// the pair sums (GX, PX, GXX) from the table and S0 = Ghat[v][r] from the
+// set-up-time table of the pair.
 template <int E>
 __device__ inline void md_det_rows(int N, int NS, unsigned w0, unsigned w1, unsigned w2,
-                                   const float2* gh, const float2* pw, const float2* x2,
-                                   const float2* tab, Cx trx0, Cx trx2, Cx& c1, Cx& c2) {
+                                   const float2* pw, const float2* x2, const float2* tab,
+                                   const float2* s0t, Cx trx0, Cx trx2, Cx& c1, Cx& c2) {
   const int hole[2] = {(int)((w0 >> 2) & 31u), (int)((w0 >> 7) & 31u)};
   const int part[2] = {(int)((w0 >> 12) & 255u), (int)((w0 >> 20) & 255u)};
   const int pidx[2][2] = {{(int)(w1 & 0xffffu), (int)(w1 >> 16)},
@@ -578,11 +603,12 @@ __device__ inline void md_det_rows(int N, int NS, unsigned w0, unsigned w1, unsi
   for (int e = 0; e < E; ++e)
 #pragma unroll
     for (int f = 0; f < E; ++f) {
-      const float2 g = gh[part[e] * N + hole[f]];
+      const int k = pidx[e][f];
+      const float2 g = s0t[k];
       const float2 q = pw[(N + part[e]) * NS + hole[f]];
       const float2 x = pw[hole[e] * NS + hole[f]];
       const float2 y = x2[hole[e] * NS + hole[f]];
-      const float2* tb = tab + 3 * pidx[e][f];
+      const float2* tb = tab + 3 * k;
       const float2 t0 = tb[0], t1 = tb[1], t2 = tb[2];
       S0[e][f] = cx(g.x, g.y);
       Q[e][f] = cx(q.x, q.y);
@@ -595,67 +621,57 @@ __device__ inline void md_det_rows(int N, int NS, unsigned w0, unsigned w1, unsi
   md_det_algebra<E>(S0, Q, GX, PX, GXX, XR, X2R, trx0, trx2, c1, c2);
 }
 
-// Phase ph of the compact-row kernel works on slot md_rows_slot(ph, G) for
-// spin ph & 1: slot G+1 (the rows of C) first, then the operators 0..G.
-__device__ __forceinline__ int md_rows_slot(int ph, int G) { return ph < 2 ? G + 1 : (ph >> 1) - 1; }
+// Phase q of the compact-row kernel works on slot md_rows_slot(q, G) for
+// spin q & 1: slot G+1 (the rows of C) first, then the operators 0..G.
+__device__ __forceinline__ int md_rows_slot(int q, int G) { return q < 2 ? G + 1 : (q >> 1) - 1; }
 
-// Loads phase ph's operator (4 KS x RP floats in fragment order, contiguous)
-// into the staging registers, 16 bytes per thread and register; every thread
-// loads all of them (indices past the end are clamped; the set-up gives a
-// spin without electrons a 16-float table) so that the array stays in
-// registers.
+// Loads phase q's operator (4 KS x RP floats in fragment order, contiguous)
+// into the staging registers of the producer threads (256), 16 bytes per
+// thread and register; every thread loads all of them (indices past the end
+// are clamped; the set-up gives a spin without electrons a 16-float table) so
+// that the array stays in registers.
 template <int KS>
-__device__ __forceinline__ void md_rows_issue(const MDParams& p, int G, int ph,
+__device__ __forceinline__ void md_rows_issue(const MDParams& p, int G, int q, int tid,
                                               afq_f4 (&pf)[kMdRowsPF]) {
-  const int s = ph & 1, rp = s ? p.rows.RP[1] : p.rows.RP[0];
+  const int s = q & 1, rp = s ? p.rows.RP[1] : p.rows.RP[0];
   const float* base = s ? p.rows.LCc[1] : p.rows.LCc[0];
   const int n4 = KS * rp;
   const int last = n4 > 0 ? n4 - 1 : 0;
-  const afq_f4* src = (const afq_f4*)(base + (size_t)md_rows_slot(ph, G) * 4 * KS * rp);
+  const afq_f4* src = (const afq_f4*)(base + (size_t)md_rows_slot(q, G) * 4 * KS * rp);
 #pragma unroll
   for (int u = 0; u < kMdRowsPF; ++u) {
-    const int q = threadIdx.x + 256 * u;
-    pf[u] = src[q < last ? q : last];
+    const int e = tid + 256 * u;
+    pf[u] = src[e < last ? e : last];
   }
 }
 
 // Stores the staging registers into the LDS operator buffer (same order).
 template <int KS>
-__device__ __forceinline__ void md_rows_stage(const MDParams& p, int ph,
+__device__ __forceinline__ void md_rows_stage(const MDParams& p, int q, int tid,
                                               const afq_f4 (&pf)[kMdRowsPF], afq_f4* abuf) {
-  const int s = ph & 1, rp = s ? p.rows.RP[1] : p.rows.RP[0];
+  const int s = q & 1, rp = s ? p.rows.RP[1] : p.rows.RP[0];
   const int n4 = KS * rp;
 #pragma unroll
   for (int u = 0; u < kMdRowsPF; ++u) {
-    const int q = threadIdx.x + 256 * u;
-    if (q < n4) abuf[q] = pf[u];
+    const int e = tid + 256 * u;
+    if (e < n4) abuf[e] = pf[u];
   }
 }
 
-template <int KS, int DPL>
-__global__ __launch_bounds__(256) void k_md_energy_rows(
-    MDParams p, MdRowsLds L, int W, const double* __restrict__ thr, const double* __restrict__ thi,
-    const double* __restrict__ c0_re, const double* __restrict__ c0_im, const double* tot_re,
-    const double* tot_im, double* v_re, double* v_im, double* eln_re, double* eln_im, int* vfin) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
+// Producer: Theta_0 as B fragments (lane (li, lk) holds row 4 j + lk, column
+// li of each spin; zero past M and past N), then per step the product of the
+// staged operator into the P buffer of the step.
+template <int KS>
+__device__ void md_rows_producer(const MDParams& p, const MdRowsLds& L, unsigned char* lds,
+                                 int wl, long wb, const double* __restrict__ thr,
+                                 const double* __restrict__ thi) {
   typedef Mfma<float> MM;
   typedef MM::acc_t acc_t;
-  const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
-  const int w = blockIdx.x * kMdWaves + wv;
-  const bool live = w < W;
-  const int wr = live ? w : W - 1;  // the last block's idle wavefronts read a real walker
-  const int M = p.M, Nt = p.Nt, G = p.G, NS = L.ns, n_det = p.n_det;
-  const long wb = (long)wr * M * Nt;
-  afq_f4* abuf = (afq_f4*)lds_raw;
-  unsigned char* reg = lds_raw + L.wave0 + wv * L.wbytes;
-  float2* pw = (float2*)(reg + L.pw);
-  float2* x2 = (float2*)(reg + L.x2);
-  float2* gh0 = (float2*)(reg + L.gh0);
-  float2* gh1 = (float2*)(reg + L.gh1);
-  float2* tab = (float2*)(reg + L.tab);
-
-  // Theta_0 as B fragments: lane (li, lk) holds row 4 j + lk, column li of
-  // each spin (zero past M and past N)
+  const int l = lane_id(), li = l & 15, lk = l >> 4;
+  const int tid = 64 * (wave_id() >> 1) + l;  // 0 .. 255 over the four producers
+  const int M = p.M, Nt = p.Nt, G = p.G, NS = L.ns, NPH = 2 * (G + 2);
+  afq_f4* abuf = (afq_f4*)lds;
+  unsigned char* reg = lds + L.wave0 + wl * L.wbytes;
   float b0r[KS], b0i[KS], b1r[KS], b1i[KS];
   {
     const int N0 = p.sp[0].N, N1 = p.sp[1].N, o1 = p.sp[1].off;
@@ -671,15 +687,64 @@ __global__ __launch_bounds__(256) void k_md_energy_rows(
       b1i[j] = ok1 ? (float)thi[i1] : 0.f;
     }
   }
+  afq_f4 pf[kMdRowsPF];
+  md_rows_issue<KS>(p, G, 0, tid, pf);
+  md_rows_stage<KS>(p, 0, tid, pf, abuf);
+  md_rows_issue<KS>(p, G, 1, tid, pf);
+  __syncthreads();
+  for (int tau = 0; tau <= NPH; ++tau) {
+    if (tau < NPH) {
+      const int s = tau & 1;
+      const int N = s ? p.sp[1].N : p.sp[0].N;
+      const int R = s ? p.rows.R[1] : p.rows.R[0];
+      const int RT = (R + 15) >> 4;
+      const int RTP = (s ? p.rows.RP[1] : p.rows.RP[0]) >> 4;
+      float2* pw = (float2*)(reg + ((tau & 1) ? L.pw1 : L.pw0));
+      for (int rt = 0; rt < RT; ++rt) {
+        acc_t er = MM::zero(), ei = MM::zero(), orr = MM::zero(), oi = MM::zero();
+        const afq_f4* a4 = abuf + rt * 64 + l;
+        if (s == 0)
+          md_rows_tile<KS>(a4, RTP * 64, b0r, b0i, er, ei, orr, oi);
+        else
+          md_rows_tile<KS>(a4, RTP * 64, b1r, b1i, er, ei, orr, oi);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * rt + 4 * lk + v;
+          if (li < N && row < R) pw[row * NS + li] = make_float2(er[v] + orr[v], ei[v] + oi[v]);
+        }
+      }
+    }
+    __syncthreads();  // P(tau) written; every producer is done with the operator
+    if (tau + 1 < NPH) md_rows_stage<KS>(p, tau + 1, tid, pf, abuf);
+    if (tau + 2 < NPH) md_rows_issue<KS>(p, G, tau + 2, tid, pf);
+    __syncthreads();  // the next operator is in LDS
+  }
+}
 
-  // per-determinant state: determinant i = l + 64 k of this walker
+// Consumer: the determinant algebra of phase tau - 1 in step tau.
+template <int DPL>
+__device__ void md_rows_consumer(const MDParams& p, const MdRowsLds& L, unsigned char* lds, int wl,
+                                 int w, int wr, bool live, const double* __restrict__ c0_re,
+                                 const double* __restrict__ c0_im, const double* tot_re,
+                                 const double* tot_im, double* v_re, double* v_im, double* eln_re,
+                                 double* eln_im, int* vfin) {
+  const int l = lane_id();
+  const int G = p.G, NS = L.ns, n_det = p.n_det, NPH = 2 * (G + 2);
+  unsigned char* reg = lds + L.wave0 + wl * L.wbytes;
+  float2* x2 = (float2*)(reg + L.x2);
+  float2* tab = (float2*)(reg + L.tab);
+  double2* e1t = (double2*)(reg + L.e1);
+  float2* s0a = (float2*)(reg + L.s0a);
+  float2* s0b = (float2*)(reg + L.s0b);
+  // per-determinant state: slot i = l + 64 k holds determinant dx[i][6];
+  // acc accumulates cd c2_up + cu c2_dn + coef c1_up c1_dn over the vectors,
+  // plus cd c1_up + cu c1_dn for h and e_core coef c0_up c0_dn, with
+  // cu = coef c0_up and cd = coef c0_dn
   unsigned dxw[DPL][2][3];
   double coef[DPL];
-  Cx c0u[DPL], c0d[DPL], a2u[DPL], a2d[DPL], a11[DPL], c1p[DPL], c1h0[DPL], c1h1[DPL];
+  Cx cu[DPL], cd[DPL], acc[DPL], c1p[DPL];
 #pragma unroll
   for (int k = 0; k < DPL; ++k) {
-    // slot i holds determinant dx[i][6] (the set-up orders the determinants so
-    // that each 64-lane slot mixes as few excitation ranks per spin as it can)
     const int i = l + 64 * k;
     const bool ok = i < n_det;
     const int* dr = p.rows.dx + (ok ? i : 0) * kMdDx;
@@ -690,152 +755,166 @@ __global__ __launch_bounds__(256) void k_md_energy_rows(
 #pragma unroll
       for (int q = 0; q < 3; ++q) dxw[k][s][q] = ok ? (unsigned)dr[s * 3 + q] : 0u;
     const long u = ((long)wr * 2) * n_det + ic, d = ((long)wr * 2 + 1) * n_det + ic;
-    c0u[k] = ok ? cx(c0_re[u], c0_im[u]) : cx(0, 0);
-    c0d[k] = ok ? cx(c0_re[d], c0_im[d]) : cx(0, 0);
-    a2u[k] = a2d[k] = a11[k] = c1p[k] = c1h0[k] = c1h1[k] = cx(0, 0);
+    const Cx c0u = ok ? cx(c0_re[u], c0_im[u]) : cx(0, 0);
+    const Cx c0d = ok ? cx(c0_re[d], c0_im[d]) : cx(0, 0);
+    cu[k] = coef[k] * c0u;
+    cd[k] = coef[k] * c0d;
+    acc[k] = p.e_core * (cu[k] * c0d);
+    c1p[k] = cx(0, 0);
   }
   const Cx tot = cx(tot_re[wr], tot_im[wr]);
   int fin = 1;
-
-  // operator staging: phase ph = (slot, spin), slots G+1 (C) first, then 0..G
-  const int NPH = 2 * (G + 2);
-  afq_f4 pf[kMdRowsPF];
-  md_rows_issue<KS>(p, G, 0, pf);
-  md_rows_stage<KS>(p, 0, pf, abuf);
-  md_rows_issue<KS>(p, G, 1, pf);
-  __syncthreads();
-
-  for (int ph = 0; ph < NPH; ++ph) {
-    const int s = ph & 1, slot = md_rows_slot(ph, G);
-    const int N = s ? p.sp[1].N : p.sp[0].N;
-    const int R = s ? p.rows.R[1] : p.rows.R[0];
-    const int RT = (R + 15) >> 4;
-    const int RTP = (s ? p.rows.RP[1] : p.rows.RP[0]) >> 4;
-    float2* gh = s ? gh1 : gh0;
-    // P (or, in the leading phases, Ghat) one 16-row tile at a time; lane
-    // (li, lk) of tile rt holds rows 16 rt + 4 lk + v, column li
-    wave_lds_sync();
-    for (int rt = 0; rt < RT; ++rt) {
-      acc_t er = MM::zero(), ei = MM::zero(), orr = MM::zero(), oi = MM::zero();
-      const afq_f4* a4 = abuf + rt * 64 + l;
-      if (s == 0)
-        md_rows_tile<KS>(a4, RTP * 64, b0r, b0i, er, ei, orr, oi);
-      else
-        md_rows_tile<KS>(a4, RTP * 64, b1r, b1i, er, ei, orr, oi);
+  // the Ghat row of particle t = l of each spin (FP32), owned by lane t
+  float2 gh0[kMdRowsMaxN], gh1[kMdRowsMaxN];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 16 * rt + 4 * lk + v;
-        const float2 val = make_float2(er[v] + orr[v], ei[v] + oi[v]);
-        if (li < N && row < R) {
-          if (slot > G) {
-            if (row >= N) gh[(row - N) * N + li] = val;
-          } else {
-            pw[row * NS + li] = val;
-          }
-        }
-      }
-    }
-    __syncthreads();  // every wavefront is done with this phase's operator
-    if (ph + 1 < NPH) md_rows_stage<KS>(p, ph + 1, pf, abuf);
-    if (ph + 2 < NPH) md_rows_issue<KS>(p, G, ph + 2, pf);
-    if (slot <= G) {
-      wave_lds_sync();
-      // X0^2 and the sums of the pairs below in FP32 (the contraction type);
-      // the traces and the determinant algebra in FP64
-      for (int e = l; e < N * N; e += 64) {
-        const int a = e / N, b = e - a * N;
-        float sr = 0.f, si = 0.f;
-        for (int c = 0; c < N; ++c) {
-          const float2 x = pw[a * NS + c], y = pw[c * NS + b];
-          sr = fmaf(x.x, y.x, fmaf(-x.y, y.y, sr));
-          si = fmaf(x.x, y.y, fmaf(x.y, y.x, si));
-        }
-        x2[a * NS + b] = make_float2(sr, si);
-      }
-      wave_lds_sync();
-      double t0r = 0.0, t0i = 0.0, t2r = 0.0, t2i = 0.0;
-      if (l < N) {
-        const float2 d = pw[l * NS + l], d2 = x2[l * NS + l];
-        t0r = d.x;
-        t0i = d.y;
-        t2r = d2.x;
-        t2i = d2.y;
-      }
-      const Cx trx0 = cx(wave_sum(t0r), wave_sum(t0i)), trx2 = cx(wave_sum(t2r), wave_sum(t2i));
-      // sums over the occupied index c of the listed (particle t, hole r) pairs
-      const int np = s ? p.rows.npair[1] : p.rows.npair[0];
+  for (int c = 0; c < kMdRowsMaxN; ++c) gh0[c] = gh1[c] = make_float2(0.f, 0.f);
+  __syncthreads();  // the producers' first operator is staged
+  for (int tau = 0; tau <= NPH; ++tau) {
+    if (tau >= 1) {
+      const int q = tau - 1, s = q & 1, slot = md_rows_slot(q, G);
+      const int N = s ? p.sp[1].N : p.sp[0].N;
+      const int R = s ? p.rows.R[1] : p.rows.R[0];
+      const int nv = R - N;
+      const float2* pw = (const float2*)(reg + ((q & 1) ? L.pw1 : L.pw0));
       const int* pl = s ? p.rows.pair[1] : p.rows.pair[0];
-      for (int k = l; k < np; k += 64) {
-        const int pr = pl[k], t = pr >> 8, r = pr & 255;
-        const float2* gv = gh + t * N;
-        const float2* pv = pw + (N + t) * NS;
-        float gxr = 0.f, gxi = 0.f, pxr = 0.f, pxi = 0.f, ggr = 0.f, ggi = 0.f;
-        for (int c = 0; c < N; ++c) {
-          const float2 g = gv[c], q = pv[c], x = pw[c * NS + r], y = x2[c * NS + r];
-          gxr = fmaf(g.x, x.x, fmaf(-g.y, x.y, gxr));
-          gxi = fmaf(g.x, x.y, fmaf(g.y, x.x, gxi));
-          pxr = fmaf(q.x, x.x, fmaf(-q.y, x.y, pxr));
-          pxi = fmaf(q.x, x.y, fmaf(q.y, x.x, pxi));
-          ggr = fmaf(g.x, y.x, fmaf(-g.y, y.y, ggr));
-          ggi = fmaf(g.x, y.y, fmaf(g.y, y.x, ggi));
-        }
-        tab[3 * k] = make_float2(gxr, gxi);
-        tab[3 * k + 1] = make_float2(pxr, pxi);
-        tab[3 * k + 2] = make_float2(ggr, ggi);
-      }
-      wave_lds_sync();
-      Cx vn = cx(0, 0);
+      const int* pb = s ? p.rows.pbeg[1] : p.rows.pbeg[0];
+      float2* s0t = s ? s0b : s0a;
+      if (slot > G) {
+        // Ghat rows: into the owner's registers, and S0 = Ghat[v][r] of every
+        // pair of the particle into the spin's table
+        if (l < nv) {
+          const float2* row = pw + (N + l) * NS;
 #pragma unroll
-      for (int k = 0; k < DPL; ++k) {
-        const unsigned w0 = s ? dxw[k][1][0] : dxw[k][0][0];
-        const unsigned w1 = s ? dxw[k][1][1] : dxw[k][0][1];
-        const unsigned w2 = s ? dxw[k][1][2] : dxw[k][0][2];
-        const int E = (int)(w0 & 3u);
-        Cx c1, c2;
-        if (E == 0) {
-          c1 = trx0;
-          c2 = 0.5 * (trx0 * trx0 - trx2);
-        } else if (E == 1) {
-          md_det_rows<1>(N, NS, w0, w1, w2, gh, pw, x2, tab, trx0, trx2, c1, c2);
-        } else {
-          md_det_rows<2>(N, NS, w0, w1, w2, gh, pw, x2, tab, trx0, trx2, c1, c2);
+          for (int c = 0; c < kMdRowsMaxN; ++c) {
+            const float2 v = c < N ? row[c] : make_float2(0.f, 0.f);
+            if (s)
+              gh1[c] = v;
+            else
+              gh0[c] = v;
+          }
+          for (int k = pb[l]; k < pb[l + 1]; ++k) s0t[k] = row[pl[k] & 255];
         }
-        if (slot < G) {
-          if (s == 0) {
-            a2u[k] = a2u[k] + c2;
-            c1p[k] = c1;
+      } else {
+        // X0^2 (one 16x16 tile, four real products over four k steps) and
+        // the pair sums in FP32 (the contraction type); the traces and the
+        // determinant algebra in FP64
+        {
+          typedef Mfma<float> MM;
+          const int li = l & 15, lk = l >> 4;
+          MM::acc_t rr = MM::zero(), ri = MM::zero(), ir = MM::zero(), ii = MM::zero();
+#pragma unroll
+          for (int kk = 0; kk < kMdRowsMaxN / 4; ++kk) {
+            const int k = 4 * kk + lk;
+            const bool ka = li < N && k < N;
+            const float2 a = ka ? pw[li * NS + k] : make_float2(0.f, 0.f);
+            const float2 b = ka ? pw[k * NS + li] : make_float2(0.f, 0.f);
+            rr = MM::mma(a.x, b.x, rr);
+            ii = MM::mma(a.y, b.y, ii);
+            ri = MM::mma(a.x, b.y, ri);
+            ir = MM::mma(a.y, b.x, ir);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 4 * lk + v;
+            if (row < N && li < N) x2[row * NS + li] = make_float2(rr[v] - ii[v], ri[v] + ir[v]);
+          }
+        }
+        wave_lds_sync();
+        double t0r = 0.0, t0i = 0.0, t2r = 0.0, t2i = 0.0;
+        if (l < N) {
+          const float2 d = pw[l * NS + l], d2 = x2[l * NS + l];
+          t0r = d.x;
+          t0i = d.y;
+          t2r = d2.x;
+          t2i = d2.y;
+        }
+        const Cx trx0 = cx(wave_sum(t0r), wave_sum(t0i)), trx2 = cx(wave_sum(t2r), wave_sum(t2i));
+        // the pairs of particle t = l: GX = Ghat[v] X0[:, r], PX = P[v] X0[:, r],
+        // GXX = Ghat[v] X0^2[:, r] (sums over the occupied index), and the
+        // t^1 / t^2 coefficients of the single excitation r -> v
+        const Cx e2 = 0.5 * (trx0 * trx0 - trx2);
+        if (l < nv) {
+          const float2* pv = pw + (N + l) * NS;
+          for (int k = pb[l]; k < pb[l + 1]; ++k) {
+            const int r = pl[k] & 255;
+            float gxr = 0.f, gxi = 0.f, pxr = 0.f, pxi = 0.f, ggr = 0.f, ggi = 0.f;
+#pragma unroll
+            for (int c = 0; c < kMdRowsMaxN; ++c) {
+              if (c < N) {
+                const float2 g = s ? gh1[c] : gh0[c];
+                const float2 qv = pv[c], x = pw[c * NS + r], y = x2[c * NS + r];
+                gxr = fmaf(g.x, x.x, fmaf(-g.y, x.y, gxr));
+                gxi = fmaf(g.x, x.y, fmaf(g.y, x.x, gxi));
+                pxr = fmaf(qv.x, x.x, fmaf(-qv.y, x.y, pxr));
+                pxi = fmaf(qv.x, x.y, fmaf(qv.y, x.x, pxi));
+                ggr = fmaf(g.x, y.x, fmaf(-g.y, y.y, ggr));
+                ggi = fmaf(g.x, y.y, fmaf(g.y, y.x, ggi));
+              }
+            }
+            tab[3 * k] = make_float2(gxr, gxi);
+            tab[3 * k + 1] = make_float2(pxr, pxi);
+            tab[3 * k + 2] = make_float2(ggr, ggi);
+            const float2 sv = s0t[k], qv = pv[r], xv = pw[r * NS + r], yv = x2[r * NS + r];
+            Cx c1, c2;
+            md_single(cx(sv.x, sv.y), cx(qv.x, qv.y), cx(gxr, gxi), cx(pxr, pxi), cx(ggr, ggi),
+                      cx(xv.x, xv.y), cx(yv.x, yv.y), trx0, e2, c1, c2);
+            e1t[2 * k] = make_double2(c1.r, c1.i);
+            e1t[2 * k + 1] = make_double2(c2.r, c2.i);
+          }
+        }
+        wave_lds_sync();
+        Cx vn = cx(0, 0);
+#pragma unroll
+        for (int k = 0; k < DPL; ++k) {
+          const unsigned w0 = s ? dxw[k][1][0] : dxw[k][0][0];
+          const unsigned w1 = s ? dxw[k][1][1] : dxw[k][0][1];
+          const unsigned w2 = s ? dxw[k][1][2] : dxw[k][0][2];
+          const int E = (int)(w0 & 3u);
+          Cx c1, c2;
+          if (E == 0) {
+            c1 = trx0;
+            c2 = 0.5 * (trx0 * trx0 - trx2);
+          } else if (E == 1) {
+            const int k1 = (int)(w1 & 0xffffu);
+            const double2 a = e1t[2 * k1], b = e1t[2 * k1 + 1];
+            c1 = cx(a.x, a.y);
+            c2 = cx(b.x, b.y);
           } else {
-            a2d[k] = a2d[k] + c2;
-            a11[k] = a11[k] + c1p[k] * c1;
-            vn = vn + coef[k] * (c1p[k] * c0d[k] + c0u[k] * c1);
+            md_det_rows<2>(N, NS, w0, w1, w2, pw, x2, tab, s0t, trx0, trx2, c1, c2);
           }
-        } else if (s == 0) {
-          c1h0[k] = c1;
-        } else {
-          c1h1[k] = c1;
+          if (slot < G) {
+            if (s == 0) {
+              acc[k] = acc[k] + cd[k] * c2;
+              c1p[k] = c1;
+            } else {
+              acc[k] = acc[k] + cu[k] * c2 + coef[k] * (c1p[k] * c1);
+              vn = vn + (c1p[k] * cd[k] + cu[k] * c1);
+            }
+          } else {
+            acc[k] = acc[k] + (s ? cu[k] * c1 : cd[k] * c1);
+          }
         }
-      }
-      if (slot < G && s == 1) {
-        const double vr = wave_sum(vn.r), vi = wave_sum(vn.i);
-        if (l == 0) {
-          const Cx v = cdiv(cx(vr, vi), tot);
-          if (live) {
-            v_re[(long)w * G + slot] = v.r;
-            v_im[(long)w * G + slot] = v.i;
+        if (slot < G && s == 1) {
+          const double vr = wave_sum(vn.r), vi = wave_sum(vn.i);
+          if (l == 0) {
+            const Cx v = cdiv(cx(vr, vi), tot);
+            if (live) {
+              v_re[(long)w * G + slot] = v.r;
+              v_im[(long)w * G + slot] = v.i;
+            }
+            if (!isfinite(v.r) || !isfinite(v.i)) fin = 0;
           }
-          if (!isfinite(v.r) || !isfinite(v.i)) fin = 0;
         }
       }
     }
-    __syncthreads();  // the next phase's operator is in LDS
+    __syncthreads();  // step tau done: P(tau) written, P(tau - 1) consumed
+    __syncthreads();  // the producers' next operator is in LDS
   }
   double nr = 0.0, ni = 0.0;
 #pragma unroll
   for (int k = 0; k < DPL; ++k) {
-    const Cx n = coef[k] * (p.e_core * (c0u[k] * c0d[k]) + c1h0[k] * c0d[k] + c0u[k] * c1h1[k] +
-                            c0d[k] * a2u[k] + c0u[k] * a2d[k] + a11[k]);
-    nr += n.r;
-    ni += n.i;
+    nr += acc[k].r;
+    ni += acc[k].i;
   }
   nr = wave_sum(nr);
   ni = wave_sum(ni);
@@ -845,6 +924,28 @@ __global__ __launch_bounds__(256) void k_md_energy_rows(
     eln_im[w] = e.i;
     vfin[w] = fin;
   }
+}
+
+template <int KS, int DPL>
+__global__ __launch_bounds__(512) void k_md_energy_rows(
+    MDParams p, MdRowsLds L, int W, const double* __restrict__ thr, const double* __restrict__ thi,
+    const double* __restrict__ c0_re, const double* __restrict__ c0_im, const double* tot_re,
+    const double* tot_im, double* v_re, double* v_im, double* eln_re, double* eln_im, int* vfin) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int wv = wave_id(), wl = wv >> 1;
+  const int w = blockIdx.x * kMdWalkers + wl;
+  const bool live = w < W;
+  const int wr = live ? w : W - 1;  // the last block's idle walkers read a real one
+  // both roles pass the same number of block barriers: 1 + 2 (NPH + 1).
+  // Even wavefronts produce, odd ones consume: a block's wavefronts w and
+  // w + 4 share a SIMD, so the producers occupy two SIMDs and the consumers
+  // (FP64 vector work, which runs slower beside another wavefront's MFMAs)
+  // the other two.
+  if ((wv & 1) == 0)
+    md_rows_producer<KS>(p, L, lds_raw, wl, (long)wr * p.M * p.Nt, thr, thi);
+  else
+    md_rows_consumer<DPL>(p, L, lds_raw, wl, w, wr, live, c0_re, c0_im, tot_re, tot_im, v_re, v_im,
+                          eln_re, eln_im, vfin);
 }
 
 // Launches the compact-row kernel when its tables exist and its LDS fits;
@@ -859,7 +960,7 @@ static bool md_energy_rows(hipStream_t st, int W, const MDParams& p, const doubl
   const MdRowsLds L = md_rows_lds(p, ks);
   if ((size_t)L.total > max_lds) return false;
   const int dpl = (p.n_det + 63) / 64;
-  const dim3 grid((W + kMdWaves - 1) / kMdWaves), block(64 * kMdWaves);
+  const dim3 grid((W + kMdWalkers - 1) / kMdWalkers), block(128 * kMdWalkers);
 #define AFQ_MDR_LAUNCH(K, D)                                                                   \
   hipLaunchKernelGGL((k_md_energy_rows<K, D>), grid, block, L.total, st, p, L, W, thr, thi, \
                      c0_re, c0_im, tot_re, tot_im, v_re, v_im, eln_re, eln_im, vfin)
