@@ -51,8 +51,12 @@ def _inputs():
 
 
 def source_digest() -> str:
+    """SHA-256 over the flags and every input file.  Paths enter relative to
+    the repository root, so a copy of the tree elsewhere (same sources) finds
+    its shipped library current."""
     h = hashlib.sha256()
-    h.update(" ".join(_flags() + SOURCES).encode())
+    flags = [os.path.relpath(f, ROOT) if f in (INCLUDE, CSRC) else f for f in _flags()]
+    h.update(" ".join(flags + SOURCES).encode())
     for p in _inputs():
         h.update(os.path.relpath(p, ROOT).encode())
         with open(p, "rb") as f:

@@ -493,8 +493,9 @@ __global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s
 // result R relates to the inverse by S^-1[k][j] = R[pi(k)][pi^-1(j)], pi(k)
 // being the pivot row of column k, and is written to LDS in that order;
 // det S = sign(pi) prod of the pivots.  Theta = phi S^-1 is a second FP64
-// MFMA product over 16-row tiles of phi (the first tile's operands are
-// requested before the elimination starts) with S^-1 held in registers.
+// MFMA product over 16-row tiles of phi, three real products per complex one
+// (Gauss), with S^-1 held in registers; each tile's operands are requested
+// one tile ahead (the first before the elimination starts).
 __device__ inline double readlane_d(double v, int lane) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
@@ -769,8 +770,8 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
   const int RT = (M + 15) >> 4;
   double er = 0.0, ei = 0.0;
   for (int R = 0; R < RT; ++R) {
-    // this tile's phi and h~ entries requested together (h~ clamped to valid
-    // entries, used only where stored), so that their latencies overlap
+    // this tile's h~ entries (clamped to valid entries, used only where
+    // stored), and the next tile's phi requested before this tile's MFMAs
     double hvt[NT][4];
 #pragma unroll
     for (int J = 0; J < NT; ++J)
@@ -780,18 +781,20 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
         hvt[J][v] = g.htil[(long)b * M + m];
       }
     if (R > 0) load_phi_tile(par, pai, R);
-    acc_t tr[NT], ti[NT];
+    // complex product by three real ones (Gauss): p1 = Ar Br, p2 = Ai Bi,
+    // p3 = (Ar + Ai)(Br + Bi); re = p1 - p2, im = p3 - p1 - p2
+    acc_t p1[NT], p2[NT], p3[NT];
 #pragma unroll
-    for (int J = 0; J < NT; ++J) { tr[J] = MM::zero(); ti[J] = MM::zero(); }
+    for (int J = 0; J < NT; ++J) { p1[J] = MM::zero(); p2[J] = MM::zero(); p3[J] = MM::zero(); }
 #pragma unroll
     for (int ka = 0; ka < KA; ++ka) {
       if (ka < KN) {
+        const double as = par[ka] + pai[ka];
 #pragma unroll
         for (int J = 0; J < NT; ++J) {
-          tr[J] = MM::mma(par[ka], sbr[ka][J], tr[J]);
-          tr[J] = MM::mma(-pai[ka], sbi[ka][J], tr[J]);
-          ti[J] = MM::mma(par[ka], sbi[ka][J], ti[J]);
-          ti[J] = MM::mma(pai[ka], sbr[ka][J], ti[J]);
+          p1[J] = MM::mma(par[ka], sbr[ka][J], p1[J]);
+          p2[J] = MM::mma(pai[ka], sbi[ka][J], p2[J]);
+          p3[J] = MM::mma(as, sbr[ka][J] + sbi[ka][J], p3[J]);
         }
       }
     }
@@ -800,10 +803,11 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = 16 * R + MM::row(lk, v), b = 16 * J + li;
+        const double tr = p1[J][v] - p2[J][v], ti = p3[J][v] - p1[J][v] - p2[J][v];
         if (m < M && b < N) {
-          theta_store(to, w, M, Nt, off, s, N, m, b, tr[J][v], ti[J][v]);
-          er += hvt[J][v] * tr[J][v];
-          ei += hvt[J][v] * ti[J][v];
+          theta_store(to, w, M, Nt, off, s, N, m, b, tr, ti);
+          er += hvt[J][v] * tr;
+          ei += hvt[J][v] * ti;
         }
       }
   }

@@ -23,10 +23,11 @@ template <typename T> struct V4;
 template <> struct V4<float> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct V4<double> { typedef double type __attribute__((ext_vector_type(4))); };
 
-// Row groups of 16 per wave in the A-build: two for FP32 (each B fragment
-// feeds the MFMAs of both), one for FP64 (register budget).
+// Row groups of 16 per wave in the A-build: one (at the headline size two
+// groups per wave left the launch at 1.25 blocks per CU; one group gives
+// twice the blocks and measured faster).
 template <typename T> struct QGeom {
-  static constexpr int GW = sizeof(T) == 4 ? 2 : 1;
+  static constexpr int GW = 1;
 };
 
 constexpr int QT = 64;       // tile edge along k and along the output columns
