@@ -2102,48 +2102,67 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
   T* Bm = Ai + M * LDK;  // (B1 - I)[i][k]
   T* TT = Bm + M * LDK;  // ping-pong term buffers, transposed [Nt][LDK] (re, im)
   auto tt = [&](int buf, int part) { return TT + (2 * buf + part) * Nt * LDK; };
-  // rows by wavefronts, the contiguous index by lanes (no index division)
-  if (packed) {
-    // A symmetric, stored as its upper triangle [2][M (M + 1) / 2] (row i holds
-    // columns i .. M - 1): each entry goes to (i, k) and (k, i)
-    const long mp = (long)M * (M + 1) / 2;
-    const T* Ag = A + (long)w * 2 * mp;
-    for (int i = wv; i < M; i += NWAVE) {
-      const long rs = (long)i * M - (long)i * (i - 1) / 2 - i;
-      for (int k = l; k < LDK; k += AFQ_WAVE) {
-        if (k >= i && k < M) {
-          const T xr = Ag[rs + k], xi = Ag[mp + rs + k];
-          Ar[i * LDK + k] = xr;
-          Ai[i * LDK + k] = xi;
-          Ar[k * LDK + i] = xr;
-          Ai[k * LDK + i] = xi;
-        } else if (k >= M) {
-          Ar[i * LDK + k] = (T)0;
-          Ai[i * LDK + k] = (T)0;
-        }
-        Bm[i * LDK + k] = k < M ? B1m[(long)i * M + k] : (T)0;
-      }
-    }
-  } else {
-    const T* Ag = A + (long)w * 2 * mm;
-    for (int i = wv; i < M; i += NWAVE)
-      for (int k = l; k < LDK; k += AFQ_WAVE) {
-        const bool ok = k < M;
-        Ar[i * LDK + k] = ok ? Ag[(long)i * M + k] : (T)0;
-        Ai[i * LDK + k] = ok ? Ag[mm + (long)i * M + k] : (T)0;
-        Bm[i * LDK + k] = ok ? B1m[(long)i * M + k] : (T)0;
-      }
-  }
+  // Staging, rows by wavefronts and the contiguous index by lanes (two
+  // passes of 64 cover LDK and Nt): each group of RPW rows per wavefront has
+  // all its global loads (A, B1 - I, phi) requested before its first LDS
+  // store, so that their latencies overlap (a load-store chain per row left
+  // most of the block idle during the staging).  Fewer rows per group where
+  // registers are scarcer (FP64, one tile per wavefront).
   const long wb = (long)w * mn;
-  // phi read row-major (coalesced), stored transposed; padding k >= M zero
-  for (int k = wv; k < MP4; k += NWAVE)
-    for (int c = l; c < Nt; c += AFQ_WAVE) {
-      const bool ok = k < M;
-      tt(0, 0)[c * LDK + k] = ok ? (T)phr[wb + (long)k * Nt + c] : (T)0;
-      tt(0, 1)[c * LDK + k] = ok ? (T)phi[wb + (long)k * Nt + c] : (T)0;
-      tt(1, 0)[c * LDK + k] = (T)0;
-      tt(1, 1)[c * LDK + k] = (T)0;
+  constexpr int RPW = sizeof(T) == 4 ? (MT >= 2 ? 8 : 4) : 2;
+  const long mp = (long)M * (M + 1) / 2;
+  const T* Agp = A + (long)w * 2 * mp;
+  const T* Agf = A + (long)w * 2 * mm;
+  for (int i0 = 0; i0 < MP4; i0 += NWAVE * RPW) {
+    T xr[RPW][2], xi[RPW][2], bm[RPW][2];
+    double pr[RPW][2], pi[RPW][2];
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+      const int i = i0 + wv + NWAVE * j;  // row of A and B1 - I; k index of phi
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = l + AFQ_WAVE * h;  // column of A and B1 - I, column of phi
+        const bool oka = i < M && k < M && (!packed || k >= i);
+        const long offp = (long)i * M - (long)i * (i - 1) / 2 - i + k;
+        xr[j][h] = oka ? (packed ? Agp[offp] : Agf[(long)i * M + k]) : (T)0;
+        xi[j][h] = oka ? (packed ? Agp[mp + offp] : Agf[mm + (long)i * M + k]) : (T)0;
+        bm[j][h] = (i < M && k < M) ? B1m[(long)i * M + k] : (T)0;
+        const bool okp = i < M && k < Nt;
+        pr[j][h] = okp ? phr[wb + (long)i * Nt + k] : 0.0;
+        pi[j][h] = okp ? phi[wb + (long)i * Nt + k] : 0.0;
+      }
     }
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+      const int i = i0 + wv + NWAVE * j;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = l + AFQ_WAVE * h;
+        if (i < M && k < LDK) {
+          if (!packed || k >= M) {
+            Ar[i * LDK + k] = xr[j][h];  // zero for k >= M
+            Ai[i * LDK + k] = xi[j][h];
+          } else if (k >= i) {
+            // A symmetric, stored as its upper triangle [2][M (M + 1) / 2]
+            // (row i holds columns i .. M - 1): entry (i, k) goes to (i, k)
+            // and (k, i)
+            Ar[i * LDK + k] = xr[j][h];
+            Ai[i * LDK + k] = xi[j][h];
+            Ar[k * LDK + i] = xr[j][h];
+            Ai[k * LDK + i] = xi[j][h];
+          }
+          Bm[i * LDK + k] = bm[j][h];
+        }
+        // phi stored transposed, [c][k] with k = i; rows M .. MP4 - 1 zero
+        if (i < MP4 && k < Nt) {
+          tt(0, 0)[k * LDK + i] = (T)pr[j][h];
+          tt(0, 1)[k * LDK + i] = (T)pi[j][h];
+          tt(1, 0)[k * LDK + i] = (T)0;
+          tt(1, 1)[k * LDK + i] = (T)0;
+        }
+      }
+    }
+  }
   const int RT = (M + 15) / 16, CT = (Nt + 15) / 16, ntile = RT * CT;
   double sr[MT][4], si[MT][4];
 #pragma unroll
