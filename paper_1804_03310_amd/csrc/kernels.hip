@@ -1888,20 +1888,37 @@ hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double*
 // ===========================================================================
 __global__ __launch_bounds__(1024) void k_comb_parents(int W, const double* __restrict__ weight,
                                                        uint64_t seed, uint64_t pc_index,
-                                                       int system_id, double* cbuf, int* parent,
-                                                       double* norm_out, int use_lds) {
+                                                       int system_id, double* __restrict__ cbuf,
+                                                       int* parent, double* norm_out, int use_lds) {
   extern __shared__ double cs[];
   __shared__ double sh[2];
   __shared__ int last_sh;
-  double* C = use_lds ? cs : cbuf;
+  // LDS: the weights [W], then their prefix sums [W]
+  double* C = use_lds ? cs + W : cbuf;
+  const double* Wt = use_lds ? cs : weight;
   if (use_lds)
-    for (int k = threadIdx.x; k < W; k += blockDim.x) C[k] = weight[k];
+    for (int k = threadIdx.x; k < W; k += blockDim.x) cs[k] = weight[k];
   __syncthreads();
   if (threadIdx.x == 0) {
+    // one thread, left to right (the order fixes the rounding of every
+    // prefix); the weights are read eight ahead of the sums, from an array
+    // the sums are not written to
     double acc = 0.0;
     int last = W - 1;
-    for (int k = 0; k < W; ++k) {
-      const double wk = use_lds ? C[k] : weight[k];
+    int k = 0;
+    for (; k + 8 <= W; k += 8) {
+      double wk[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) wk[u] = Wt[k + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (wk[u] > 0.0) last = k + u;
+        acc = acc + wk[u];
+        C[k + u] = acc;
+      }
+    }
+    for (; k < W; ++k) {
+      const double wk = Wt[k];
       if (wk > 0.0) last = k;
       acc = acc + wk;
       C[k] = acc;
@@ -1937,7 +1954,7 @@ __global__ __launch_bounds__(1024) void k_comb_parents(int W, const double* __re
 hipError_t comb_parents(hipStream_t st, int W, const double* weight, uint64_t seed,
                         uint64_t pc_index, int system_id, double* cbuf, int* parent,
                         double* norm_out) {
-  const size_t lds = (size_t)W * sizeof(double);
+  const size_t lds = (size_t)2 * W * sizeof(double);
   const int use_lds = lds <= 65536 ? 1 : 0;
   hipLaunchKernelGGL(k_comb_parents, dim3(1), dim3(1024), use_lds ? lds : 0, st, W, weight, seed,
                      pc_index, system_id, cbuf, parent, norm_out, use_lds);
