@@ -607,6 +607,34 @@ def test_sweep_fp64_trajectory_walker_subset(afq):
     assert np.allclose(_np(w.eloc[0]), st.eloc.real, rtol=0, atol=1e-8)
 
 
+@pytest.mark.parametrize("dt_scale", [1.0, 0.1])
+def test_literal_hchain_fp64_trajectory_walker_subset(afq, dt_scale):
+    """The unscaled hydrogen-chain recipe (|E_L| ~ 4e3 Ha) in FP64 over six
+    steps on 16 walkers, without population control.  At the workload's
+    dt the phaseless constraint kills walkers step by step (all 16 by the
+    sixth step in the oracle): the GPU must kill the same walkers at the same
+    steps, and E_mix must agree at every step while any walker lives (NaN
+    where none does).  At dt / 10 every walker survives: E_mix, weights and
+    E_L per walker within FP64 rounding of the oracle."""
+    wl = syn.WORKLOADS["hchain-M50-literal"]
+    inp = syn.workload_system(wl)
+    dt = wl.dt * dt_scale
+    _say(f"hchain-M50-literal fp64 6 steps, 16 walkers, dt {dt}")
+    em, oe, w, st = _run_both(afq, inp, 16, 6, dt, dict(taylor_order=6, ortho_every=10, pc_every=0))
+    alive_gpu = _np(w.weight) > 0
+    print(f"literal dt={dt}: E_mix gpu {em}, oracle {oe}, alive gpu {int(alive_gpu.sum())}"
+          f" oracle {int((st.weight > 0).sum())}")
+    assert np.array_equal(np.isnan(em), np.isnan(oe))
+    fin = np.isfinite(oe)
+    assert fin[0]
+    assert np.max(np.abs(em[fin] - oe[fin]) / np.abs(oe[fin])) <= 1e-9
+    assert np.array_equal(alive_gpu, st.weight > 0)
+    if dt_scale < 1.0:
+        assert alive_gpu.all()
+        assert np.allclose(_np(w.weight), st.weight, rtol=1e-9, atol=0)
+        assert np.allclose(_np(w.eloc[0]), st.eloc.real, rtol=1e-9, atol=0)
+
+
 # --------------------------------------------------------------------------
 # Edge cases
 # --------------------------------------------------------------------------
