@@ -494,8 +494,10 @@ class Oracle:
 
     @staticmethod
     def mixed_energy(st: WalkerState) -> float:
-        """E_mix = sum_w W_w Re E_L,w / sum_w W_w."""
-        return float(np.sum(st.weight * st.eloc.real) / np.sum(st.weight))
+        """E_mix = sum_w W_w Re E_L,w / sum_w W_w (NaN once every walker has
+        died: 0 / 0, without a warning)."""
+        with np.errstate(invalid="ignore"):
+            return float(np.sum(st.weight * st.eloc.real) / np.sum(st.weight))
 
     # -- propagation ---------------------------------------------------------
     def propagator_matrix(self, xs: np.ndarray, dt: float) -> np.ndarray:

@@ -92,7 +92,13 @@ template hipError_t gemm_real<double, double, false>(hipStream_t, int, int, int,
 // Walker-batched complex GEMM for the one-body factors B1 and the Taylor
 // terms of exp(A) (Thouless: the propagator acts on a determinant by a
 // matrix product on its orbitals).  Block = one 64x64 output tile of one
-// walker; complex products as 4 real MFMAs (2 for a real operator).
+// walker, four wavefronts of 32x32 (2x2 MFMA tiles).  The k range goes in
+// chunks of 16 through double-buffered LDS: each thread loads its part of the
+// next chunk (four consecutive elements of a row, 16-byte or 32-byte reads)
+// into registers before the current chunk's MFMAs and stores it after them,
+// so one barrier per chunk remains.  A complex product takes three real ones
+// (Gauss: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); re = P1 - P2,
+// im = P3 - P1 - P2), a real operator (B1) two.
 // ===========================================================================
 template <typename T, typename TIn, bool A_CPLX, int MODE>
 __global__ __launch_bounds__(256) void k_cgemm_walkers(
@@ -101,11 +107,12 @@ __global__ __launch_bounds__(256) void k_cgemm_walkers(
     T* __restrict__ Outr, T* __restrict__ Outi, double* __restrict__ D1r, double* __restrict__ D1i,
     double* __restrict__ D2r, double* __restrict__ D2i, int ldo, long sO, double alpha) {
   constexpr int BM = 64, BN = 64, KC = 16;
-  __shared__ T Asr[KC][BM + 1];
-  __shared__ T Asi[A_CPLX ? KC : 1][BM + 1];
-  __shared__ T Bsr[KC][BN + 1];
-  __shared__ T Bsi[KC][BN + 1];
+  __shared__ T Asr[2][KC][BM + 1];
+  __shared__ T Asi[2][A_CPLX ? KC : 1][BM + 1];
+  __shared__ T Bsr[2][KC][BN + 1];
+  __shared__ T Bsi[2][KC][BN + 1];
   typedef Mfma<T> MM;
+  typedef typename MM::acc_t acc_t;
   const long w = blockIdx.z;
   const int nmt = (Mr + BM - 1) / BM;
   const int m0 = (blockIdx.x % nmt) * BM, n0 = (blockIdx.x / nmt) * BN;
@@ -115,51 +122,75 @@ __global__ __launch_bounds__(256) void k_cgemm_walkers(
   const int wv = wave_id(), l = lane_id();
   const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
   const int li = l & 15, lk = l >> 4;
-  typename MM::acc_t cr[2][2], ci[2][2];
+  // staging assignment: A chunk [64 rows][16 k], thread -> row ta, k 4 tq ..;
+  // B chunk [16 k][64 columns], thread -> k tb, columns 4 tc ..
+  const int ta = threadIdx.x >> 2, tq = (threadIdx.x & 3) * 4;
+  const int tb = threadIdx.x >> 4, tc = (threadIdx.x & 15) * 4;
+  T pa_r[4], pa_i[4], pb_r[4], pb_i[4];
+  auto fetch = [&](int k0) {
+    const int gm = m0 + ta, gk = k0 + tq;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool ok = gm < Mr && gk + j < K;
+      pa_r[j] = ok ? Ar[(long)gm * lda + gk + j] : (T)0;
+      pa_i[j] = (A_CPLX && ok) ? Ai[(long)gm * lda + gk + j] : (T)0;
+    }
+    const int gkb = k0 + tb, gn = n0 + tc;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool ok = gkb < K && gn + j < Nc;
+      pb_r[j] = ok ? (T)Inr[(long)gkb * ldin + gn + j] : (T)0;
+      pb_i[j] = ok ? (T)Ini[(long)gkb * ldin + gn + j] : (T)0;
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Asr[buf][tq + j][ta] = pa_r[j];
+      if (A_CPLX) Asi[buf][tq + j][ta] = pa_i[j];
+      Bsr[buf][tb][tc + j] = pb_r[j];
+      Bsi[buf][tb][tc + j] = pb_i[j];
+    }
+  };
+  acc_t p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) { cr[i][j] = MM::zero(); ci[i][j] = MM::zero(); }
-
+    for (int j = 0; j < 2; ++j) { p1[i][j] = MM::zero(); p2[i][j] = MM::zero(); p3[i][j] = MM::zero(); }
+  fetch(0);
+  stage(0);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < K; k0 += KC) {
-    for (int e = threadIdx.x; e < KC * BM; e += 256) {
-      const int mm = e / KC, kk = e % KC;
-      const int gm = m0 + mm, gk = k0 + kk;
-      const bool ok = gm < Mr && gk < K;
-      Asr[kk][mm] = ok ? Ar[(long)gm * lda + gk] : (T)0;
-      if (A_CPLX) Asi[kk][mm] = ok ? Ai[(long)gm * lda + gk] : (T)0;
-    }
-    for (int e = threadIdx.x; e < KC * BN; e += 256) {
-      const int kk = e / BN, nn = e % BN;
-      const int gk = k0 + kk, gn = n0 + nn;
-      const bool ok = gk < K && gn < Nc;
-      Bsr[kk][nn] = ok ? (T)Inr[(long)gk * ldin + gn] : (T)0;
-      Bsi[kk][nn] = ok ? (T)Ini[(long)gk * ldin + gn] : (T)0;
-    }
-    __syncthreads();
+    const bool more = k0 + KC < K;
+    if (more) fetch(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       T ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        ar[i] = Asr[kk + lk][wm + 16 * i + li];
-        ai[i] = A_CPLX ? Asi[kk + lk][wm + 16 * i + li] : (T)0;
-        br[i] = Bsr[kk + lk][wn + 16 * i + li];
-        bi[i] = Bsi[kk + lk][wn + 16 * i + li];
+        ar[i] = Asr[buf][kk + lk][wm + 16 * i + li];
+        ai[i] = A_CPLX ? Asi[buf][kk + lk][wm + 16 * i + li] : (T)0;
+        br[i] = Bsr[buf][kk + lk][wn + 16 * i + li];
+        bi[i] = Bsi[buf][kk + lk][wn + 16 * i + li];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          cr[i][j] = MM::mma(ar[i], br[j], cr[i][j]);
-          ci[i][j] = MM::mma(ar[i], bi[j], ci[i][j]);
+          // real operator: p1 = A Br, p2 = A Bi; complex: Gauss's three
+          p1[i][j] = MM::mma(ar[i], br[j], p1[i][j]);
           if (A_CPLX) {
-            cr[i][j] = MM::mma(-ai[i], bi[j], cr[i][j]);
-            ci[i][j] = MM::mma(ai[i], br[j], ci[i][j]);
+            p2[i][j] = MM::mma(ai[i], bi[j], p2[i][j]);
+            p3[i][j] = MM::mma(ar[i] + ai[i], br[j] + bi[j], p3[i][j]);
+          } else {
+            p2[i][j] = MM::mma(ar[i], bi[j], p2[i][j]);
           }
         }
     }
+    if (more) stage(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   const long ob = w * sO;
 #pragma unroll
@@ -171,7 +202,10 @@ __global__ __launch_bounds__(256) void k_cgemm_walkers(
         const int r = m0 + wm + 16 * i + MM::row(lk, v), c = n0 + wn + 16 * j + li;
         if (r >= Mr || c >= Nc) continue;
         const long o = ob + (long)r * ldo + c;
-        const double xr = alpha * (double)cr[i][j][v], xi = alpha * (double)ci[i][j][v];
+        const double cre = A_CPLX ? (double)p1[i][j][v] - (double)p2[i][j][v] : (double)p1[i][j][v];
+        const double cim = A_CPLX ? (double)p3[i][j][v] - (double)p1[i][j][v] - (double)p2[i][j][v]
+                                  : (double)p2[i][j][v];
+        const double xr = alpha * cre, xi = alpha * cim;
         if (MODE == 0) {
           const double yr = (double)Inr[(long)r * ldin + c] + xr;
           const double yi = (double)Ini[(long)r * ldin + c] + xi;
