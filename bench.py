@@ -818,8 +818,11 @@ def main():
         ex_name = "k_qform (theta^T Q theta, upper-triangular tile pairs)"
     else:
         ex_flops = exchange_flops_per_walker(wl.M, wl.n_up, wl.n_dn, wl.n_chol) * W
-        ex_name = ("k_exchange_full (fused Ltil*Theta, Tr X, Tr XX)"
-                   if max(wl.n_up, wl.n_dn) <= 32 else "k_exchange (fused Ltil*Theta, Tr X, Tr XX)")
+        if chol_prec in ("bf16", "bf16x3"):
+            ex_name = "k_exchange_bf16_rf (fused Ltil*Theta with X^T tiles, Tr X, Tr XX)"
+        else:
+            ex_name = ("k_exchange_full (fused Ltil*Theta, Tr X, Tr XX)"
+                       if max(wl.n_up, wl.n_dn) <= 32 else "k_exchange (fused Ltil*Theta, Tr X, Tr XX)")
     # the Q route's contractions are FP32 only under FP32 and while
     # M max(N) <= AFQMC_QROUTE_FP32_MAX_K, FP64 otherwise
     q32 = chol_prec == "fp32" and wl.M * max(wl.n_up, wl.n_dn) <= afq._abi.QROUTE_FP32_MAX_K

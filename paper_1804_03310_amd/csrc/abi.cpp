@@ -223,7 +223,7 @@ struct afqmc_trial {
   float* Lt32[2] = {nullptr, nullptr};
   double* Apk64[2] = {nullptr, nullptr};  // NP <= 32: exchange A operand, repacked
   float* Apk32[2] = {nullptr, nullptr};
-  void* Ltbf[2] = {nullptr, nullptr};  // [G][NP][MP32] bf16 (m contiguous)
+  void* Ltbf[2] = {nullptr, nullptr};  // bf16, fragment order of pack_ltilde_bf16
   void* Ltbf_lo[2] = {nullptr, nullptr};  // the split's second terms (BF16X3)
   int MP32 = 32;
   double* lbar = nullptr;
@@ -1164,11 +1164,12 @@ afqmc_status afqmc_footprint_bytes(int M, int n_chol, int n_up, int n_dn, int n_
   const size_t MP4 = round_up(M, 4), MP32 = round_up(M, 32), Nt = (size_t)n_up + n_dn;
   size_t tot = rnd(mm * 8) * 2 + rnd(g * mm * 8) + rnd(g * mm * 4) + 2 * rnd(g * mm * 2) +
                rnd(g * (mm + m) / 2 * 12);  // ham (with the packed L copies)
+  const size_t NPX = round_up(std::max({n_up, n_dn, 1}), 16);  // the bf16 copies' row tiles
   for (int s = 0; s < 2; ++s) {                                                        // trial
     const size_t NP = round_up(std::max(nel[s], 1), 16);
     const size_t nlt = (g * MP4 + 16) * NP;
     tot += rnd(mm * 8) + rnd(std::max(nel[s], 1) * m * 8) + rnd(nlt * 8) + rnd(nlt * 4) +
-           2 * rnd(g * NP * MP32 * 2);
+           2 * rnd(g * NPX * MP32 * 2);
     if (NP <= 32 && g > 0) {
       const size_t npk = pack_exchange_elems(g, MP4, NP);
       tot += rnd(npk * 8) + rnd(npk * 4);
@@ -1328,18 +1329,16 @@ afqmc_status afqmc_init_trial(afqmc_trial** out, afqmc_ham* hm, int n_up, int n_
         return bad(AFQMC_ERR_DEVICE, "exchange operand repack");
     }
     {
+      // both spins with the larger spin's row tiles, so one kernel instance serves both
+      const int NPX = std::max(tr->NP[0], tr->NP[1]);
       void *pb = nullptr, *pbl = nullptr;
-      const size_t nb = (size_t)G * tr->NP[s] * tr->MP32;
+      const size_t nb = (size_t)G * NPX * tr->MP32;
       if (tr->arena.alloc(&pb, nb * 2) || tr->arena.alloc(&pbl, nb * 2))
         return bad(AFQMC_ERR_OOM, "trial allocation failed");
       tr->Ltbf[s] = pb;
       tr->Ltbf_lo[s] = pbl;
-      if (hipMemsetAsync(pb, 0, nb * 2, st) != hipSuccess ||
-          hipMemsetAsync(pbl, 0, nb * 2, st) != hipSuccess)
-        return bad(AFQMC_ERR_DEVICE, "memset");
-      if (G > 0 && afq::transpose_f64_bf16(st, tr->MP4, tr->NP[s], tr->MP32, (long)tr->MP4 * tr->NP[s],
-                                           (long)tr->NP[s] * tr->MP32, G, tr->Lt64[s], pb,
-                                           pbl) != hipSuccess)
+      if (afq::pack_ltilde_bf16(st, G, tr->MP4, tr->NP[s], NPX, tr->MP32, tr->Lt64[s], pb, pbl) !=
+          hipSuccess)
         return bad(AFQMC_ERR_DEVICE, "bf16 half-rotation");
     }
     if (nel[s] > 0) {

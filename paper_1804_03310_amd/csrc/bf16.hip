@@ -39,25 +39,42 @@ hipError_t convert_f64_bf16_lo(hipStream_t st, const double* src, void* dst, lon
   return hipGetLastError();
 }
 
-// dst[r][c] = src[c][r] (src rows x cols FP64 -> bf16), batched over z;
-// dst_lo (nullable) receives the split's second term.
-__global__ void k_transpose_bf16(int rows, int cols, int ld_dst, long s_src, long s_dst,
-                                 const double* src, __bf16* dst, __bf16* dst_lo) {
-  const long z = blockIdx.z;
-  const int c = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int r = blockIdx.y * 16 + (threadIdx.x >> 4);
-  if (r < rows && c < cols) {
-    const double x = src[z * s_src + (long)r * cols + c];
-    dst[z * s_dst + (long)c * ld_dst + r] = (__bf16)(float)x;
-    if (dst_lo) dst_lo[z * s_dst + (long)c * ld_dst + r] = bf16_lo(x);
+// Fragment order of an operand with 16 NT rows and 32 KC columns as one
+// 16x16x32 bf16 MFMA reads it: [I][kc][lane] groups of eight, lane = li + 16 lk
+// holding row 16 I + li, columns 32 kc + 8 lk .. 32 kc + 8 lk + 7.
+//
+// Ltil_g (rows a < NP, columns m < MP4 read from the FP64 [G][MP4][NP] copy)
+// into that order, one fragment per thread; lo (nullable) receives the
+// split's second terms.
+__global__ void k_pack_ltilde_bf16(long nfrag, int MP4, int NP, int NTX, int KC,
+                                   const double* __restrict__ src, afq_bf8* __restrict__ hi,
+                                   afq_bf8* __restrict__ lo) {
+  const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nfrag) return;
+  const int lane = (int)(f & 63);
+  long r = f >> 6;
+  const int kc = (int)(r % KC);
+  r /= KC;
+  const int I = (int)(r % NTX);
+  const long g = r / NTX;
+  const int a = 16 * I + (lane & 15), m0 = 32 * kc + 8 * (lane >> 4);
+  afq_bf8 h, o;
+  for (int e = 0; e < 8; ++e) {
+    const int m = m0 + e;
+    const double x = (m < MP4 && a < NP) ? src[(g * MP4 + m) * NP + a] : 0.0;
+    h[e] = (__bf16)(float)x;
+    o[e] = bf16_lo(x);
   }
+  hi[f] = h;
+  if (lo) lo[f] = o;
 }
 
-hipError_t transpose_f64_bf16(hipStream_t st, int rows, int cols, int ld_dst, long s_src,
-                              long s_dst, int batch, const double* src, void* dst, void* dst_lo) {
-  dim3 grid((cols + 15) / 16, (rows + 15) / 16, batch);
-  hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(256), 0, st, rows, cols, ld_dst, s_src, s_dst, src,
-                     (__bf16*)dst, (__bf16*)dst_lo);
+hipError_t pack_ltilde_bf16(hipStream_t st, int G, int MP4, int NP, int NPX, int MP32,
+                            const double* src, void* hi, void* lo) {
+  const long nfrag = (long)G * (NPX / 16) * (MP32 / 32) * 64;
+  if (nfrag <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_ltilde_bf16, dim3((unsigned)((nfrag + 255) / 256)), dim3(256), 0, st,
+                     nfrag, MP4, NP, NPX / 16, MP32 / 32, src, (afq_bf8*)hi, (afq_bf8*)lo);
   return hipGetLastError();
 }
 
@@ -206,26 +223,26 @@ hipError_t fields_coeff_bf16(hipStream_t st, int W, int G, int ldg, uint64_t see
   return hipGetLastError();
 }
 
-// Fused exchange in bf16: X_g = Ltil_g Theta with Ltil stored [g][a][MP32]
-// (m contiguous) and Theta staged in LDS as [b][MP32] bf16; same tile pairing
-// and reductions as the FP32/FP64 kernel.  X3: both operands split in two
-// bf16 terms, three products per tile (the lo-lo one dropped), FP32
-// accumulation.
-template <bool X3>
-__global__ __launch_bounds__(256) void k_exchange_bf16(int M, int MP32, int Nt, int G, SpinGeom s0,
-                                                       SpinGeom s1, const __bf16* __restrict__ Ltl0,
-                                                       const __bf16* __restrict__ Ltl1,
-                                                       const double* __restrict__ thr,
-                                                       const double* __restrict__ thi,
-                                                       double* __restrict__ vs_re,
-                                                       double* __restrict__ vs_im, double* exx_re,
-                                                       double* exx_im) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds_bf[];
+// Fused exchange (N_P <= 64, so at most four row tiles) with Ltil_g held in registers: one block per
+// (walker, spin) stages Theta once in LDS in fragment order (hi, im and, X3,
+// their second terms); each wavefront takes every fourth g and, over the
+// k chunks, accumulates for every tile pair I <= J both X_IJ = Ltil_I Theta_J
+// and the tile of X^T at the same place, X^T_IJ = Theta_I^T Ltil_J^T, so that
+// sum_ij X_ij X_ji is an element-by-element product of the two (twice for
+// I < J) and no transposition through LDS is needed.  The next chunk's Ltil
+// fragments are loaded while the current chunk's products run.
+template <bool X3, int NT>
+__global__ __launch_bounds__(256) void k_exchange_bf16_rf(
+    int M, int KC, int Nt, int G, SpinGeom s0, SpinGeom s1, const afq_bf8* __restrict__ Ll0,
+    const afq_bf8* __restrict__ Ll1, const double* __restrict__ thr,
+    const double* __restrict__ thi, double* __restrict__ vs_re, double* __restrict__ vs_im,
+    double* exx_re, double* exx_im) {
+  extern __shared__ afq_bf8 tfr[];  // [X3 ? 4 : 2][NT][KC][64]
   __shared__ double red[8];
+  constexpr int NPR = NT * (NT + 1) / 2;
   const int w = blockIdx.x, s = blockIdx.y;
-  const SpinGeom g = s ? s1 : s0;
-  const int N = g.N, NP = g.NP, off = g.off;
-  const __bf16* __restrict__ Lt = (const __bf16*)g.Lt;
+  const SpinGeom gm = s ? s1 : s0;
+  const int N = gm.N, off = gm.off;
   const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
   if (N == 0) {
     for (int q = threadIdx.x; q < G; q += blockDim.x) {
@@ -235,94 +252,127 @@ __global__ __launch_bounds__(256) void k_exchange_bf16(int M, int MP32, int Nt, 
     if (threadIdx.x == 0) { exx_re[2 * w + s] = 0.0; exx_im[2 * w + s] = 0.0; }
     return;
   }
-  const __bf16* __restrict__ Ltl = s ? Ltl1 : Ltl0;
-  __bf16* Tr = (__bf16*)lds_bf;          // [NP][MP32]
-  __bf16* Ti = Tr + NP * MP32;
-  __bf16* Trl = Ti + NP * MP32;          // X3: second terms
-  __bf16* Til = Trl + (X3 ? NP * MP32 : 0);
-  float* scr = (float*)(Til + (X3 ? NP * MP32 : 0));  // 4 waves x 2 x 256
-  float* myr = scr + wv * 512;
-  float* myi = myr + 256;
+  const afq_bf8* __restrict__ Lh = (const afq_bf8*)gm.Lt;
+  const afq_bf8* __restrict__ Ll = s ? Ll1 : Ll0;
+  const int NP = 16 * NT, FR = NT * KC * 64;
   const long wb = (long)w * M * Nt;
-  const __bf16 zero = (__bf16)0.0f;
-  for (int e = threadIdx.x; e < NP * MP32; e += blockDim.x) {
-    const int b = e / MP32, m = e % MP32;
-    const bool ok = m < M && b < N;
-    const double xr = ok ? thr[wb + (long)m * Nt + off + b] : 0.0;
-    const double xi = ok ? thi[wb + (long)m * Nt + off + b] : 0.0;
-    Tr[e] = ok ? (__bf16)(float)xr : zero;
-    Ti[e] = ok ? (__bf16)(float)xi : zero;
+  // fragment (J, kc, lane) of a component holds Theta[32 kc + 8 lk + e][16 J + li];
+  // consecutive threads take consecutive columns so that the FP64 reads coalesce
+  for (int f = threadIdx.x; f < NP * KC * 4; f += blockDim.x) {
+    const int b = f % NP, mg = f / NP;
+    afq_bf8 hr, hm, lr, lm;
+    for (int e = 0; e < 8; ++e) {
+      const int m = 8 * mg + e;
+      const bool ok = m < M && b < N;
+      const double xr = ok ? thr[wb + (long)m * Nt + off + b] : 0.0;
+      const double xi = ok ? thi[wb + (long)m * Nt + off + b] : 0.0;
+      hr[e] = (__bf16)(float)xr;
+      hm[e] = (__bf16)(float)xi;
+      if (X3) {
+        lr[e] = bf16_lo(xr);
+        lm[e] = bf16_lo(xi);
+      }
+    }
+    const int at = ((b >> 4) * KC + (mg >> 2)) * 64 + (b & 15) + 16 * (mg & 3);
+    tfr[at] = hr;
+    tfr[FR + at] = hm;
     if (X3) {
-      Trl[e] = ok ? bf16_lo(xr) : zero;
-      Til[e] = ok ? bf16_lo(xi) : zero;
+      tfr[2 * FR + at] = lr;
+      tfr[3 * FR + at] = lm;
     }
   }
   __syncthreads();
-  const int NT = NP / 16;
   double xx_re = 0.0, xx_im = 0.0;
-  for (int q = wv; q < G; q += 4) {
-    const __bf16* Lq = Lt + (long)q * NP * MP32;
-    double tr_re = 0.0, tr_im = 0.0;
+  afq_bf8 a[NT], al[NT];
+  if (wv < G) {
+#pragma unroll
     for (int I = 0; I < NT; ++I) {
-      for (int J = I; J < NT; ++J) {
-        afq_f4 pr = {0, 0, 0, 0}, pi = {0, 0, 0, 0}, qr = {0, 0, 0, 0}, qi = {0, 0, 0, 0};
-        for (int k = 0; k < MP32; k += 32) {
-          const afq_bf8 aI = *(const afq_bf8*)&Lq[(long)(16 * I + li) * MP32 + k + 8 * lk];
-          const afq_bf8 bJr = *(const afq_bf8*)&Tr[(16 * J + li) * MP32 + k + 8 * lk];
-          const afq_bf8 bJi = *(const afq_bf8*)&Ti[(16 * J + li) * MP32 + k + 8 * lk];
+      a[I] = Lh[(long)wv * FR + I * KC * 64 + l];
+      if (X3) al[I] = Ll[(long)wv * FR + I * KC * 64 + l];
+    }
+  }
+  for (int q = wv; q < G; q += 4) {
+    afq_f4 acc[NPR][4];
+#pragma unroll
+    for (int p = 0; p < NPR; ++p)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[p][c] = afq_f4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < KC; ++kc) {
+      int qn = q, kn = kc + 1;
+      if (kn == KC) {
+        kn = 0;
+        qn = q + 4 < G ? q + 4 : q;
+      }
+      afq_bf8 an[NT], aln[NT];
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        an[I] = Lh[(long)qn * FR + (I * KC + kn) * 64 + l];
+        if (X3) aln[I] = Ll[(long)qn * FR + (I * KC + kn) * 64 + l];
+      }
+      afq_bf8 br[NT], bi[NT], brl[NT], bil[NT];
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+        br[J] = tfr[(J * KC + kc) * 64 + l];
+        bi[J] = tfr[FR + (J * KC + kc) * 64 + l];
+        if (X3) {
+          brl[J] = tfr[2 * FR + (J * KC + kc) * 64 + l];
+          bil[J] = tfr[3 * FR + (J * KC + kc) * 64 + l];
+        }
+      }
+      int p = 0;
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = I; J < NT; ++J, ++p) {
           if (X3) {
-            const __bf16* Lql = Ltl + (long)q * NP * MP32;
-            const afq_bf8 aIl = *(const afq_bf8*)&Lql[(long)(16 * I + li) * MP32 + k + 8 * lk];
-            const afq_bf8 bJrl = *(const afq_bf8*)&Trl[(16 * J + li) * MP32 + k + 8 * lk];
-            const afq_bf8 bJil = *(const afq_bf8*)&Til[(16 * J + li) * MP32 + k + 8 * lk];
-            pr = mfma_bf16(aIl, bJr, pr);
-            pr = mfma_bf16(aI, bJrl, pr);
-            pi = mfma_bf16(aIl, bJi, pi);
-            pi = mfma_bf16(aI, bJil, pi);
+            acc[p][0] = mfma_bf16(al[I], br[J], acc[p][0]);
+            acc[p][0] = mfma_bf16(a[I], brl[J], acc[p][0]);
+            acc[p][1] = mfma_bf16(al[I], bi[J], acc[p][1]);
+            acc[p][1] = mfma_bf16(a[I], bil[J], acc[p][1]);
+            acc[p][2] = mfma_bf16(brl[I], a[J], acc[p][2]);
+            acc[p][2] = mfma_bf16(br[I], al[J], acc[p][2]);
+            acc[p][3] = mfma_bf16(bil[I], a[J], acc[p][3]);
+            acc[p][3] = mfma_bf16(bi[I], al[J], acc[p][3]);
           }
-          pr = mfma_bf16(aI, bJr, pr);
-          pi = mfma_bf16(aI, bJi, pi);
-          if (I != J) {
-            const afq_bf8 aJ = *(const afq_bf8*)&Lq[(long)(16 * J + li) * MP32 + k + 8 * lk];
-            const afq_bf8 bIr = *(const afq_bf8*)&Tr[(16 * I + li) * MP32 + k + 8 * lk];
-            const afq_bf8 bIi = *(const afq_bf8*)&Ti[(16 * I + li) * MP32 + k + 8 * lk];
-            if (X3) {
-              const __bf16* Lql = Ltl + (long)q * NP * MP32;
-              const afq_bf8 aJl = *(const afq_bf8*)&Lql[(long)(16 * J + li) * MP32 + k + 8 * lk];
-              const afq_bf8 bIrl = *(const afq_bf8*)&Trl[(16 * I + li) * MP32 + k + 8 * lk];
-              const afq_bf8 bIil = *(const afq_bf8*)&Til[(16 * I + li) * MP32 + k + 8 * lk];
-              qr = mfma_bf16(aJl, bIr, qr);
-              qr = mfma_bf16(aJ, bIrl, qr);
-              qi = mfma_bf16(aJl, bIi, qi);
-              qi = mfma_bf16(aJ, bIil, qi);
-            }
-            qr = mfma_bf16(aJ, bIr, qr);
-            qi = mfma_bf16(aJ, bIi, qi);
-          }
+          acc[p][0] = mfma_bf16(a[I], br[J], acc[p][0]);
+          acc[p][1] = mfma_bf16(a[I], bi[J], acc[p][1]);
+          acc[p][2] = mfma_bf16(br[I], a[J], acc[p][2]);
+          acc[p][3] = mfma_bf16(bi[I], a[J], acc[p][3]);
         }
-        for (int v = 0; v < 4; ++v) {
-          const int r = row_bf16(lk, v);
-          myr[r * 16 + li] = (I != J) ? qr[v] : pr[v];
-          myi[r * 16 + li] = (I != J) ? qi[v] : pi[v];
-        }
-        wave_lds_sync();
-        const double mult = (I != J) ? 2.0 : 1.0;
-        for (int v = 0; v < 4; ++v) {
-          const int r = row_bf16(lk, v);
-          const double ar = (double)pr[v], ai = (double)pi[v];
-          const double br = (double)myr[li * 16 + r], bi = (double)myi[li * 16 + r];
-          xx_re += mult * (ar * br - ai * bi);
-          xx_im += mult * (ar * bi + ai * br);
-          if (I == J && r == li) { tr_re += ar; tr_im += ai; }
-        }
-        wave_lds_sync();
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        a[I] = an[I];
+        if (X3) al[I] = aln[I];
       }
     }
-    tr_re = wave_sum(tr_re);
-    tr_im = wave_sum(tr_im);
+    // X_IJ and X^T_IJ hold X_ij and X_ji at the same place of the same lane
+    float dr = 0.f, di = 0.f, orr = 0.f, oi = 0.f, tre = 0.f, tim = 0.f;
+    int p = 0;
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+      for (int J = I; J < NT; ++J, ++p)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float xr = acc[p][0][v], xi = acc[p][1][v], yr = acc[p][2][v], yi = acc[p][3][v];
+          if (I == J) {
+            dr += xr * yr - xi * yi;
+            di += xr * yi + xi * yr;
+            if (row_bf16(lk, v) == li) {
+              tre += xr;
+              tim += xi;
+            }
+          } else {
+            orr += xr * yr - xi * yi;
+            oi += xr * yi + xi * yr;
+          }
+        }
+    xx_re += (double)dr + 2.0 * (double)orr;
+    xx_im += (double)di + 2.0 * (double)oi;
+    const double t_re = wave_sum((double)tre), t_im = wave_sum((double)tim);
     if (l == 0) {
-      vs_re[((long)w * 2 + s) * G + q] = tr_re;
-      vs_im[((long)w * 2 + s) * G + q] = tr_im;
+      vs_re[((long)w * 2 + s) * G + q] = t_re;
+      vs_im[((long)w * 2 + s) * G + q] = t_im;
     }
   }
   xx_re = wave_sum(xx_re);
@@ -341,16 +391,29 @@ hipError_t exchange_bf16(hipStream_t st, int W, int M, int MP32, int Nt, int G, 
                          double* exx_im, size_t max_lds) {
   const int NP = s0.NP > s1.NP ? s0.NP : s1.NP;
   const bool x3 = Lt_lo0 && Lt_lo1;
-  const size_t lds = (size_t)(x3 ? 4 : 2) * NP * MP32 * 2 + (size_t)4 * 512 * 4;
-  if (lds > max_lds) return hipErrorInvalidValue;
-  if (x3)
-    hipLaunchKernelGGL(k_exchange_bf16<true>, dim3(W, 2), dim3(256), lds, st, M, MP32, Nt, G, s0, s1,
-                       (const __bf16*)Lt_lo0, (const __bf16*)Lt_lo1, thr, thi, vs_re, vs_im, exx_re,
-                       exx_im);
-  else
-    hipLaunchKernelGGL(k_exchange_bf16<false>, dim3(W, 2), dim3(256), lds, st, M, MP32, Nt, G, s0,
-                       s1, nullptr, nullptr, thr, thi, vs_re, vs_im, exx_re, exx_im);
-  return hipGetLastError();
+  const int KC = MP32 / 32;
+  const afq_bf8 *l0 = (const afq_bf8*)Lt_lo0, *l1 = (const afq_bf8*)Lt_lo1;
+  if (NP <= 64) {
+    const size_t lds = (size_t)(x3 ? 4 : 2) * (NP / 16) * KC * 64 * sizeof(afq_bf8);
+    if (lds > max_lds) return hipErrorInvalidValue;
+#define AFQ_XRF(X, NTT)                                                                            \
+  hipLaunchKernelGGL((k_exchange_bf16_rf<X, NTT>), dim3(W, 2), dim3(256), lds, st, M, KC, Nt, G, s0, \
+                     s1, l0, l1, thr, thi, vs_re, vs_im, exx_re, exx_im)
+    switch ((x3 ? 8 : 0) + NP / 16) {
+      case 1: AFQ_XRF(false, 1); break;
+      case 2: AFQ_XRF(false, 2); break;
+      case 3: AFQ_XRF(false, 3); break;
+      case 4: AFQ_XRF(false, 4); break;
+      case 9: AFQ_XRF(true, 1); break;
+      case 10: AFQ_XRF(true, 2); break;
+      case 11: AFQ_XRF(true, 3); break;
+      case 12: AFQ_XRF(true, 4); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef AFQ_XRF
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;  // N_P <= 64 always (at most 64 electrons per spin)
 }
 
 }  // namespace afq

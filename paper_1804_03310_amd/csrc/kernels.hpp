@@ -206,8 +206,11 @@ namespace afq {
 // Split bf16 operands (BF16X3): x = hi + lo, hi = bf16(x), lo = bf16(x - hi).
 hipError_t convert_f64_bf16(hipStream_t st, const double* src, void* dst, long n);
 hipError_t convert_f64_bf16_lo(hipStream_t st, const double* src, void* dst, long n);
-hipError_t transpose_f64_bf16(hipStream_t st, int rows, int cols, int ld_dst, long s_src,
-                              long s_dst, int batch, const double* src, void* dst, void* dst_lo);
+// Ltil_g from its FP64 [G][MP4][NP] copy into the bf16 exchange kernels' fragment order,
+// [G][NPX / 16][MP32 / 32][64 lanes] groups of eight (rows a >= NP and columns m >= MP4 zero);
+// lo (nullable) receives the split's second terms.
+hipError_t pack_ltilde_bf16(hipStream_t st, int G, int MP4, int NP, int NPX, int MP32,
+                            const double* src, void* hi, void* lo);
 // Al / Bl non-null: the three-product split form.
 template <typename TOut>
 hipError_t gemm_bf16(hipStream_t st, int Mr, int Nc, int K, const void* A, const void* Al, int lda,

@@ -134,6 +134,36 @@ def test_local_energy_random_walkers_fp32(afq, M, n_up, n_dn, G, W):
         assert err.max() <= 1e-5
 
 
+@pytest.mark.parametrize("M,n_up,n_dn,G,W", [(23, 7, 4, 37, 9), (50, 25, 25, 250, 6),
+                                               (40, 17, 0, 30, 5), (80, 40, 20, 21, 3),
+                                               (90, 50, 64, 19, 2), (75, 49, 0, 17, 2),
+                                               (130, 64, 64, 9, 2), (12, 5, 0, 30, 130),
+                                               (16, 7, 6, 40, 65)])
+@pytest.mark.parametrize("prec,tol", [("bf16", 5e-3), ("bf16x3", 2e-5)])
+def test_local_energy_random_walkers_bf16(afq, M, n_up, n_dn, G, W, prec, tol):
+    """BF16 and split-BF16 exchange contraction (Ltil Theta with FP32
+    accumulation; Sec. III single-precision contractions) on row-tile counts
+    1 to 4 (the register-resident kernel, unequal and empty spins, G not a
+    multiple of the four wavefronts, ragged k chunks, the largest spin of 64
+    electrons): E_L against the FP64 oracle, relative bound 5e-3 for BF16
+    (8 significant bits per operand) and 2e-5 for the split form (16)."""
+    _say(f"local energy random walkers {prec} M={M} N={n_up}/{n_dn} G={G} W={W}")
+    inp = syn.make_system(M, n_up, n_dn, G, 8.0, seed=M + G, e_core=0.75)
+    ham, trial, w = _make(afq, inp, W)
+    trial.exchange_route = "ltilde"
+    re, im = syn.random_walkers(M, n_up, n_dn, W, seed=3, scale=0.1)
+    D0 = np.concatenate([inp.C_up[:, :n_up], inp.C_dn[:, :n_dn]], axis=1)
+    phi = D0[None] + re + 1j * im
+    m = Oracle.from_inputs(inp).measure(phi)
+    _set_phi(w, phi)
+    afq.propagate(ham, trial, w, 0, 0.01, 0, 0, afq.Options(chol_prec=prec, taylor_prec="fp32"))
+    el = _np(w.eloc[0]) + 1j * _np(w.eloc[1])
+    err = np.abs(el - m["eloc"]) / np.abs(m["eloc"])
+    print(f"{prec}: max rel dE_L = {err.max():.3e}")
+    assert np.all(np.isfinite(el))
+    assert err.max() <= tol
+
+
 def _run_both(afq, inp, W, n_steps, dt, opt_kw, prec=("fp64", "fp64"), seed=0, oracle_walkers=None):
     ham, trial, w = _make(afq, inp, W)
     afq.walkers_from_trial(ham, trial, w)
