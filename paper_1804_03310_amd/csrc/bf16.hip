@@ -232,7 +232,7 @@ hipError_t fields_coeff_bf16(hipStream_t st, int W, int G, int ldg, uint64_t see
 // I < J) and no transposition through LDS is needed.  The next chunk's Ltil
 // fragments are loaded while the current chunk's products run.
 template <bool X3, int NT>
-__global__ __launch_bounds__(256) void k_exchange_bf16_rf(
+__global__ __launch_bounds__(256, X3 ? 1 : 2) void k_exchange_bf16_rf(
     int M, int KC, int Nt, int G, SpinGeom s0, SpinGeom s1, const afq_bf8* __restrict__ Ll0,
     const afq_bf8* __restrict__ Ll1, const double* __restrict__ thr,
     const double* __restrict__ thi, double* __restrict__ vs_re, double* __restrict__ vs_im,
@@ -283,13 +283,30 @@ __global__ __launch_bounds__(256) void k_exchange_bf16_rf(
   }
   __syncthreads();
   double xx_re = 0.0, xx_im = 0.0;
-  afq_bf8 a[NT], al[NT];
+  // X3 runs one wavefront per SIMD (its accumulators and split operands
+  // take over 256 registers), so it also reads the next chunk's Theta
+  // fragments from LDS ahead; BF16 runs two per SIMD and reads them in place
+  constexpr bool TP = X3;
+  afq_bf8 a[NT], al[NT], br[NT], bi[NT], brl[NT], bil[NT];
+  auto load_theta = [&](int kc, afq_bf8 (&r)[NT], afq_bf8 (&i)[NT], afq_bf8 (&rl)[NT],
+                        afq_bf8 (&il)[NT]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      r[J] = tfr[(J * KC + kc) * 64 + l];
+      i[J] = tfr[FR + (J * KC + kc) * 64 + l];
+      if (X3) {
+        rl[J] = tfr[2 * FR + (J * KC + kc) * 64 + l];
+        il[J] = tfr[3 * FR + (J * KC + kc) * 64 + l];
+      }
+    }
+  };
   if (wv < G) {
 #pragma unroll
     for (int I = 0; I < NT; ++I) {
       a[I] = Lh[(long)wv * FR + I * KC * 64 + l];
       if (X3) al[I] = Ll[(long)wv * FR + I * KC * 64 + l];
     }
+    if (TP) load_theta(0, br, bi, brl, bil);
   }
   for (int q = wv; q < G; q += 4) {
     afq_f4 acc[NPR][4];
@@ -309,16 +326,9 @@ __global__ __launch_bounds__(256) void k_exchange_bf16_rf(
         an[I] = Lh[(long)qn * FR + (I * KC + kn) * 64 + l];
         if (X3) aln[I] = Ll[(long)qn * FR + (I * KC + kn) * 64 + l];
       }
-      afq_bf8 br[NT], bi[NT], brl[NT], bil[NT];
-#pragma unroll
-      for (int J = 0; J < NT; ++J) {
-        br[J] = tfr[(J * KC + kc) * 64 + l];
-        bi[J] = tfr[FR + (J * KC + kc) * 64 + l];
-        if (X3) {
-          brl[J] = tfr[2 * FR + (J * KC + kc) * 64 + l];
-          bil[J] = tfr[3 * FR + (J * KC + kc) * 64 + l];
-        }
-      }
+      afq_bf8 bnr[NT], bni[NT], bnrl[NT], bnil[NT];
+      if (TP) load_theta(kn, bnr, bni, bnrl, bnil);
+      else load_theta(kc, br, bi, brl, bil);
       int p = 0;
 #pragma unroll
       for (int I = 0; I < NT; ++I)
@@ -343,6 +353,12 @@ __global__ __launch_bounds__(256) void k_exchange_bf16_rf(
       for (int I = 0; I < NT; ++I) {
         a[I] = an[I];
         if (X3) al[I] = aln[I];
+        if (TP) {
+          br[I] = bnr[I];
+          bi[I] = bni[I];
+          brl[I] = bnrl[I];
+          bil[I] = bnil[I];
+        }
       }
     }
     // X_IJ and X^T_IJ hold X_ij and X_ji at the same place of the same lane
