@@ -701,6 +701,9 @@ def test_propagate_edge_shapes_fp64(afq, W, nu, nd):
     (12, 4, 0, 7, 30, 5, 5),      # no electrons of one spin
     (70, 9, 8, 20, 60, 9, 21),    # M > 64: 32 k steps, several row tiles
     (40, 17, 3, 10, 30, 5, 3),    # N > 16: the full-row kernel
+    (100, 13, 11, 12, 100, 6, 40),  # 67 rows up (a last row tile of 3), M = 100 of 128 k rows
+    (118, 12, 9, 10, 120, 5, 41),   # 67 rows down (a last row tile of 3), M = 118
+    (20, 2, 1, 6, 3, 3, 53),      # 4 and 2 rows: one partial row tile per spin
 ])
 def test_multidet_fp32_compact_rows_vs_oracle(afq, M, nu, nd, G, n_det, W, seed):
     """FP32 multi-determinant E_L from the compact-row kernel (only the rows of
@@ -708,7 +711,8 @@ def test_multidet_fp32_compact_rows_vs_oracle(afq, M, nu, nd, G, n_det, W, seed)
     kernel) against the oracle's direct per-determinant evaluation, on walkers
     perturbed from the reference; one walker sits on the reference, where
     every excited overlap is zero.  W is not a multiple of the kernel's four
-    walkers per block."""
+    walkers per block; the shapes include nearly empty last row tiles and
+    k rows past M within the last k block."""
     _say(f"multidet fp32 compact rows M={M} {nu}+{nd} G={G} n_det={n_det} W={W}")
     inp = syn.make_system(M, nu, nd, G, 4.0, n_det=n_det, seed=seed, e_core=0.3)
     ham, trial, w = _make(afq, inp, W)
