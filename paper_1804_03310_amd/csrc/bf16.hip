@@ -223,27 +223,164 @@ hipError_t fields_coeff_bf16(hipStream_t st, int W, int G, int ldg, uint64_t see
   return hipGetLastError();
 }
 
-// Fused exchange (N_P <= 64, so at most four row tiles) with Ltil_g held in registers: one block per
-// (walker, spin) stages Theta once in LDS in fragment order (hi, im and, X3,
-// their second terms); each wavefront takes every fourth g and, over the
-// k chunks, accumulates for every tile pair I <= J both X_IJ = Ltil_I Theta_J
-// and the tile of X^T at the same place, X^T_IJ = Theta_I^T Ltil_J^T, so that
+// Index of the tile pair (I, J), I <= J, among the NT (NT + 1) / 2: the
+// diagonal pairs first, then I < J in row order.
+__host__ __device__ constexpr int xch_pair(int NT, int I, int J) {
+  return I == J ? I : NT + I * (2 * NT - I - 1) / 2 + (J - I - 1);
+}
+
+// One wavefront's share of the fused exchange: every fourth g from wq on and,
+// for each, the tile pairs LO <= xch_pair < HI (role 0 of NR = 2, or all of
+// them for NR = 1, holds the diagonal pairs and so the traces).  Over the k
+// chunks it accumulates for each pair I <= J both X_IJ = Ltil_I Theta_J and
+// the tile of X^T at the same place, X^T_IJ = Theta_I^T Ltil_J^T, so that
 // sum_ij X_ij X_ji is an element-by-element product of the two (twice for
 // I < J) and no transposition through LDS is needed.  The next chunk's Ltil
-// fragments are loaded while the current chunk's products run.
-template <bool X3, int NT>
-__global__ __launch_bounds__(256, X3 ? 1 : 2) void k_exchange_bf16_rf(
+// fragments are loaded while the current chunk's products run; TP: its
+// Theta fragments are read from LDS ahead too.
+template <bool X3, int NT, int NR, int ROLE, bool TP>
+__device__ __forceinline__ void xch_waves(int wq, int KC, int G, long vsb,
+                                          const afq_bf8* __restrict__ Lh,
+                                          const afq_bf8* __restrict__ Ll, const afq_bf8* tfr,
+                                          double* __restrict__ vs_re, double* __restrict__ vs_im,
+                                          double& xx_re, double& xx_im) {
+  constexpr int NPR = NT * (NT + 1) / 2, NA = NR == 1 ? NPR : (NPR + 1) / 2;
+  constexpr int LO = ROLE == 0 ? 0 : NA, HI = ROLE == 0 ? NA : NPR, NL = HI - LO;
+  const int l = lane_id(), li = l & 15, lk = l >> 4;
+  const int FR = NT * KC * 64;
+  afq_bf8 a[NT], al[NT], br[NT], bi[NT], brl[NT], bil[NT];
+  auto load_theta = [&](int kc, afq_bf8 (&r)[NT], afq_bf8 (&i)[NT], afq_bf8 (&rl)[NT],
+                        afq_bf8 (&il)[NT]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      r[J] = tfr[(J * KC + kc) * 64 + l];
+      i[J] = tfr[FR + (J * KC + kc) * 64 + l];
+      if (X3) {
+        rl[J] = tfr[2 * FR + (J * KC + kc) * 64 + l];
+        il[J] = tfr[3 * FR + (J * KC + kc) * 64 + l];
+      }
+    }
+  };
+  if (wq < G) {
+#pragma unroll
+    for (int I = 0; I < NT; ++I) {
+      a[I] = Lh[(long)wq * FR + I * KC * 64 + l];
+      if (X3) al[I] = Ll[(long)wq * FR + I * KC * 64 + l];
+    }
+    if (TP) load_theta(0, br, bi, brl, bil);
+  }
+  for (int q = wq; q < G; q += 4) {
+    afq_f4 acc[NL][4];
+#pragma unroll
+    for (int p = 0; p < NL; ++p)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[p][c] = afq_f4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < KC; ++kc) {
+      int qn = q, kn = kc + 1;
+      if (kn == KC) {
+        kn = 0;
+        qn = q + 4 < G ? q + 4 : q;
+      }
+      afq_bf8 an[NT], aln[NT];
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        an[I] = Lh[(long)qn * FR + (I * KC + kn) * 64 + l];
+        if (X3) aln[I] = Ll[(long)qn * FR + (I * KC + kn) * 64 + l];
+      }
+      afq_bf8 bnr[NT], bni[NT], bnrl[NT], bnil[NT];
+      if (TP) load_theta(kn, bnr, bni, bnrl, bnil);
+      else load_theta(kc, br, bi, brl, bil);
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = I; J < NT; ++J) {
+          const int gq = xch_pair(NT, I, J);
+          if (gq < LO || gq >= HI) continue;
+          const int p = gq - LO;
+          if (X3) {
+            acc[p][0] = mfma_bf16(al[I], br[J], acc[p][0]);
+            acc[p][0] = mfma_bf16(a[I], brl[J], acc[p][0]);
+            acc[p][1] = mfma_bf16(al[I], bi[J], acc[p][1]);
+            acc[p][1] = mfma_bf16(a[I], bil[J], acc[p][1]);
+            acc[p][2] = mfma_bf16(brl[I], a[J], acc[p][2]);
+            acc[p][2] = mfma_bf16(br[I], al[J], acc[p][2]);
+            acc[p][3] = mfma_bf16(bil[I], a[J], acc[p][3]);
+            acc[p][3] = mfma_bf16(bi[I], al[J], acc[p][3]);
+          }
+          acc[p][0] = mfma_bf16(a[I], br[J], acc[p][0]);
+          acc[p][1] = mfma_bf16(a[I], bi[J], acc[p][1]);
+          acc[p][2] = mfma_bf16(br[I], a[J], acc[p][2]);
+          acc[p][3] = mfma_bf16(bi[I], a[J], acc[p][3]);
+        }
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        a[I] = an[I];
+        if (X3) al[I] = aln[I];
+        if (TP) {
+          br[I] = bnr[I];
+          bi[I] = bni[I];
+          brl[I] = bnrl[I];
+          bil[I] = bnil[I];
+        }
+      }
+    }
+    // X_IJ and X^T_IJ hold X_ij and X_ji at the same place of the same lane
+    float dr = 0.f, di = 0.f, orr = 0.f, oi = 0.f, tre = 0.f, tim = 0.f;
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+      for (int J = I; J < NT; ++J) {
+        const int gq = xch_pair(NT, I, J);
+        if (gq < LO || gq >= HI) continue;
+        const int p = gq - LO;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float xr = acc[p][0][v], xi = acc[p][1][v], yr = acc[p][2][v], yi = acc[p][3][v];
+          if (I == J) {
+            dr += xr * yr - xi * yi;
+            di += xr * yi + xi * yr;
+            if (row_bf16(lk, v) == li) {
+              tre += xr;
+              tim += xi;
+            }
+          } else {
+            orr += xr * yr - xi * yi;
+            oi += xr * yi + xi * yr;
+          }
+        }
+      }
+    xx_re += (double)dr + 2.0 * (double)orr;
+    xx_im += (double)di + 2.0 * (double)oi;
+    if (ROLE == 0) {
+      const double t_re = wave_sum((double)tre), t_im = wave_sum((double)tim);
+      if (l == 0) {
+        vs_re[vsb + q] = t_re;
+        vs_im[vsb + q] = t_im;
+      }
+    }
+  }
+}
+
+// Fused exchange (N_P <= 64, so at most four row tiles) with Ltil_g held in
+// registers: one block per (walker, spin) stages Theta once in LDS in
+// fragment order (hi, im and, X3, their second terms); four wavefronts (NR =
+// 1) take every fourth g each with all tile pairs, or eight (NR = 2) split
+// the pairs of each g in two halves between the two wavefronts of a SIMD,
+// which halves their accumulators (the split form's operands and
+// accumulators need over 256 registers for all pairs, so one wavefront per
+// SIMD otherwise).
+template <bool X3, int NT, int NR>
+__global__ __launch_bounds__(256 * NR, (X3 || NR == 2) ? 1 : 2) void k_exchange_bf16_rf(
     int M, int KC, int Nt, int G, SpinGeom s0, SpinGeom s1, const afq_bf8* __restrict__ Ll0,
     const afq_bf8* __restrict__ Ll1, const double* __restrict__ thr,
     const double* __restrict__ thi, double* __restrict__ vs_re, double* __restrict__ vs_im,
     double* exx_re, double* exx_im) {
   extern __shared__ afq_bf8 tfr[];  // [X3 ? 4 : 2][NT][KC][64]
-  __shared__ double red[8];
-  constexpr int NPR = NT * (NT + 1) / 2;
+  __shared__ double red[16];
   const int w = blockIdx.x, s = blockIdx.y;
   const SpinGeom gm = s ? s1 : s0;
   const int N = gm.N, off = gm.off;
-  const int wv = wave_id(), l = lane_id(), li = l & 15, lk = l >> 4;
+  const int wv = wave_id(), l = lane_id();
   if (N == 0) {
     for (int q = threadIdx.x; q < G; q += blockDim.x) {
       vs_re[((long)w * 2 + s) * G + q] = 0.0;
@@ -283,121 +420,28 @@ __global__ __launch_bounds__(256, X3 ? 1 : 2) void k_exchange_bf16_rf(
   }
   __syncthreads();
   double xx_re = 0.0, xx_im = 0.0;
-  // X3 runs one wavefront per SIMD (its accumulators and split operands
-  // take over 256 registers), so it also reads the next chunk's Theta
-  // fragments from LDS ahead; BF16 runs two per SIMD and reads them in place
-  constexpr bool TP = X3;
-  afq_bf8 a[NT], al[NT], br[NT], bi[NT], brl[NT], bil[NT];
-  auto load_theta = [&](int kc, afq_bf8 (&r)[NT], afq_bf8 (&i)[NT], afq_bf8 (&rl)[NT],
-                        afq_bf8 (&il)[NT]) __attribute__((always_inline)) {
-#pragma unroll
-    for (int J = 0; J < NT; ++J) {
-      r[J] = tfr[(J * KC + kc) * 64 + l];
-      i[J] = tfr[FR + (J * KC + kc) * 64 + l];
-      if (X3) {
-        rl[J] = tfr[2 * FR + (J * KC + kc) * 64 + l];
-        il[J] = tfr[3 * FR + (J * KC + kc) * 64 + l];
-      }
-    }
-  };
-  if (wv < G) {
-#pragma unroll
-    for (int I = 0; I < NT; ++I) {
-      a[I] = Lh[(long)wv * FR + I * KC * 64 + l];
-      if (X3) al[I] = Ll[(long)wv * FR + I * KC * 64 + l];
-    }
-    if (TP) load_theta(0, br, bi, brl, bil);
-  }
-  for (int q = wv; q < G; q += 4) {
-    afq_f4 acc[NPR][4];
-#pragma unroll
-    for (int p = 0; p < NPR; ++p)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[p][c] = afq_f4{0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < KC; ++kc) {
-      int qn = q, kn = kc + 1;
-      if (kn == KC) {
-        kn = 0;
-        qn = q + 4 < G ? q + 4 : q;
-      }
-      afq_bf8 an[NT], aln[NT];
-#pragma unroll
-      for (int I = 0; I < NT; ++I) {
-        an[I] = Lh[(long)qn * FR + (I * KC + kn) * 64 + l];
-        if (X3) aln[I] = Ll[(long)qn * FR + (I * KC + kn) * 64 + l];
-      }
-      afq_bf8 bnr[NT], bni[NT], bnrl[NT], bnil[NT];
-      if (TP) load_theta(kn, bnr, bni, bnrl, bnil);
-      else load_theta(kc, br, bi, brl, bil);
-      int p = 0;
-#pragma unroll
-      for (int I = 0; I < NT; ++I)
-#pragma unroll
-        for (int J = I; J < NT; ++J, ++p) {
-          if (X3) {
-            acc[p][0] = mfma_bf16(al[I], br[J], acc[p][0]);
-            acc[p][0] = mfma_bf16(a[I], brl[J], acc[p][0]);
-            acc[p][1] = mfma_bf16(al[I], bi[J], acc[p][1]);
-            acc[p][1] = mfma_bf16(a[I], bil[J], acc[p][1]);
-            acc[p][2] = mfma_bf16(brl[I], a[J], acc[p][2]);
-            acc[p][2] = mfma_bf16(br[I], al[J], acc[p][2]);
-            acc[p][3] = mfma_bf16(bil[I], a[J], acc[p][3]);
-            acc[p][3] = mfma_bf16(bi[I], al[J], acc[p][3]);
-          }
-          acc[p][0] = mfma_bf16(a[I], br[J], acc[p][0]);
-          acc[p][1] = mfma_bf16(a[I], bi[J], acc[p][1]);
-          acc[p][2] = mfma_bf16(br[I], a[J], acc[p][2]);
-          acc[p][3] = mfma_bf16(bi[I], a[J], acc[p][3]);
-        }
-#pragma unroll
-      for (int I = 0; I < NT; ++I) {
-        a[I] = an[I];
-        if (X3) al[I] = aln[I];
-        if (TP) {
-          br[I] = bnr[I];
-          bi[I] = bni[I];
-          brl[I] = bnrl[I];
-          bil[I] = bnil[I];
-        }
-      }
-    }
-    // X_IJ and X^T_IJ hold X_ij and X_ji at the same place of the same lane
-    float dr = 0.f, di = 0.f, orr = 0.f, oi = 0.f, tre = 0.f, tim = 0.f;
-    int p = 0;
-#pragma unroll
-    for (int I = 0; I < NT; ++I)
-#pragma unroll
-      for (int J = I; J < NT; ++J, ++p)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float xr = acc[p][0][v], xi = acc[p][1][v], yr = acc[p][2][v], yi = acc[p][3][v];
-          if (I == J) {
-            dr += xr * yr - xi * yi;
-            di += xr * yi + xi * yr;
-            if (row_bf16(lk, v) == li) {
-              tre += xr;
-              tim += xi;
-            }
-          } else {
-            orr += xr * yr - xi * yi;
-            oi += xr * yi + xi * yr;
-          }
-        }
-    xx_re += (double)dr + 2.0 * (double)orr;
-    xx_im += (double)di + 2.0 * (double)oi;
-    const double t_re = wave_sum((double)tre), t_im = wave_sum((double)tim);
-    if (l == 0) {
-      vs_re[((long)w * 2 + s) * G + q] = t_re;
-      vs_im[((long)w * 2 + s) * G + q] = t_im;
-    }
+  const long vsb = ((long)w * 2 + s) * G;
+  if constexpr (NR == 1) {
+    // one wavefront per SIMD in the split form: Theta read ahead as well
+    xch_waves<X3, NT, 1, 0, X3>(wv, KC, G, vsb, Lh, Ll, tfr, vs_re, vs_im, xx_re, xx_im);
+  } else {
+    if (wv < 4)
+      xch_waves<X3, NT, 2, 0, false>(wv, KC, G, vsb, Lh, Ll, tfr, vs_re, vs_im, xx_re, xx_im);
+    else
+      xch_waves<X3, NT, 2, 1, false>(wv - 4, KC, G, vsb, Lh, Ll, tfr, vs_re, vs_im, xx_re, xx_im);
   }
   xx_re = wave_sum(xx_re);
   xx_im = wave_sum(xx_im);
-  if (l == 0) { red[wv] = xx_re; red[4 + wv] = xx_im; }
+  if (l == 0) { red[wv] = xx_re; red[8 + wv] = xx_im; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    exx_re[2 * w + s] = (red[0] + red[1]) + (red[2] + red[3]);
-    exx_im[2 * w + s] = (red[4] + red[5]) + (red[6] + red[7]);
+    double er = 0.0, ei = 0.0;
+    for (int k = 0; k < 4 * NR; ++k) {
+      er += red[k];
+      ei += red[8 + k];
+    }
+    exx_re[2 * w + s] = er;
+    exx_im[2 * w + s] = ei;
   }
 }
 
@@ -412,18 +456,18 @@ hipError_t exchange_bf16(hipStream_t st, int W, int M, int MP32, int Nt, int G, 
   if (NP <= 64) {
     const size_t lds = (size_t)(x3 ? 4 : 2) * (NP / 16) * KC * 64 * sizeof(afq_bf8);
     if (lds > max_lds) return hipErrorInvalidValue;
-#define AFQ_XRF(X, NTT)                                                                            \
-  hipLaunchKernelGGL((k_exchange_bf16_rf<X, NTT>), dim3(W, 2), dim3(256), lds, st, M, KC, Nt, G, s0, \
-                     s1, l0, l1, thr, thi, vs_re, vs_im, exx_re, exx_im)
+#define AFQ_XRF(X, NTT, NRR)                                                                       \
+  hipLaunchKernelGGL((k_exchange_bf16_rf<X, NTT, NRR>), dim3(W, 2), dim3(256 * NRR), lds, st, M, KC, \
+                     Nt, G, s0, s1, l0, l1, thr, thi, vs_re, vs_im, exx_re, exx_im)
     switch ((x3 ? 8 : 0) + NP / 16) {
-      case 1: AFQ_XRF(false, 1); break;
-      case 2: AFQ_XRF(false, 2); break;
-      case 3: AFQ_XRF(false, 3); break;
-      case 4: AFQ_XRF(false, 4); break;
-      case 9: AFQ_XRF(true, 1); break;
-      case 10: AFQ_XRF(true, 2); break;
-      case 11: AFQ_XRF(true, 3); break;
-      case 12: AFQ_XRF(true, 4); break;
+      case 1: AFQ_XRF(false, 1, 1); break;
+      case 2: AFQ_XRF(false, 2, 1); break;
+      case 3: AFQ_XRF(false, 3, 1); break;
+      case 4: AFQ_XRF(false, 4, 1); break;
+      case 9: AFQ_XRF(true, 1, 1); break;
+      case 10: AFQ_XRF(true, 2, 1); break;
+      case 11: AFQ_XRF(true, 3, 2); break;
+      case 12: AFQ_XRF(true, 4, 2); break;
       default: return hipErrorInvalidValue;
     }
 #undef AFQ_XRF
