@@ -2153,34 +2153,47 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
   T* Bm = Ai + M * LDK;  // (B1 - I)[i][k]
   T* TT = Bm + M * LDK;  // ping-pong term buffers, transposed [Nt][LDK] (re, im)
   auto tt = [&](int buf, int part) { return TT + (2 * buf + part) * Nt * LDK; };
-  // Staging, rows by wavefronts and the contiguous index by lanes (two
-  // passes of 64 cover LDK and Nt): each group of RPW rows per wavefront has
-  // all its global loads (A, B1 - I, phi) requested before its first LDS
-  // store, so that their latencies overlap (a load-store chain per row left
-  // most of the block idle during the staging).  Fewer rows per group where
-  // registers are scarcer (FP64, one tile per wavefront).
+  // phi in the lanes' output ownership: the FP64 running sum S starts from
+  // it, and the first term is stored from it (rounded) once A is staged.
+  // Requested first, so that these loads overlap the staging of A.
   const long wb = (long)w * mn;
+  const int RT = (M + 15) / 16, CT = (Nt + 15) / 16, ntile = RT * CT;
+  double sr[MT][4], si[MT][4];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const int tile = wv + NWAVE * t;
+    const int rt = tile / CT, ct = tile % CT;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * rt + MM::row(lk, v), c = 16 * ct + li;
+      const bool ok = tile < ntile && r < M && c < Nt;
+      sr[t][v] = ok ? phr[wb + (long)r * Nt + c] : 0.0;
+      si[t][v] = ok ? phi[wb + (long)r * Nt + c] : 0.0;
+    }
+  }
+  // Staging of A and B1 - I, rows by wavefronts and the contiguous index by
+  // lanes (two passes of 64 cover LDK): each group of RPW rows per wavefront
+  // has all its global loads requested before its first LDS store, so that
+  // their latencies overlap (a load-store chain per row left most of the
+  // block idle during the staging).  Fewer rows per group where registers
+  // are scarcer (FP64, one tile per wavefront).
   constexpr int RPW = sizeof(T) == 4 ? (MT >= 2 ? 8 : 4) : 2;
   const long mp = (long)M * (M + 1) / 2;
   const T* Agp = A + (long)w * 2 * mp;
   const T* Agf = A + (long)w * 2 * mm;
   for (int i0 = 0; i0 < MP4; i0 += NWAVE * RPW) {
     T xr[RPW][2], xi[RPW][2], bm[RPW][2];
-    double pr[RPW][2], pi[RPW][2];
 #pragma unroll
     for (int j = 0; j < RPW; ++j) {
-      const int i = i0 + wv + NWAVE * j;  // row of A and B1 - I; k index of phi
+      const int i = i0 + wv + NWAVE * j;  // row of A and B1 - I
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int k = l + AFQ_WAVE * h;  // column of A and B1 - I, column of phi
+        const int k = l + AFQ_WAVE * h;  // column of A and B1 - I
         const bool oka = i < M && k < M && (!packed || k >= i);
         const long offp = (long)i * M - (long)i * (i - 1) / 2 - i + k;
         xr[j][h] = oka ? (packed ? Agp[offp] : Agf[(long)i * M + k]) : (T)0;
         xi[j][h] = oka ? (packed ? Agp[mp + offp] : Agf[mm + (long)i * M + k]) : (T)0;
         bm[j][h] = (i < M && k < M) ? B1m[(long)i * M + k] : (T)0;
-        const bool okp = i < M && k < Nt;
-        pr[j][h] = okp ? phr[wb + (long)i * Nt + k] : 0.0;
-        pi[j][h] = okp ? phi[wb + (long)i * Nt + k] : 0.0;
       }
     }
 #pragma unroll
@@ -2204,31 +2217,9 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
           }
           Bm[i * LDK + k] = bm[j][h];
         }
-        // phi stored transposed, [c][k] with k = i; rows M .. MP4 - 1 zero
-        if (i < MP4 && k < Nt) {
-          tt(0, 0)[k * LDK + i] = (T)pr[j][h];
-          tt(0, 1)[k * LDK + i] = (T)pi[j][h];
-          tt(1, 0)[k * LDK + i] = (T)0;
-          tt(1, 1)[k * LDK + i] = (T)0;
-        }
       }
     }
   }
-  const int RT = (M + 15) / 16, CT = (Nt + 15) / 16, ntile = RT * CT;
-  double sr[MT][4], si[MT][4];
-#pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    const int tile = wv + NWAVE * t;
-    const int rt = tile / CT, ct = tile % CT;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * rt + MM::row(lk, v), c = 16 * ct + li;
-      const bool ok = tile < ntile && r < M && c < Nt;
-      sr[t][v] = ok ? phr[wb + (long)r * Nt + c] : 0.0;
-      si[t][v] = ok ? phi[wb + (long)r * Nt + c] : 0.0;
-    }
-  }
-  __syncthreads();
   int cur = 0;
   // LDS offsets of the lane's A row and term column per tile, clamped to the
   // last row / column: the clamped lanes read real (finite) entries, so the
@@ -2347,6 +2338,10 @@ __global__ __launch_bounds__(512) void k_propagate_fused(int M, int Nt, int MP4,
       }
     }
   };
+  // the first term: phi, stored transposed from the lanes' S (rows M .. MP4
+  // - 1 zero); the block's barrier also publishes A and B1 - I
+  store_term(cur, sr, si);
+  __syncthreads();
   acc_t cr[MT], ci[MT];
   double xr[MT][4], xi[MT][4];
   // phi1 = phi + (B1 - I) phi
