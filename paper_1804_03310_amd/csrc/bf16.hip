@@ -232,19 +232,25 @@ __host__ __device__ constexpr int xch_pair(int NT, int I, int J) {
 // One wavefront's share of the fused exchange: every fourth g from wq on and,
 // for each, the tile pairs LO <= xch_pair < HI (role 0 of NR = 2, or all of
 // them for NR = 1, holds the diagonal pairs and so the traces).  Over the k
-// chunks it accumulates for each pair I <= J both X_IJ = Ltil_I Theta_J and
-// the tile of X^T at the same place, X^T_IJ = Theta_I^T Ltil_J^T, so that
-// sum_ij X_ij X_ji is an element-by-element product of the two (twice for
-// I < J) and no transposition through LDS is needed.  The next chunk's Ltil
-// fragments are loaded while the current chunk's products run; TP: its
-// Theta fragments are read from LDS ahead too.
+// chunks it accumulates X_IJ = Ltil_I Theta_J and, for I < J, the tile of X^T
+// at the same place, X^T_IJ = Theta_I^T Ltil_J^T, so that sum_ij X_ij X_ji is
+// an element-by-element product of the two (twice for I < J); a diagonal
+// tile's own transpose is taken through the wavefront's LDS scratch instead
+// of by two more products.  The next chunk's Ltil fragments are loaded while
+// the current chunk's products run; TP: its Theta fragments are read from
+// LDS ahead too.
 template <bool X3, int NT, int NR, int ROLE, bool TP>
 __device__ __forceinline__ void xch_waves(int wq, int KC, int G, long vsb,
                                           const afq_bf8* __restrict__ Lh,
                                           const afq_bf8* __restrict__ Ll, const afq_bf8* tfr,
-                                          double* __restrict__ vs_re, double* __restrict__ vs_im,
-                                          double& xx_re, double& xx_im) {
-  constexpr int NPR = NT * (NT + 1) / 2, NA = NR == 1 ? NPR : (NPR + 1) / 2;
+                                          float* scr, double* __restrict__ vs_re,
+                                          double* __restrict__ vs_im, double& xx_re,
+                                          double& xx_im) {
+  // role 0 of NR = 2: the diagonal pairs (two products each: X and, by an
+  // LDS transposition, its own transpose) and about as many off-diagonal
+  // pairs (four products each) as leave the two roles equal work
+  constexpr int NPR = NT * (NT + 1) / 2;
+  constexpr int NA = NR == 1 ? NPR : NT + (4 * (NPR - NT) - 2 * NT + 4) / 8;
   constexpr int LO = ROLE == 0 ? 0 : NA, HI = ROLE == 0 ? NA : NPR, NL = HI - LO;
   const int l = lane_id(), li = l & 15, lk = l >> 4;
   const int FR = NT * KC * 64;
@@ -302,15 +308,19 @@ __device__ __forceinline__ void xch_waves(int wq, int KC, int G, long vsb,
             acc[p][0] = mfma_bf16(a[I], brl[J], acc[p][0]);
             acc[p][1] = mfma_bf16(al[I], bi[J], acc[p][1]);
             acc[p][1] = mfma_bf16(a[I], bil[J], acc[p][1]);
-            acc[p][2] = mfma_bf16(brl[I], a[J], acc[p][2]);
-            acc[p][2] = mfma_bf16(br[I], al[J], acc[p][2]);
-            acc[p][3] = mfma_bf16(bil[I], a[J], acc[p][3]);
-            acc[p][3] = mfma_bf16(bi[I], al[J], acc[p][3]);
+            if (I != J) {
+              acc[p][2] = mfma_bf16(brl[I], a[J], acc[p][2]);
+              acc[p][2] = mfma_bf16(br[I], al[J], acc[p][2]);
+              acc[p][3] = mfma_bf16(bil[I], a[J], acc[p][3]);
+              acc[p][3] = mfma_bf16(bi[I], al[J], acc[p][3]);
+            }
           }
           acc[p][0] = mfma_bf16(a[I], br[J], acc[p][0]);
           acc[p][1] = mfma_bf16(a[I], bi[J], acc[p][1]);
-          acc[p][2] = mfma_bf16(br[I], a[J], acc[p][2]);
-          acc[p][3] = mfma_bf16(bi[I], a[J], acc[p][3]);
+          if (I != J) {
+            acc[p][2] = mfma_bf16(br[I], a[J], acc[p][2]);
+            acc[p][3] = mfma_bf16(bi[I], a[J], acc[p][3]);
+          }
         }
 #pragma unroll
       for (int I = 0; I < NT; ++I) {
@@ -333,6 +343,20 @@ __device__ __forceinline__ void xch_waves(int wq, int KC, int G, long vsb,
         const int gq = xch_pair(NT, I, J);
         if (gq < LO || gq >= HI) continue;
         const int p = gq - LO;
+        if (I == J) {
+          // X_II^T at the lane's places: X_II written as [row][col] (row
+          // stride 20 floats: conflict-free writes, 16-byte aligned reads),
+          // read back as [col][row]
+          wave_lds_sync();
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            scr[(4 * lk + v) * 20 + li] = acc[p][0][v];
+            scr[320 + (4 * lk + v) * 20 + li] = acc[p][1][v];
+          }
+          wave_lds_sync();
+          acc[p][2] = *(const afq_f4*)(scr + li * 20 + 4 * lk);
+          acc[p][3] = *(const afq_f4*)(scr + 320 + li * 20 + 4 * lk);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float xr = acc[p][0][v], xi = acc[p][1][v], yr = acc[p][2][v], yi = acc[p][3][v];
@@ -421,14 +445,18 @@ __global__ __launch_bounds__(256 * NR, (X3 || NR == 2) ? 1 : 2) void k_exchange_
   __syncthreads();
   double xx_re = 0.0, xx_im = 0.0;
   const long vsb = ((long)w * 2 + s) * G;
+  // the wavefront's transposition scratch (2 x 16 x 20 floats) after Theta
+  float* scr = (float*)(tfr + (X3 ? 4 : 2) * FR) + wv * 640;
   if constexpr (NR == 1) {
     // one wavefront per SIMD in the split form: Theta read ahead as well
-    xch_waves<X3, NT, 1, 0, X3>(wv, KC, G, vsb, Lh, Ll, tfr, vs_re, vs_im, xx_re, xx_im);
+    xch_waves<X3, NT, 1, 0, X3>(wv, KC, G, vsb, Lh, Ll, tfr, scr, vs_re, vs_im, xx_re, xx_im);
   } else {
     if (wv < 4)
-      xch_waves<X3, NT, 2, 0, false>(wv, KC, G, vsb, Lh, Ll, tfr, vs_re, vs_im, xx_re, xx_im);
+      xch_waves<X3, NT, 2, 0, false>(wv, KC, G, vsb, Lh, Ll, tfr, scr, vs_re, vs_im, xx_re,
+                                     xx_im);
     else
-      xch_waves<X3, NT, 2, 1, false>(wv - 4, KC, G, vsb, Lh, Ll, tfr, vs_re, vs_im, xx_re, xx_im);
+      xch_waves<X3, NT, 2, 1, false>(wv - 4, KC, G, vsb, Lh, Ll, tfr, scr, vs_re, vs_im, xx_re,
+                                     xx_im);
   }
   xx_re = wave_sum(xx_re);
   xx_im = wave_sum(xx_im);
@@ -454,7 +482,9 @@ hipError_t exchange_bf16(hipStream_t st, int W, int M, int MP32, int Nt, int G, 
   const int KC = MP32 / 32;
   const afq_bf8 *l0 = (const afq_bf8*)Lt_lo0, *l1 = (const afq_bf8*)Lt_lo1;
   if (NP <= 64) {
-    const size_t lds = (size_t)(x3 ? 4 : 2) * (NP / 16) * KC * 64 * sizeof(afq_bf8);
+    const int nrr = (x3 && NP > 32) ? 2 : 1;  // eight wavefronts per block for the split form's NT >= 3
+    const size_t lds = (size_t)(x3 ? 4 : 2) * (NP / 16) * KC * 64 * sizeof(afq_bf8) +
+                       (size_t)4 * nrr * 640 * sizeof(float);
     if (lds > max_lds) return hipErrorInvalidValue;
 #define AFQ_XRF(X, NTT, NRR)                                                                       \
   hipLaunchKernelGGL((k_exchange_bf16_rf<X, NTT, NRR>), dim3(W, 2), dim3(256 * NRR), lds, st, M, KC, \
