@@ -157,6 +157,12 @@ __global__ __launch_bounds__(256) void k_cgemm_walkers(
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) { p1[i][j] = MM::zero(); p2[i][j] = MM::zero(); p3[i][j] = MM::zero(); }
+  bool live[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      live[i][j] = m0 + wm + 16 * i < Mr && n0 + wn + 16 * j < Nc;
   fetch(0);
   stage(0);
   __syncthreads();
@@ -178,6 +184,9 @@ __global__ __launch_bounds__(256) void k_cgemm_walkers(
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
+          // 16 x 16 tiles wholly past the last row or column (the remainders of
+          // the 64 x 64 block) are not issued
+          if (!live[i][j]) continue;
           // real operator: p1 = A Br, p2 = A Bi; complex: Gauss's three
           p1[i][j] = MM::mma(ar[i], br[j], p1[i][j]);
           if (A_CPLX) {
