@@ -102,7 +102,7 @@ template hipError_t gemm_real<double, double, false>(hipStream_t, int, int, int,
 // ===========================================================================
 template <typename T, typename TIn, bool A_CPLX, int MODE>
 __global__ __launch_bounds__(256) void k_cgemm_walkers(
-    int Mr, int Nc, int K, const T* __restrict__ Ar, const T* __restrict__ Ai, int lda, long sA,
+    int W, int Mr, int Nc, int K, const T* __restrict__ Ar, const T* __restrict__ Ai, int lda, long sA,
     const TIn* __restrict__ Inr, const TIn* __restrict__ Ini, int ldin, long sIn,
     T* __restrict__ Outr, T* __restrict__ Outi, double* __restrict__ D1r, double* __restrict__ D1i,
     double* __restrict__ D2r, double* __restrict__ D2i, int ldo, long sO, double alpha) {
@@ -113,9 +113,16 @@ __global__ __launch_bounds__(256) void k_cgemm_walkers(
   __shared__ T Bsi[2][KC][BN + 1];
   typedef Mfma<T> MM;
   typedef typename MM::acc_t acc_t;
-  const long w = blockIdx.z;
-  const int nmt = (Mr + BM - 1) / BM;
-  const int m0 = (blockIdx.x % nmt) * BM, n0 = (blockIdx.x / nmt) * BN;
+  // Blocks go to the eight XCDs in turn (block b to XCD b mod 8), so the
+  // tiles of eight consecutive walkers are interleaved: every tile of walker w
+  // lands on XCD w mod 8, whose L2 then serves the A rows and term columns
+  // that its tiles share.  Walkers past W (the last group of eight) return.
+  const int nmt = (Mr + BM - 1) / BM, ntl = nmt * ((Nc + BN - 1) / BN);
+  const long grp = blockIdx.x / (8 * ntl);
+  const int rem = (int)(blockIdx.x % (8 * ntl)), tile = rem / 8;
+  const long w = grp * 8 + (rem % 8);
+  if (w >= W) return;
+  const int m0 = (tile % nmt) * BM, n0 = (tile / nmt) * BN;
   if (A_CPLX) { Ar += w * sA; Ai += w * sA; }
   Inr += w * sIn;
   Ini += w * sIn;
@@ -235,9 +242,10 @@ hipError_t cgemm_walkers(hipStream_t st, int W, int Mr, int Nc, int K, const T* 
                          int lda, long sA, const TIn* Inr, const TIn* Ini, int ldin, long sIn,
                          T* Outr, T* Outi, double* D1r, double* D1i, double* D2r, double* D2i,
                          int ldo, long sO, double alpha) {
-  dim3 grid(((Mr + 63) / 64) * ((Nc + 63) / 64), 1, W);
-  hipLaunchKernelGGL((k_cgemm_walkers<T, TIn, A_CPLX, MODE>), grid, dim3(256), 0, st, Mr, Nc, K,
-                     Ar, Ai, lda, sA, Inr, Ini, ldin, sIn, Outr, Outi, D1r, D1i, D2r, D2i, ldo, sO,
+  const long ntl = (long)((Mr + 63) / 64) * ((Nc + 63) / 64);
+  dim3 grid((unsigned)(ntl * 8 * ((W + 7) / 8)));
+  hipLaunchKernelGGL((k_cgemm_walkers<T, TIn, A_CPLX, MODE>), grid, dim3(256), 0, st, W, Mr, Nc,
+                     K, Ar, Ai, lda, sA, Inr, Ini, ldin, sIn, Outr, Outi, D1r, D1i, D2r, D2i, ldo, sO,
                      alpha);
   return hipGetLastError();
 }
