@@ -786,6 +786,26 @@ def test_propagate_large_m_unfused_chain_fp64(afq):
     assert np.max(np.abs(em - oe)[fin]) <= 1e-10 * np.max(np.abs(oe[fin]))
 
 
+@pytest.mark.parametrize("prec,rtol", [(("fp64", "fp64"), 1e-12), (("fp32", "fp32"), 1e-7)])
+def test_propagate_unfused_chain_ragged_walkers(afq, prec, rtol):
+    """The walker-batched GEMM chain on a ragged shape: M=100 (the last 64-row
+    block holds 36 rows), 21/18 electrons (39 columns), 11 walkers (the
+    blocks of eight consecutive walkers are interleaved across the XCDs, and
+    the last group of eight is partly empty): E_mix over four steps against
+    the oracle, relative bound 1e-12 in FP64 and 1e-7 (the FP32 unit
+    roundoff) with FP32 contractions and Taylor products."""
+    _say(f"propagate M=100 21/18 W=11 unfused chain {prec}")
+    inp = syn.make_system(100, 21, 18, 30, 20.0, seed=19)
+    inp.L = 0.3 * inp.L
+    em, oe, w, st = _run_both(afq, inp, 11, 4, 0.005,
+                              dict(taylor_order=6, ortho_every=2, pc_every=0), prec=prec)
+    fin = np.isfinite(oe)
+    err = np.max(np.abs(em - oe)[fin]) / np.max(np.abs(oe[fin]))
+    print(f"ragged chain {prec}: E_mix {oe}, max rel dE_mix {err:.3e}")
+    assert np.array_equal(fin, np.isfinite(em)) and fin[0]
+    assert err <= rtol
+
+
 @pytest.mark.parametrize("prec,n_pin,tol", [(("fp64", "fp64"), 150, 1e-8),
                                             (("fp32", "fp32"), 100, 1e-4)])
 def test_hchain_subset_1000_steps(afq, prec, n_pin, tol):
