@@ -386,13 +386,13 @@ __device__ inline void theta_pad(const ThetaOut& to, long w, int M, int s, int N
 }
 
 template <bool STAGE>
-__global__ __launch_bounds__(256) void k_overlap_theta(int M, int Nt, SpinGeom s0, SpinGeom s1,
+__global__ __launch_bounds__(512) void k_overlap_theta(int M, int Nt, SpinGeom s0, SpinGeom s1,
                                                        const double* __restrict__ phr,
                                                        const double* __restrict__ phi,
                                                        ThetaOut to, double* ld_re,
                                                        double* ld_im, double* e1_re, double* e1_im) {
   extern __shared__ double lds[];
-  __shared__ double red[4];
+  __shared__ double red[16];
   __shared__ int piv[AFQ_WAVE];
   __shared__ int pk_sh;
   const int w = blockIdx.x, s = blockIdx.y;
@@ -874,6 +874,7 @@ __global__ __launch_bounds__(128, 2) void k_overlap_theta_wave(int M, int Nt, Sp
   }
 }
 
+constexpr int kOvlThreads = 512;  // the block form (N > 32): eight wavefronts
 hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, SpinGeom s1,
                          const double* phr, const double* phi, ThetaOut to, double* ld_re,
                          double* ld_im, double* e1_re, double* e1_im, size_t max_lds) {
@@ -893,11 +894,11 @@ hipError_t overlap_theta(hipStream_t st, int W, int M, int Nt, SpinGeom s0, Spin
   const size_t base = (size_t)(2 * N * (N + 1) + 4 * N) * sizeof(double);
   const size_t staged = base + (size_t)3 * M * N * sizeof(double);
   if (staged <= 65536 && staged <= max_lds) {
-    hipLaunchKernelGGL(k_overlap_theta<true>, dim3(W, 2), dim3(256), staged, st, M, Nt, s0, s1, phr,
+    hipLaunchKernelGGL(k_overlap_theta<true>, dim3(W, 2), dim3(kOvlThreads), staged, st, M, Nt, s0, s1, phr,
                        phi, to, ld_re, ld_im, e1_re, e1_im);
   } else {
     if (base > max_lds) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_overlap_theta<false>, dim3(W, 2), dim3(256), base, st, M, Nt, s0, s1, phr,
+    hipLaunchKernelGGL(k_overlap_theta<false>, dim3(W, 2), dim3(kOvlThreads), base, st, M, Nt, s0, s1, phr,
                        phi, to, ld_re, ld_im, e1_re, e1_im);
   }
   return hipGetLastError();
@@ -1771,14 +1772,14 @@ hipError_t mixed_energy(hipStream_t st, int W, const double* weight, const doubl
 // updated in place in global memory.
 // ===========================================================================
 template <bool STAGE>
-__global__ __launch_bounds__(256) void k_mgs(int M, int Nt, int n_up, int n_dn,
-                                             double* __restrict__ phr, double* __restrict__ phi) {
+__global__ __launch_bounds__(1024) void k_mgs(int M, int Nt, int n_up, int n_dn,
+                                              double* __restrict__ phr, double* __restrict__ phi) {
   extern __shared__ double qs[];
-  __shared__ double red[4];
+  __shared__ double red[16];
   const int w = blockIdx.x, s = blockIdx.y;
   const int N = s ? n_dn : n_up, off = s ? n_up : 0;
   const long wb = (long)w * M * Nt;
-  const int wv = wave_id(), l = lane_id();
+  const int wv = wave_id(), l = lane_id(), nw = blockDim.x / AFQ_WAVE;
   double* Qr = qs;
   double* Qi = qs + (STAGE ? M * N : 0);
   if (STAGE) {
@@ -1804,7 +1805,7 @@ __global__ __launch_bounds__(256) void k_mgs(int M, int Nt, int n_up, int n_dn,
       I(m, j) /= r;
     }
     __syncthreads();
-    for (int k = j + 1 + wv; k < N; k += 4) {
+    for (int k = j + 1 + wv; k < N; k += nw) {  // one wavefront per later column
       double dr = 0.0, di = 0.0;
       for (int m = l; m < M; m += AFQ_WAVE) {
         const double qr = R(m, j), qi = I(m, j);
@@ -1924,9 +1925,9 @@ hipError_t mgs(hipStream_t st, int W, int M, int Nt, int n_up, int n_dn, double*
   }
   const size_t lds = (size_t)2 * M * N * sizeof(double);
   if (lds <= max_lds)
-    hipLaunchKernelGGL(k_mgs<true>, dim3(W, 2), dim3(256), lds, st, M, Nt, n_up, n_dn, phr, phi);
+    hipLaunchKernelGGL(k_mgs<true>, dim3(W, 2), dim3(1024), lds, st, M, Nt, n_up, n_dn, phr, phi);
   else
-    hipLaunchKernelGGL(k_mgs<false>, dim3(W, 2), dim3(256), 0, st, M, Nt, n_up, n_dn, phr, phi);
+    hipLaunchKernelGGL(k_mgs<false>, dim3(W, 2), dim3(1024), 0, st, M, Nt, n_up, n_dn, phr, phi);
   return hipGetLastError();
 }
 
