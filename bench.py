@@ -145,7 +145,8 @@ GOLDEN = {"hchain-M50": ("hchain-M50_W1024_T100.txt", 1024, 100, 1)}
 
 TRAFFIC = {("hchain-M50", "exchange"): "hchain-M50_qform_traffic.json",
            ("hchain-M50", "taylor_b1"): "hchain-M50_taylor_traffic.json",
-           ("tm-multidet-M120", "exchange"): "tm-multidet-M120_md_traffic.json"}
+           ("tm-multidet-M120", "exchange"): "tm-multidet-M120_md_traffic.json",
+           ("sweep-M200", "exchange"): "sweep-M200_bf16x3_exchange_traffic.json"}
 
 
 def measured_traffic(wl_name, cls, chol_prec, taylor_prec):
