@@ -712,8 +712,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(walker sharding is described in DESIGN.md but not built)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(walker sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.serving:
