@@ -50,7 +50,7 @@ typedef enum {
   AFQMC_ERR_STATE = -4,       /* objects do not belong together                */
   AFQMC_ERR_SINGULAR = -5,    /* trial overlap with itself is singular         */
   AFQMC_ERR_NONFINITE = -6,   /* every walker is dead (sum of weights is 0)    */
-  AFQMC_ERR_UNSUPPORTED = -7  /* size or precision outside this build's limits */
+  AFQMC_ERR_UNSUPPORTED = -7  /* size or precision outside the library's limits */
 } afqmc_status;
 
 /* Arithmetic of a contraction (Sec. III: single- vs double-precision).
